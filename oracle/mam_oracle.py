@@ -1,0 +1,255 @@
+"""Plain FP64 CPU oracle of the Method of Averaged Marginals (MAM).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import or run this module.  The HIP library
+never calls it, and it shares no code with the HIP library: it takes plain
+arrays (cost blocks c^(m), weights q^(m)) and follows the paper's steps in the
+paper's notation, one numpy statement per step, in float64, with no blocking,
+fusion or reordering beyond what the paper itself writes.
+
+Paper: Mimouni, Malisani, Zhu, de Oliveira, "Computing Wasserstein barycenter
+via operator splitting: the method of averaged marginals" (arXiv 2309.05315).
+
+Functions and the passage each follows:
+
+* ``proj_simplex_sort``  Prop. 3 (eq. (proj-s)) and the Remark on Delta_R(tau):
+  exact Euclidean projection onto {u >= 0, sum u = tau}; the exact
+  sort-based threshold method that the paper delegates to (Condat 2016).
+* ``marginals``, ``averaging_weights``, ``proj_L``  Prop. 2 (eqs. (pr), (row_sol)).
+* ``dist_L``  the reduction of dist_L to R-vectors stated after Alg. 1.
+* ``unbalanced_prox``  eq. (Unbalanced-prox).
+* ``damping``  the t^k rule of Alg. 1 (Step 1).
+* ``mam``  Alg. 1 with the deterministic choice M^k = {1, ..., M}.
+* ``diagnostics``  the stopping quantities of Sec. 5 (Stopping criteria) and
+  the objective/feasibility figures used in Sec. 6.3.
+
+Readings where the paper is silent or loose (each is listed in the design doc):
+
+* theta^0_rs = q_s / R (Alg. 1 leaves theta^0 arbitrary);
+* the returned barycenter is sum_m a_m p^(m) of the final theta^K (Alg. 1
+  returns p^k without advancing k: one more Step 1 is taken);
+* a zero weight q_s = 0 gives the zero column (Remark on Delta_R(tau));
+* when tau is below the rounding resolution of w, the threshold index j* is
+  clamped to 1, so the column becomes 0 (the sort formula's own result in
+  floating point, stated explicitly so it never divides by zero).
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "proj_simplex_sort",
+    "averaging_weights",
+    "marginals",
+    "proj_L",
+    "dist_L",
+    "unbalanced_prox",
+    "damping",
+    "mam_step",
+    "mam",
+    "diagnostics",
+    "sq_euclid_cost",
+]
+
+
+# ---------------------------------------------------------------------------
+# Prop. 3 / Remark: projection onto the scaled simplex Delta_R(tau)
+# ---------------------------------------------------------------------------
+def proj_simplex_sort(w: np.ndarray, tau) -> tuple:
+    """Project every column of ``w`` (R x n) onto Delta_R(tau_s).
+
+    Sort-based exact method: with u the column sorted in decreasing order,
+    j* = max{ j : u_j > (sum_{i<=j} u_i - tau) / j },
+    lambda = (sum_{i<=j*} u_i - tau) / j*,  result = max(w - lambda, 0).
+    A column with tau_s = 0 projects to 0 (Delta_R(0) = {0}).
+
+    Returns (pi_hat, lam) with lam = +inf for tau_s = 0 columns.
+    """
+    w = np.asarray(w, dtype=np.float64)
+    if w.ndim == 1:
+        p, lam = proj_simplex_sort(w[:, None], np.atleast_1d(tau))
+        return p[:, 0], lam[0]
+    R, n = w.shape
+    tau = np.broadcast_to(np.asarray(tau, dtype=np.float64), (n,))
+    out = np.zeros_like(w)
+    lam = np.full(n, np.inf)
+    pos = tau > 0
+    if not np.any(pos):
+        return out, lam
+    wp = w[:, pos]
+    tp = tau[pos]
+    u = -np.sort(-wp, axis=0)                   # decreasing
+    cs = np.cumsum(u, axis=0)
+    j = np.arange(1, R + 1, dtype=np.float64)[:, None]
+    cond = u > (cs - tp[None, :]) / j
+    # j* = largest j with cond true (cond holds on a prefix); clamp to 1.
+    last_true = R - 1 - np.argmax(cond[::-1, :], axis=0)
+    any_true = cond.any(axis=0)
+    jstar = np.where(any_true, last_true + 1, 1)
+    cols = np.arange(wp.shape[1])
+    lam_p = (cs[jstar - 1, cols] - tp) / jstar
+    out[:, pos] = np.maximum(wp - lam_p[None, :], 0.0)
+    lam[pos] = lam_p
+    return out, lam
+
+
+# ---------------------------------------------------------------------------
+# Prop. 2: projection onto the subspace L of balanced plans
+# ---------------------------------------------------------------------------
+def averaging_weights(S: Sequence[int]) -> np.ndarray:
+    """a_m = (1/S^m) / sum_j (1/S^j), eq. (pr)."""
+    inv = 1.0 / np.asarray(S, dtype=np.float64)
+    return inv / inv.sum()
+
+
+def marginals(theta: List[np.ndarray]) -> np.ndarray:
+    """p^(m)_r = sum_s theta^(m)_rs, eq. (pr); returns an M x R array."""
+    return np.stack([th.sum(axis=1) for th in theta])
+
+
+def proj_L(theta: List[np.ndarray]):
+    """Prop. 2: pi^(m)_rs = theta^(m)_rs + (p_r - p^(m)_r) / S^m.
+
+    Returns (pi, p, pm) with p = sum_m a_m p^(m) and pm the M x R marginals.
+    """
+    S = [th.shape[1] for th in theta]
+    a = averaging_weights(S)
+    pm = marginals(theta)
+    p = (a[:, None] * pm).sum(axis=0)
+    pi = [th + ((p - pm[m]) / S[m])[:, None] for m, th in enumerate(theta)]
+    return pi, p, pm
+
+
+def dist_L(theta: List[np.ndarray]) -> float:
+    """dist_L(theta) = sqrt(sum_m ||p - p^(m)||^2 / S^m) (text after Alg. 1)."""
+    S = [th.shape[1] for th in theta]
+    a = averaging_weights(S)
+    pm = marginals(theta)
+    p = (a[:, None] * pm).sum(axis=0)
+    return math.sqrt(sum(float(((p - pm[m]) ** 2).sum()) / S[m] for m in range(len(S))))
+
+
+def unbalanced_prox(theta: List[np.ndarray], rho: float, gamma: float) -> List[np.ndarray]:
+    """eq. (Unbalanced-prox): prox of gamma * dist_L with parameter rho."""
+    pi, _, _ = proj_L(theta)
+    d = dist_L(theta)
+    if math.isinf(gamma) or rho * d <= gamma:
+        return pi
+    t = gamma / (rho * d)
+    return [th + t * (pl - th) for th, pl in zip(theta, pi)]
+
+
+def damping(p: np.ndarray, pm: np.ndarray, S: Sequence[int], rho: float, gamma: float):
+    """Alg. 1, Step 1: t = 1 if rho * sqrt(sum_m ||p - p^(m)||^2 / S^m) <= gamma,
+    else gamma / (rho * sqrt(...)).  gamma = inf is the balanced case."""
+    d = math.sqrt(sum(float(((p - pm[m]) ** 2).sum()) / S[m] for m in range(len(S))))
+    if math.isinf(gamma) or rho * d <= gamma:
+        return 1.0, d
+    return gamma / (rho * d), d
+
+
+# ---------------------------------------------------------------------------
+# Alg. 1 (deterministic MAM)
+# ---------------------------------------------------------------------------
+def mam_step(theta: List[np.ndarray], pm: np.ndarray, cost: List[np.ndarray],
+             q: List[np.ndarray], rho: float, gamma: float):
+    """One pass of Alg. 1's loop body with M^k = {1, ..., M}.
+
+    Step 1: p^k = sum_m a_m p^(m); t^k from the damping rule.
+    Step 2 (every m, every column s, all with the marginal p^(m) of theta^k):
+        w      = theta^(m)_{:,s} + 2 t^k (p^k - p^(m)) / S^m - c^(m)_{:,s} / rho
+        pi_hat = Proj_{Delta_R(q_s)}(w)
+        theta' = pi_hat - t^k (p^k - p^(m)) / S^m
+    Step 3: p^(m) = row sums of the new theta^(m).
+
+    Returns (theta_new, pm_new, info) where info holds p^k, t^k, the
+    distance d^k and the pi_hat blocks.
+    """
+    S = [th.shape[1] for th in theta]
+    M = len(S)
+    a = averaging_weights(S)
+    p = (a[:, None] * pm).sum(axis=0)                    # Step 1
+    t, d = damping(p, pm, S, rho, gamma)
+    new_theta, pi_hat = [], []
+    for m in range(M):                                    # Step 2
+        corr = t * (p - pm[m]) / S[m]
+        w = theta[m] + 2.0 * corr[:, None] - cost[m] / rho
+        ph, _ = proj_simplex_sort(w, q[m])
+        pi_hat.append(ph)
+        new_theta.append(ph - corr[:, None])
+    pm_new = marginals(new_theta)                         # Step 3
+    return new_theta, pm_new, {"p": p, "t": t, "d": d, "pi_hat": pi_hat}
+
+
+def mam(cost: List[np.ndarray], q: List[np.ndarray], rho: float,
+        gamma: float = math.inf, iters: int = 1,
+        theta0: Optional[List[np.ndarray]] = None, record: bool = False) -> Dict:
+    """Run Alg. 1 for ``iters`` iterations from theta^0.
+
+    cost[m]: R x S^m cost matrix c^(m) (taken as given, Sec. 4 eq. (fm));
+    q[m]: weights q^(m) (length S^m); rho > 0; gamma in [0, inf].
+    theta^0_rs = q_s / R unless ``theta0`` is given.
+
+    Returns a dict with ``p_bar`` (= sum_m a_m p^(m) of theta^K), ``theta``,
+    ``pm``, the last ``pi_hat``, the last ``t`` and, if ``record``, the
+    per-iteration t, d and p histories.
+    """
+    cost = [np.asarray(c, dtype=np.float64) for c in cost]
+    q = [np.asarray(v, dtype=np.float64) for v in q]
+    R = cost[0].shape[0]
+    S = [c.shape[1] for c in cost]
+    if theta0 is None:
+        theta = [np.repeat((qm / R)[None, :], R, axis=0) for qm in q]
+    else:
+        theta = [np.array(th, dtype=np.float64, copy=True) for th in theta0]
+    pm = marginals(theta)                                 # Step 0
+    hist = {"t": [], "d": [], "p": []}
+    info = {"pi_hat": None, "t": None, "p": None}
+    for _ in range(iters):
+        theta, pm_new, info = mam_step(theta, pm, cost, q, rho, gamma)
+        if record:
+            hist["t"].append(info["t"])
+            hist["d"].append(info["d"])
+            hist["p"].append(info["p"])
+        info["pm_old"] = pm
+        pm = pm_new
+    a = averaging_weights(S)
+    p_bar = (a[:, None] * pm).sum(axis=0)
+    out = {"p_bar": p_bar, "theta": theta, "pm": pm, "pi_hat": info["pi_hat"],
+           "t": info["t"], "p_prev": info["p"], "pm_prev": info.get("pm_old")}
+    if record:
+        out["hist"] = hist
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Diagnostics (stopping tests of Sec. 5; objective of Sec. 6.3)
+# ---------------------------------------------------------------------------
+def diagnostics(cost: List[np.ndarray], q: List[np.ndarray], pi_hat: List[np.ndarray],
+                theta_new: List[np.ndarray], theta_old: List[np.ndarray]) -> Dict:
+    """Figures reported for the last iteration.
+
+    W_hat       = sum_m <c^(m), pi_hat^(m)> (the plan objective);
+    dist_L      = dist_L(pi_hat);
+    meas_resid  = max_{m,s} |sum_r pi_hat^(m)_rs - q^(m)_s|;
+    dtheta_inf  = ||theta^{k+1} - theta^k||_inf.
+    """
+    W = sum(float((c * ph).sum()) for c, ph in zip(cost, pi_hat))
+    res = max(float(np.abs(ph.sum(axis=0) - qm).max()) for ph, qm in zip(pi_hat, q))
+    dth = max(float(np.abs(a - b).max()) for a, b in zip(theta_new, theta_old))
+    return {"W_hat": W, "dist_L": dist_L(pi_hat), "meas_resid": res, "dtheta_inf": dth}
+
+
+def sq_euclid_cost(xi: np.ndarray, zeta: np.ndarray, normalize_max: bool = False) -> np.ndarray:
+    """c_rs = ||xi_r - zeta_s||^2 (the cost of (HugeLP)), optionally / max."""
+    xi = np.asarray(xi, dtype=np.float64)
+    zeta = np.asarray(zeta, dtype=np.float64)
+    c = np.zeros((xi.shape[0], zeta.shape[0]))
+    for k in range(xi.shape[1]):
+        c += (xi[:, k][:, None] - zeta[:, k][None, :]) ** 2
+    if normalize_max:
+        c = c / c.max()
+    return c

@@ -1,0 +1,204 @@
+/*
+ * mam.h -- C ABI of the MI355X (gfx950) Method of Averaged Marginals library.
+ *
+ * MAM (Mimouni, Malisani, Zhu, de Oliveira, arXiv 2309.05315) computes a
+ * fixed-support Wasserstein barycenter, balanced or unbalanced, by running
+ * the Douglas-Rachford iteration of Alg. 1 on the M transport plans
+ * theta^(m) in R^{R x S^m}.  One iteration (Alg. 1, Steps 1-3) is
+ *
+ *   p      = sum_m a_m p^(m),  a_m = (1/S^m) / sum_j (1/S^j)      (Prop. 2, eq. (pr))
+ *   t      = 1 if rho*d <= gamma, else gamma/(rho*d),
+ *            d = sqrt(sum_m ||p - p^(m)||^2 / S^m)                (Alg. 1, t^k rule)
+ *   b^(m)  = t (p - p^(m)) / S^m                                  (Prop. 2, eq. (row_sol))
+ *   per column s of measure m:
+ *     w      = theta_{:,s} + 2 b^(m) - c_{:,s} / rho
+ *     pi_hat = Proj_{Delta_R(q_s)}(w)                             (Prop. 3, eq. (proj-s))
+ *     theta_{:,s} <- pi_hat - b^(m)
+ *   p^(m)  = row sums of the new theta^(m)                        (Alg. 1, Step 3)
+ *
+ * and the barycenter is p-bar = sum_m a_m p^(m) of the current plans.
+ *
+ * Conventions shared by every call:
+ *
+ *  * Status: every call returns mam_status; 0 (MAM_OK) is success, negative
+ *    values are errors.  mam_last_error() returns a message for the last
+ *    failure on the calling thread.  No C++ exception crosses this ABI.  A
+ *    failed mam_create leaves nothing allocated.
+ *  * Memory: every device buffer is owned by the caller and must stay valid
+ *    while a handle uses it.  The library allocates no device memory: its
+ *    scratch state lives in a caller-provided workspace whose size
+ *    mam_workspace_bytes() reports.  The library owns only the host handle.
+ *  * Layout: plans are stored column-major.  Global column j = off_m + s
+ *    (off_m = S^1 + ... + S^(m-1)) starts at element j*ld of theta, and its R
+ *    entries are contiguous; rows R..ld-1 are padding that is never written.
+ *    theta holds T*ld elements, T = sum_m S^m.  Cost columns follow the same
+ *    rule with cost_ld.  q (length T) holds every q^(m) concatenated.
+ *    Element type of theta, cost and q: float (MAM_F32) or double (MAM_F64).
+ *    Marginals, barycenter and thresholds are always double.
+ *  * Streams: 'stream' is a hipStream_t passed as void* (NULL = default
+ *    stream).  Work is enqueued on it in order and returns at once, except
+ *    where a call says it synchronizes.
+ *  * Threading: a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef MAM_H
+#define MAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mam_status;
+
+#define MAM_OK             0
+#define MAM_EINVAL        -1  /* invalid argument or size */
+#define MAM_ENOMEM        -2  /* workspace missing or too small */
+#define MAM_EHIP          -3  /* a HIP runtime call failed */
+#define MAM_ENOTBALANCED  -4  /* balanced mode (gamma = inf) with unequal masses */
+#define MAM_ENONFINITE    -5  /* a NaN/Inf or negative weight in the inputs or state */
+#define MAM_EUNSUPPORTED  -6  /* size outside what the kernels handle (R > 8192) */
+#define MAM_ESTATE        -7  /* call out of order (e.g. iterate before init) */
+
+#define MAM_F32 0
+#define MAM_F64 1
+
+/* Cost layout (mam_desc.cost_mode). */
+#define MAM_COST_PER_COLUMN 0  /* cost column j for plan column j (R x T) */
+#define MAM_COST_SHARED     1  /* one R x S cost for every measure: column s of
+                                  measure m uses cost column s (all S^m <= cost_ncols) */
+#define MAM_COST_INDEXED    2  /* plan column j uses cost column cost_col_index[j] */
+
+/* mam_desc.flags */
+#define MAM_FLAG_DIAG 1u       /* compute diagnostics on the last iteration of
+                                  every mam_iterate call */
+
+typedef struct mam_problem mam_problem;
+
+/* Problem description.  The measures' support points enter only through the
+ * cost (squared Euclidean in the paper, (HugeLP)); mam_cost_sq_euclid builds
+ * it from points. */
+typedef struct mam_desc {
+  int32_t dtype;        /* MAM_F32 or MAM_F64: element type of theta, cost, q   */
+  int32_t cost_mode;    /* MAM_COST_*                                           */
+  int64_t R;            /* barycenter support size = rows of every plan, >= 1  */
+  int64_t M;            /* number of measures, >= 1                             */
+  const int64_t* S;     /* host array of M column counts S^m >= 1               */
+  int64_t ld;           /* column stride of theta in elements (0 -> R)          */
+  int64_t cost_ld;      /* column stride of the cost in elements (0 -> R)       */
+  int64_t cost_ncols;   /* number of cost columns held by the cost buffer       */
+  double rho;           /* DR prox parameter rho > 0 (step tau = 1/rho)         */
+  double gamma;         /* unbalanced penalty in [0, inf]; INFINITY = balanced  */
+  uint32_t flags;       /* MAM_FLAG_*                                           */
+} mam_desc;
+
+/* Figures of the last iteration run with diagnostics (Sec. 5, stopping
+ * criteria; Sec. 6.3 objective and feasibility figures). */
+typedef struct mam_diag {
+  int64_t iterations;   /* iterations run since mam_init                        */
+  double t;             /* damping t^k of that iteration (1 when balanced)      */
+  double W_hat;         /* sum_m <c^(m), pi_hat^(m)>                             */
+  double dist_L;        /* dist_L(pi_hat): distance of the plans to balance     */
+  double meas_resid;    /* max_{m,s} |sum_r pi_hat_rs - q_s|                    */
+  double dtheta_inf;    /* ||theta^{k+1} - theta^k||_inf                        */
+  double dp_norm;       /* ||p^{k+1} - p^k||_2                                  */
+  double p_mass;        /* sum_r p_r of the current barycenter                  */
+} mam_diag;
+
+/* Launch schedule of the column kernel (normally chosen by the library). */
+typedef struct mam_schedule {
+  int32_t threads_per_column; /* 64, 256 or 1024 (0 = automatic)               */
+  int32_t workgroups;         /* persistent workgroups per iteration (0 = auto) */
+  int32_t xcd_remap;          /* 1: map consecutive column blocks onto one XCD  */
+  int32_t reserved;
+} mam_schedule;
+
+/* ABI version of this header (1). */
+int32_t mam_abi_version(void);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* mam_last_error(void);
+
+/* Validate d and create a handle.  No HIP call is made.  Errors: MAM_EINVAL
+ * (R, M, S^m < 1; ld < R; rho <= 0 or not finite; gamma < 0 or NaN; unknown
+ * dtype or cost_mode; shared cost with some S^m > cost_ncols),
+ * MAM_EUNSUPPORTED (R > 8192).  On error *out is set to NULL. */
+mam_status mam_create(mam_problem** out, const mam_desc* d);
+
+/* Override the launch schedule; must precede mam_set_workspace. */
+mam_status mam_set_schedule(mam_problem* p, const mam_schedule* s);
+
+/* Read back the schedule in use. */
+mam_status mam_get_schedule(const mam_problem* p, mam_schedule* s);
+
+/* Bytes of device workspace the handle needs (0 for a NULL handle). */
+size_t mam_workspace_bytes(const mam_problem* p);
+
+/* Give the handle its workspace: 'dev' is a device pointer aligned to 256
+ * bytes holding at least mam_workspace_bytes(p) bytes.  Errors: MAM_ENOMEM
+ * if too small, MAM_EINVAL if misaligned. */
+mam_status mam_set_workspace(mam_problem* p, void* dev, size_t bytes);
+
+/* Bind the caller's device buffers: theta (T*ld elements, read and written),
+ * cost (cost_ncols*cost_ld elements, read only), q (T elements, read only),
+ * cost_col_index (T int32 values in [0, cost_ncols), MAM_COST_INDEXED only,
+ * else NULL).  No HIP call is made.  Errors: MAM_EINVAL on NULL buffers or a
+ * missing/unexpected index. */
+mam_status mam_bind(mam_problem* p, void* theta, const void* cost,
+                    const int32_t* cost_col_index, const void* q);
+
+/* Alg. 1, Step 0: theta^0 = q_s/R in every entry of column s (theta0 NULL),
+ * or a copy of the caller's theta0 (same layout); then p^(m) and p.
+ * Validates the inputs on the device and SYNCHRONIZES the stream:
+ * MAM_ENONFINITE for a negative or non-finite weight or cost,
+ * MAM_ENOTBALANCED when gamma = inf and the masses sum q^(m) differ by more
+ * than 1e-6 (MAM_F32) or 1e-12 (MAM_F64) relative. */
+mam_status mam_init(mam_problem* p, const void* theta0, void* stream);
+
+/* Run 'iters' >= 0 deterministic MAM iterations (M^k = all measures,
+ * Alg. 1).  Asynchronous.  Errors: MAM_ESTATE before mam_init. */
+mam_status mam_iterate(mam_problem* p, int64_t iters, void* stream);
+
+/* Barycenter p-bar = sum_m a_m p^(m) of the current plans: R doubles into
+ * the device buffer p_dev (asynchronous) or the host buffer p_host
+ * (synchronizes). */
+mam_status mam_barycenter(mam_problem* p, double* p_dev, void* stream);
+mam_status mam_barycenter_host(mam_problem* p, double* p_host, void* stream);
+
+/* Marginals p^(m) of the current plans: M*R doubles, row m at m*R, into a
+ * device buffer.  Asynchronous. */
+mam_status mam_marginals(mam_problem* p, double* pm_dev, void* stream);
+
+/* Diagnostics of the last iteration that ran with MAM_FLAG_DIAG.
+ * SYNCHRONIZES the stream.  MAM_ESTATE if none ran yet, MAM_ENONFINITE if
+ * the barycenter holds a NaN or Inf (the struct is still filled). */
+mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream);
+
+/* Kernel timing: while enabled, HIP events bracket every launch of the
+ * column kernel on the stream.  mam_timing_read synchronizes and returns the
+ * summed milliseconds and the launch count since the last reset. */
+mam_status mam_timing_enable(mam_problem* p, int32_t enable);
+mam_status mam_timing_read(mam_problem* p, double* total_ms, int64_t* launches);
+
+/* Destroy a handle (NULL is allowed).  Device buffers stay with the caller. */
+void mam_destroy(mam_problem* p);
+
+/* Cost helper (the cost of (HugeLP) from support points):
+ * out[s*out_ld + r] = ||xi_r - zeta_s||^2, divided by its maximum over all
+ * (r, s) when normalize_max != 0.  xi: R*dim doubles (point r at r*dim) and
+ * zeta: S*dim doubles, device pointers; out: S*out_ld elements of 'dtype'
+ * (device).  Distances are formed in double and rounded once to 'dtype'.
+ * normalize_max needs 'scratch', one device double the call overwrites.
+ * Asynchronous.  Errors: MAM_EINVAL on NULL buffers, sizes < 1,
+ * out_ld < R, unknown dtype, or normalize_max without scratch. */
+mam_status mam_cost_sq_euclid(const double* xi, int64_t R, const double* zeta,
+                              int64_t S, int32_t dim, int32_t normalize_max,
+                              void* out, int64_t out_ld, int32_t dtype,
+                              double* scratch, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAM_H */

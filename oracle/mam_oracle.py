@@ -20,6 +20,8 @@ Functions and the passage each follows:
 * ``unbalanced_prox``  eq. (Unbalanced-prox).
 * ``damping``  the t^k rule of Alg. 1 (Step 1).
 * ``mam``  Alg. 1 with the deterministic choice M^k = {1, ..., M}.
+* ``mam_step_columns``  Step 2 of Alg. 1 for a sample of columns (exact,
+  since the columns are independent given the marginals, Prop. 3).
 * ``diagnostics``  the stopping quantities of Sec. 5 (Stopping criteria) and
   the objective/feasibility figures used in Sec. 6.3.
 
@@ -49,6 +51,7 @@ __all__ = [
     "unbalanced_prox",
     "damping",
     "mam_step",
+    "mam_step_columns",
     "mam",
     "diagnostics",
     "sq_euclid_cost",
@@ -182,6 +185,30 @@ def mam_step(theta: List[np.ndarray], pm: np.ndarray, cost: List[np.ndarray],
         new_theta.append(ph - corr[:, None])
     pm_new = marginals(new_theta)                         # Step 3
     return new_theta, pm_new, {"p": p, "t": t, "d": d, "pi_hat": pi_hat}
+
+
+def mam_step_columns(theta_cols: np.ndarray, measure_of_col: Sequence[int], pm: np.ndarray,
+                     cost_cols: np.ndarray, q_cols: np.ndarray, S: Sequence[int],
+                     rho: float, gamma: float):
+    """Alg. 1 Step 2 for a chosen set of columns only.
+
+    Given the marginals p^(m) of theta^k (M x R), every column is updated
+    independently of the others (Prop. 3), so a sample of columns can be
+    advanced exactly: column k belongs to measure measure_of_col[k] and has
+    values theta_cols[:, k], cost cost_cols[:, k] and weight q_cols[k].
+    Returns (theta' columns, pi_hat columns, t).
+    """
+    a = averaging_weights(S)
+    p = (a[:, None] * pm).sum(axis=0)
+    t, _ = damping(p, pm, S, rho, gamma)
+    new, ph_all = [], []
+    for k, m in enumerate(measure_of_col):
+        corr = t * (p - pm[m]) / S[m]
+        w = theta_cols[:, k] + 2.0 * corr - cost_cols[:, k] / rho
+        ph, _ = proj_simplex_sort(w[:, None], np.asarray(q_cols[k:k + 1], dtype=np.float64))
+        ph_all.append(ph[:, 0])
+        new.append(ph[:, 0] - corr)
+    return np.stack(new, axis=1), np.stack(ph_all, axis=1), t
 
 
 def mam(cost: List[np.ndarray], q: List[np.ndarray], rho: float,

@@ -1,0 +1,280 @@
+"""Python binding of libmam.so (ctypes): argument marshalling only.
+
+Every step of the iteration runs in the HIP kernels behind the C ABI of
+``include/mam.h``; torch supplies device memory and the stream.  There is
+no CPU path: if the library is missing, ``lib()`` raises.
+
+Names follow the paper: R (barycenter support size), S (columns S^m of each
+plan), rho (DR prox parameter), gamma (unbalanced penalty, inf = balanced),
+q (measure weights), theta (the DR iterate), p (barycenter).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+__all__ = ["lib", "MAMError", "Solver", "solver_for", "cost_sq_euclid",
+           "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "FLAG_DIAG",
+           "EXPORTED"]
+
+F32, F64 = 0, 1
+COST_PER_COLUMN, COST_SHARED, COST_INDEXED = 0, 1, 2
+FLAG_DIAG = 1
+
+STATUS = {0: "MAM_OK", -1: "MAM_EINVAL", -2: "MAM_ENOMEM", -3: "MAM_EHIP",
+          -4: "MAM_ENOTBALANCED", -5: "MAM_ENONFINITE", -6: "MAM_EUNSUPPORTED",
+          -7: "MAM_ESTATE"}
+
+EXPORTED = ["mam_abi_version", "mam_last_error", "mam_create", "mam_set_schedule",
+            "mam_get_schedule", "mam_workspace_bytes", "mam_set_workspace", "mam_bind",
+            "mam_init", "mam_iterate", "mam_barycenter", "mam_barycenter_host",
+            "mam_marginals", "mam_diagnostics", "mam_timing_enable", "mam_timing_read",
+            "mam_destroy", "mam_cost_sq_euclid"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmam.so")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("cost_mode", ctypes.c_int32),
+                ("R", ctypes.c_int64), ("M", ctypes.c_int64),
+                ("S", ctypes.POINTER(ctypes.c_int64)), ("ld", ctypes.c_int64),
+                ("cost_ld", ctypes.c_int64), ("cost_ncols", ctypes.c_int64),
+                ("rho", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("t", ctypes.c_double),
+                ("W_hat", ctypes.c_double), ("dist_L", ctypes.c_double),
+                ("meas_resid", ctypes.c_double), ("dtheta_inf", ctypes.c_double),
+                ("dp_norm", ctypes.c_double), ("p_mass", ctypes.c_double)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("threads_per_column", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class MAMError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+_LIB = None
+_vp = ctypes.c_void_p
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmam.so from this package directory (raises if it is not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2309_05315_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "mam_abi_version": (ctypes.c_int32, []),
+        "mam_last_error": (ctypes.c_char_p, []),
+        "mam_create": (ctypes.c_int32, [ctypes.POINTER(_vp), ctypes.POINTER(Desc)]),
+        "mam_set_schedule": (ctypes.c_int32, [_vp, ctypes.POINTER(Schedule)]),
+        "mam_get_schedule": (ctypes.c_int32, [_vp, ctypes.POINTER(Schedule)]),
+        "mam_workspace_bytes": (ctypes.c_size_t, [_vp]),
+        "mam_set_workspace": (ctypes.c_int32, [_vp, _vp, ctypes.c_size_t]),
+        "mam_bind": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+        "mam_init": (ctypes.c_int32, [_vp, _vp, _vp]),
+        "mam_iterate": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp]),
+        "mam_barycenter": (ctypes.c_int32, [_vp, _vp, _vp]),
+        "mam_barycenter_host": (ctypes.c_int32, [_vp, _vp, _vp]),
+        "mam_marginals": (ctypes.c_int32, [_vp, _vp, _vp]),
+        "mam_diagnostics": (ctypes.c_int32, [_vp, ctypes.POINTER(Diag), _vp]),
+        "mam_timing_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
+        "mam_timing_read": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_int64)]),
+        "mam_destroy": (None, [_vp]),
+        "mam_cost_sq_euclid": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, ctypes.c_int64,
+                                                ctypes.c_int32, ctypes.c_int32, _vp,
+                                                ctypes.c_int64, ctypes.c_int32, _vp, _vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = L
+    return L
+
+
+def _check(code: int, where: str) -> None:
+    if code != 0:
+        raise MAMError(code, where, lib().mam_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _round_up(x: int, k: int) -> int:
+    return (x + k - 1) // k * k
+
+
+class Solver:
+    """One MAM problem on one GPU: a handle, its workspace and bound buffers.
+
+    theta: (T, ld) tensor, row j = plan column j (column-major R x T plans).
+    cost:  (ncols, cost_ld) tensor, row k = cost column k.
+    q:     (T,) tensor of the weights of every measure, concatenated.
+    """
+
+    def __init__(self, R: int, S: Sequence[int], rho: float = 1.0, gamma: float = math.inf,
+                 dtype: torch.dtype = torch.float32, cost_mode: int = COST_SHARED,
+                 cost_ncols: Optional[int] = None, ld: Optional[int] = None,
+                 cost_ld: Optional[int] = None, diag: bool = False,
+                 threads_per_column: int = 0, workgroups: int = 0, xcd_remap: int = 0,
+                 device="cuda"):
+        L = lib()
+        self.device = torch.device(device)
+        self.R, self.S = int(R), [int(s) for s in S]
+        self.M, self.T = len(self.S), int(sum(self.S))
+        self.dtype = dtype
+        vec = 4 if dtype == torch.float32 else 2
+        self.ld = int(ld) if ld else _round_up(self.R, vec)
+        self.cost_ld = int(cost_ld) if cost_ld else _round_up(self.R, vec)
+        if cost_ncols is None:
+            cost_ncols = self.T if cost_mode == COST_PER_COLUMN else max(self.S)
+        self.cost_ncols = int(cost_ncols)
+        self.cost_mode = cost_mode
+        self._S_arr = (ctypes.c_int64 * self.M)(*self.S)
+        d = Desc(dtype=F32 if dtype == torch.float32 else F64, cost_mode=cost_mode,
+                 R=self.R, M=self.M, S=self._S_arr, ld=self.ld, cost_ld=self.cost_ld,
+                 cost_ncols=self.cost_ncols, rho=float(rho), gamma=float(gamma),
+                 flags=FLAG_DIAG if diag else 0)
+        h = _vp()
+        _check(L.mam_create(ctypes.byref(h), ctypes.byref(d)), "mam_create")
+        self._h = h
+        if threads_per_column or workgroups or xcd_remap:
+            sc = Schedule(threads_per_column, workgroups, xcd_remap, 0)
+            _check(L.mam_set_schedule(h, ctypes.byref(sc)), "mam_set_schedule")
+        nbytes = int(L.mam_workspace_bytes(h))
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        _check(L.mam_set_workspace(h, _ptr(self.workspace), nbytes), "mam_set_workspace")
+        self.theta = self.cost = self.q = self.index = None
+
+    # -- buffers -----------------------------------------------------------
+    def bind(self, theta: torch.Tensor, cost: torch.Tensor, q: torch.Tensor,
+             index: Optional[torch.Tensor] = None) -> None:
+        for name, t in (("theta", theta), ("cost", cost), ("q", q)):
+            if t.dtype != self.dtype or t.device.type != "cuda" or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {self.dtype} CUDA tensor")
+        if theta.shape != (self.T, self.ld):
+            raise ValueError(f"theta must have shape {(self.T, self.ld)}")
+        if cost.shape != (self.cost_ncols, self.cost_ld):
+            raise ValueError(f"cost must have shape {(self.cost_ncols, self.cost_ld)}")
+        if q.shape != (self.T,):
+            raise ValueError(f"q must have shape {(self.T,)}")
+        if index is not None and (index.dtype != torch.int32 or index.shape != (self.T,)):
+            raise ValueError("index must be an int32 tensor of length T")
+        self.theta, self.cost, self.q, self.index = theta, cost, q, index
+        _check(lib().mam_bind(self._h, _ptr(theta), _ptr(cost), _ptr(index), _ptr(q)), "mam_bind")
+
+    def schedule(self) -> dict:
+        sc = Schedule()
+        _check(lib().mam_get_schedule(self._h, ctypes.byref(sc)), "mam_get_schedule")
+        return {"threads_per_column": sc.threads_per_column, "workgroups": sc.workgroups,
+                "xcd_remap": sc.xcd_remap, "values_per_thread": sc.reserved}
+
+    # -- iteration ---------------------------------------------------------
+    def init(self, theta0: Optional[torch.Tensor] = None) -> None:
+        _check(lib().mam_init(self._h, _ptr(theta0), _stream(self.device)), "mam_init")
+
+    def iterate(self, iters: int) -> None:
+        _check(lib().mam_iterate(self._h, int(iters), _stream(self.device)), "mam_iterate")
+
+    def barycenter(self) -> torch.Tensor:
+        out = torch.empty(self.R, dtype=torch.float64, device=self.device)
+        _check(lib().mam_barycenter(self._h, _ptr(out), _stream(self.device)), "mam_barycenter")
+        return out
+
+    def marginals(self) -> torch.Tensor:
+        out = torch.empty(self.M, self.R, dtype=torch.float64, device=self.device)
+        _check(lib().mam_marginals(self._h, _ptr(out), _stream(self.device)), "mam_marginals")
+        return out
+
+    def diagnostics(self) -> dict:
+        d = Diag()
+        _check(lib().mam_diagnostics(self._h, ctypes.byref(d), _stream(self.device)),
+               "mam_diagnostics")
+        return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+    def timing(self, enable: bool) -> None:
+        _check(lib().mam_timing_enable(self._h, int(enable)), "mam_timing_enable")
+
+    def timing_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().mam_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)), "mam_timing_read")
+        return ms.value, n.value
+
+    def plans(self) -> list:
+        """theta^(m) as R x S^m float64 numpy arrays (copies, for checking)."""
+        th = self.theta[:, :self.R].double().cpu().numpy()
+        off = np.concatenate([[0], np.cumsum(self.S)])
+        return [th[off[m]:off[m + 1]].T.copy() for m in range(self.M)]
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().mam_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solver_for(problem, device="cuda", diag: bool = False, **sched) -> Solver:
+    """Allocate device buffers for an ``inputs.Problem`` and bind them."""
+    dt = torch.float32 if problem.dtype == "f32" else torch.float64
+    if problem.col_index is None:
+        mode, ncols = COST_SHARED, problem.cost.shape[0]
+    elif np.array_equal(problem.col_index, np.arange(problem.T)):
+        mode, ncols = COST_PER_COLUMN, problem.cost.shape[0]
+    else:
+        mode, ncols = COST_INDEXED, problem.cost.shape[0]
+    s = Solver(problem.R, problem.S, rho=problem.rho, gamma=problem.gamma, dtype=dt,
+               cost_mode=mode, cost_ncols=ncols, diag=diag, device=device, **sched)
+    cost = torch.zeros(ncols, s.cost_ld, dtype=dt)
+    cost[:, :problem.R] = torch.from_numpy(problem.cost).to(dt)
+    theta = torch.zeros(problem.T, s.ld, dtype=dt, device=device)
+    idx = None
+    if mode == COST_INDEXED:
+        idx = torch.from_numpy(problem.col_index.astype(np.int32)).to(device)
+    s.bind(theta, cost.to(device), torch.from_numpy(problem.q).to(dt).to(device), idx)
+    return s
+
+
+def cost_sq_euclid(xi: torch.Tensor, zeta: torch.Tensor, normalize_max: bool = False,
+                   dtype: torch.dtype = torch.float64, ld: Optional[int] = None) -> torch.Tensor:
+    """||xi_r - zeta_s||^2 on the GPU as an (S, ld) tensor (row s = cost column s)."""
+    if xi.dtype != torch.float64 or zeta.dtype != torch.float64:
+        raise ValueError("points must be float64")
+    R, dim = xi.shape
+    S = zeta.shape[0]
+    ld = int(ld) if ld else R
+    out = torch.zeros(S, ld, dtype=dtype, device=xi.device)
+    scratch = torch.empty(1, dtype=torch.float64, device=xi.device)
+    _check(lib().mam_cost_sq_euclid(_ptr(xi.contiguous()), R, _ptr(zeta.contiguous()), S, dim,
+                                    int(normalize_max), _ptr(out), ld,
+                                    F32 if dtype == torch.float32 else F64, _ptr(scratch),
+                                    _stream(xi.device)), "mam_cost_sq_euclid")
+    return out

@@ -1,0 +1,123 @@
+"""The C-ABI library loads, exports every declared symbol, and validates its
+arguments before touching the GPU (CPU only: no compute call is made)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2309_05315_amd import mam
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "mam.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mam_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = mam.lib()
+    decl = declared_functions()
+    assert len(decl) >= 18
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(mam.EXPORTED) == decl
+    assert L.mam_abi_version() == 1
+
+
+def desc(**kw):
+    S = kw.pop("S", [5, 7])
+    arr = (ctypes.c_int64 * len(S))(*S)
+    d = mam.Desc(dtype=kw.pop("dtype", mam.F64), cost_mode=kw.pop("cost_mode", mam.COST_PER_COLUMN),
+                 R=kw.pop("R", 16), M=len(S), S=arr, ld=kw.pop("ld", 0), cost_ld=kw.pop("cost_ld", 0),
+                 cost_ncols=kw.pop("cost_ncols", sum(S)), rho=kw.pop("rho", 1.0),
+                 gamma=kw.pop("gamma", math.inf), flags=0)
+    assert not kw
+    return d, arr
+
+
+def create(**kw):
+    d, arr = desc(**kw)
+    h = ctypes.c_void_p()
+    rc = mam.lib().mam_create(ctypes.byref(h), ctypes.byref(d))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(R=0), -1), (dict(S=[3, 0]), -1), (dict(rho=0.0), -1), (dict(rho=-2.0), -1),
+    (dict(rho=math.inf), -1), (dict(gamma=-1.0), -1), (dict(gamma=math.nan), -1),
+    (dict(dtype=7), -1), (dict(cost_mode=9), -1), (dict(ld=8), -1), (dict(cost_ld=3), -1),
+    (dict(cost_mode=mam.COST_SHARED, cost_ncols=5), -1),
+    (dict(cost_ncols=3), -1), (dict(R=8193), -6),
+])
+def test_create_rejects(kw, code):
+    rc, h = create(**kw)
+    assert rc == code
+    assert not h.value
+    assert mam.lib().mam_last_error()
+
+
+def test_create_accepts_and_sizes_workspace():
+    L = mam.lib()
+    rc, h = create(R=300, S=[40, 1, 17])
+    assert rc == 0 and h.value
+    n = L.mam_workspace_bytes(h)
+    assert n > 0 and n % 256 == 0
+    sc = mam.Schedule()
+    assert L.mam_get_schedule(h, ctypes.byref(sc)) == 0
+    assert sc.threads_per_column == 64 and sc.reserved == 8
+    # workspace checks are pure pointer/size checks
+    assert L.mam_set_workspace(h, ctypes.c_void_p(0x100000 + 8), n) == -1
+    assert L.mam_set_workspace(h, ctypes.c_void_p(0x100000), n - 1) == -2
+    assert L.mam_set_workspace(h, None, n) == -2
+    # out-of-order calls
+    assert L.mam_iterate(h, 1, None) == -7
+    assert L.mam_init(h, None, None) == -7
+    assert L.mam_bind(h, None, None, None, None) == -1
+    L.mam_destroy(h)
+    L.mam_destroy(None)
+
+
+def test_schedule_override_validation():
+    L = mam.lib()
+    rc, h = create(R=4096, S=[100])
+    assert rc == 0
+    bad = mam.Schedule(100, 0, 0, 0)
+    assert L.mam_set_schedule(h, ctypes.byref(bad)) == -1
+    small = mam.Schedule(64, 0, 0, 0)       # 4096 rows at 64 threads = 64 values per lane
+    assert L.mam_set_schedule(h, ctypes.byref(small)) == -6
+    tiny = mam.Schedule(128, 0, 0, 0)       # 32 values per thread
+    assert L.mam_set_schedule(h, ctypes.byref(tiny)) == -6
+    ok = mam.Schedule(1024, 37, 1, 0)
+    assert L.mam_set_schedule(h, ctypes.byref(ok)) == 0
+    sc = mam.Schedule()
+    L.mam_get_schedule(h, ctypes.byref(sc))
+    assert (sc.threads_per_column, sc.workgroups, sc.xcd_remap, sc.reserved) == (1024, 37, 1, 4)
+    L.mam_destroy(h)
+
+
+def test_indexed_mode_requires_index():
+    L = mam.lib()
+    rc, h = create(cost_mode=mam.COST_INDEXED, cost_ncols=4)
+    assert rc == 0
+    fake = ctypes.c_void_p(0x200000)
+    assert L.mam_bind(h, fake, fake, None, fake) == -1
+    rc2, h2 = create()
+    assert L.mam_bind(h2, fake, fake, fake, fake) == -1       # index given in per-column mode
+    assert L.mam_bind(h2, ctypes.c_void_p(0x200001), fake, None, fake) == -1   # misaligned
+    assert L.mam_bind(h2, fake, fake, None, fake) == 0
+    L.mam_destroy(h)
+    L.mam_destroy(h2)
+
+
+def test_cost_helper_validation():
+    L = mam.lib()
+    fake = ctypes.c_void_p(0x300000)
+    assert L.mam_cost_sq_euclid(None, 4, fake, 4, 2, 0, fake, 4, 1, None, None) == -1
+    assert L.mam_cost_sq_euclid(fake, 4, fake, 4, 2, 0, fake, 3, 1, None, None) == -1
+    assert L.mam_cost_sq_euclid(fake, 4, fake, 4, 2, 1, fake, 4, 1, None, None) == -1
+    assert L.mam_cost_sq_euclid(fake, 4, fake, 4, 2, 0, fake, 4, 5, None, None) == -1

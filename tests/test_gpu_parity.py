@@ -1,0 +1,233 @@
+"""HIP path vs the FP64 oracle, element by element (MI355X only).
+
+Tolerances (relative): 1e-10 for FP64 plans, 1e-5 for FP32 plans, on the
+barycenter (L1 and max norms) and, for FP64, on the plans themselves.  The
+oracle consumes exactly the (rounded) inputs the GPU consumes.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mam_oracle as O
+from paper_2309_05315_amd import inputs
+from paper_2309_05315_amd import mam
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def blocks(p):
+    return [p.cost_block(m) for m in range(p.M)], [p.q_block(m) for m in range(p.M)]
+
+
+def rel(a, b, ord=1):
+    a, b = np.asarray(a, dtype=np.float64).ravel(), np.asarray(b, dtype=np.float64).ravel()
+    if ord == 1:
+        return float(np.abs(a - b).sum() / max(np.abs(b).sum(), 1e-300))
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def run_gpu(p, iters, diag=False, **sched):
+    s = mam.solver_for(p, diag=diag, **sched)
+    s.init()
+    s.iterate(iters)
+    pb = s.barycenter().cpu().numpy()
+    out = {"p_bar": pb, "theta": s.plans(), "pm": s.marginals().cpu().numpy(), "solver": s}
+    if diag:
+        out["diag"] = s.diagnostics()
+    return out
+
+
+def check(p, iters, gate_theta=True, **sched):
+    say(f"case {p.name} dtype={p.dtype} R={p.R} S={p.S[:4]}... iters={iters} sched={sched}")
+    cost, q = blocks(p)
+    ora = O.mam(cost, q, p.rho, p.gamma, iters)
+    g = run_gpu(p, iters, **sched)
+    tol = TOL[p.dtype]
+    e1, einf = rel(g["p_bar"], ora["p_bar"]), rel(g["p_bar"], ora["p_bar"], np.inf)
+    eth = max(rel(a, b, np.inf) for a, b in zip(g["theta"], ora["theta"]))
+    say(f"  p_bar rel L1 {e1:.3e}  max {einf:.3e}  theta rel max {eth:.3e}")
+    assert e1 <= tol and einf <= tol
+    if gate_theta and p.dtype == "f64":
+        assert eth <= tol
+    np.testing.assert_allclose(g["pm"], ora["pm"], rtol=0, atol=tol * np.abs(ora["pm"]).max() * 10)
+    return g, ora
+
+
+def test_gpu_present():
+    assert torch.cuda.is_available(), "the gpu tests need an MI355X"
+    mam.lib()
+
+
+def test_balanced_plain_full_run_fp64():
+    """16x16 grid, M = 4, FP64, 200 iterations (Gaussian-tail weights down to ~1e-87)."""
+    check(inputs.balanced_plain(), 200)
+
+
+@pytest.mark.parametrize("R,S,dtype", [
+    (1, [3, 2], "f64"), (5, [7, 1, 4], "f64"), (63, [9, 17], "f32"), (64, [40], "f64"),
+    (65, [20, 30], "f32"), (200, [33, 12, 50], "f64"), (257, [31, 8], "f32"),
+    (513, [40, 21], "f64"), (1000, [25, 19, 7], "f32"), (1024, [30, 30], "f64"),
+    (1030, [17, 23], "f32"), (2049, [20, 11], "f64"), (4096, [24, 9], "f32"),
+    (4099, [10, 13], "f64"), (5000, [6, 5], "f64"), (8192, [4, 3], "f32"),
+])
+def test_shapes_ragged(R, S, dtype):
+    """Every column shape (threads per column x values per thread, vector and
+    scalar tails), per-column costs, zero weights, uneven S^m."""
+    p = inputs.tiny_problem(R + len(S), R=R, S=S, dtype=dtype, zero_frac=0.15, iters=12)
+    check(p, 12)
+
+
+@pytest.mark.parametrize("gamma,dtype", [(0.01, "f64"), (0.01, "f32"), (0.3, "f64"), (0.0, "f64")])
+def test_unbalanced(gamma, dtype):
+    p = inputs.unbalanced_dense(K=16, M=10, iters=60, gamma=gamma, dtype=dtype)
+    g, ora = check(p, 60)
+    if gamma > 0:
+        assert ora["t"] < 1.0           # the damping branch is exercised
+
+
+def test_unbalanced_damping_history():
+    """t^k of every iteration equals the oracle's."""
+    p = inputs.unbalanced_dense(K=8, M=5, gamma=0.01, dtype="f64")
+    cost, q = blocks(p)
+    ora = O.mam(cost, q, p.rho, p.gamma, 25, record=True)
+    s = mam.solver_for(p, diag=True)
+    s.init()
+    ts = []
+    for k in range(25):
+        s.iterate(1)
+        ts.append(s.diagnostics()["t"])
+    np.testing.assert_allclose(ts, ora["hist"]["t"], rtol=1e-12)
+    assert min(ts) < 1.0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_indexed_sparse_quarter_scale(dtype):
+    """Sparse supports (zero pixels removed) with the grid cost gathered by index."""
+    p = inputs.balanced_sparse(K=24, M=8, iters=40, dtype=dtype)
+    check(p, 40)
+
+
+@pytest.mark.parametrize("nt,nwg,remap", [
+    (64, 1, 0), (64, 0, 1), (128, 7, 0), (256, 0, 0), (512, 3, 1), (1024, 0, 0), (256, 10000, 0),
+])
+def test_schedules(nt, nwg, remap):
+    p = inputs.tiny_problem(77, R=900, S=[37, 5, 61, 12], dtype="f64", zero_frac=0.1, iters=15)
+    check(p, 15, threads_per_column=nt, workgroups=nwg, xcd_remap=remap)
+
+
+def test_bitwise_determinism():
+    p = inputs.balanced_sparse(K=16, M=6, iters=30, dtype="f32")
+    a = run_gpu(p, 30)
+    b = run_gpu(p, 30)
+    assert np.array_equal(a["p_bar"], b["p_bar"])
+    for x, y in zip(a["theta"], b["theta"]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("gamma", [math.inf, 0.05])
+def test_diagnostics_match_oracle(gamma):
+    masses = None if math.isinf(gamma) else [0.7, 1.0, 1.3]
+    p = inputs.tiny_problem(5, R=300, S=[40, 70, 25], masses=masses, gamma=gamma, dtype="f64")
+    cost, q = blocks(p)
+    k = 9
+    prev = O.mam(cost, q, p.rho, p.gamma, k - 1)
+    ora = O.mam(cost, q, p.rho, p.gamma, k)
+    od = O.diagnostics(cost, q, ora["pi_hat"], ora["theta"], prev["theta"])
+    g = run_gpu(p, k, diag=True)
+    gd = g["diag"]
+    assert gd["iterations"] == k
+    assert abs(gd["W_hat"] - od["W_hat"]) <= 1e-10 * abs(od["W_hat"])
+    assert abs(gd["dist_L"] - od["dist_L"]) <= 1e-8 * max(od["dist_L"], 1e-12)
+    assert gd["meas_resid"] <= 1e-14 and od["meas_resid"] <= 1e-14
+    assert abs(gd["dtheta_inf"] - od["dtheta_inf"]) <= 1e-10 * od["dtheta_inf"]
+    np.testing.assert_allclose(gd["dp_norm"], np.linalg.norm(ora["p_bar"] - prev["p_bar"]), rtol=1e-8)
+    np.testing.assert_allclose(gd["t"], ora["t"], rtol=1e-12)
+
+
+def test_custom_start_and_resume():
+    """theta^0 given by the caller; iterate(a) then iterate(b) equals iterate(a+b)."""
+    p = inputs.tiny_problem(8, R=128, S=[20, 30], dtype="f64")
+    cost, q = blocks(p)
+    rng = np.random.default_rng(3)
+    th0 = [np.abs(rng.normal(size=(128, s))) * 1e-3 for s in p.S]
+    ora = O.mam(cost, q, p.rho, p.gamma, 10, theta0=th0)
+    s = mam.solver_for(p)
+    t0 = torch.zeros_like(s.theta)
+    t0[:, :128] = torch.from_numpy(np.concatenate([t.T for t in th0])).to(s.theta)
+    s.init(t0)
+    s.iterate(4)
+    s.iterate(6)
+    assert rel(s.barycenter().cpu().numpy(), ora["p_bar"]) <= 1e-10
+    for a, b in zip(s.plans(), ora["theta"]):
+        assert rel(a, b, np.inf) <= 1e-10
+
+
+def test_edge_cases():
+    # M = 1 (the barycenter of one measure), S^m = 1 columns, all-zero measure columns
+    for p in (inputs.tiny_problem(1, R=50, S=[30], dtype="f64"),
+              inputs.tiny_problem(2, R=70, S=[1, 1, 1], dtype="f64"),
+              inputs.tiny_problem(3, R=33, S=[12, 9], dtype="f64", zero_frac=0.9)):
+        check(p, 20)
+    # zero iterations: the barycenter of theta^0 = q/R is (mass / R) everywhere
+    p = inputs.tiny_problem(4, R=10, S=[3, 4], dtype="f64")
+    g = run_gpu(p, 0)
+    np.testing.assert_allclose(g["p_bar"], np.full(10, 0.1), rtol=1e-15)
+
+
+def test_input_errors():
+    p = inputs.tiny_problem(6, R=40, S=[5, 6], dtype="f64")
+    s = mam.solver_for(p)
+    q_bad = s.q.clone()
+    q_bad[0] = q_bad[0] * 1.5                      # masses differ in balanced mode
+    s.bind(s.theta, s.cost, q_bad)
+    with pytest.raises(mam.MAMError) as e:
+        s.init()
+    assert e.value.status == "MAM_ENOTBALANCED"
+    q_neg = s.q.clone()
+    q_neg[1] = -q_neg[1]
+    s.bind(s.theta, s.cost, q_neg)
+    with pytest.raises(mam.MAMError) as e:
+        s.init()
+    assert e.value.status == "MAM_ENONFINITE"
+    c_nan = s.cost.clone()
+    c_nan[2, 3] = float("nan")
+    s.bind(s.theta, c_nan, s.q.new_tensor(p.q))
+    with pytest.raises(mam.MAMError) as e:
+        s.init()
+    assert e.value.status == "MAM_ENONFINITE"
+    with pytest.raises(mam.MAMError):
+        mam.Solver(40, [5, 6], dtype=torch.float64, cost_mode=mam.COST_PER_COLUMN).iterate(1)
+
+
+def test_index_out_of_range_rejected():
+    p = inputs.balanced_sparse(K=8, M=3, dtype="f64")
+    s = mam.solver_for(p)
+    bad = s.index.clone()
+    bad[5] = p.cost.shape[0]
+    s.bind(s.theta, s.cost, s.q, bad)
+    with pytest.raises(mam.MAMError) as e:
+        s.init()
+    assert e.value.status == "MAM_ENONFINITE"
+
+
+def test_cost_helper():
+    K = 12
+    pts = inputs.grid_points(K)
+    zeta = np.random.default_rng(1).uniform(0, 1, size=(37, 2))
+    xi_t = torch.from_numpy(pts).cuda()
+    z_t = torch.from_numpy(zeta).cuda()
+    for norm in (False, True):
+        ref = O.sq_euclid_cost(pts, zeta, normalize_max=norm)
+        got = mam.cost_sq_euclid(xi_t, z_t, normalize_max=norm, dtype=torch.float64).cpu().numpy()
+        np.testing.assert_allclose(got.T, ref, rtol=1e-14, atol=1e-16)
+        g32 = mam.cost_sq_euclid(xi_t, z_t, normalize_max=norm, dtype=torch.float32, ld=K * K + 3)
+        np.testing.assert_allclose(g32[:, :K * K].cpu().numpy().T, ref, rtol=1e-7, atol=1e-8)

@@ -229,3 +229,19 @@ def test_init_and_return_readings():
     r1 = O.mam(cost, q, 1.0, iters=3)
     pi, p_proj, _ = O.proj_L(r1["theta"])
     np.testing.assert_allclose(r1["p_bar"], p_proj, atol=1e-16)
+
+
+def test_sampled_columns_match_full_step():
+    p = inputs.tiny_problem(4, R=9, S=[5, 7, 3], masses=[0.9, 1.0, 1.1])
+    cost, q = blocks(p)
+    rng = np.random.default_rng(0)
+    theta = [rng.normal(scale=0.1, size=(9, s)) for s in p.S]
+    pm = O.marginals(theta)
+    full, _, _ = O.mam_step(theta, pm, cost, q, 1.7, 0.05)
+    picks = [(0, 1), (1, 6), (2, 0), (1, 2)]
+    cols = np.stack([theta[m][:, s] for m, s in picks], axis=1)
+    ccols = np.stack([cost[m][:, s] for m, s in picks], axis=1)
+    qcols = np.array([q[m][s] for m, s in picks])
+    got, _, _ = O.mam_step_columns(cols, [m for m, _ in picks], pm, ccols, qcols, p.S, 1.7, 0.05)
+    for k, (m, s) in enumerate(picks):
+        np.testing.assert_array_equal(got[:, k], full[m][:, s])

@@ -73,6 +73,9 @@ typedef int32_t mam_status;
 /* mam_desc.flags */
 #define MAM_FLAG_DIAG 1u       /* compute diagnostics on the last iteration of
                                   every mam_iterate call */
+#define MAM_FLAG_COLD 2u       /* start every threshold search from w_max - q_s
+                                  instead of the column's previous threshold
+                                  (same results; for testing and timing) */
 
 typedef struct mam_problem mam_problem;
 
@@ -104,14 +107,21 @@ typedef struct mam_diag {
   double dtheta_inf;    /* ||theta^{k+1} - theta^k||_inf                        */
   double dp_norm;       /* ||p^{k+1} - p^k||_2                                  */
   double p_mass;        /* sum_r p_r of the current barycenter                  */
+  double rounds_per_column;  /* threshold rounds per column with q_s > 0        */
+  double active_per_column;  /* entries with pi_hat > 0 per such column         */
 } mam_diag;
 
-/* Launch schedule of the column kernel (normally chosen by the library). */
+/* Launch schedule of the column kernel (normally chosen by the library).
+ * In mam_set_schedule a 0 field means automatic; values_per_thread and
+ * vector_width are outputs of mam_get_schedule only. */
 typedef struct mam_schedule {
-  int32_t threads_per_column; /* 64, 256 or 1024 (0 = automatic)               */
-  int32_t workgroups;         /* persistent workgroups per iteration (0 = auto) */
-  int32_t xcd_remap;          /* 1: map consecutive column blocks onto one XCD  */
-  int32_t reserved;
+  int32_t threads_per_column; /* 64, 128, 256, 512 or 1024 threads per column  */
+  int32_t values_per_thread;  /* rows held per thread (out)                     */
+  int32_t columns_in_flight;  /* columns a group advances together: 1, 2 or 4   */
+  int32_t workgroups;         /* workgroups per iteration, each owning a
+                                 contiguous run of columns                       */
+  int32_t xcd_remap;          /* 1: consecutive runs on one XCD (shared L2)      */
+  int32_t vector_width;       /* elements per load: 4 (float), 2 (double) or 1 (out) */
 } mam_schedule;
 
 /* ABI version of this header (1). */

@@ -45,10 +45,11 @@ mam_status fail(mam_status code, const char* fmt, ...) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kMaxLds = 160 * 1024;  // LDS per compute unit on gfx950
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t partial, pm, pm_prev, p, p_prev, d2part, tval, diag, check;
+  size_t partial, pm, pm_prev, p, p_prev, d2part, tval, diag, check, lam;
   size_t seg_m, seg_j0, seg_j1, wg_seg, mseg, col_off, Sd, aw;
   size_t total;
 };
@@ -65,8 +66,8 @@ struct mam_problem {
   std::vector<double> Sd, aw;
 
   // schedule
-  int nt = 0, vpt = 0, ng = 0, nwg = 0, xcd_remap = 0;
-  int nt_req = 0, nwg_req = 0;
+  int nt = 0, vpt = 0, ng = 0, nwg = 0, xcd_remap = 0, kc = 1;
+  int nt_req = 0, nwg_req = 0, kc_req = 0;
   std::vector<int32_t> seg_m, wg_seg, mseg;
   std::vector<int64_t> seg_j0, seg_j1;
   int nb = 0;  // average-kernel blocks = d^2 partials
@@ -108,22 +109,28 @@ mam_status choose_shape(mam_problem* p) {
   const int64_t R = p->R;
   int nt = p->nt_req;
   if (nt == 0) {
-    // one wave per column while a lane holds at most 16 values; beyond
-    // that the smallest workgroup that keeps 8 values per thread
-    if (R <= 1024) nt = 64;
-    else if (R <= 2048) nt = 256;
-    else if (R <= 4096) nt = 512;
-    else nt = 1024;
+    // The fewest threads per column that keep a thread at 16 (float) or 8
+    // (double) values: a column group then fits twice per compute unit
+    // (registers and LDS), which measured fastest on MI355X; one wave per
+    // column whenever that suffices (no barriers in the threshold rounds).
+    const int64_t target = p->dtype == MAM_F32 ? 16 : 8;
+    nt = 64;
+    while (nt < 1024 && (int64_t)nt * target < R) nt *= 2;
   }
   if (nt != 64 && nt != 128 && nt != 256 && nt != 512 && nt != 1024)
     return fail(MAM_EINVAL, "threads_per_column must be 64, 128, 256, 512 or 1024 (got %d)", nt);
   int64_t per = (R + nt - 1) / nt;
   int vpt = pow2_ceil(per);
+  if (nt >= 128 && vpt < 4) vpt = 4;  // multi-wave groups hold at least 4 values per thread
   if (vpt > 16) return fail(MAM_EUNSUPPORTED, "R = %lld needs more than 16 values per thread at %d threads per column", (long long)R, nt);
-  if ((int64_t)vpt * nt * 8 > 65536)
-    return fail(MAM_EUNSUPPORTED, "R = %lld at %d threads per column needs more than 64 KiB of LDS", (long long)R, nt);
+  const int ng = nt == 64 ? 4 : 1;
+  if ((int64_t)vpt * nt * 8 * (1 + ng) > kMaxLds)
+    return fail(MAM_EUNSUPPORTED, "R = %lld at %d threads per column needs more than 160 KiB of LDS", (long long)R, nt);
+  int kc = p->kc_req ? p->kc_req : 1;
+  if (kc != 1 && kc != 2 && kc != 4) return fail(MAM_EINVAL, "columns_in_flight must be 1, 2 or 4 (got %d)", kc);
   p->nt = nt;
   p->vpt = vpt;
+  p->kc = kc;
   p->ng = nt == 64 ? 4 : 1;
   return MAM_OK;
 }
@@ -179,7 +186,8 @@ void build_schedule(mam_problem* p) {
   L.p_prev = take(R * 8);
   L.d2part = take((size_t)p->nb * 8);
   L.tval = take(8);
-  L.diag = take((size_t)nwg * 4 * 8);
+  L.diag = take((size_t)nwg * mam::DIAG_STRIDE * 8);
+  L.lam = take((size_t)p->T * 8);
   L.check = take((M + 2) * 8);
   L.seg_m = take(nseg * 4);
   L.seg_j0 = take(nseg * 8);
@@ -230,7 +238,7 @@ mam_status launch_column(mam_problem* p, hipStream_t st, int diag) {
   a.p = at<double>(p, L.p);
   a.d2part = at<double>(p, L.d2part);
   a.nb = p->nb;
-  a.diag_on = diag;
+  a.warm = (p->flags & MAM_FLAG_COLD) ? 0 : 1;
   a.rho = p->rho;
   a.inv_rho = 1.0 / p->rho;
   a.gamma = p->gamma;
@@ -241,14 +249,21 @@ mam_status launch_column(mam_problem* p, hipStream_t st, int diag) {
   a.seg_j1 = at<int64_t>(p, L.seg_j1);
   a.wg_seg = at<int32_t>(p, L.wg_seg);
   a.partial = at<double>(p, L.partial);
+  a.lam = at<double>(p, L.lam);
   a.t_out = at<double>(p, L.tval);
   a.diag = at<double>(p, L.diag);
   a.nwg = p->nwg;
   a.xcd_remap = p->xcd_remap;
-  mam::ColFn<T> fn = mam::pick_column<T>(p->nt, p->vpt, p->vec, diag);
-  if (!fn) return fail(MAM_EUNSUPPORTED, "no column kernel for nt=%d vpt=%d", p->nt, p->vpt);
+  const int kc = p->vec == 1 ? 1 : p->kc;
+  mam::ColFn<T> fn = mam::pick_column<T>(p->nt, p->vpt, p->vec, kc, diag);
+  if (!fn) return fail(MAM_EUNSUPPORTED, "no column kernel for nt=%d vpt=%d vec=%d kc=%d", p->nt, p->vpt, p->vec, kc);
   const int wgsize = p->nt == 64 ? 256 : p->nt;
-  const size_t shmem = (size_t)p->vpt * p->nt * 8 + (p->ng > 1 ? (size_t)p->R * 8 : 0);
+  const size_t shmem = (size_t)p->vpt * p->nt * 8 * (1 + p->ng);
+  if (shmem > 65536) {
+    // above the default dynamic-LDS limit: opt this kernel in once
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shmem));
+  }
   hipLaunchKernelGGL(fn, dim3(p->nwg), dim3(wgsize), shmem, st, a);
   LAUNCH_CHECK("column_kernel");
   return MAM_OK;
@@ -280,6 +295,9 @@ mam_status launch_init(mam_problem* p, const void* theta0, hipStream_t st) {
                        (int)p->R, static_cast<const T*>(p->q), p->T);
     LAUNCH_CHECK("fill_kernel");
   }
+  hipLaunchKernelGGL(mam::fill_value_kernel, dim3((unsigned)std::min<int64_t>(4096, (p->T + 255) / 256)), dim3(256), 0,
+                     st, at<double>(p, L.lam), p->T, (double)NAN);
+  LAUNCH_CHECK("fill_value_kernel");
   hipLaunchKernelGGL(mam::rowsum_kernel<T>, dim3(p->nwg), dim3(256), 0, st, static_cast<const T*>(p->theta),
                      p->ld, (int)p->R, at<int64_t>(p, L.seg_j0), at<int64_t>(p, L.seg_j1),
                      at<int32_t>(p, L.wg_seg), at<double>(p, L.partial));
@@ -375,6 +393,7 @@ mam_status mam_create(mam_problem** out, const mam_desc* d) {
   p->rho = d->rho;
   p->gamma = d->gamma;
   p->flags = d->flags;
+  p->vec = vec_width(d->dtype);  // until mam_bind checks the alignment
   p->S.assign(d->S, d->S + d->M);
   p->col_off.assign(d->M + 1, 0);
   for (int64_t m = 0; m < d->M; ++m) p->col_off[m + 1] = p->col_off[m] + d->S[m];
@@ -399,15 +418,18 @@ mam_status mam_create(mam_problem** out, const mam_desc* d) {
 mam_status mam_set_schedule(mam_problem* p, const mam_schedule* s) {
   if (!p || !s) return fail(MAM_EINVAL, "NULL argument");
   if (p->ws) return fail(MAM_ESTATE, "schedule must be set before the workspace");
+  const int nt0 = p->nt_req, kc0 = p->kc_req;
   p->nt_req = s->threads_per_column;
-  p->nwg_req = s->workgroups;
-  p->xcd_remap = s->xcd_remap ? 1 : 0;
+  p->kc_req = s->columns_in_flight;
   mam_status st = choose_shape(p);
   if (st != MAM_OK) {
-    p->nt_req = 0;
+    p->nt_req = nt0;
+    p->kc_req = kc0;
     choose_shape(p);
     return st;
   }
+  p->nwg_req = s->workgroups;
+  p->xcd_remap = s->xcd_remap ? 1 : 0;
   build_schedule(p);
   return MAM_OK;
 }
@@ -415,9 +437,11 @@ mam_status mam_set_schedule(mam_problem* p, const mam_schedule* s) {
 mam_status mam_get_schedule(const mam_problem* p, mam_schedule* s) {
   if (!p || !s) return fail(MAM_EINVAL, "NULL argument");
   s->threads_per_column = p->nt;
+  s->values_per_thread = p->vpt;
+  s->columns_in_flight = p->vec == 1 ? 1 : p->kc;
   s->workgroups = p->nwg;
   s->xcd_remap = p->xcd_remap;
-  s->reserved = p->vpt;
+  s->vector_width = p->vec;
   return MAM_OK;
 }
 
@@ -545,7 +569,7 @@ mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream) {
   if (!p->inited || !p->diag_valid) return fail(MAM_ESTATE, "no iteration ran with MAM_FLAG_DIAG");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t R = p->R, M = p->M;
-  std::vector<double> pm(M * R), pmp(M * R), pv(R), pp(R), dg((size_t)p->nwg * 4);
+  std::vector<double> pm(M * R), pmp(M * R), pv(R), pp(R), dg((size_t)p->nwg * mam::DIAG_STRIDE);
   double t = 0.0;
   const Layout& L = p->lay;
   HIP_TRY(hipMemcpyAsync(pm.data(), p->ws + L.pm, M * R * 8, hipMemcpyDeviceToHost, st));
@@ -558,11 +582,18 @@ mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream) {
   mam_diag r{};
   r.iterations = p->iters_done;
   r.t = t;
+  double rounds = 0.0, active = 0.0, cols = 0.0;
   for (int w = 0; w < p->nwg; ++w) {
-    r.W_hat += dg[(size_t)w * 4];
-    r.meas_resid = std::max(r.meas_resid, dg[(size_t)w * 4 + 1]);
-    r.dtheta_inf = std::max(r.dtheta_inf, dg[(size_t)w * 4 + 2]);
+    const double* o = &dg[(size_t)w * mam::DIAG_STRIDE];
+    r.W_hat += o[0];
+    r.meas_resid = std::max(r.meas_resid, o[1]);
+    r.dtheta_inf = std::max(r.dtheta_inf, o[2]);
+    rounds += o[3];
+    active += o[4];
+    cols += o[5];
   }
+  r.rounds_per_column = cols > 0 ? rounds / cols : 0.0;
+  r.active_per_column = cols > 0 ? active / cols : 0.0;
   // row sums of pi_hat^(m) = p^(m),new + t (p_old - p^(m),old)
   std::vector<double> ph(M * R), phbar(R, 0.0);
   for (size_t m = 0; m < M; ++m)

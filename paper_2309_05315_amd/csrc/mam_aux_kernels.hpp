@@ -174,6 +174,11 @@ cost_write_kernel(const double* __restrict__ xi, int R, const double* __restrict
   }
 }
 
+__global__ void __launch_bounds__(256)
+fill_value_kernel(double* __restrict__ p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
 __global__ void zero_kernel(double* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;

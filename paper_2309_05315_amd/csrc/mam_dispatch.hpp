@@ -11,18 +11,33 @@ template <typename T>
 using ColFn = void (*)(ColArgs<T>);
 
 // Returns the instance for (threads per column, values per thread, vector
-// width, diagnostics) or nullptr if none exists.
-template <typename T, bool DIAG>
-ColFn<T> pick_column_impl(int nt, int vpt, int vec);
+// width, columns in flight, diagnostics) or nullptr if none exists.
+// Instances: 64 threads with 1-16 values per thread, 128-1024 threads with
+// 4-16; columns in flight 1, 2, 4 for vector loads without diagnostics,
+// otherwise 1.
+template <typename T, int KC>
+ColFn<T> pick_column_kc(int nt, int vpt, int vec);
+template <typename T>
+ColFn<T> pick_column_diag(int nt, int vpt, int vec);
 
 template <typename T>
-inline ColFn<T> pick_column(int nt, int vpt, int vec, int diag) {
-  return diag ? pick_column_impl<T, true>(nt, vpt, vec) : pick_column_impl<T, false>(nt, vpt, vec);
+inline ColFn<T> pick_column(int nt, int vpt, int vec, int kc, int diag) {
+  if (diag) return pick_column_diag<T>(nt, vpt, vec);
+  switch (kc) {
+    case 1: return pick_column_kc<T, 1>(nt, vpt, vec);
+    case 2: return pick_column_kc<T, 2>(nt, vpt, vec);
+    case 4: return pick_column_kc<T, 4>(nt, vpt, vec);
+    default: return nullptr;
+  }
 }
 
-extern template ColFn<float> pick_column_impl<float, false>(int, int, int);
-extern template ColFn<float> pick_column_impl<float, true>(int, int, int);
-extern template ColFn<double> pick_column_impl<double, false>(int, int, int);
-extern template ColFn<double> pick_column_impl<double, true>(int, int, int);
+extern template ColFn<float> pick_column_kc<float, 1>(int, int, int);
+extern template ColFn<float> pick_column_kc<float, 2>(int, int, int);
+extern template ColFn<float> pick_column_kc<float, 4>(int, int, int);
+extern template ColFn<double> pick_column_kc<double, 1>(int, int, int);
+extern template ColFn<double> pick_column_kc<double, 2>(int, int, int);
+extern template ColFn<double> pick_column_kc<double, 4>(int, int, int);
+extern template ColFn<float> pick_column_diag<float>(int, int, int);
+extern template ColFn<double> pick_column_diag<double>(int, int, int);
 
 }  // namespace mam

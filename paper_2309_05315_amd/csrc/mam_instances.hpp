@@ -1,46 +1,66 @@
 // Instantiation of the column kernel over the supported shapes; included
-// by one translation unit per (element type, diagnostics) pair, which
-// defines MAM_INST_T and MAM_INST_DIAG first.
+// by one translation unit per (element type, columns in flight) pair, which
+// defines MAM_INST_T and MAM_INST_KC first (MAM_INST_KC 0 = the
+// diagnostics instances, one column in flight).
 #pragma once
 
 #include "mam_dispatch.hpp"
 
 namespace mam {
 
-template <typename T, int NT, int VPT, bool DIAG>
+template <typename T, int NT, int VPT, int KC, bool DIAG>
 ColFn<T> pick_vec(int vec) {
   constexpr int VN = VecOf<T>::N;
   if constexpr (VPT >= VN) {
-    if (vec == VN) return &column_kernel<T, NT, VPT, VN, DIAG>;
+    if (vec == VN) return &column_kernel<T, NT, VPT, VN, KC, DIAG>;
   }
-  if (vec != 1) return nullptr;
-  return &column_kernel<T, NT, VPT, 1, DIAG>;
+  if constexpr (KC == 1) {
+    if (vec == 1) return &column_kernel<T, NT, VPT, 1, 1, DIAG>;
+  }
+  return nullptr;
 }
 
-template <typename T, int NT, bool DIAG>
+template <typename T, int NT, int KC, bool DIAG>
 ColFn<T> pick_vpt(int vpt, int vec) {
+  if constexpr (NT == 64) {
+    switch (vpt) {
+      case 1: return pick_vec<T, NT, 1, KC, DIAG>(vec);
+      case 2: return pick_vec<T, NT, 2, KC, DIAG>(vec);
+      default: break;
+    }
+  }
   switch (vpt) {
-    case 1: return pick_vec<T, NT, 1, DIAG>(vec);
-    case 2: return pick_vec<T, NT, 2, DIAG>(vec);
-    case 4: return pick_vec<T, NT, 4, DIAG>(vec);
-    case 8: return pick_vec<T, NT, 8, DIAG>(vec);
-    case 16: return pick_vec<T, NT, 16, DIAG>(vec);
+    case 4: return pick_vec<T, NT, 4, KC, DIAG>(vec);
+    case 8: return pick_vec<T, NT, 8, KC, DIAG>(vec);
+    case 16: return pick_vec<T, NT, 16, KC, DIAG>(vec);
     default: return nullptr;
   }
 }
 
-template <typename T, bool DIAG>
-ColFn<T> pick_column_impl(int nt, int vpt, int vec) {
+template <typename T, int KC, bool DIAG>
+ColFn<T> pick_nt(int nt, int vpt, int vec) {
   switch (nt) {
-    case 64: return pick_vpt<T, 64, DIAG>(vpt, vec);
-    case 128: return pick_vpt<T, 128, DIAG>(vpt, vec);
-    case 256: return pick_vpt<T, 256, DIAG>(vpt, vec);
-    case 512: return pick_vpt<T, 512, DIAG>(vpt, vec);
-    case 1024: return pick_vpt<T, 1024, DIAG>(vpt, vec);
+    case 64: return pick_vpt<T, 64, KC, DIAG>(vpt, vec);
+    case 128: return pick_vpt<T, 128, KC, DIAG>(vpt, vec);
+    case 256: return pick_vpt<T, 256, KC, DIAG>(vpt, vec);
+    case 512: return pick_vpt<T, 512, KC, DIAG>(vpt, vec);
+    case 1024: return pick_vpt<T, 1024, KC, DIAG>(vpt, vec);
     default: return nullptr;
   }
 }
 
-template ColFn<MAM_INST_T> pick_column_impl<MAM_INST_T, MAM_INST_DIAG>(int, int, int);
+#if MAM_INST_KC == 0
+template <typename T>
+ColFn<T> pick_column_diag(int nt, int vpt, int vec) {
+  return pick_nt<T, 1, true>(nt, vpt, vec);
+}
+template ColFn<MAM_INST_T> pick_column_diag<MAM_INST_T>(int, int, int);
+#else
+template <typename T, int KC>
+ColFn<T> pick_column_kc(int nt, int vpt, int vec) {
+  return pick_nt<T, KC, false>(nt, vpt, vec);
+}
+template ColFn<MAM_INST_T> pick_column_kc<MAM_INST_T, MAM_INST_KC>(int, int, int);
+#endif
 
 }  // namespace mam

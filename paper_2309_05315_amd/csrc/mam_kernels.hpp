@@ -91,69 +91,90 @@ template <> struct RowAcc<float> {
   __device__ __forceinline__ double value() const { return (double)s - (double)c; }
 };
 
-__device__ __forceinline__ double uniform_d(double v) {
-  const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readfirstlane((int)(bits & 0xffffffffll));
-  const int hi = __builtin_amdgcn_readfirstlane((int)(bits >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+// ---------------------------------------------------------------------------
+// Wave reductions with DPP (data-parallel primitives): butterfly steps inside
+// rows of 16 lanes, then row broadcasts; the total lands in lane 63 and is
+// read back as a wave-uniform scalar.  Fixed order: bitwise reproducible.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v, double identity) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(identity), __double2loint(v), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(identity), __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return uniform_d(v);
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Reductions over one column group of NW waves.  NW == 1 needs no barrier;
-// NW > 1 means the group is the whole workgroup, so __syncthreads is safe.
-// 'slots' holds 2 parities x NW x 2 doubles; alternating parities make one
-// barrier per reduction enough.
-template <int NW>
-struct GroupReduce {
-  double* slots;
-  int par;
-
-  __device__ __forceinline__ double max(double v, int wv, int lane) {
-    v = wave_max(v);
-    if constexpr (NW == 1) {
-      return v;
-    } else {
-      if (lane == 0) slots[(par * NW + wv) * 2] = v;
-      __syncthreads();
-      double r = slots[(par * NW) * 2];
-#pragma unroll
-      for (int i = 1; i < NW; ++i) r = fmax(r, slots[(par * NW + i) * 2]);
-      par ^= 1;
-      return r;
-    }
-  }
-
-  __device__ __forceinline__ void sum2(double& s, double& c, int wv, int lane) {
-    s = wave_sum(s);
-    if constexpr (NW > 1) {
-      if (lane == 0) {
-        slots[(par * NW + wv) * 2] = s;
-        slots[(par * NW + wv) * 2 + 1] = c;
-      }
-      __syncthreads();
-      double rs = 0.0, rc = 0.0;
-#pragma unroll
-      for (int i = 0; i < NW; ++i) {
-        rs += slots[(par * NW + i) * 2];
-        rc += slots[(par * NW + i) * 2 + 1];
-      }
-      par ^= 1;
-      s = rs;
-      c = rc;
-    }
-  }
+struct OpSum {
+  static constexpr double id() { return 0.0; }
+  __device__ static double f(double a, double b) { return a + b; }
 };
+struct OpMax {
+  static constexpr double id() { return -__builtin_huge_val(); }
+  __device__ static double f(double a, double b) { return fmax(a, b); }
+};
+struct OpMin {
+  static constexpr double id() { return __builtin_huge_val(); }
+  __device__ static double f(double a, double b) { return fmin(a, b); }
+};
+
+__device__ __forceinline__ double read_lane63(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_move_f(float v, float identity) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(identity), __float_as_int(v), CTRL, ROWMASK, 0xf, false));
+}
+
+struct OpMaxF {
+  static constexpr float id() { return -__builtin_huge_valf(); }
+  __device__ static float f(float a, float b) { return fmaxf(a, b); }
+};
+struct OpMinF {
+  static constexpr float id() { return __builtin_huge_valf(); }
+  __device__ static float f(float a, float b) { return fminf(a, b); }
+};
+
+template <class Op>
+__device__ __forceinline__ float wave_reduce_f(float v) {
+  v = Op::f(v, dpp_move_f<0xb1, 0xf>(v, Op::id()));
+  v = Op::f(v, dpp_move_f<0x4e, 0xf>(v, Op::id()));
+  v = Op::f(v, dpp_move_f<0x141, 0xf>(v, Op::id()));
+  v = Op::f(v, dpp_move_f<0x140, 0xf>(v, Op::id()));
+  v = Op::f(v, dpp_move_f<0x142, 0xa>(v, Op::id()));
+  v = Op::f(v, dpp_move_f<0x143, 0xc>(v, Op::id()));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ double uniform_d(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform_l(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double v) {
+  v = Op::f(v, dpp_move<0xb1, 0xf>(v, Op::id()));   // quad_perm [1,0,3,2]
+  v = Op::f(v, dpp_move<0x4e, 0xf>(v, Op::id()));   // quad_perm [2,3,0,1]
+  v = Op::f(v, dpp_move<0x141, 0xf>(v, Op::id()));  // row_half_mirror
+  v = Op::f(v, dpp_move<0x140, 0xf>(v, Op::id()));  // row_mirror
+  v = Op::f(v, dpp_move<0x142, 0xa>(v, Op::id()));  // row_bcast:15 into rows 1, 3
+  v = Op::f(v, dpp_move<0x143, 0xc>(v, Op::id()));  // row_bcast:31 into rows 2, 3
+  return read_lane63(v);
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return wave_reduce<OpSum>(v); }
+__device__ __forceinline__ double wave_max(double v) { return wave_reduce<OpMax>(v); }
 
 template <typename T>
 struct ColArgs {
@@ -166,7 +187,7 @@ struct ColArgs {
   const double* pm;       // M x R marginals of the current plans
   const double* p;        // R, averaged marginal
   const double* d2part;   // nb partial sums of d^2
-  int32_t nb, diag_on;
+  int32_t nb, warm;       // warm: use the stored thresholds as Newton starts
   double rho, inv_rho, gamma;
   const int64_t* col_off; // M+1
   const double* Sd;       // S^m as double
@@ -175,10 +196,13 @@ struct ColArgs {
   const int64_t* seg_j1;
   const int32_t* wg_seg;  // nwg+1
   double* partial;        // nseg x R
+  double* lam;            // T thresholds of the last projection (NaN = none)
   double* t_out;          // 1
-  double* diag;           // nwg x 4
+  double* diag;           // nwg x DIAG_STRIDE
   int32_t nwg, xcd_remap;
 };
+
+constexpr int DIAG_STRIDE = 8;  // W_hat, meas_resid, dtheta_inf, rounds, active, columns
 
 // XCD-aware block order: the hardware deals consecutive workgroup ids round
 // robin over the 8 XCDs; remapping gives each XCD a contiguous run of
@@ -194,9 +218,8 @@ __device__ __forceinline__ int logical_block(int bid, int nblocks, int remap) {
   return base + k;
 }
 
-// Dynamic LDS: VPT*NT doubles of b^(m) (each thread reads only its own
-// slots: no sharing, no bank conflicts), then R doubles for the cross-group
-// row-sum reduction when NG > 1.
+constexpr int KB = 4;  // column block a group owns at a time (multiple of every KC)
+
 template <int NT> struct GroupShape {
   // a 64-thread group is one wave: four of them share a workgroup;
   // larger groups are the whole workgroup
@@ -204,29 +227,135 @@ template <int NT> struct GroupShape {
   static constexpr int WG = NT * NG;
 };
 
-template <typename T, int NT, int VPT, int VEC, bool DIAG>
+// One threshold round for KC columns: per column, over the entries of w,
+//   S = sum of w > lam (double), n = #{w > lam},
+//   mnA = min of w > lam rounded down to float,
+//   mxN = max of w <= lam rounded up to float,
+//   wmx = max of w in double, on cold rounds (lam = NaN) only,
+// reduced over the column group (NW waves) in a fixed order.  The float
+// bounds are conservative (mnA <= true min, mxN >= true max), so a test
+// passed on them holds for the exact values; they cost a third of a double
+// reduction.
+template <int NW, int KC>
+struct Rounds {
+  double* red_d;  // [2][KC][2][NW]
+  float* red_f;   // [2][KC][2][NW]
+  int* red_i;     // [2][KC][NW]
+  int par;
+
+  __device__ __forceinline__ void reduce(double (&S)[KC], float (&mnA)[KC], float (&mxN)[KC],
+                                         double (&wmx)[KC], int (&n)[KC], const bool (&act)[KC],
+                                         const bool (&cold)[KC], int wv, int lane) {
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      if (act[kc]) {
+        if (n[kc] != 0) {  // wave-uniform: some lane of this wave is active
+          S[kc] = wave_reduce<OpSum>(S[kc]);
+          mnA[kc] = wave_reduce_f<OpMinF>(mnA[kc]);
+        } else {
+          S[kc] = 0.0;
+          mnA[kc] = __builtin_huge_valf();
+        }
+        mxN[kc] = wave_reduce_f<OpMaxF>(mxN[kc]);
+        if (cold[kc]) wmx[kc] = wave_reduce<OpMax>(wmx[kc]);
+      }
+    }
+    if constexpr (NW > 1) {
+      if (lane == 0) {
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+          red_d[((par * KC + kc) * 2 + 0) * NW + wv] = S[kc];
+          red_d[((par * KC + kc) * 2 + 1) * NW + wv] = wmx[kc];
+          red_f[((par * KC + kc) * 2 + 0) * NW + wv] = mnA[kc];
+          red_f[((par * KC + kc) * 2 + 1) * NW + wv] = mxN[kc];
+          red_i[(par * KC + kc) * NW + wv] = n[kc];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const double* d = red_d + ((par * KC + kc) * 2 + 0) * NW;
+        const double* d1 = red_d + ((par * KC + kc) * 2 + 1) * NW;
+        const float* f0 = red_f + ((par * KC + kc) * 2 + 0) * NW;
+        const float* f1 = red_f + ((par * KC + kc) * 2 + 1) * NW;
+        const int* ni = red_i + (par * KC + kc) * NW;
+        double sum = d[0], mx = d1[0];
+        float a = f0[0], b = f1[0];
+        int nn = ni[0];
+#pragma unroll
+        for (int i = 1; i < NW; ++i) {
+          sum += d[i];
+          mx = fmax(mx, d1[i]);
+          a = fminf(a, f0[i]);
+          b = fmaxf(b, f1[i]);
+          nn += ni[i];
+        }
+        S[kc] = uniform_d(sum);
+        wmx[kc] = uniform_d(mx);
+        mnA[kc] = uniform_f(a);
+        mxN[kc] = uniform_f(b);
+        n[kc] = __builtin_amdgcn_readfirstlane(nn);
+      }
+      par ^= 1;
+    }
+  }
+};
+
+// Column kernel.  Workgroup = NG groups of NT threads; a group advances KC
+// columns of one segment at a time.  Thread tid of a group holds rows
+// (c*NT + tid)*VEC + v (c < VPT/VEC, v < VEC) of each of its KC columns.
+//
+// Inactive entries.  An entry with w_r <= lambda has pi_hat_r = 0, so its
+// update is theta'_r = -b_r whatever theta and c were: every column of a
+// segment is the constant vector -b^(m) except at its active rows.  The
+// kernel therefore keeps no per-entry state beyond the raw theta and c of
+// the columns in flight: w is recomputed where needed, each column writes
+// -b^(m) patched at its active rows, and the segment's row sums are
+// (#columns) * (-b^(m)) plus the patches' differences, accumulated in LDS.
+//
+// Threshold of a column (tau = q_s > 0): Newton steps
+//   lam' = (sum_{w > lam} w - tau) / #{w > lam}
+// from the column's threshold of the previous iteration (warm start) or,
+// without one, from w_max - tau (a lower bound, since one entry carries at
+// most tau).  A step from any start lands at or below the root (the tangent
+// of a convex decreasing function meets zero before it does); from there the
+// steps increase monotonically and the active set shrinks.  The set A used
+// for lam' is exact when it did not change (the level sets are nested, so
+// equal counts mean equal sets) or when min_A w >= lam' >= max_{not A} w;
+// then lam' is the root itself, so one round usually both moves and
+// verifies.  Entries equal to lam' contribute 0 either way.
+//
+// Dynamic LDS: VPT*NT doubles of b^(m) (each thread reads only its own
+// slots), then NG*VPT*NT doubles of row-sum patches, one block per group.
+template <typename T, int NT, int VPT, int VEC, int KC, bool DIAG>
 __global__ void __launch_bounds__(GroupShape<NT>::WG)
 column_kernel(ColArgs<T> a) {
   constexpr int WG = GroupShape<NT>::WG;
   constexpr int NG = GroupShape<NT>::NG;  // independent column groups per workgroup
-  constexpr int NW = NT / 64;     // waves per group
-  constexpr int NCH = VPT / VEC;  // vector chunks per thread
+  constexpr int NW = NT / 64;             // waves per group
+  constexpr int NCH = VPT / VEC;          // vector chunks per thread
   static_assert(VPT % VEC == 0, "VPT must be a multiple of VEC");
+  static_assert(VPT <= 32, "the active mask is one 32-bit word");
   static_assert(NG == 1 || NW == 1, "multi-wave groups fill the workgroup");
 
-  __shared__ double slots[2 * NW * 2];
+  __shared__ double red_d[NW > 1 ? 2 * KC * 2 * NW : 1];
+  __shared__ float red_f[NW > 1 ? 2 * KC * 2 * NW : 1];
+  __shared__ int red_i[NW > 1 ? 2 * KC * NW : 1];
   __shared__ double sh_t;
-  __shared__ double sh_diag[WG / 64][3];
+  __shared__ double sh_diag[WG / 64][6];
   extern __shared__ double lds_dyn[];
-  double* lds_b = lds_dyn;               // [VPT][NT]
-  double* lds_acc = lds_dyn + VPT * NT;  // [R], used when NG > 1
+  double* lds_b = lds_dyn;                // [VPT][NT]
+  double* lds_fix = lds_dyn + VPT * NT;   // [NG][VPT][NT]
 
   const int gtid = threadIdx.x;
-  const int g = gtid / NT;
+  // the group index is wave-uniform (a group is one wave, or the whole
+  // workgroup); saying so keeps all column bookkeeping in scalar registers
+  const int g = NG == 1 ? 0 : __builtin_amdgcn_readfirstlane(gtid / NT);
   const int tid = gtid % NT;
   const int lane = gtid & 63;
-  const int wv = tid >> 6;
+  const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
   const int R = a.R;
+  double* fix = lds_fix + (size_t)g * VPT * NT;
 
   if (gtid == 0) {
     double d2 = 0.0;
@@ -237,18 +366,21 @@ column_kernel(ColArgs<T> a) {
     if (blockIdx.x == 0) a.t_out[0] = t;
   }
   __syncthreads();
-  const double t = sh_t;
+  const double t = uniform_d(sh_t);
+  const double inv_rho = a.inv_rho;
 
-  GroupReduce<NW> red{slots, 0};
-  double dW = 0.0, dRes = 0.0, dTh = 0.0;
+  Rounds<NW, KC> rounds{red_d, red_f, red_i, 0};
+  double dW = 0.0, dRes = 0.0, dTh = 0.0, dRounds = 0.0, dAct = 0.0, dCols = 0.0;
 
   const int wg = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  const int sb = a.wg_seg[wg], se = a.wg_seg[wg + 1];
+  // table entries are read through vector loads (the compiler cannot prove
+  // them constant); readfirstlane makes them scalar again
+  const int sb = uniform_i(a.wg_seg[wg]), se = uniform_i(a.wg_seg[wg + 1]);
   for (int si = sb; si < se; ++si) {
-    const int m = a.seg_m[si];
-    const int64_t j0 = a.seg_j0[si], j1 = a.seg_j1[si];
-    const double Sm = a.Sd[m];
-    const int64_t off_m = a.col_off[m];
+    const int m = uniform_i(a.seg_m[si]);
+    const int64_t j0 = uniform_l(a.seg_j0[si]), j1 = uniform_l(a.seg_j1[si]);
+    const double Sm = uniform_d(a.Sd[m]);
+    const int64_t off_m = uniform_l(a.col_off[m]);
     const double* __restrict__ pmm = a.pm + (size_t)m * R;
 
     // b^(m) = t (p - p^(m)) / S^m for this thread's rows, kept in LDS
@@ -263,154 +395,278 @@ column_kernel(ColArgs<T> a) {
         }
       }
     }
-    __syncthreads();
-    RowAcc<T> acc[VPT];
 #pragma unroll
-    for (int k = 0; k < VPT; ++k) acc[k].zero();
+    for (int k = 0; k < VPT; ++k) fix[k * NT + tid] = 0.0;
+    __syncthreads();
+    T nb[VPT];  // -b^(m) rounded to the storage type: every inactive entry's new value
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) nb[k] = (T)(-lds_b[k * NT + tid]);
 
-    for (int64_t j = j0 + g; j < j1; j += NG) {
-      T* __restrict__ thp = a.theta + j * a.ld;
+    // Column steps of this group: blocks of KB columns taken in turn by the
+    // NG groups, each walked KC columns at a time.  The raw loads of the
+    // next step are issued before the current step's threshold rounds and
+    // stores, so their HBM latency overlaps that work.
+    static_assert(KB % KC == 0, "KC must divide the column block");
+    constexpr int SPB = KB / KC;  // steps per block
+    const int64_t gbase = j0 + (int64_t)g * KB;
+    auto step_exists = [&](int64_t i) -> bool { return gbase + (i / SPB) * (int64_t)(NG * KB) < j1; };
+    auto step_col = [&](int64_t i, int kc, int64_t& j) -> bool {
+      const int64_t base = gbase + (i / SPB) * (int64_t)(NG * KB);
+      const int64_t bend = base + KB < j1 ? base + KB : j1;
+      j = base + (i % SPB) * KC + kc;
+      return j < bend;
+    };
+    auto cost_col = [&](int64_t j) -> const T* {
       int64_t cc;
-      if (a.cost_mode == MAM_COST_INDEXED) cc = a.cidx[j];
+      if (a.cost_mode == MAM_COST_INDEXED) cc = uniform_i(a.cidx[j]);
       else if (a.cost_mode == MAM_COST_SHARED) cc = j - off_m;
       else cc = j;
-      const T* __restrict__ cp = a.cost + cc * a.cost_ld;
-
-      // reflection w = theta + 2b - c/rho, widened to double
-      double w[VPT];
-      double mx = -INFINITY;
+      return a.cost + cc * a.cost_ld;
+    };
+    T rt[KC][VPT], rc[KC][VPT];  // raw theta and cost of the next step
+    auto issue = [&](int64_t i) {
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const int r0 = (c * NT + tid) * VEC;
-        if (r0 < R) {
-          T tv[VEC], cv[VEC];
-          load_vec<T, VEC>(thp + r0, tv);
-          load_vec<T, VEC>(cp + r0, cv);
+      for (int kc = 0; kc < KC; ++kc) {
+        int64_t j;
+        if (step_col(i, kc, j)) {
+          const T* __restrict__ thp = a.theta + j * a.ld;
+          const T* __restrict__ cp = cost_col(j);
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) {
-            const int k = c * VEC + v;
-            const double bk = lds_b[k * NT + tid];
-            w[k] = (r0 + v < R) ? ((double)tv[v] + 2.0 * bk) - (double)cv[v] * a.inv_rho : -INFINITY;
-            mx = fmax(mx, w[k]);
-          }
-        } else {
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) w[c * VEC + v] = -INFINITY;
-        }
-      }
-      mx = red.max(mx, wv, lane);
-
-      // exact threshold: Newton from lambda_0 = w_max - tau
-      const double tau = (double)a.q[j];
-      double lam = INFINITY;
-      if (tau > 0.0) {
-        lam = mx - tau;
-        double prev = 1e300;
-        for (int it = 0; it <= R; ++it) {
-          double s = 0.0, cnt = 0.0;
-#pragma unroll
-          for (int k = 0; k < VPT; ++k) {
-            const bool act = w[k] > lam;
-            s += act ? w[k] : 0.0;
-            cnt += (double)__popcll(__ballot(act));
-          }
-          red.sum2(s, cnt, wv, lane);
-          if (cnt == 0.0 || cnt >= prev) break;
-          lam = (s - tau) / cnt;
-          prev = cnt;
-        }
-      }
-
-      // pi_hat = max(w - lambda, 0); theta' = pi_hat - b; row sums of theta'
-      double colsum = 0.0;
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const int r0 = (c * NT + tid) * VEC;
-        if (r0 < R) {
-          T out[VEC];
-          T oldv[VEC], cv[VEC];
-          if constexpr (DIAG) {
-            load_vec<T, VEC>(thp + r0, oldv);
+          for (int c = 0; c < NCH; ++c) {
+            // rows past R read the column's first vector (in bounds) and are masked later
+            const int r0 = (c * NT + tid) * VEC < R ? (c * NT + tid) * VEC : 0;
+            T tv[VEC], cv[VEC];
+            load_vec<T, VEC>(thp + r0, tv);
             load_vec<T, VEC>(cp + r0, cv);
-          }
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) {
-            const int k = c * VEC + v;
-            const double ph = fmax(w[k] - lam, 0.0);
-            out[v] = (T)(ph - lds_b[k * NT + tid]);
-            if (DIAG && r0 + v < R) {
-              colsum += ph;
-              dW += (double)cv[v] * ph;
-              dTh = fmax(dTh, fabs((double)out[v] - (double)oldv[v]));
+            for (int v = 0; v < VEC; ++v) {
+              rt[kc][c * VEC + v] = tv[v];
+              rc[kc][c * VEC + v] = cv[v];
             }
           }
-          if (r0 + VEC <= R) {
-            store_vec<T, VEC>(thp + r0, out);
-          } else {
-#pragma unroll
-            for (int v = 0; v < VEC; ++v)
-              if (r0 + v < R) thp[r0 + v] = out[v];
-          }
-#pragma unroll
-          for (int v = 0; v < VEC; ++v)
-            if (r0 + v < R) acc[c * VEC + v].add(out[v]);
         }
       }
-      if constexpr (DIAG) {
-        double zero = 0.0;
-        red.sum2(colsum, zero, wv, lane);
-        dRes = fmax(dRes, fabs(colsum - (tau > 0.0 ? tau : 0.0)));
+    };
+    if (step_exists(0)) issue(0);
+    for (int64_t step = 0; step_exists(step); ++step) {
+      // ---- reflect the step's columns: w = theta + 2b - c/rho (double) ----
+      double w[KC][VPT];
+      T told[DIAG ? KC : 1][DIAG ? VPT : 1];
+      bool valid[KC];
+      int64_t jj[KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        valid[kc] = step_col(step, kc, jj[kc]);
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+          const int r = ((k / VEC) * NT + tid) * VEC + (k % VEC);
+          const double x = ((double)rt[kc][k] + 2.0 * lds_b[k * NT + tid]) - (double)rc[kc][k] * inv_rho;
+          w[kc][k] = (valid[kc] && r < R) ? x : -__builtin_huge_val();
+          if constexpr (DIAG) told[kc][k] = rt[kc][k];
+        }
+      }
+      if (step_exists(step + 1)) issue(step + 1);
+
+      // ---- thresholds ----
+      double tau[KC], lam[KC];
+      bool act[KC];
+      int mask[KC], nrounds[KC], nact[KC], nprev[KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int64_t j = jj[kc];
+        tau[kc] = valid[kc] ? uniform_d((double)a.q[j]) : 0.0;
+        act[kc] = valid[kc] && tau[kc] > 0.0;
+        lam[kc] = (act[kc] && a.warm) ? uniform_d(a.lam[j]) : __builtin_nan("");
+        if (!act[kc]) lam[kc] = __builtin_huge_val();
+        mask[kc] = 0;
+        nrounds[kc] = 0;
+        nact[kc] = 0;
+        nprev[kc] = -1;
+      }
+      for (int it = 0; it < R + 4; ++it) {
+        bool any = false;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) any |= act[kc];
+        if (!any) break;
+        double S[KC], wmx[KC];
+        float mnA[KC], mxN[KC];
+        int n[KC];
+        bool cold[KC];
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+          S[kc] = 0.0;
+          wmx[kc] = -__builtin_huge_val();
+          mnA[kc] = __builtin_huge_valf();
+          mxN[kc] = -__builtin_huge_valf();
+          n[kc] = 0;
+          cold[kc] = lam[kc] != lam[kc];
+          if (act[kc]) {
+            const double l = lam[kc];
+            double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
+            int bits = 0;
+#pragma unroll
+            for (int k = 0; k < VPT; ++k) {
+              // usually no lane of the wave holds an active entry in slot k:
+              // a uniform branch keeps that case to one compare and one max
+              const double x = w[kc][k];
+              const unsigned long long bal = __ballot(x > l);
+              if (bal == 0ull) {
+                hi = fmax(hi, x);
+              } else {
+                const bool in = x > l;
+                n[kc] += __popcll(bal);
+                bits |= (int)in << k;
+                S[kc] += in ? x : 0.0;
+                lo = fmin(lo, in ? x : __builtin_huge_val());
+                hi = fmax(hi, in ? -__builtin_huge_val() : x);
+              }
+            }
+            mask[kc] = bits;
+            mnA[kc] = __double2float_rd(lo);
+            mxN[kc] = __double2float_ru(hi);
+            wmx[kc] = hi;  // with lam = NaN nothing is active: hi = w_max
+          }
+        }
+        rounds.reduce(S, mnA, mxN, wmx, n, act, cold, wv, lane);
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+          if (!act[kc]) continue;
+          ++nrounds[kc];
+          if (n[kc] == 0) {
+            if (cold[kc]) {
+              // start from the exact lower bound w_max - tau
+              lam[kc] = wmx[kc] - tau[kc];
+              nprev[kc] = 0x7fffffff;
+            } else if (nprev[kc] < 0) {
+              // the warm start lay above w_max: take a cold round
+              lam[kc] = __builtin_nan("");
+            } else {
+              // w_max - tau rounded to w_max (tau below half an ulp of
+              // w_max): nothing is active and the column is 0
+              act[kc] = false;
+              mask[kc] = 0;
+            }
+          } else {
+            const double ln = (S[kc] - tau[kc]) / (double)n[kc];
+            if (n[kc] == nprev[kc] || ((double)mnA[kc] >= ln && (double)mxN[kc] <= ln)) {
+              act[kc] = false;  // mask[kc] is the exact active set
+              nact[kc] = n[kc];
+            }
+            nprev[kc] = n[kc];
+            lam[kc] = ln;
+          }
+        }
+      }
+
+      // ---- theta' = -b, patched at the active rows with max(w - lam, 0) - b ----
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        if (!valid[kc]) continue;
+        const int64_t j = jj[kc];
+        T* __restrict__ thp = a.theta + j * a.ld;
+        double colsum = 0.0;
+        const T* __restrict__ cp = a.cost;
+        if constexpr (DIAG) cp = cost_col(j);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const int r0 = (c * NT + tid) * VEC;
+          if (r0 < R) {
+            T out[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+              const int k = c * VEC + v;
+              out[v] = nb[k];
+              if ((mask[kc] >> k) & 1) {
+                const double ph = fmax(w[kc][k] - lam[kc], 0.0);
+                out[v] = (T)(ph - lds_b[k * NT + tid]);
+                fix[k * NT + tid] += (double)out[v] - (double)nb[k];
+                if constexpr (DIAG) {
+                  colsum += ph;
+                  dW += (double)cp[r0 + v] * ph;
+                }
+              }
+              if constexpr (DIAG) {
+                if (r0 + v < R) dTh = fmax(dTh, fabs((double)out[v] - (double)told[kc][k]));
+              }
+            }
+            if (r0 + VEC <= R) {
+              store_vec<T, VEC>(thp + r0, out);
+            } else {
+#pragma unroll
+              for (int v = 0; v < VEC; ++v)
+                if (r0 + v < R) thp[r0 + v] = out[v];
+            }
+          }
+        }
+        if (tid == 0) a.lam[j] = lam[kc];
+        if constexpr (DIAG) {
+          colsum = wave_sum(colsum);
+          if constexpr (NW > 1) {
+            // reuse the round slots (parity keeps them apart from the last round)
+            if (lane == 0) red_d[(rounds.par * KC * 2) * NW + wv] = colsum;
+            __syncthreads();
+            double cs = 0.0;
+            for (int i = 0; i < NW; ++i) cs += red_d[(rounds.par * KC * 2) * NW + i];
+            colsum = cs;
+            rounds.par ^= 1;
+          }
+          dRes = fmax(dRes, fabs(colsum - tau[kc]));
+          if (tid == 0) {
+            dRounds += nrounds[kc];
+            dAct += nact[kc];
+            dCols += 1.0;
+          }
+        }
       }
     }
 
-    // fixed-order partial row sums of this segment
-    if constexpr (NG == 1) {
+    // partial row sums of the segment: (#columns) * (-b) + patches, groups in order
+    __syncthreads();
+    const double ncols = (double)(j1 - j0);
+    for (int i = gtid; i < VPT * NT; i += WG) {
+      const int k = i / NT, tt = i % NT;
+      const int r = ((k / VEC) * NT + tt) * VEC + (k % VEC);
+      if (r < R) {
+        double f = lds_fix[i];
 #pragma unroll
-      for (int c = 0; c < NCH; ++c)
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const int r = (c * NT + tid) * VEC + v;
-          if (r < R) a.partial[(size_t)si * R + r] = acc[c * VEC + v].value();
-        }
-    } else {
-      for (int gg = 0; gg < NG; ++gg) {
-        if (g == gg) {
-#pragma unroll
-          for (int c = 0; c < NCH; ++c)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-              const int r = (c * NT + tid) * VEC + v;
-              if (r < R) lds_acc[r] = (gg == 0 ? 0.0 : lds_acc[r]) + acc[c * VEC + v].value();
-            }
-        }
-        __syncthreads();
+        for (int gg = 1; gg < NG; ++gg) f += lds_fix[(size_t)gg * VPT * NT + i];
+        a.partial[(size_t)si * R + r] = ncols * (double)(T)(-lds_b[i]) + f;
       }
-      for (int r = gtid; r < R; r += WG) a.partial[(size_t)si * R + r] = lds_acc[r];
-      __syncthreads();
     }
   }
 
   if constexpr (DIAG) {
-    // dW sums per thread; dRes, dTh maxima.  Fixed order over waves.
-    double s = wave_sum(dW);
-    double r1 = wave_max(dRes), r2 = wave_max(dTh);
+    // sums of W_hat, rounds, active entries, columns; maxima of residual and change
+    const double s0 = wave_sum(dW), r1 = wave_max(dRes), r2 = wave_max(dTh);
+    const double s3 = wave_sum(dRounds), s4 = wave_sum(dAct), s5 = wave_sum(dCols);
     if (lane == 0) {
-      sh_diag[gtid >> 6][0] = s;
+      sh_diag[gtid >> 6][0] = s0;
       sh_diag[gtid >> 6][1] = r1;
       sh_diag[gtid >> 6][2] = r2;
+      sh_diag[gtid >> 6][3] = s3;
+      sh_diag[gtid >> 6][4] = s4;
+      sh_diag[gtid >> 6][5] = s5;
     }
     __syncthreads();
     if (gtid == 0) {
-      double S0 = 0.0, m1 = 0.0, m2 = 0.0;
+      double S0 = 0.0, m1 = 0.0, m2 = 0.0, S3 = 0.0, S4 = 0.0, S5 = 0.0;
       for (int i = 0; i < WG / 64; ++i) {
         S0 += sh_diag[i][0];
         m1 = fmax(m1, sh_diag[i][1]);
         m2 = fmax(m2, sh_diag[i][2]);
+        S3 += sh_diag[i][3];
+        S4 += sh_diag[i][4];
+        S5 += sh_diag[i][5];
       }
-      a.diag[(size_t)wg * 4 + 0] = S0;
-      a.diag[(size_t)wg * 4 + 1] = m1;
-      a.diag[(size_t)wg * 4 + 2] = m2;
-      a.diag[(size_t)wg * 4 + 3] = 0.0;
+      double* o = a.diag + (size_t)wg * DIAG_STRIDE;
+      o[0] = S0;
+      o[1] = m1;
+      o[2] = m2;
+      o[3] = S3;
+      o[4] = S4;
+      o[5] = S5;
+      o[6] = 0.0;
+      o[7] = 0.0;
     }
   }
 }

@@ -19,12 +19,12 @@ import numpy as np
 import torch
 
 __all__ = ["lib", "MAMError", "Solver", "solver_for", "cost_sq_euclid",
-           "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "FLAG_DIAG",
+           "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "FLAG_DIAG", "FLAG_COLD",
            "EXPORTED"]
 
 F32, F64 = 0, 1
 COST_PER_COLUMN, COST_SHARED, COST_INDEXED = 0, 1, 2
-FLAG_DIAG = 1
+FLAG_DIAG, FLAG_COLD = 1, 2
 
 STATUS = {0: "MAM_OK", -1: "MAM_EINVAL", -2: "MAM_ENOMEM", -3: "MAM_EHIP",
           -4: "MAM_ENOTBALANCED", -5: "MAM_ENONFINITE", -6: "MAM_EUNSUPPORTED",
@@ -52,12 +52,14 @@ class Diag(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("t", ctypes.c_double),
                 ("W_hat", ctypes.c_double), ("dist_L", ctypes.c_double),
                 ("meas_resid", ctypes.c_double), ("dtheta_inf", ctypes.c_double),
-                ("dp_norm", ctypes.c_double), ("p_mass", ctypes.c_double)]
+                ("dp_norm", ctypes.c_double), ("p_mass", ctypes.c_double),
+                ("rounds_per_column", ctypes.c_double), ("active_per_column", ctypes.c_double)]
 
 
 class Schedule(ctypes.Structure):
-    _fields_ = [("threads_per_column", ctypes.c_int32), ("workgroups", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("threads_per_column", ctypes.c_int32), ("values_per_thread", ctypes.c_int32),
+                ("columns_in_flight", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32), ("vector_width", ctypes.c_int32)]
 
 
 class MAMError(RuntimeError):
@@ -139,9 +141,9 @@ class Solver:
     def __init__(self, R: int, S: Sequence[int], rho: float = 1.0, gamma: float = math.inf,
                  dtype: torch.dtype = torch.float32, cost_mode: int = COST_SHARED,
                  cost_ncols: Optional[int] = None, ld: Optional[int] = None,
-                 cost_ld: Optional[int] = None, diag: bool = False,
-                 threads_per_column: int = 0, workgroups: int = 0, xcd_remap: int = 0,
-                 device="cuda"):
+                 cost_ld: Optional[int] = None, diag: bool = False, cold: bool = False,
+                 threads_per_column: int = 0, columns_in_flight: int = 0,
+                 workgroups: int = 0, xcd_remap: int = 0, device="cuda"):
         L = lib()
         self.device = torch.device(device)
         self.R, self.S = int(R), [int(s) for s in S]
@@ -158,12 +160,13 @@ class Solver:
         d = Desc(dtype=F32 if dtype == torch.float32 else F64, cost_mode=cost_mode,
                  R=self.R, M=self.M, S=self._S_arr, ld=self.ld, cost_ld=self.cost_ld,
                  cost_ncols=self.cost_ncols, rho=float(rho), gamma=float(gamma),
-                 flags=FLAG_DIAG if diag else 0)
+                 flags=(FLAG_DIAG if diag else 0) | (FLAG_COLD if cold else 0))
         h = _vp()
         _check(L.mam_create(ctypes.byref(h), ctypes.byref(d)), "mam_create")
         self._h = h
-        if threads_per_column or workgroups or xcd_remap:
-            sc = Schedule(threads_per_column, workgroups, xcd_remap, 0)
+        if threads_per_column or columns_in_flight or workgroups or xcd_remap:
+            sc = Schedule(threads_per_column=threads_per_column, columns_in_flight=columns_in_flight,
+                          workgroups=workgroups, xcd_remap=xcd_remap)
             _check(L.mam_set_schedule(h, ctypes.byref(sc)), "mam_set_schedule")
         nbytes = int(L.mam_workspace_bytes(h))
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
@@ -190,8 +193,7 @@ class Solver:
     def schedule(self) -> dict:
         sc = Schedule()
         _check(lib().mam_get_schedule(self._h, ctypes.byref(sc)), "mam_get_schedule")
-        return {"threads_per_column": sc.threads_per_column, "workgroups": sc.workgroups,
-                "xcd_remap": sc.xcd_remap, "values_per_thread": sc.reserved}
+        return {k: getattr(sc, k) for k, _ in Schedule._fields_}
 
     # -- iteration ---------------------------------------------------------
     def init(self, theta0: Optional[torch.Tensor] = None) -> None:
@@ -242,7 +244,7 @@ class Solver:
             pass
 
 
-def solver_for(problem, device="cuda", diag: bool = False, **sched) -> Solver:
+def solver_for(problem, device="cuda", diag: bool = False, cold: bool = False, **sched) -> Solver:
     """Allocate device buffers for an ``inputs.Problem`` and bind them."""
     dt = torch.float32 if problem.dtype == "f32" else torch.float64
     if problem.col_index is None:
@@ -252,7 +254,7 @@ def solver_for(problem, device="cuda", diag: bool = False, **sched) -> Solver:
     else:
         mode, ncols = COST_INDEXED, problem.cost.shape[0]
     s = Solver(problem.R, problem.S, rho=problem.rho, gamma=problem.gamma, dtype=dt,
-               cost_mode=mode, cost_ncols=ncols, diag=diag, device=device, **sched)
+               cost_mode=mode, cost_ncols=ncols, diag=diag, cold=cold, device=device, **sched)
     cost = torch.zeros(ncols, s.cost_ld, dtype=dt)
     cost[:, :problem.R] = torch.from_numpy(problem.cost).to(dt)
     theta = torch.zeros(problem.T, s.ld, dtype=dt, device=device)

@@ -69,7 +69,7 @@ def test_create_accepts_and_sizes_workspace():
     assert n > 0 and n % 256 == 0
     sc = mam.Schedule()
     assert L.mam_get_schedule(h, ctypes.byref(sc)) == 0
-    assert sc.threads_per_column == 64 and sc.reserved == 8
+    assert sc.threads_per_column == 64 and sc.values_per_thread == 8   # double, R = 300
     # workspace checks are pure pointer/size checks
     assert L.mam_set_workspace(h, ctypes.c_void_p(0x100000 + 8), n) == -1
     assert L.mam_set_workspace(h, ctypes.c_void_p(0x100000), n - 1) == -2
@@ -86,17 +86,20 @@ def test_schedule_override_validation():
     L = mam.lib()
     rc, h = create(R=4096, S=[100])
     assert rc == 0
-    bad = mam.Schedule(100, 0, 0, 0)
+    bad = mam.Schedule(threads_per_column=100)
     assert L.mam_set_schedule(h, ctypes.byref(bad)) == -1
-    small = mam.Schedule(64, 0, 0, 0)       # 4096 rows at 64 threads = 64 values per lane
+    small = mam.Schedule(threads_per_column=64)     # 4096 rows at 64 threads = 64 values per lane
     assert L.mam_set_schedule(h, ctypes.byref(small)) == -6
-    tiny = mam.Schedule(128, 0, 0, 0)       # 32 values per thread
+    tiny = mam.Schedule(threads_per_column=128)     # 32 values per thread
     assert L.mam_set_schedule(h, ctypes.byref(tiny)) == -6
-    ok = mam.Schedule(1024, 37, 1, 0)
+    kc3 = mam.Schedule(columns_in_flight=3)
+    assert L.mam_set_schedule(h, ctypes.byref(kc3)) == -1
+    ok = mam.Schedule(threads_per_column=1024, columns_in_flight=4, workgroups=37, xcd_remap=1)
     assert L.mam_set_schedule(h, ctypes.byref(ok)) == 0
     sc = mam.Schedule()
     L.mam_get_schedule(h, ctypes.byref(sc))
-    assert (sc.threads_per_column, sc.workgroups, sc.xcd_remap, sc.reserved) == (1024, 37, 1, 4)
+    assert (sc.threads_per_column, sc.values_per_thread, sc.columns_in_flight, sc.workgroups,
+            sc.xcd_remap) == (1024, 4, 4, 37, 1)
     L.mam_destroy(h)
 
 

@@ -35,8 +35,8 @@ def rel(a, b, ord=1):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def run_gpu(p, iters, diag=False, **sched):
-    s = mam.solver_for(p, diag=diag, **sched)
+def run_gpu(p, iters, diag=False, cold=False, **sched):
+    s = mam.solver_for(p, diag=diag, cold=cold, **sched)
     s.init()
     s.iterate(iters)
     pb = s.barycenter().cpu().numpy()
@@ -145,6 +145,7 @@ def test_diagnostics_match_oracle(gamma):
     g = run_gpu(p, k, diag=True)
     gd = g["diag"]
     assert gd["iterations"] == k
+    assert gd["rounds_per_column"] >= 1.0 and gd["active_per_column"] >= 1.0
     assert abs(gd["W_hat"] - od["W_hat"]) <= 1e-10 * abs(od["W_hat"])
     assert abs(gd["dist_L"] - od["dist_L"]) <= 1e-8 * max(od["dist_L"], 1e-12)
     assert gd["meas_resid"] <= 1e-14 and od["meas_resid"] <= 1e-14
@@ -231,3 +232,21 @@ def test_cost_helper():
         np.testing.assert_allclose(got.T, ref, rtol=1e-14, atol=1e-16)
         g32 = mam.cost_sq_euclid(xi_t, z_t, normalize_max=norm, dtype=torch.float32, ld=K * K + 3)
         np.testing.assert_allclose(g32[:, :K * K].cpu().numpy().T, ref, rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("nt,kc", [(64, 1), (64, 2), (64, 4), (256, 2), (512, 4), (1024, 2)])
+def test_columns_in_flight_and_warm_start(nt, kc):
+    """Warm-started thresholds and any number of columns in flight give the
+    same plans, bitwise, as cold starts one column at a time."""
+    p = inputs.balanced_sparse(K=16, M=5, iters=25, dtype="f32")
+    ref = run_gpu(p, 25, threads_per_column=64, columns_in_flight=1, cold=True)
+    got = run_gpu(p, 25, threads_per_column=nt, columns_in_flight=kc)
+    if nt == 64:
+        assert np.array_equal(ref["p_bar"], got["p_bar"])
+        for x, y in zip(ref["theta"], got["theta"]):
+            assert np.array_equal(x, y)
+    else:   # a different group width sums in a different order
+        assert rel(got["p_bar"], ref["p_bar"]) <= 1e-6
+    cost, q = blocks(p)
+    ora = O.mam(cost, q, p.rho, p.gamma, 25)
+    assert rel(got["p_bar"], ora["p_bar"]) <= TOL["f32"]

@@ -120,8 +120,14 @@ typedef struct mam_schedule {
   int32_t columns_in_flight;  /* columns a group advances together: 1, 2 or 4   */
   int32_t workgroups;         /* workgroups per iteration, each owning a
                                  contiguous run of columns                       */
-  int32_t xcd_remap;          /* 1: consecutive runs on one XCD (shared L2)      */
+  int32_t xcd_remap;          /* consecutive runs on one XCD (shared L2): 1 on,
+                                 -1 off, 0 automatic (on when the columns are
+                                 ordered cost-block-major)                        */
   int32_t vector_width;       /* elements per load: 4 (float), 2 (double) or 1 (out) */
+  int32_t order;              /* column order: 1 measure-major, 2 cost-block-major
+                                 (columns sharing cost columns close in time;
+                                 shared costs, or indexed costs sorted within
+                                 each measure), 0 automatic                       */
 } mam_schedule;
 
 /* ABI version of this header (1). */

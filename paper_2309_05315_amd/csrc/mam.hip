@@ -50,7 +50,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t partial, pm, pm_prev, p, p_prev, d2part, tval, diag, check, lam;
-  size_t seg_m, seg_j0, seg_j1, wg_seg, mseg, col_off, Sd, aw;
+  size_t seg_m, seg_j0, seg_j1, seg_idx, wg_seg, mseg, col_off, Sd, aw;
   size_t total;
 };
 
@@ -68,7 +68,10 @@ struct mam_problem {
   // schedule
   int nt = 0, vpt = 0, ng = 0, nwg = 0, xcd_remap = 0, kc = 1;
   int nt_req = 0, nwg_req = 0, kc_req = 0;
-  std::vector<int32_t> seg_m, wg_seg, mseg;
+  std::vector<int32_t> seg_m, wg_seg, mseg, seg_idx;
+  bool blocked = false;
+  int xcd_req = 0;    // >0 on, <0 off, 0 automatic (on for cost-block-major orders)
+  int order_req = 0;  // 0 automatic, 1 measure-major, 2 cost-block-major
   std::vector<int64_t> seg_j0, seg_j1;
   int nb = 0;  // average-kernel blocks = d^2 partials
   Layout lay{};
@@ -135,7 +138,74 @@ mam_status choose_shape(mam_problem* p) {
   return MAM_OK;
 }
 
-void build_schedule(mam_problem* p) {
+// Columns that share a cost column (the same s under a shared cost, the
+// same index under an indexed cost) should be streamed close together in
+// time so the cost column is fetched into L2 once.  The column order is a
+// list of tasks (measure, contiguous column range): cost-block-major when
+// the cost layout allows it (block = B cost columns, about 2 MiB), else
+// measure-major.  Workgroups take equal shares of the concatenated order;
+// every piece of a task a workgroup owns is one segment (one row-sum
+// partial).
+struct Task {
+  int m;
+  int64_t lo, hi;
+};
+
+int64_t cost_block(const mam_problem* p) {
+  const int64_t col_bytes = p->R * (int64_t)elem_bytes(p->dtype);
+  int64_t b = 1;
+  while (b * 2 * col_bytes <= (int64_t)(2 << 20) && b < 4096) b *= 2;
+  return b;
+}
+
+// Upper bound on the number of segments, fixed before the index is known.
+int64_t segment_bound(const mam_problem* p, int nwg) {
+  if (p->cost_mode == MAM_COST_PER_COLUMN) return p->M + nwg;
+  const int64_t nkb = (p->cost_ncols + cost_block(p) - 1) / cost_block(p);
+  return nkb * p->M + nwg;
+}
+
+std::vector<Task> task_order(const mam_problem* p, const std::vector<int32_t>* idx, bool* is_blocked) {
+  std::vector<Task> tasks;
+  // automatic: cost-block-major for a shared cost, measure-major for an
+  // indexed cost (the faster of the two on the measured workloads)
+  const int order = p->order_req ? p->order_req : (p->cost_mode == MAM_COST_SHARED ? 2 : 1);
+  bool blocked = p->cost_mode == MAM_COST_SHARED && order == 2;
+  if (p->cost_mode == MAM_COST_INDEXED && idx && order == 2) {
+    blocked = true;
+    for (int64_t m = 0; m < p->M && blocked; ++m)
+      for (int64_t j = p->col_off[m] + 1; j < p->col_off[m + 1]; ++j)
+        if ((*idx)[j] < (*idx)[j - 1]) {
+          blocked = false;
+          break;
+        }
+  }
+  *is_blocked = blocked;
+  if (!blocked) {
+    for (int64_t m = 0; m < p->M; ++m) tasks.push_back({(int)m, p->col_off[m], p->col_off[m + 1]});
+    return tasks;
+  }
+  const int64_t B = cost_block(p);
+  const int64_t nkb = (p->cost_ncols + B - 1) / B;
+  for (int64_t kb = 0; kb < nkb; ++kb) {
+    for (int64_t m = 0; m < p->M; ++m) {
+      const int64_t o = p->col_off[m], S = p->S[m];
+      int64_t lo, hi;
+      if (p->cost_mode == MAM_COST_SHARED) {
+        lo = o + std::min(S, kb * B);
+        hi = o + std::min(S, (kb + 1) * B);
+      } else {
+        const int32_t* b = idx->data() + o;
+        lo = o + (std::lower_bound(b, b + S, (int32_t)std::min<int64_t>(kb * B, INT32_MAX)) - b);
+        hi = o + (std::lower_bound(b, b + S, (int32_t)std::min<int64_t>((kb + 1) * B, INT32_MAX)) - b);
+      }
+      if (hi > lo) tasks.push_back({(int)m, lo, hi});
+    }
+  }
+  return tasks;
+}
+
+void build_schedule(mam_problem* p, const std::vector<int32_t>* idx = nullptr) {
   const int64_t T = p->T;
   const int ng = p->ng;
   int nwg = p->nwg_req;
@@ -146,35 +216,46 @@ void build_schedule(mam_problem* p) {
   }
   nwg = (int)std::max<int64_t>(1, std::min<int64_t>(nwg, T));
   p->nwg = nwg;
+  bool blocked = false;
+  const std::vector<Task> tasks = task_order(p, idx, &blocked);
+  p->blocked = blocked;
+  p->xcd_remap = p->xcd_req > 0 ? 1 : (p->xcd_req < 0 ? 0 : (p->blocked ? 1 : 0));
   p->seg_m.clear();
   p->seg_j0.clear();
   p->seg_j1.clear();
   p->wg_seg.assign(nwg + 1, 0);
-  int m = 0;
+  size_t ti = 0;
+  int64_t tpos = 0;  // columns of tasks[ti] already assigned
   for (int w = 0; w < nwg; ++w) {
-    int64_t a = T * w / nwg, b = T * (w + 1) / nwg;
+    int64_t need = T * (w + 1) / nwg - T * w / nwg;
     p->wg_seg[w] = (int32_t)p->seg_m.size();
-    while (a < b) {
-      while (p->col_off[m + 1] <= a) ++m;
-      int64_t e = std::min(b, p->col_off[m + 1]);
-      p->seg_m.push_back(m);
-      p->seg_j0.push_back(a);
-      p->seg_j1.push_back(e);
-      a = e;
+    while (need > 0 && ti < tasks.size()) {
+      const Task& tk = tasks[ti];
+      const int64_t take = std::min(need, tk.hi - tk.lo - tpos);
+      p->seg_m.push_back(tk.m);
+      p->seg_j0.push_back(tk.lo + tpos);
+      p->seg_j1.push_back(tk.lo + tpos + take);
+      need -= take;
+      tpos += take;
+      if (tpos == tk.hi - tk.lo) {
+        ++ti;
+        tpos = 0;
+      }
     }
   }
   p->wg_seg[nwg] = (int32_t)p->seg_m.size();
-  // measures' segment ranges (segments are sorted by measure, then column)
+  // each measure's segments, in schedule order, for the marginal kernel
   p->mseg.assign(p->M + 1, 0);
-  size_t k = 0;
-  for (int64_t mm = 0; mm < p->M; ++mm) {
-    p->mseg[mm] = (int32_t)k;
-    while (k < p->seg_m.size() && p->seg_m[k] == mm) ++k;
+  for (int32_t m : p->seg_m) ++p->mseg[m + 1];
+  for (int64_t m = 0; m < p->M; ++m) p->mseg[m + 1] += p->mseg[m];
+  p->seg_idx.assign(p->seg_m.size(), 0);
+  {
+    std::vector<int32_t> fill(p->mseg.begin(), p->mseg.end() - 1);
+    for (size_t k = 0; k < p->seg_m.size(); ++k) p->seg_idx[fill[p->seg_m[k]]++] = (int32_t)k;
   }
-  p->mseg[p->M] = (int32_t)k;
   p->nb = (int)((p->R + 255) / 256);
 
-  const size_t nseg = p->seg_m.size();
+  const size_t nseg = (size_t)std::max<int64_t>(segment_bound(p, nwg), (int64_t)p->seg_m.size());
   const size_t R = (size_t)p->R, M = (size_t)p->M;
   Layout& L = p->lay;
   size_t o = 0;
@@ -192,6 +273,7 @@ void build_schedule(mam_problem* p) {
   L.seg_m = take(nseg * 4);
   L.seg_j0 = take(nseg * 8);
   L.seg_j1 = take(nseg * 8);
+  L.seg_idx = take(nseg * 4);
   L.wg_seg = take((size_t)(nwg + 1) * 4);
   L.mseg = take((M + 1) * 4);
   L.col_off = take((M + 1) * 8);
@@ -212,6 +294,7 @@ mam_status upload_tables(mam_problem* p, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(p->ws + L.seg_j1, p->seg_j1.data(), p->seg_j1.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(p->ws + L.wg_seg, p->wg_seg.data(), p->wg_seg.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(p->ws + L.mseg, p->mseg.data(), p->mseg.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(p->ws + L.seg_idx, p->seg_idx.data(), p->seg_idx.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(p->ws + L.col_off, p->col_off.data(), p->col_off.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(p->ws + L.Sd, p->Sd.data(), p->Sd.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(p->ws + L.aw, p->aw.data(), p->aw.size() * 8, hipMemcpyHostToDevice, st));
@@ -273,7 +356,8 @@ mam_status launch_marginals(mam_problem* p, hipStream_t st, int save_prev) {
   const Layout& L = p->lay;
   dim3 g1((unsigned)((p->R + 255) / 256), (unsigned)p->M);
   hipLaunchKernelGGL(mam::marginal_kernel, g1, dim3(256), 0, st, at<double>(p, L.partial), (int)p->R,
-                     at<int32_t>(p, L.mseg), at<double>(p, L.pm), at<double>(p, L.pm_prev), save_prev);
+                     at<int32_t>(p, L.mseg), at<int32_t>(p, L.seg_idx), at<double>(p, L.pm),
+                     at<double>(p, L.pm_prev), save_prev);
   LAUNCH_CHECK("marginal_kernel");
   hipLaunchKernelGGL(mam::average_kernel, dim3(p->nb), dim3(256), 0, st, at<double>(p, L.pm), (int)p->R,
                      (int)p->M, at<double>(p, L.aw), at<double>(p, L.Sd), at<double>(p, L.p),
@@ -428,8 +512,10 @@ mam_status mam_set_schedule(mam_problem* p, const mam_schedule* s) {
     choose_shape(p);
     return st;
   }
+  if (s->order < 0 || s->order > 2) return fail(MAM_EINVAL, "order must be 0, 1 or 2 (got %d)", s->order);
   p->nwg_req = s->workgroups;
-  p->xcd_remap = s->xcd_remap ? 1 : 0;
+  p->xcd_req = s->xcd_remap;
+  p->order_req = s->order;
   build_schedule(p);
   return MAM_OK;
 }
@@ -442,6 +528,7 @@ mam_status mam_get_schedule(const mam_problem* p, mam_schedule* s) {
   s->workgroups = p->nwg;
   s->xcd_remap = p->xcd_remap;
   s->vector_width = p->vec;
+  s->order = p->blocked ? 2 : 1;
   return MAM_OK;
 }
 
@@ -488,6 +575,17 @@ mam_status mam_init(mam_problem* p, const void* theta0, void* stream) {
   if (!p->ws) return fail(MAM_ESTATE, "no workspace");
   if (!p->theta) return fail(MAM_ESTATE, "no buffers bound");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->cost_mode == MAM_COST_INDEXED) {
+    // the column order depends on the index (sorted within each measure:
+    // cost-block-major); it is read once here
+    std::vector<int32_t> idx(p->T);
+    HIP_TRY(hipMemcpyAsync(idx.data(), p->cidx, p->T * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t j = 0; j < p->T; ++j)
+      if (idx[j] < 0 || idx[j] >= p->cost_ncols)
+        return fail(MAM_ENONFINITE, "cost_col_index[%lld] = %d is out of range", (long long)j, idx[j]);
+    build_schedule(p, &idx);
+  }
   mam_status s = upload_tables(p, st);
   if (s != MAM_OK) return s;
   s = p->dtype == MAM_F32 ? launch_checks<float>(p, st) : launch_checks<double>(p, st);

@@ -7,16 +7,17 @@
 
 namespace mam {
 
-// p^(m)_r = sum over the segments of measure m (in segment order).
+// p^(m)_r = sum over the segments of measure m (in schedule order).
 __global__ void __launch_bounds__(256)
 marginal_kernel(const double* __restrict__ partial, int R, const int32_t* __restrict__ mseg,
-                double* __restrict__ pm, double* __restrict__ pm_prev, int save_prev) {
+                const int32_t* __restrict__ seg_idx, double* __restrict__ pm, double* __restrict__ pm_prev,
+                int save_prev) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   const int m = blockIdx.y;
   if (r >= R) return;
   double s = 0.0;
   const int e = mseg[m + 1];
-  for (int si = mseg[m]; si < e; ++si) s += partial[(size_t)si * R + r];
+  for (int i = mseg[m]; i < e; ++i) s += partial[(size_t)seg_idx[i] * R + r];
   const size_t o = (size_t)m * R + r;
   if (save_prev) pm_prev[o] = pm[o];
   pm[o] = s;

@@ -94,12 +94,12 @@ def test_schedule_override_validation():
     assert L.mam_set_schedule(h, ctypes.byref(tiny)) == -6
     kc3 = mam.Schedule(columns_in_flight=3)
     assert L.mam_set_schedule(h, ctypes.byref(kc3)) == -1
-    ok = mam.Schedule(threads_per_column=1024, columns_in_flight=4, workgroups=37, xcd_remap=1)
+    ok = mam.Schedule(threads_per_column=1024, columns_in_flight=4, workgroups=37, xcd_remap=-1)
     assert L.mam_set_schedule(h, ctypes.byref(ok)) == 0
     sc = mam.Schedule()
     L.mam_get_schedule(h, ctypes.byref(sc))
     assert (sc.threads_per_column, sc.values_per_thread, sc.columns_in_flight, sc.workgroups,
-            sc.xcd_remap) == (1024, 4, 4, 37, 1)
+            sc.xcd_remap) == (1024, 4, 4, 37, 0)
     L.mam_destroy(h)
 
 

@@ -109,15 +109,16 @@ def test_unbalanced_damping_history():
     assert min(ts) < 1.0
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_indexed_sparse_quarter_scale(dtype):
-    """Sparse supports (zero pixels removed) with the grid cost gathered by index."""
+@pytest.mark.parametrize("dtype,order", [("f64", 0), ("f32", 0), ("f32", 2)])
+def test_indexed_sparse_quarter_scale(dtype, order):
+    """Sparse supports (zero pixels removed) with the grid cost gathered by
+    index, in measure-major and cost-block-major column order."""
     p = inputs.balanced_sparse(K=24, M=8, iters=40, dtype=dtype)
-    check(p, 40)
+    check(p, 40, order=order)
 
 
 @pytest.mark.parametrize("nt,nwg,remap", [
-    (64, 1, 0), (64, 0, 1), (128, 7, 0), (256, 0, 0), (512, 3, 1), (1024, 0, 0), (256, 10000, 0),
+    (64, 1, -1), (64, 0, 1), (128, 7, -1), (256, 0, 0), (512, 3, 1), (1024, 0, 0), (256, 10000, -1),
 ])
 def test_schedules(nt, nwg, remap):
     p = inputs.tiny_problem(77, R=900, S=[37, 5, 61, 12], dtype="f64", zero_frac=0.1, iters=15)

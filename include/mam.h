@@ -192,13 +192,70 @@ mam_status mam_marginals(mam_problem* p, double* pm_dev, void* stream);
 mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream);
 
 /* Kernel timing: while enabled, HIP events bracket every launch of the
- * column kernel on the stream.  mam_timing_read synchronizes and returns the
+ * column kernel on the stream (graph replay is off meanwhile).  mam_timing_read synchronizes and returns the
  * summed milliseconds and the launch count since the last reset. */
 mam_status mam_timing_enable(mam_problem* p, int32_t enable);
 mam_status mam_timing_read(mam_problem* p, double* total_ms, int64_t* launches);
 
 /* Destroy a handle (NULL is allowed).  Device buffers stay with the caller. */
 void mam_destroy(mam_problem* p);
+
+/* Graph replay: capture 'iters_per_launch' iterations once as a HIP graph
+ * (on a stream of the library's own) and let mam_iterate replay it on the
+ * caller's stream, running any remainder (and a diagnostics iteration)
+ * directly.  0 turns graphs off.  Rebinding or re-initialising drops the
+ * captured graph.  No memset nodes are captured. */
+mam_status mam_graph(mam_problem* p, int64_t iters_per_launch);
+
+/* ---- batches -------------------------------------------------------------
+ * Many independent problems (same dtype; any R <= 8192, M, S^m, cost mode,
+ * rho, gamma) advanced together: each iteration is one column-kernel launch
+ * per shape group (problems whose columns need the same threads per column
+ * and values per thread), then one marginal and one averaging launch for
+ * all problems; mam_batch_graph captures whole iterations as one graph.
+ * Diagnostics (MAM_FLAG_DIAG) are not computed for batches. */
+typedef struct mam_batch mam_batch;
+
+/* Validate n >= 1 descriptions (rules of mam_create) and create a batch. */
+mam_status mam_batch_create(mam_batch** out, const mam_desc* descs, int32_t n);
+
+/* Number of shape groups, and the group of problem i (-1 if none). */
+int32_t mam_batch_groups(const mam_batch* b);
+int32_t mam_batch_group_of(const mam_batch* b, int32_t i);
+
+/* Schedule of one shape group (rules of mam_set_schedule). */
+mam_status mam_batch_set_schedule(mam_batch* b, int32_t group, const mam_schedule* s);
+mam_status mam_batch_get_schedule(const mam_batch* b, int32_t group, mam_schedule* s);
+
+/* Workspace for the whole batch (rules of mam_workspace_bytes and
+ * mam_set_workspace). */
+size_t mam_batch_workspace_bytes(const mam_batch* b);
+mam_status mam_batch_set_workspace(mam_batch* b, void* dev, size_t bytes);
+
+/* Buffers of problem i (rules of mam_bind). */
+mam_status mam_batch_bind(mam_batch* b, int32_t i, void* theta, const void* cost,
+                          const int32_t* cost_col_index, const void* q);
+
+/* Alg. 1 Step 0 for every problem (theta^0 = q_s/R) with the checks of
+ * mam_init; SYNCHRONIZES the stream. */
+mam_status mam_batch_init(mam_batch* b, void* stream);
+
+/* 'iters' iterations of every problem; asynchronous. */
+mam_status mam_batch_iterate(mam_batch* b, int64_t iters, void* stream);
+
+/* Graph replay for batches (rules of mam_graph). */
+mam_status mam_batch_graph(mam_batch* b, int64_t iters_per_launch);
+
+/* Barycenter of problem i: R_i doubles into a device buffer; asynchronous. */
+mam_status mam_batch_barycenter(mam_batch* b, int32_t i, double* p_dev, void* stream);
+
+/* Column-kernel timing for batches (rules of mam_timing_enable/read; one
+ * launch = all groups' column kernels of one iteration). */
+mam_status mam_batch_timing_enable(mam_batch* b, int32_t enable);
+mam_status mam_batch_timing_read(mam_batch* b, double* total_ms, int64_t* launches);
+
+/* Destroy a batch (NULL is allowed). */
+void mam_batch_destroy(mam_batch* b);
 
 /* Cost helper (the cost of (HugeLP) from support points):
  * out[s*out_ld + r] = ||xi_r - zeta_s||^2, divided by its maximum over all

@@ -1,6 +1,13 @@
-// Host side of the MAM library: C ABI, validation, column schedule,
-// workspace layout and kernel launches.  See mam.h for the contract and
-// mam_kernels.hpp for the device code.
+// Host side of the MAM library: C ABI, validation, column schedules,
+// workspace layout, kernel launches and graph capture.  See mam.h for the
+// contract, mam_kernels.hpp and mam_aux_kernels.hpp for the device code.
+//
+// Internally every handle is a Plan of one or more independent problems.  A
+// single problem (mam_create) is a plan of one; a batch (mam_batch_create)
+// is a plan of many.  Problems are grouped by column shape (threads per
+// column, values per thread); one iteration of the whole plan is one
+// column-kernel launch per group, then one marginal and one averaging
+// launch for all problems.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -44,58 +52,15 @@ mam_status fail(mam_status code, const char* fmt, ...) {
       return fail(MAM_EHIP, "launch of %s failed: %s", name, hipGetErrorString(e_)); \
   } while (0)
 
+#define TRY(expr)                      \
+  do {                                 \
+    mam_status s_ = (expr);            \
+    if (s_ != MAM_OK) return s_;       \
+  } while (0)
+
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxLds = 160 * 1024;  // LDS per compute unit on gfx950
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-  size_t partial, pm, pm_prev, p, p_prev, d2part, tval, diag, check, lam;
-  size_t seg_m, seg_j0, seg_j1, seg_idx, wg_seg, mseg, col_off, Sd, aw;
-  size_t total;
-};
-
-}  // namespace
-
-struct mam_problem {
-  int dtype = MAM_F64;
-  int cost_mode = MAM_COST_PER_COLUMN;
-  int64_t R = 0, M = 0, T = 0, ld = 0, cost_ld = 0, cost_ncols = 0;
-  double rho = 1.0, gamma = INFINITY;
-  uint32_t flags = 0;
-  std::vector<int64_t> S, col_off;
-  std::vector<double> Sd, aw;
-
-  // schedule
-  int nt = 0, vpt = 0, ng = 0, nwg = 0, xcd_remap = 0, kc = 1;
-  int nt_req = 0, nwg_req = 0, kc_req = 0;
-  std::vector<int32_t> seg_m, wg_seg, mseg, seg_idx;
-  bool blocked = false;
-  int xcd_req = 0;    // >0 on, <0 off, 0 automatic (on for cost-block-major orders)
-  int order_req = 0;  // 0 automatic, 1 measure-major, 2 cost-block-major
-  std::vector<int64_t> seg_j0, seg_j1;
-  int nb = 0;  // average-kernel blocks = d^2 partials
-  Layout lay{};
-
-  // bound state
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  void* theta = nullptr;
-  const void* cost = nullptr;
-  const int32_t* cidx = nullptr;
-  const void* q = nullptr;
-  int vec = 1;
-  bool inited = false;
-  bool tables_uploaded = false;
-  int64_t iters_done = 0;
-  bool diag_valid = false;
-
-  // timing
-  bool timing = false;
-  std::vector<hipEvent_t> ev;
-  size_t ev_used = 0;
-};
-
-namespace {
 
 int vec_width(int dtype) { return dtype == MAM_F32 ? 4 : 2; }
 size_t elem_bytes(int dtype) { return dtype == MAM_F32 ? 4 : 8; }
@@ -106,336 +71,93 @@ int pow2_ceil(int64_t x) {
   return v;
 }
 
-// Pick threads per column and values per thread.  A column of R rows is held
-// in registers: NT threads x VPT values, VPT <= 16.
-mam_status choose_shape(mam_problem* p) {
-  const int64_t R = p->R;
-  int nt = p->nt_req;
-  if (nt == 0) {
-    // The fewest threads per column that keep a thread at 16 (float) or 8
-    // (double) values: a column group then fits twice per compute unit
-    // (registers and LDS), which measured fastest on MI355X; one wave per
-    // column whenever that suffices (no barriers in the threshold rounds).
-    const int64_t target = p->dtype == MAM_F32 ? 16 : 8;
-    nt = 64;
-    while (nt < 1024 && (int64_t)nt * target < R) nt *= 2;
-  }
-  if (nt != 64 && nt != 128 && nt != 256 && nt != 512 && nt != 1024)
-    return fail(MAM_EINVAL, "threads_per_column must be 64, 128, 256, 512 or 1024 (got %d)", nt);
-  int64_t per = (R + nt - 1) / nt;
-  int vpt = pow2_ceil(per);
-  if (nt >= 128 && vpt < 4) vpt = 4;  // multi-wave groups hold at least 4 values per thread
-  if (vpt > 16) return fail(MAM_EUNSUPPORTED, "R = %lld needs more than 16 values per thread at %d threads per column", (long long)R, nt);
-  const int ng = nt == 64 ? 4 : 1;
-  if ((int64_t)vpt * nt * 8 * (1 + ng) > kMaxLds)
-    return fail(MAM_EUNSUPPORTED, "R = %lld at %d threads per column needs more than 160 KiB of LDS", (long long)R, nt);
-  int kc = p->kc_req ? p->kc_req : 1;
-  if (kc != 1 && kc != 2 && kc != 4) return fail(MAM_EINVAL, "columns_in_flight must be 1, 2 or 4 (got %d)", kc);
-  p->nt = nt;
-  p->vpt = vpt;
-  p->kc = kc;
-  p->ng = nt == 64 ? 4 : 1;
-  return MAM_OK;
-}
-
-// Columns that share a cost column (the same s under a shared cost, the
-// same index under an indexed cost) should be streamed close together in
-// time so the cost column is fetched into L2 once.  The column order is a
-// list of tasks (measure, contiguous column range): cost-block-major when
-// the cost layout allows it (block = B cost columns, about 2 MiB), else
-// measure-major.  Workgroups take equal shares of the concatenated order;
-// every piece of a task a workgroup owns is one segment (one row-sum
-// partial).
+// A contiguous column range of one measure.
 struct Task {
   int m;
   int64_t lo, hi;
 };
 
-int64_t cost_block(const mam_problem* p) {
-  const int64_t col_bytes = p->R * (int64_t)elem_bytes(p->dtype);
-  int64_t b = 1;
-  while (b * 2 * col_bytes <= (int64_t)(2 << 20) && b < 4096) b *= 2;
-  return b;
-}
+struct Prob {
+  int64_t R = 0, M = 0, T = 0, ld = 0, cost_ld = 0, cost_ncols = 0;
+  int cost_mode = MAM_COST_PER_COLUMN;
+  double rho = 1.0, gamma = INFINITY;
+  uint32_t flags = 0;
+  std::vector<int64_t> S, col_off;
+  std::vector<double> Sd, aw;
+  // bound buffers
+  void* theta = nullptr;
+  const void* cost = nullptr;
+  const int32_t* cidx = nullptr;
+  const void* q = nullptr;
+  bool aligned = true;
+  std::vector<int32_t> idx;  // host copy of an indexed cost's column index
+  // workspace offsets of the problem's own region
+  size_t o_pm = 0, o_pm_prev = 0, o_p = 0, o_p_prev = 0, o_d2 = 0, o_t = 0, o_lam = 0, o_check = 0;
+  size_t o_coloff = 0, o_Sd = 0, o_aw = 0;
+  int nb = 0;
+  int group = 0;
+  int mbase = 0;
+};
 
-// Upper bound on the number of segments, fixed before the index is known.
-int64_t segment_bound(const mam_problem* p, int nwg) {
-  if (p->cost_mode == MAM_COST_PER_COLUMN) return p->M + nwg;
-  const int64_t nkb = (p->cost_ncols + cost_block(p) - 1) / cost_block(p);
-  return nkb * p->M + nwg;
-}
-
-std::vector<Task> task_order(const mam_problem* p, const std::vector<int32_t>* idx, bool* is_blocked) {
-  std::vector<Task> tasks;
-  // automatic: cost-block-major for a shared cost, measure-major for an
-  // indexed cost (the faster of the two on the measured workloads)
-  const int order = p->order_req ? p->order_req : (p->cost_mode == MAM_COST_SHARED ? 2 : 1);
-  bool blocked = p->cost_mode == MAM_COST_SHARED && order == 2;
-  if (p->cost_mode == MAM_COST_INDEXED && idx && order == 2) {
-    blocked = true;
-    for (int64_t m = 0; m < p->M && blocked; ++m)
-      for (int64_t j = p->col_off[m] + 1; j < p->col_off[m + 1]; ++j)
-        if ((*idx)[j] < (*idx)[j - 1]) {
-          blocked = false;
-          break;
-        }
-  }
-  *is_blocked = blocked;
-  if (!blocked) {
-    for (int64_t m = 0; m < p->M; ++m) tasks.push_back({(int)m, p->col_off[m], p->col_off[m + 1]});
-    return tasks;
-  }
-  const int64_t B = cost_block(p);
-  const int64_t nkb = (p->cost_ncols + B - 1) / B;
-  for (int64_t kb = 0; kb < nkb; ++kb) {
-    for (int64_t m = 0; m < p->M; ++m) {
-      const int64_t o = p->col_off[m], S = p->S[m];
-      int64_t lo, hi;
-      if (p->cost_mode == MAM_COST_SHARED) {
-        lo = o + std::min(S, kb * B);
-        hi = o + std::min(S, (kb + 1) * B);
-      } else {
-        const int32_t* b = idx->data() + o;
-        lo = o + (std::lower_bound(b, b + S, (int32_t)std::min<int64_t>(kb * B, INT32_MAX)) - b);
-        hi = o + (std::lower_bound(b, b + S, (int32_t)std::min<int64_t>((kb + 1) * B, INT32_MAX)) - b);
-      }
-      if (hi > lo) tasks.push_back({(int)m, lo, hi});
-    }
-  }
-  return tasks;
-}
-
-void build_schedule(mam_problem* p, const std::vector<int32_t>* idx = nullptr) {
-  const int64_t T = p->T;
-  const int ng = p->ng;
-  int nwg = p->nwg_req;
-  if (nwg <= 0) {
-    const int64_t cap = 1024;
-    int64_t cpw = std::max<int64_t>(1, (T + ng * cap - 1) / (ng * cap));
-    nwg = (int)std::min<int64_t>(cap, (T + ng * cpw - 1) / (ng * cpw));
-  }
-  nwg = (int)std::max<int64_t>(1, std::min<int64_t>(nwg, T));
-  p->nwg = nwg;
+struct Group {
+  int nt = 64, vpt = 1, ng = 4, kc = 1, vec = 1;
+  int nt_req = 0, kc_req = 0, nwg_req = 0, xcd_req = 0, order_req = 0;
+  int nwg = 1, wg_base = 0, xcd_remap = 0;
+  int64_t Rmax = 0;
   bool blocked = false;
-  const std::vector<Task> tasks = task_order(p, idx, &blocked);
-  p->blocked = blocked;
-  p->xcd_remap = p->xcd_req > 0 ? 1 : (p->xcd_req < 0 ? 0 : (p->blocked ? 1 : 0));
-  p->seg_m.clear();
-  p->seg_j0.clear();
-  p->seg_j1.clear();
-  p->wg_seg.assign(nwg + 1, 0);
-  size_t ti = 0;
-  int64_t tpos = 0;  // columns of tasks[ti] already assigned
-  for (int w = 0; w < nwg; ++w) {
-    int64_t need = T * (w + 1) / nwg - T * w / nwg;
-    p->wg_seg[w] = (int32_t)p->seg_m.size();
-    while (need > 0 && ti < tasks.size()) {
-      const Task& tk = tasks[ti];
-      const int64_t take = std::min(need, tk.hi - tk.lo - tpos);
-      p->seg_m.push_back(tk.m);
-      p->seg_j0.push_back(tk.lo + tpos);
-      p->seg_j1.push_back(tk.lo + tpos + take);
-      need -= take;
-      tpos += take;
-      if (tpos == tk.hi - tk.lo) {
-        ++ti;
-        tpos = 0;
-      }
-    }
-  }
-  p->wg_seg[nwg] = (int32_t)p->seg_m.size();
-  // each measure's segments, in schedule order, for the marginal kernel
-  p->mseg.assign(p->M + 1, 0);
-  for (int32_t m : p->seg_m) ++p->mseg[m + 1];
-  for (int64_t m = 0; m < p->M; ++m) p->mseg[m + 1] += p->mseg[m];
-  p->seg_idx.assign(p->seg_m.size(), 0);
-  {
-    std::vector<int32_t> fill(p->mseg.begin(), p->mseg.end() - 1);
-    for (size_t k = 0; k < p->seg_m.size(); ++k) p->seg_idx[fill[p->seg_m[k]]++] = (int32_t)k;
-  }
-  p->nb = (int)((p->R + 255) / 256);
+  std::vector<int> probs;
+};
 
-  const size_t nseg = (size_t)std::max<int64_t>(segment_bound(p, nwg), (int64_t)p->seg_m.size());
-  const size_t R = (size_t)p->R, M = (size_t)p->M;
-  Layout& L = p->lay;
-  size_t o = 0;
-  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
-  L.partial = take(nseg * R * 8);
-  L.pm = take(M * R * 8);
-  L.pm_prev = take(M * R * 8);
-  L.p = take(R * 8);
-  L.p_prev = take(R * 8);
-  L.d2part = take((size_t)p->nb * 8);
-  L.tval = take(8);
-  L.diag = take((size_t)nwg * mam::DIAG_STRIDE * 8);
-  L.lam = take((size_t)p->T * 8);
-  L.check = take((M + 2) * 8);
-  L.seg_m = take(nseg * 4);
-  L.seg_j0 = take(nseg * 8);
-  L.seg_j1 = take(nseg * 8);
-  L.seg_idx = take(nseg * 4);
-  L.wg_seg = take((size_t)(nwg + 1) * 4);
-  L.mseg = take((M + 1) * 4);
-  L.col_off = take((M + 1) * 8);
-  L.Sd = take(M * 8);
-  L.aw = take(M * 8);
-  L.total = o;
-  p->tables_uploaded = false;
-}
+struct Layout {
+  size_t partial = 0, diag = 0, seg_p = 0, seg_m = 0, seg_j0 = 0, seg_j1 = 0, seg_poff = 0, seg_idx = 0;
+  size_t wg_seg = 0, mseg = 0, probdev = 0, probaux = 0, mtasks = 0, atasks = 0;
+  size_t total = 0;
+};
+
+struct Plan {
+  int dtype = MAM_F64;
+  bool batch = false;
+  std::vector<Prob> P;
+  std::vector<Group> G;
+  // schedule tables
+  std::vector<int32_t> seg_p, seg_m, wg_seg, mseg, seg_idx;
+  std::vector<int64_t> seg_j0, seg_j1, seg_poff;
+  std::vector<mam::MargTask> mtasks;
+  std::vector<mam::AvgTask> atasks;
+  size_t nseg_cap = 0, partial_cap = 0;
+  int nwg_total = 0;
+  Layout lay;
+  // state
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool tables_uploaded = false;
+  bool inited = false;
+  int64_t iters_done = 0;
+  bool diag_valid = false;
+  // graph of a fixed number of iterations
+  int64_t graph_iters = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t capture_stream = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+
+  ~Plan() {
+    for (hipEvent_t e : ev) hipEventDestroy(e);
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (capture_stream) hipStreamDestroy(capture_stream);
+  }
+};
 
 template <typename U>
-U* at(mam_problem* p, size_t off) { return reinterpret_cast<U*>(p->ws + off); }
-
-mam_status upload_tables(mam_problem* p, hipStream_t st) {
-  if (p->tables_uploaded) return MAM_OK;
-  const Layout& L = p->lay;
-  HIP_TRY(hipMemcpyAsync(p->ws + L.seg_m, p->seg_m.data(), p->seg_m.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(p->ws + L.seg_j0, p->seg_j0.data(), p->seg_j0.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(p->ws + L.seg_j1, p->seg_j1.data(), p->seg_j1.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(p->ws + L.wg_seg, p->wg_seg.data(), p->wg_seg.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(p->ws + L.mseg, p->mseg.data(), p->mseg.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(p->ws + L.seg_idx, p->seg_idx.data(), p->seg_idx.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(p->ws + L.col_off, p->col_off.data(), p->col_off.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(p->ws + L.Sd, p->Sd.data(), p->Sd.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(p->ws + L.aw, p->aw.data(), p->aw.size() * 8, hipMemcpyHostToDevice, st));
-  p->tables_uploaded = true;
-  return MAM_OK;
-}
+U* at(Plan* pl, size_t off) { return reinterpret_cast<U*>(pl->ws + off); }
 
 // ---------------------------------------------------------------------------
-// column-kernel dispatch
+// problem description and shapes
 // ---------------------------------------------------------------------------
-template <typename T>
-mam_status launch_column(mam_problem* p, hipStream_t st, int diag) {
-  const Layout& L = p->lay;
-  mam::ColArgs<T> a;
-  a.theta = static_cast<T*>(p->theta);
-  a.cost = static_cast<const T*>(p->cost);
-  a.q = static_cast<const T*>(p->q);
-  a.cidx = p->cidx;
-  a.ld = p->ld;
-  a.cost_ld = p->cost_ld;
-  a.R = (int32_t)p->R;
-  a.cost_mode = p->cost_mode;
-  a.pm = at<double>(p, L.pm);
-  a.p = at<double>(p, L.p);
-  a.d2part = at<double>(p, L.d2part);
-  a.nb = p->nb;
-  a.warm = (p->flags & MAM_FLAG_COLD) ? 0 : 1;
-  a.rho = p->rho;
-  a.inv_rho = 1.0 / p->rho;
-  a.gamma = p->gamma;
-  a.col_off = at<int64_t>(p, L.col_off);
-  a.Sd = at<double>(p, L.Sd);
-  a.seg_m = at<int32_t>(p, L.seg_m);
-  a.seg_j0 = at<int64_t>(p, L.seg_j0);
-  a.seg_j1 = at<int64_t>(p, L.seg_j1);
-  a.wg_seg = at<int32_t>(p, L.wg_seg);
-  a.partial = at<double>(p, L.partial);
-  a.lam = at<double>(p, L.lam);
-  a.t_out = at<double>(p, L.tval);
-  a.diag = at<double>(p, L.diag);
-  a.nwg = p->nwg;
-  a.xcd_remap = p->xcd_remap;
-  const int kc = p->vec == 1 ? 1 : p->kc;
-  mam::ColFn<T> fn = mam::pick_column<T>(p->nt, p->vpt, p->vec, kc, diag);
-  if (!fn) return fail(MAM_EUNSUPPORTED, "no column kernel for nt=%d vpt=%d vec=%d kc=%d", p->nt, p->vpt, p->vec, kc);
-  const int wgsize = p->nt == 64 ? 256 : p->nt;
-  const size_t shmem = (size_t)p->vpt * p->nt * 8 * (1 + p->ng);
-  if (shmem > 65536) {
-    // above the default dynamic-LDS limit: opt this kernel in once
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shmem));
-  }
-  hipLaunchKernelGGL(fn, dim3(p->nwg), dim3(wgsize), shmem, st, a);
-  LAUNCH_CHECK("column_kernel");
-  return MAM_OK;
-}
-
-mam_status launch_marginals(mam_problem* p, hipStream_t st, int save_prev) {
-  const Layout& L = p->lay;
-  dim3 g1((unsigned)((p->R + 255) / 256), (unsigned)p->M);
-  hipLaunchKernelGGL(mam::marginal_kernel, g1, dim3(256), 0, st, at<double>(p, L.partial), (int)p->R,
-                     at<int32_t>(p, L.mseg), at<int32_t>(p, L.seg_idx), at<double>(p, L.pm),
-                     at<double>(p, L.pm_prev), save_prev);
-  LAUNCH_CHECK("marginal_kernel");
-  hipLaunchKernelGGL(mam::average_kernel, dim3(p->nb), dim3(256), 0, st, at<double>(p, L.pm), (int)p->R,
-                     (int)p->M, at<double>(p, L.aw), at<double>(p, L.Sd), at<double>(p, L.p),
-                     at<double>(p, L.p_prev), save_prev, at<double>(p, L.d2part));
-  LAUNCH_CHECK("average_kernel");
-  return MAM_OK;
-}
-
-template <typename T>
-mam_status launch_init(mam_problem* p, const void* theta0, hipStream_t st) {
-  const Layout& L = p->lay;
-  const int blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (p->T * p->R + 255) / 256));
-  if (theta0) {
-    hipLaunchKernelGGL(mam::copy_kernel<T>, dim3(blocks), dim3(256), 0, st, static_cast<T*>(p->theta), p->ld,
-                       (int)p->R, static_cast<const T*>(theta0), p->T);
-    LAUNCH_CHECK("copy_kernel");
-  } else {
-    hipLaunchKernelGGL(mam::fill_kernel<T>, dim3(blocks), dim3(256), 0, st, static_cast<T*>(p->theta), p->ld,
-                       (int)p->R, static_cast<const T*>(p->q), p->T);
-    LAUNCH_CHECK("fill_kernel");
-  }
-  hipLaunchKernelGGL(mam::fill_value_kernel, dim3((unsigned)std::min<int64_t>(4096, (p->T + 255) / 256)), dim3(256), 0,
-                     st, at<double>(p, L.lam), p->T, (double)NAN);
-  LAUNCH_CHECK("fill_value_kernel");
-  hipLaunchKernelGGL(mam::rowsum_kernel<T>, dim3(p->nwg), dim3(256), 0, st, static_cast<const T*>(p->theta),
-                     p->ld, (int)p->R, at<int64_t>(p, L.seg_j0), at<int64_t>(p, L.seg_j1),
-                     at<int32_t>(p, L.wg_seg), at<double>(p, L.partial));
-  LAUNCH_CHECK("rowsum_kernel");
-  return launch_marginals(p, st, 0);
-}
-
-template <typename T>
-mam_status launch_checks(mam_problem* p, hipStream_t st) {
-  const Layout& L = p->lay;
-  double* chk = at<double>(p, L.check);
-  hipLaunchKernelGGL(mam::zero_kernel, dim3((unsigned)((p->M + 2 + 255) / 256)), dim3(256), 0, st, chk,
-                     (int)(p->M + 2));
-  LAUNCH_CHECK("zero_kernel");
-  hipLaunchKernelGGL(mam::check_q_kernel<T>, dim3((unsigned)p->M), dim3(256), 0, st, static_cast<const T*>(p->q),
-                     at<int64_t>(p, L.col_off), chk, (int)p->M);
-  LAUNCH_CHECK("check_q_kernel");
-  const int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (p->cost_ncols * p->R + 255) / 256));
-  hipLaunchKernelGGL(mam::check_cost_kernel<T>, dim3(blocks), dim3(256), 0, st, static_cast<const T*>(p->cost),
-                     p->cost_ld, (int)p->R, p->cost_ncols, chk + p->M + 1);
-  LAUNCH_CHECK("check_cost_kernel");
-  if (p->cost_mode == MAM_COST_INDEXED) {
-    const int ib = (int)std::min<int64_t>(1024, (p->T + 255) / 256);
-    hipLaunchKernelGGL(mam::check_index_kernel, dim3(ib), dim3(256), 0, st, p->cidx, p->T, p->cost_ncols,
-                       chk + p->M + 1);
-    LAUNCH_CHECK("check_index_kernel");
-  }
-  return MAM_OK;
-}
-
-hipEvent_t next_event(mam_problem* p) {
-  if (p->ev_used == p->ev.size()) {
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    p->ev.push_back(e);
-  }
-  return p->ev[p->ev_used++];
-}
-
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// C ABI
-// ---------------------------------------------------------------------------
-extern "C" {
-
-int32_t mam_abi_version(void) { return 1; }
-
-const char* mam_last_error(void) { return g_err.c_str(); }
-
-mam_status mam_create(mam_problem** out, const mam_desc* d) {
-  if (!out) return fail(MAM_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!d) return fail(MAM_EINVAL, "desc is NULL");
+mam_status read_desc(const mam_desc* d, int index, Prob* out) {
+  if (!d) return fail(MAM_EINVAL, "desc %d is NULL", index);
   if (d->dtype != MAM_F32 && d->dtype != MAM_F64) return fail(MAM_EINVAL, "unknown dtype %d", d->dtype);
   if (d->cost_mode < MAM_COST_PER_COLUMN || d->cost_mode > MAM_COST_INDEXED)
     return fail(MAM_EINVAL, "unknown cost_mode %d", d->cost_mode);
@@ -463,225 +185,815 @@ mam_status mam_create(mam_problem** out, const mam_desc* d) {
   if (d->cost_mode == MAM_COST_PER_COLUMN && d->cost_ncols < T)
     return fail(MAM_EINVAL, "per-column cost needs T = %lld columns (got %lld)", (long long)T,
                 (long long)d->cost_ncols);
-
-  mam_problem* p = new (std::nothrow) mam_problem();
-  if (!p) return fail(MAM_ENOMEM, "host allocation failed");
-  p->dtype = d->dtype;
-  p->cost_mode = d->cost_mode;
-  p->R = d->R;
-  p->M = d->M;
-  p->T = T;
-  p->ld = ld;
-  p->cost_ld = cld;
-  p->cost_ncols = d->cost_ncols;
-  p->rho = d->rho;
-  p->gamma = d->gamma;
-  p->flags = d->flags;
-  p->vec = vec_width(d->dtype);  // until mam_bind checks the alignment
-  p->S.assign(d->S, d->S + d->M);
-  p->col_off.assign(d->M + 1, 0);
-  for (int64_t m = 0; m < d->M; ++m) p->col_off[m + 1] = p->col_off[m] + d->S[m];
-  p->Sd.resize(d->M);
-  p->aw.resize(d->M);
+  out->R = d->R;
+  out->M = d->M;
+  out->T = T;
+  out->ld = ld;
+  out->cost_ld = cld;
+  out->cost_ncols = d->cost_ncols;
+  out->cost_mode = d->cost_mode;
+  out->rho = d->rho;
+  out->gamma = d->gamma;
+  out->flags = d->flags;
+  out->S.assign(d->S, d->S + d->M);
+  out->col_off.assign(d->M + 1, 0);
+  for (int64_t m = 0; m < d->M; ++m) out->col_off[m + 1] = out->col_off[m] + d->S[m];
+  out->Sd.resize(d->M);
+  out->aw.resize(d->M);
   double inv_sum = 0.0;
   for (int64_t m = 0; m < d->M; ++m) {
-    p->Sd[m] = (double)d->S[m];
+    out->Sd[m] = (double)d->S[m];
     inv_sum += 1.0 / (double)d->S[m];
   }
-  for (int64_t m = 0; m < d->M; ++m) p->aw[m] = (1.0 / (double)d->S[m]) / inv_sum;
-  mam_status st = choose_shape(p);
+  for (int64_t m = 0; m < d->M; ++m) out->aw[m] = (1.0 / (double)d->S[m]) / inv_sum;
+  out->nb = (int)((d->R + 255) / 256);
+  return MAM_OK;
+}
+
+// Threads per column and values per thread for R rows.  Default: the fewest
+// threads that keep a thread at 16 (float) or 8 (double) values, so a column
+// group fits twice per compute unit (registers and LDS); one wave per
+// column whenever that suffices (no barriers in the threshold rounds).
+mam_status shape_for(int dtype, int64_t R, int nt_req, int* nt_out, int* vpt_out) {
+  int nt = nt_req;
+  if (nt == 0) {
+    const int64_t target = dtype == MAM_F32 ? 16 : 8;
+    nt = 64;
+    while (nt < 1024 && (int64_t)nt * target < R) nt *= 2;
+  }
+  if (nt != 64 && nt != 128 && nt != 256 && nt != 512 && nt != 1024)
+    return fail(MAM_EINVAL, "threads_per_column must be 64, 128, 256, 512 or 1024 (got %d)", nt);
+  int vpt = pow2_ceil((R + nt - 1) / nt);
+  if (nt >= 128 && vpt < 4) vpt = 4;  // multi-wave groups hold at least 4 values per thread
+  if (vpt > 16)
+    return fail(MAM_EUNSUPPORTED, "R = %lld needs more than 16 values per thread at %d threads per column",
+                (long long)R, nt);
+  const int ng = nt == 64 ? 4 : 1;
+  if ((int64_t)vpt * nt * 8 * (1 + ng) > kMaxLds)
+    return fail(MAM_EUNSUPPORTED, "R = %lld at %d threads per column needs more than 160 KiB of LDS",
+                (long long)R, nt);
+  *nt_out = nt;
+  *vpt_out = vpt;
+  return MAM_OK;
+}
+
+mam_status group_shape(Plan* pl, Group& g) {
+  int nt = 0, vpt = 0;
+  TRY(shape_for(pl->dtype, g.Rmax, g.nt_req, &nt, &vpt));
+  const int kc = g.kc_req ? g.kc_req : 1;
+  if (kc != 1 && kc != 2 && kc != 4) return fail(MAM_EINVAL, "columns_in_flight must be 1, 2 or 4 (got %d)", kc);
+  g.nt = nt;
+  g.vpt = vpt;
+  g.kc = kc;
+  g.ng = nt == 64 ? 4 : 1;
+  g.vec = vec_width(pl->dtype);  // until binding checks the alignment
+  return MAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// column order and segments
+//
+// Columns sharing a cost column (the same s under a shared cost, the same
+// index under an indexed cost) should be streamed close together in time so
+// the cost column is fetched into L2 once.  A problem's column order is a
+// list of tasks: cost-block-major when the cost layout allows it (block = B
+// cost columns, about 2 MiB), else measure-major.  A group's workgroups
+// take equal shares of its problems' concatenated orders; every piece of a
+// task a workgroup owns is one segment (one row-sum partial).
+// ---------------------------------------------------------------------------
+int64_t cost_block(int dtype, const Prob& p) {
+  const int64_t col_bytes = p.R * (int64_t)elem_bytes(dtype);
+  int64_t b = 1;
+  while (b * 2 * col_bytes <= (int64_t)(2 << 20) && b < 4096) b *= 2;
+  return b;
+}
+
+int64_t task_bound(int dtype, const Prob& p) {
+  if (p.cost_mode == MAM_COST_PER_COLUMN) return p.M;
+  const int64_t B = cost_block(dtype, p);
+  return std::max<int64_t>(p.M, ((p.cost_ncols + B - 1) / B) * p.M);
+}
+
+std::vector<Task> task_order(int dtype, const Prob& p, int order_req, bool* is_blocked) {
+  std::vector<Task> tasks;
+  // automatic: cost-block-major for a shared cost, measure-major for an
+  // indexed cost (the faster of the two on the measured workloads)
+  const int order = order_req ? order_req : (p.cost_mode == MAM_COST_SHARED ? 2 : 1);
+  bool blocked = p.cost_mode == MAM_COST_SHARED && order == 2;
+  if (p.cost_mode == MAM_COST_INDEXED && !p.idx.empty() && order == 2) {
+    blocked = true;
+    for (int64_t m = 0; m < p.M && blocked; ++m)
+      for (int64_t j = p.col_off[m] + 1; j < p.col_off[m + 1]; ++j)
+        if (p.idx[j] < p.idx[j - 1]) {
+          blocked = false;
+          break;
+        }
+  }
+  *is_blocked = blocked;
+  if (!blocked) {
+    for (int64_t m = 0; m < p.M; ++m) tasks.push_back({(int)m, p.col_off[m], p.col_off[m + 1]});
+    return tasks;
+  }
+  const int64_t B = cost_block(dtype, p);
+  const int64_t nkb = (p.cost_ncols + B - 1) / B;
+  for (int64_t kb = 0; kb < nkb; ++kb) {
+    for (int64_t m = 0; m < p.M; ++m) {
+      const int64_t o = p.col_off[m], S = p.S[m];
+      int64_t lo, hi;
+      if (p.cost_mode == MAM_COST_SHARED) {
+        lo = o + std::min(S, kb * B);
+        hi = o + std::min(S, (kb + 1) * B);
+      } else {
+        const int32_t* b = p.idx.data() + o;
+        lo = o + (std::lower_bound(b, b + S, (int32_t)std::min<int64_t>(kb * B, INT32_MAX)) - b);
+        hi = o + (std::lower_bound(b, b + S, (int32_t)std::min<int64_t>((kb + 1) * B, INT32_MAX)) - b);
+      }
+      if (hi > lo) tasks.push_back({(int)m, lo, hi});
+    }
+  }
+  return tasks;
+}
+
+int default_nwg(int64_t T, int ng, int req) {
+  int nwg = req;
+  if (nwg <= 0) {
+    const int64_t cap = 1024;
+    const int64_t cpw = std::max<int64_t>(1, (T + ng * cap - 1) / (ng * cap));
+    nwg = (int)std::min<int64_t>(cap, (T + ng * cpw - 1) / (ng * cpw));
+  }
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nwg, T));
+}
+
+// Build the tables of every group.  The workspace capacity depends only on
+// the problem sizes and workgroup counts (not on an indexed cost's index),
+// so rebuilding after the index is known never grows it.
+void build_schedule(Plan* pl) {
+  pl->seg_p.clear();
+  pl->seg_m.clear();
+  pl->seg_j0.clear();
+  pl->seg_j1.clear();
+  pl->seg_poff.clear();
+  pl->wg_seg.clear();
+  size_t poff = 0, cap_segs = 0, cap_part = 0;
+  int wg_base = 0;
+  for (Group& g : pl->G) {
+    int64_t Tg = 0;
+    for (int pi : g.probs) Tg += pl->P[pi].T;
+    g.nwg = default_nwg(Tg, g.ng, g.nwg_req);
+    g.wg_base = wg_base;
+    // concatenated task order of the group's problems
+    std::vector<std::pair<int, Task>> tasks;
+    bool all_blocked = true;
+    for (int pi : g.probs) {
+      bool blocked = false;
+      for (const Task& t : task_order(pl->dtype, pl->P[pi], g.order_req, &blocked)) tasks.push_back({pi, t});
+      all_blocked = all_blocked && blocked;
+      cap_segs += (size_t)task_bound(pl->dtype, pl->P[pi]);
+      cap_part += (size_t)task_bound(pl->dtype, pl->P[pi]) * (size_t)pl->P[pi].R;
+    }
+    cap_segs += (size_t)g.nwg;
+    cap_part += (size_t)g.nwg * (size_t)g.Rmax;
+    g.blocked = all_blocked;
+    g.xcd_remap = g.xcd_req > 0 ? 1 : (g.xcd_req < 0 ? 0 : (g.blocked ? 1 : 0));
+    size_t ti = 0;
+    int64_t tpos = 0;
+    for (int w = 0; w < g.nwg; ++w) {
+      int64_t need = Tg * (w + 1) / g.nwg - Tg * w / g.nwg;
+      pl->wg_seg.push_back((int32_t)pl->seg_p.size());
+      while (need > 0 && ti < tasks.size()) {
+        const int pi = tasks[ti].first;
+        const Task& tk = tasks[ti].second;
+        const int64_t take = std::min(need, tk.hi - tk.lo - tpos);
+        pl->seg_p.push_back(pi);
+        pl->seg_m.push_back(tk.m);
+        pl->seg_j0.push_back(tk.lo + tpos);
+        pl->seg_j1.push_back(tk.lo + tpos + take);
+        pl->seg_poff.push_back((int64_t)poff);
+        poff += (size_t)pl->P[pi].R;
+        need -= take;
+        tpos += take;
+        if (tpos == tk.hi - tk.lo) {
+          ++ti;
+          tpos = 0;
+        }
+      }
+    }
+    wg_base += g.nwg;
+  }
+  pl->wg_seg.push_back((int32_t)pl->seg_p.size());
+  pl->nwg_total = wg_base;
+  // each (problem, measure)'s segments, in schedule order
+  int nmeas = 0;
+  for (Prob& p : pl->P) {
+    p.mbase = nmeas;
+    nmeas += (int)p.M;
+  }
+  pl->mseg.assign(nmeas + 1, 0);
+  for (size_t k = 0; k < pl->seg_p.size(); ++k) ++pl->mseg[pl->P[pl->seg_p[k]].mbase + pl->seg_m[k] + 1];
+  for (int k = 0; k < nmeas; ++k) pl->mseg[k + 1] += pl->mseg[k];
+  pl->seg_idx.assign(pl->seg_p.size(), 0);
+  {
+    std::vector<int32_t> fill(pl->mseg.begin(), pl->mseg.end() - 1);
+    for (size_t k = 0; k < pl->seg_p.size(); ++k)
+      pl->seg_idx[fill[pl->P[pl->seg_p[k]].mbase + pl->seg_m[k]]++] = (int32_t)k;
+  }
+  pl->mtasks.clear();
+  pl->atasks.clear();
+  for (size_t pi = 0; pi < pl->P.size(); ++pi) {
+    const Prob& p = pl->P[pi];
+    for (int64_t m = 0; m < p.M; ++m)
+      for (int64_t r0 = 0; r0 < p.R; r0 += 256) pl->mtasks.push_back({(int32_t)pi, (int32_t)m, (int32_t)r0, 0});
+    for (int rb = 0; rb < p.nb; ++rb) pl->atasks.push_back({(int32_t)pi, rb});
+  }
+  if (!pl->ws) {
+    pl->nseg_cap = cap_segs;
+    pl->partial_cap = cap_part;
+  }
+  pl->tables_uploaded = false;
+}
+
+void build_layout(Plan* pl) {
+  Layout& L = pl->lay;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t a = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return a;
+  };
+  const size_t ns = pl->nseg_cap;
+  L.partial = take(pl->partial_cap * 8);
+  L.diag = take((size_t)pl->nwg_total * mam::DIAG_STRIDE * 8);
+  L.seg_p = take(ns * 4);
+  L.seg_m = take(ns * 4);
+  L.seg_j0 = take(ns * 8);
+  L.seg_j1 = take(ns * 8);
+  L.seg_poff = take(ns * 8);
+  L.seg_idx = take(ns * 4);
+  L.wg_seg = take((size_t)(pl->nwg_total + 1) * 4);
+  size_t nmeas = 0;
+  for (const Prob& p : pl->P) nmeas += (size_t)p.M;
+  L.mseg = take((nmeas + 1) * 4);
+  L.probdev = take(pl->P.size() * std::max(sizeof(mam::ProbDev<float>), sizeof(mam::ProbDev<double>)));
+  L.probaux = take(pl->P.size() * sizeof(mam::ProbAux));
+  L.mtasks = take(pl->mtasks.size() * sizeof(mam::MargTask));
+  L.atasks = take(pl->atasks.size() * sizeof(mam::AvgTask));
+  for (Prob& p : pl->P) {
+    const size_t R = (size_t)p.R, M = (size_t)p.M;
+    p.o_pm = take(M * R * 8);
+    p.o_pm_prev = take(M * R * 8);
+    p.o_p = take(R * 8);
+    p.o_p_prev = take(R * 8);
+    p.o_d2 = take((size_t)p.nb * 8);
+    p.o_t = take(8);
+    p.o_lam = take((size_t)p.T * 8);
+    p.o_check = take((M + 2) * 8);
+    p.o_coloff = take((M + 1) * 8);
+    p.o_Sd = take(M * 8);
+    p.o_aw = take(M * 8);
+  }
+  L.total = o;
+}
+
+// Plan with problems 'descs' and the default grouping by shape.
+mam_status make_plan(Plan* pl, const mam_desc* descs, int n) {
+  if (n < 1) return fail(MAM_EINVAL, "a batch needs at least one problem");
+  pl->P.resize(n);
+  for (int i = 0; i < n; ++i) {
+    TRY(read_desc(&descs[i], i, &pl->P[i]));
+    if (descs[i].dtype != descs[0].dtype) return fail(MAM_EINVAL, "all problems of a batch share one dtype");
+  }
+  pl->dtype = descs[0].dtype;
+  std::map<std::pair<int, int>, int> by_shape;
+  for (int i = 0; i < n; ++i) {
+    int nt = 0, vpt = 0;
+    TRY(shape_for(pl->dtype, pl->P[i].R, 0, &nt, &vpt));
+    auto key = std::make_pair(nt, vpt);
+    if (!by_shape.count(key)) {
+      by_shape[key] = (int)pl->G.size();
+      pl->G.emplace_back();
+    }
+    Group& g = pl->G[by_shape[key]];
+    g.probs.push_back(i);
+    g.Rmax = std::max(g.Rmax, pl->P[i].R);
+    pl->P[i].group = by_shape[key];
+  }
+  for (Group& g : pl->G) TRY(group_shape(pl, g));
+  build_schedule(pl);
+  build_layout(pl);
+  return MAM_OK;
+}
+
+mam_status set_group_schedule(Plan* pl, int gi, const mam_schedule* s) {
+  if (pl->ws) return fail(MAM_ESTATE, "schedule must be set before the workspace");
+  if (s->order < 0 || s->order > 2) return fail(MAM_EINVAL, "order must be 0, 1 or 2 (got %d)", s->order);
+  Group& g = pl->G[gi];
+  const Group saved = g;
+  g.nt_req = s->threads_per_column;
+  g.kc_req = s->columns_in_flight;
+  mam_status st = group_shape(pl, g);
+  if (st != MAM_OK) {
+    g = saved;
+    return st;
+  }
+  g.nwg_req = s->workgroups;
+  g.xcd_req = s->xcd_remap;
+  g.order_req = s->order;
+  build_schedule(pl);
+  build_layout(pl);
+  return MAM_OK;
+}
+
+void get_group_schedule(const Plan* pl, int gi, mam_schedule* s) {
+  const Group& g = pl->G[gi];
+  s->threads_per_column = g.nt;
+  s->values_per_thread = g.vpt;
+  s->columns_in_flight = g.vec == 1 ? 1 : g.kc;
+  s->workgroups = g.nwg;
+  s->xcd_remap = g.xcd_remap;
+  s->vector_width = g.vec;
+  s->order = g.blocked ? 2 : 1;
+}
+
+mam_status set_workspace(Plan* pl, void* dev, size_t bytes) {
+  if (!dev) return fail(MAM_ENOMEM, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(dev) % kAlign) return fail(MAM_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < pl->lay.total) return fail(MAM_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, pl->lay.total);
+  pl->ws = static_cast<char*>(dev);
+  pl->ws_bytes = bytes;
+  pl->tables_uploaded = false;
+  pl->inited = false;
+  return MAM_OK;
+}
+
+mam_status bind(Plan* pl, int i, void* theta, const void* cost, const int32_t* cidx, const void* q) {
+  Prob& p = pl->P[i];
+  if (!theta || !cost || !q) return fail(MAM_EINVAL, "theta, cost and q must be non-NULL");
+  if (p.cost_mode == MAM_COST_INDEXED && !cidx) return fail(MAM_EINVAL, "MAM_COST_INDEXED needs cost_col_index");
+  if (p.cost_mode != MAM_COST_INDEXED && cidx)
+    return fail(MAM_EINVAL, "cost_col_index given but cost_mode is not MAM_COST_INDEXED");
+  const size_t eb = elem_bytes(pl->dtype);
+  if (reinterpret_cast<uintptr_t>(theta) % eb || reinterpret_cast<uintptr_t>(cost) % eb ||
+      reinterpret_cast<uintptr_t>(q) % eb)
+    return fail(MAM_EINVAL, "buffers must be aligned to their element size");
+  p.theta = theta;
+  p.cost = cost;
+  p.cidx = cidx;
+  p.q = q;
+  const int vn = vec_width(pl->dtype);
+  p.aligned = reinterpret_cast<uintptr_t>(theta) % 16 == 0 && reinterpret_cast<uintptr_t>(cost) % 16 == 0 &&
+              p.ld % vn == 0 && p.cost_ld % vn == 0;
+  Group& g = pl->G[p.group];
+  bool all = true;
+  for (int pi : g.probs) all = all && pl->P[pi].aligned;
+  g.vec = (all && g.vpt >= vn) ? vn : 1;
+  pl->inited = false;
+  pl->tables_uploaded = false;
+  if (pl->gexec) {  // a captured graph holds the old buffers
+    hipGraphExecDestroy(pl->gexec);
+    pl->gexec = nullptr;
+  }
+  return MAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device tables
+// ---------------------------------------------------------------------------
+template <typename T>
+void fill_probdev(Plan* pl, std::vector<mam::ProbDev<T>>& out) {
+  out.resize(pl->P.size());
+  for (size_t i = 0; i < pl->P.size(); ++i) {
+    const Prob& p = pl->P[i];
+    mam::ProbDev<T>& d = out[i];
+    d.theta = static_cast<T*>(p.theta);
+    d.cost = static_cast<const T*>(p.cost);
+    d.q = static_cast<const T*>(p.q);
+    d.cidx = p.cidx;
+    d.ld = p.ld;
+    d.cost_ld = p.cost_ld;
+    d.R = (int32_t)p.R;
+    d.cost_mode = p.cost_mode;
+    d.nb = p.nb;
+    d.warm = (p.flags & MAM_FLAG_COLD) ? 0 : 1;
+    d.rho = p.rho;
+    d.inv_rho = 1.0 / p.rho;
+    d.gamma = p.gamma;
+    d.pm = at<double>(pl, p.o_pm);
+    d.p = at<double>(pl, p.o_p);
+    d.d2part = at<double>(pl, p.o_d2);
+    d.lam = at<double>(pl, p.o_lam);
+    d.t_out = at<double>(pl, p.o_t);
+    d.col_off = at<int64_t>(pl, p.o_coloff);
+    d.Sd = at<double>(pl, p.o_Sd);
+  }
+}
+
+// Host staging for the table uploads; the copies complete before it is
+// released (the upload synchronizes the stream).
+mam_status upload_tables(Plan* pl, hipStream_t st) {
+  if (pl->tables_uploaded) return MAM_OK;
+  const Layout& L = pl->lay;
+  auto put = [&](size_t off, const void* src, size_t bytes) -> mam_status {
+    if (bytes) HIP_TRY(hipMemcpyAsync(pl->ws + off, src, bytes, hipMemcpyHostToDevice, st));
+    return MAM_OK;
+  };
+  TRY(put(L.seg_p, pl->seg_p.data(), pl->seg_p.size() * 4));
+  TRY(put(L.seg_m, pl->seg_m.data(), pl->seg_m.size() * 4));
+  TRY(put(L.seg_j0, pl->seg_j0.data(), pl->seg_j0.size() * 8));
+  TRY(put(L.seg_j1, pl->seg_j1.data(), pl->seg_j1.size() * 8));
+  TRY(put(L.seg_poff, pl->seg_poff.data(), pl->seg_poff.size() * 8));
+  TRY(put(L.seg_idx, pl->seg_idx.data(), pl->seg_idx.size() * 4));
+  TRY(put(L.wg_seg, pl->wg_seg.data(), pl->wg_seg.size() * 4));
+  TRY(put(L.mseg, pl->mseg.data(), pl->mseg.size() * 4));
+  TRY(put(L.mtasks, pl->mtasks.data(), pl->mtasks.size() * sizeof(mam::MargTask)));
+  TRY(put(L.atasks, pl->atasks.data(), pl->atasks.size() * sizeof(mam::AvgTask)));
+  std::vector<mam::ProbAux> aux(pl->P.size());
+  for (size_t i = 0; i < pl->P.size(); ++i) {
+    Prob& p = pl->P[i];
+    aux[i] = {at<double>(pl, p.o_pm), at<double>(pl, p.o_pm_prev), at<double>(pl, p.o_p), at<double>(pl, p.o_p_prev),
+              at<double>(pl, p.o_d2), at<double>(pl, p.o_aw), at<double>(pl, p.o_Sd), (int32_t)p.R,
+              (int32_t)p.M, p.mbase, 0};
+    TRY(put(p.o_coloff, p.col_off.data(), p.col_off.size() * 8));
+    TRY(put(p.o_Sd, p.Sd.data(), p.Sd.size() * 8));
+    TRY(put(p.o_aw, p.aw.data(), p.aw.size() * 8));
+  }
+  TRY(put(L.probaux, aux.data(), aux.size() * sizeof(mam::ProbAux)));
+  std::vector<mam::ProbDev<float>> pdf;
+  std::vector<mam::ProbDev<double>> pdd;
+  if (pl->dtype == MAM_F32) {
+    fill_probdev<float>(pl, pdf);
+    TRY(put(L.probdev, pdf.data(), pdf.size() * sizeof(pdf[0])));
+  } else {
+    fill_probdev<double>(pl, pdd);
+    TRY(put(L.probdev, pdd.data(), pdd.size() * sizeof(pdd[0])));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  pl->tables_uploaded = true;
+  return MAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+template <typename T>
+mam_status launch_columns(Plan* pl, hipStream_t st, int diag) {
+  const Layout& L = pl->lay;
+  for (const Group& g : pl->G) {
+    mam::ColArgs<T> a;
+    a.probs = at<mam::ProbDev<T>>(pl, L.probdev);
+    a.seg_p = at<int32_t>(pl, L.seg_p);
+    a.seg_m = at<int32_t>(pl, L.seg_m);
+    a.seg_j0 = at<int64_t>(pl, L.seg_j0);
+    a.seg_j1 = at<int64_t>(pl, L.seg_j1);
+    a.seg_poff = at<int64_t>(pl, L.seg_poff);
+    a.wg_seg = at<int32_t>(pl, L.wg_seg) + g.wg_base;
+    a.partial = at<double>(pl, L.partial);
+    a.diag = at<double>(pl, L.diag) + (size_t)g.wg_base * mam::DIAG_STRIDE;
+    a.nwg = g.nwg;
+    a.xcd_remap = g.xcd_remap;
+    const int kc = g.vec == 1 ? 1 : g.kc;
+    mam::ColFn<T> fn = mam::pick_column<T>(g.nt, g.vpt, g.vec, kc, diag);
+    if (!fn) return fail(MAM_EUNSUPPORTED, "no column kernel for nt=%d vpt=%d vec=%d kc=%d", g.nt, g.vpt, g.vec, kc);
+    const int wgsize = g.nt == 64 ? 256 : g.nt;
+    const size_t shmem = (size_t)g.vpt * g.nt * 8 * (1 + g.ng);
+    if (shmem > 65536) {
+      // above the default dynamic-LDS limit: opt this kernel in
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)shmem));
+    }
+    hipLaunchKernelGGL(fn, dim3(g.nwg), dim3(wgsize), shmem, st, a);
+    LAUNCH_CHECK("column_kernel");
+  }
+  return MAM_OK;
+}
+
+mam_status launch_marginals(Plan* pl, hipStream_t st, int save_prev) {
+  const Layout& L = pl->lay;
+  hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
+                     at<mam::MargTask>(pl, L.mtasks), at<mam::ProbAux>(pl, L.probaux), at<int32_t>(pl, L.mseg),
+                     at<int32_t>(pl, L.seg_idx), at<int64_t>(pl, L.seg_poff), at<double>(pl, L.partial),
+                     save_prev);
+  LAUNCH_CHECK("marginal_kernel");
+  hipLaunchKernelGGL(mam::average_kernel, dim3((unsigned)pl->atasks.size()), dim3(256), 0, st,
+                     at<mam::AvgTask>(pl, L.atasks), at<mam::ProbAux>(pl, L.probaux), save_prev);
+  LAUNCH_CHECK("average_kernel");
+  return MAM_OK;
+}
+
+template <typename T>
+mam_status launch_init(Plan* pl, const void* const* theta0, hipStream_t st) {
+  const Layout& L = pl->lay;
+  for (size_t i = 0; i < pl->P.size(); ++i) {
+    Prob& p = pl->P[i];
+    const int blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (p.T * p.R + 255) / 256));
+    if (theta0 && theta0[i]) {
+      hipLaunchKernelGGL(mam::copy_kernel<T>, dim3(blocks), dim3(256), 0, st, static_cast<T*>(p.theta), p.ld,
+                         (int)p.R, static_cast<const T*>(theta0[i]), p.T);
+      LAUNCH_CHECK("copy_kernel");
+    } else {
+      hipLaunchKernelGGL(mam::fill_kernel<T>, dim3(blocks), dim3(256), 0, st, static_cast<T*>(p.theta), p.ld,
+                         (int)p.R, static_cast<const T*>(p.q), p.T);
+      LAUNCH_CHECK("fill_kernel");
+    }
+    hipLaunchKernelGGL(mam::fill_value_kernel, dim3((unsigned)std::min<int64_t>(4096, (p.T + 255) / 256)), dim3(256),
+                       0, st, at<double>(pl, p.o_lam), p.T, (double)NAN);
+    LAUNCH_CHECK("fill_value_kernel");
+  }
+  for (const Group& g : pl->G) {
+    hipLaunchKernelGGL(mam::rowsum_kernel<T>, dim3(g.nwg), dim3(256), 0, st, at<mam::ProbDev<T>>(pl, L.probdev),
+                       at<int32_t>(pl, L.seg_p), at<int64_t>(pl, L.seg_j0), at<int64_t>(pl, L.seg_j1),
+                       at<int64_t>(pl, L.seg_poff), at<int32_t>(pl, L.wg_seg) + g.wg_base,
+                       at<double>(pl, L.partial));
+    LAUNCH_CHECK("rowsum_kernel");
+  }
+  return launch_marginals(pl, st, 0);
+}
+
+template <typename T>
+mam_status launch_checks(Plan* pl, hipStream_t st) {
+  for (Prob& p : pl->P) {
+    double* chk = at<double>(pl, p.o_check);
+    hipLaunchKernelGGL(mam::zero_kernel, dim3((unsigned)((p.M + 2 + 255) / 256)), dim3(256), 0, st, chk,
+                       (int)(p.M + 2));
+    LAUNCH_CHECK("zero_kernel");
+    hipLaunchKernelGGL(mam::check_q_kernel<T>, dim3((unsigned)p.M), dim3(256), 0, st, static_cast<const T*>(p.q),
+                       at<int64_t>(pl, p.o_coloff), chk, (int)p.M);
+    LAUNCH_CHECK("check_q_kernel");
+    const int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (p.cost_ncols * p.R + 255) / 256));
+    hipLaunchKernelGGL(mam::check_cost_kernel<T>, dim3(blocks), dim3(256), 0, st, static_cast<const T*>(p.cost),
+                       p.cost_ld, (int)p.R, p.cost_ncols, chk + p.M + 1);
+    LAUNCH_CHECK("check_cost_kernel");
+  }
+  return MAM_OK;
+}
+
+hipEvent_t next_event(Plan* pl) {
+  if (pl->ev_used == pl->ev.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pl->ev.push_back(e);
+  }
+  return pl->ev[pl->ev_used++];
+}
+
+// ---------------------------------------------------------------------------
+// plan operations shared by single problems and batches
+// ---------------------------------------------------------------------------
+mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
+  if (!pl->ws) return fail(MAM_ESTATE, "no workspace");
+  for (size_t i = 0; i < pl->P.size(); ++i)
+    if (!pl->P[i].theta) return fail(MAM_ESTATE, "problem %zu has no buffers bound", i);
+  // an indexed cost's column order depends on its index: read it once here
+  bool rebuilt = false;
+  for (Prob& p : pl->P) {
+    if (p.cost_mode != MAM_COST_INDEXED) continue;
+    p.idx.resize(p.T);
+    HIP_TRY(hipMemcpyAsync(p.idx.data(), p.cidx, p.T * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t j = 0; j < p.T; ++j)
+      if (p.idx[j] < 0 || p.idx[j] >= p.cost_ncols)
+        return fail(MAM_ENONFINITE, "cost_col_index[%lld] = %d is out of range", (long long)j, p.idx[j]);
+    rebuilt = true;
+  }
+  if (rebuilt) build_schedule(pl);
+  if (pl->gexec) {
+    hipGraphExecDestroy(pl->gexec);
+    pl->gexec = nullptr;
+  }
+  TRY(upload_tables(pl, st));
+  TRY(pl->dtype == MAM_F32 ? launch_checks<float>(pl, st) : launch_checks<double>(pl, st));
+  for (size_t i = 0; i < pl->P.size(); ++i) {
+    Prob& p = pl->P[i];
+    std::vector<double> chk(p.M + 2);
+    HIP_TRY(hipMemcpyAsync(chk.data(), pl->ws + p.o_check, (p.M + 2) * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (chk[p.M] != 0.0) return fail(MAM_ENONFINITE, "problem %zu: q holds a negative or non-finite weight", i);
+    if (chk[p.M + 1] != 0.0) return fail(MAM_ENONFINITE, "problem %zu: cost holds a non-finite entry", i);
+    if (std::isinf(p.gamma)) {
+      const double tol = pl->dtype == MAM_F32 ? 1e-6 : 1e-12;
+      double lo = chk[0], hi = chk[0];
+      for (int64_t m = 1; m < p.M; ++m) {
+        lo = std::min(lo, chk[m]);
+        hi = std::max(hi, chk[m]);
+      }
+      if (hi - lo > tol * std::max(std::fabs(hi), 1e-300))
+        return fail(MAM_ENOTBALANCED, "problem %zu: balanced mode but masses range over [%.17g, %.17g]", i, lo, hi);
+    }
+  }
+  TRY(pl->dtype == MAM_F32 ? launch_init<float>(pl, theta0, st) : launch_init<double>(pl, theta0, st));
+  pl->inited = true;
+  pl->iters_done = 0;
+  pl->diag_valid = false;
+  return MAM_OK;
+}
+
+mam_status one_iteration(Plan* pl, hipStream_t st, int diag) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (pl->timing) {
+    e0 = next_event(pl);
+    e1 = next_event(pl);
+    if (!e0 || !e1) return fail(MAM_EHIP, "hipEventCreate failed");
+    HIP_TRY(hipEventRecord(e0, st));
+  }
+  TRY(pl->dtype == MAM_F32 ? launch_columns<float>(pl, st, diag) : launch_columns<double>(pl, st, diag));
+  if (pl->timing) HIP_TRY(hipEventRecord(e1, st));
+  return launch_marginals(pl, st, diag);
+}
+
+// Capture graph_iters iterations once on a stream of the library's own (a
+// caller's legacy default stream cannot be captured); replays run on the
+// caller's stream.
+mam_status capture_graph(Plan* pl) {
+  if (!pl->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(pl->capture_stream, hipStreamCaptureModeThreadLocal));
+  mam_status s = MAM_OK;
+  for (int64_t k = 0; k < pl->graph_iters && s == MAM_OK; ++k) s = one_iteration(pl, pl->capture_stream, 0);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(pl->capture_stream, &graph);
+  if (s != MAM_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(MAM_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  const hipError_t e2 = hipGraphInstantiate(&pl->gexec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e2 != hipSuccess) {
+    pl->gexec = nullptr;
+    return fail(MAM_EHIP, "graph instantiation failed: %s", hipGetErrorString(e2));
+  }
+  return MAM_OK;
+}
+
+mam_status plan_iterate(Plan* pl, int64_t iters, hipStream_t st) {
+  if (iters < 0) return fail(MAM_EINVAL, "iters must be >= 0");
+  if (!pl->inited) return fail(MAM_ESTATE, "mam_init has not run");
+  const bool want_diag = !pl->batch && (pl->P[0].flags & MAM_FLAG_DIAG);
+  int64_t k = 0;
+  if (pl->graph_iters > 0 && !pl->timing) {
+    // keep the last iteration outside the graph when it computes diagnostics
+    const int64_t plain = want_diag ? 1 : 0;
+    if (iters - plain >= pl->graph_iters) {
+      if (!pl->gexec) TRY(capture_graph(pl));
+      while (iters - k - plain >= pl->graph_iters) {
+        HIP_TRY(hipGraphLaunch(pl->gexec, st));
+        k += pl->graph_iters;
+      }
+    }
+  }
+  for (; k < iters; ++k) {
+    const int diag = want_diag && k == iters - 1;
+    TRY(one_iteration(pl, st, diag));
+    if (diag) pl->diag_valid = true;
+  }
+  pl->iters_done += iters;
+  return MAM_OK;
+}
+
+mam_status plan_graph(Plan* pl, int64_t iters) {
+  if (iters < 0) return fail(MAM_EINVAL, "iterations per graph must be >= 0");
+  if (pl->gexec) {
+    hipGraphExecDestroy(pl->gexec);
+    pl->gexec = nullptr;
+  }
+  pl->graph_iters = iters;
+  return MAM_OK;
+}
+
+mam_status plan_timing_read(Plan* pl, double* total_ms, int64_t* launches) {
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < pl->ev_used; i += 2) {
+    HIP_TRY(hipEventSynchronize(pl->ev[i + 1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, pl->ev[i], pl->ev[i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)(pl->ev_used / 2);
+  pl->ev_used = 0;
+  return MAM_OK;
+}
+
+}  // namespace
+
+struct mam_problem {
+  Plan plan;
+};
+
+struct mam_batch {
+  Plan plan;
+};
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int32_t mam_abi_version(void) { return 1; }
+
+const char* mam_last_error(void) { return g_err.c_str(); }
+
+mam_status mam_create(mam_problem** out, const mam_desc* d) {
+  if (!out) return fail(MAM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(MAM_EINVAL, "desc is NULL");
+  mam_problem* p = new (std::nothrow) mam_problem();
+  if (!p) return fail(MAM_ENOMEM, "host allocation failed");
+  mam_status st = make_plan(&p->plan, d, 1);
   if (st != MAM_OK) {
     delete p;
     return st;
   }
-  build_schedule(p);
   *out = p;
   return MAM_OK;
 }
 
 mam_status mam_set_schedule(mam_problem* p, const mam_schedule* s) {
   if (!p || !s) return fail(MAM_EINVAL, "NULL argument");
-  if (p->ws) return fail(MAM_ESTATE, "schedule must be set before the workspace");
-  const int nt0 = p->nt_req, kc0 = p->kc_req;
-  p->nt_req = s->threads_per_column;
-  p->kc_req = s->columns_in_flight;
-  mam_status st = choose_shape(p);
-  if (st != MAM_OK) {
-    p->nt_req = nt0;
-    p->kc_req = kc0;
-    choose_shape(p);
-    return st;
-  }
-  if (s->order < 0 || s->order > 2) return fail(MAM_EINVAL, "order must be 0, 1 or 2 (got %d)", s->order);
-  p->nwg_req = s->workgroups;
-  p->xcd_req = s->xcd_remap;
-  p->order_req = s->order;
-  build_schedule(p);
-  return MAM_OK;
+  return set_group_schedule(&p->plan, 0, s);
 }
 
 mam_status mam_get_schedule(const mam_problem* p, mam_schedule* s) {
   if (!p || !s) return fail(MAM_EINVAL, "NULL argument");
-  s->threads_per_column = p->nt;
-  s->values_per_thread = p->vpt;
-  s->columns_in_flight = p->vec == 1 ? 1 : p->kc;
-  s->workgroups = p->nwg;
-  s->xcd_remap = p->xcd_remap;
-  s->vector_width = p->vec;
-  s->order = p->blocked ? 2 : 1;
+  get_group_schedule(&p->plan, 0, s);
   return MAM_OK;
 }
 
-size_t mam_workspace_bytes(const mam_problem* p) { return p ? p->lay.total : 0; }
+size_t mam_workspace_bytes(const mam_problem* p) { return p ? p->plan.lay.total : 0; }
 
 mam_status mam_set_workspace(mam_problem* p, void* dev, size_t bytes) {
   if (!p) return fail(MAM_EINVAL, "NULL handle");
-  if (!dev) return fail(MAM_ENOMEM, "workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(dev) % kAlign) return fail(MAM_EINVAL, "workspace must be 256-byte aligned");
-  if (bytes < p->lay.total)
-    return fail(MAM_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, p->lay.total);
-  p->ws = static_cast<char*>(dev);
-  p->ws_bytes = bytes;
-  p->tables_uploaded = false;
-  p->inited = false;
-  return MAM_OK;
+  return set_workspace(&p->plan, dev, bytes);
 }
 
 mam_status mam_bind(mam_problem* p, void* theta, const void* cost, const int32_t* cost_col_index, const void* q) {
   if (!p) return fail(MAM_EINVAL, "NULL handle");
-  if (!theta || !cost || !q) return fail(MAM_EINVAL, "theta, cost and q must be non-NULL");
-  if (p->cost_mode == MAM_COST_INDEXED && !cost_col_index)
-    return fail(MAM_EINVAL, "MAM_COST_INDEXED needs cost_col_index");
-  if (p->cost_mode != MAM_COST_INDEXED && cost_col_index)
-    return fail(MAM_EINVAL, "cost_col_index given but cost_mode is not MAM_COST_INDEXED");
-  const size_t eb = elem_bytes(p->dtype);
-  if (reinterpret_cast<uintptr_t>(theta) % eb || reinterpret_cast<uintptr_t>(cost) % eb ||
-      reinterpret_cast<uintptr_t>(q) % eb)
-    return fail(MAM_EINVAL, "buffers must be aligned to their element size");
-  p->theta = theta;
-  p->cost = cost;
-  p->cidx = cost_col_index;
-  p->q = q;
-  const int vn = vec_width(p->dtype);
-  const bool aligned = reinterpret_cast<uintptr_t>(theta) % 16 == 0 && reinterpret_cast<uintptr_t>(cost) % 16 == 0 &&
-                       p->ld % vn == 0 && p->cost_ld % vn == 0;
-  p->vec = (aligned && p->vpt >= vn) ? vn : 1;
-  p->inited = false;
-  return MAM_OK;
+  return bind(&p->plan, 0, theta, cost, cost_col_index, q);
 }
 
 mam_status mam_init(mam_problem* p, const void* theta0, void* stream) {
   if (!p) return fail(MAM_EINVAL, "NULL handle");
-  if (!p->ws) return fail(MAM_ESTATE, "no workspace");
-  if (!p->theta) return fail(MAM_ESTATE, "no buffers bound");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (p->cost_mode == MAM_COST_INDEXED) {
-    // the column order depends on the index (sorted within each measure:
-    // cost-block-major); it is read once here
-    std::vector<int32_t> idx(p->T);
-    HIP_TRY(hipMemcpyAsync(idx.data(), p->cidx, p->T * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    for (int64_t j = 0; j < p->T; ++j)
-      if (idx[j] < 0 || idx[j] >= p->cost_ncols)
-        return fail(MAM_ENONFINITE, "cost_col_index[%lld] = %d is out of range", (long long)j, idx[j]);
-    build_schedule(p, &idx);
-  }
-  mam_status s = upload_tables(p, st);
-  if (s != MAM_OK) return s;
-  s = p->dtype == MAM_F32 ? launch_checks<float>(p, st) : launch_checks<double>(p, st);
-  if (s != MAM_OK) return s;
-  std::vector<double> chk(p->M + 2);
-  HIP_TRY(hipMemcpyAsync(chk.data(), p->ws + p->lay.check, (p->M + 2) * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  if (chk[p->M] != 0.0) return fail(MAM_ENONFINITE, "q holds a negative or non-finite weight");
-  if (chk[p->M + 1] != 0.0) return fail(MAM_ENONFINITE, "cost holds a non-finite entry or the column index is out of range");
-  if (std::isinf(p->gamma)) {
-    const double tol = p->dtype == MAM_F32 ? 1e-6 : 1e-12;
-    double lo = chk[0], hi = chk[0];
-    for (int64_t m = 1; m < p->M; ++m) {
-      lo = std::min(lo, chk[m]);
-      hi = std::max(hi, chk[m]);
-    }
-    if (hi - lo > tol * std::max(std::fabs(hi), 1e-300))
-      return fail(MAM_ENOTBALANCED, "balanced mode but masses range over [%.17g, %.17g]", lo, hi);
-  }
-  s = p->dtype == MAM_F32 ? launch_init<float>(p, theta0, st) : launch_init<double>(p, theta0, st);
-  if (s != MAM_OK) return s;
-  p->inited = true;
-  p->iters_done = 0;
-  p->diag_valid = false;
-  return MAM_OK;
+  const void* t0[1] = {theta0};
+  return plan_init(&p->plan, t0, static_cast<hipStream_t>(stream));
 }
 
 mam_status mam_iterate(mam_problem* p, int64_t iters, void* stream) {
   if (!p) return fail(MAM_EINVAL, "NULL handle");
-  if (iters < 0) return fail(MAM_EINVAL, "iters must be >= 0");
-  if (!p->inited) return fail(MAM_ESTATE, "mam_init has not run");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  for (int64_t k = 0; k < iters; ++k) {
-    const int diag = (p->flags & MAM_FLAG_DIAG) && k == iters - 1;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (p->timing) {
-      e0 = next_event(p);
-      e1 = next_event(p);
-      if (!e0 || !e1) return fail(MAM_EHIP, "hipEventCreate failed");
-      HIP_TRY(hipEventRecord(e0, st));
-    }
-    mam_status s = p->dtype == MAM_F32 ? launch_column<float>(p, st, diag) : launch_column<double>(p, st, diag);
-    if (s != MAM_OK) return s;
-    if (p->timing) HIP_TRY(hipEventRecord(e1, st));
-    s = launch_marginals(p, st, diag);
-    if (s != MAM_OK) return s;
-    if (diag) p->diag_valid = true;
-  }
-  p->iters_done += iters;
-  return MAM_OK;
+  return plan_iterate(&p->plan, iters, static_cast<hipStream_t>(stream));
+}
+
+mam_status mam_graph(mam_problem* p, int64_t iters_per_launch) {
+  if (!p) return fail(MAM_EINVAL, "NULL handle");
+  return plan_graph(&p->plan, iters_per_launch);
 }
 
 mam_status mam_barycenter(mam_problem* p, double* p_dev, void* stream) {
   if (!p || !p_dev) return fail(MAM_EINVAL, "NULL argument");
-  if (!p->inited) return fail(MAM_ESTATE, "mam_init has not run");
-  HIP_TRY(hipMemcpyAsync(p_dev, p->ws + p->lay.p, p->R * 8, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  if (!p->plan.inited) return fail(MAM_ESTATE, "mam_init has not run");
+  const Prob& pr = p->plan.P[0];
+  HIP_TRY(hipMemcpyAsync(p_dev, p->plan.ws + pr.o_p, pr.R * 8, hipMemcpyDeviceToDevice,
+                         static_cast<hipStream_t>(stream)));
   return MAM_OK;
 }
 
 mam_status mam_barycenter_host(mam_problem* p, double* p_host, void* stream) {
   if (!p || !p_host) return fail(MAM_EINVAL, "NULL argument");
-  if (!p->inited) return fail(MAM_ESTATE, "mam_init has not run");
+  if (!p->plan.inited) return fail(MAM_ESTATE, "mam_init has not run");
+  const Prob& pr = p->plan.P[0];
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIP_TRY(hipMemcpyAsync(p_host, p->ws + p->lay.p, p->R * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(p_host, p->plan.ws + pr.o_p, pr.R * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return MAM_OK;
 }
 
 mam_status mam_marginals(mam_problem* p, double* pm_dev, void* stream) {
   if (!p || !pm_dev) return fail(MAM_EINVAL, "NULL argument");
-  if (!p->inited) return fail(MAM_ESTATE, "mam_init has not run");
-  HIP_TRY(hipMemcpyAsync(pm_dev, p->ws + p->lay.pm, p->M * p->R * 8, hipMemcpyDeviceToDevice,
+  if (!p->plan.inited) return fail(MAM_ESTATE, "mam_init has not run");
+  const Prob& pr = p->plan.P[0];
+  HIP_TRY(hipMemcpyAsync(pm_dev, p->plan.ws + pr.o_pm, pr.M * pr.R * 8, hipMemcpyDeviceToDevice,
                          static_cast<hipStream_t>(stream)));
   return MAM_OK;
 }
 
 mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream) {
   if (!p || !out) return fail(MAM_EINVAL, "NULL argument");
-  if (!p->inited || !p->diag_valid) return fail(MAM_ESTATE, "no iteration ran with MAM_FLAG_DIAG");
+  Plan* pl = &p->plan;
+  if (!pl->inited || !pl->diag_valid) return fail(MAM_ESTATE, "no iteration ran with MAM_FLAG_DIAG");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t R = p->R, M = p->M;
-  std::vector<double> pm(M * R), pmp(M * R), pv(R), pp(R), dg((size_t)p->nwg * mam::DIAG_STRIDE);
+  const Prob& pr = pl->P[0];
+  const size_t R = pr.R, M = pr.M;
+  std::vector<double> pm(M * R), pmp(M * R), pv(R), pp(R), dg((size_t)pl->nwg_total * mam::DIAG_STRIDE);
   double t = 0.0;
-  const Layout& L = p->lay;
-  HIP_TRY(hipMemcpyAsync(pm.data(), p->ws + L.pm, M * R * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(pmp.data(), p->ws + L.pm_prev, M * R * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(pv.data(), p->ws + L.p, R * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(pp.data(), p->ws + L.p_prev, R * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(dg.data(), p->ws + L.diag, dg.size() * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(&t, p->ws + L.tval, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(pm.data(), pl->ws + pr.o_pm, M * R * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(pmp.data(), pl->ws + pr.o_pm_prev, M * R * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(pv.data(), pl->ws + pr.o_p, R * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(pp.data(), pl->ws + pr.o_p_prev, R * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(dg.data(), pl->ws + pl->lay.diag, dg.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&t, pl->ws + pr.o_t, 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   mam_diag r{};
-  r.iterations = p->iters_done;
+  r.iterations = pl->iters_done;
   r.t = t;
   double rounds = 0.0, active = 0.0, cols = 0.0;
-  for (int w = 0; w < p->nwg; ++w) {
+  for (int w = 0; w < pl->nwg_total; ++w) {
     const double* o = &dg[(size_t)w * mam::DIAG_STRIDE];
     r.W_hat += o[0];
     r.meas_resid = std::max(r.meas_resid, o[1]);
@@ -695,17 +1007,17 @@ mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream) {
   // row sums of pi_hat^(m) = p^(m),new + t (p_old - p^(m),old)
   std::vector<double> ph(M * R), phbar(R, 0.0);
   for (size_t m = 0; m < M; ++m)
-    for (size_t r = 0; r < R; ++r) ph[m * R + r] = pm[m * R + r] + t * (pp[r] - pmp[m * R + r]);
+    for (size_t i = 0; i < R; ++i) ph[m * R + i] = pm[m * R + i] + t * (pp[i] - pmp[m * R + i]);
   for (size_t m = 0; m < M; ++m)
-    for (size_t r = 0; r < R; ++r) phbar[r] += p->aw[m] * ph[m * R + r];
+    for (size_t i = 0; i < R; ++i) phbar[i] += pr.aw[m] * ph[m * R + i];
   double d2 = 0.0;
   for (size_t m = 0; m < M; ++m) {
     double s = 0.0;
-    for (size_t r = 0; r < R; ++r) {
-      const double e = phbar[r] - ph[m * R + r];
+    for (size_t i = 0; i < R; ++i) {
+      const double e = phbar[i] - ph[m * R + i];
       s += e * e;
     }
-    d2 += s / p->Sd[m];
+    d2 += s / pr.Sd[m];
   }
   r.dist_L = std::sqrt(d2);
   double dp = 0.0, mass = 0.0;
@@ -724,32 +1036,109 @@ mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream) {
 
 mam_status mam_timing_enable(mam_problem* p, int32_t enable) {
   if (!p) return fail(MAM_EINVAL, "NULL handle");
-  p->timing = enable != 0;
-  p->ev_used = 0;
+  p->plan.timing = enable != 0;
+  p->plan.ev_used = 0;
   return MAM_OK;
 }
 
 mam_status mam_timing_read(mam_problem* p, double* total_ms, int64_t* launches) {
   if (!p || !total_ms || !launches) return fail(MAM_EINVAL, "NULL argument");
-  double tot = 0.0;
-  for (size_t i = 0; i + 1 < p->ev_used; i += 2) {
-    HIP_TRY(hipEventSynchronize(p->ev[i + 1]));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]));
-    tot += ms;
+  return plan_timing_read(&p->plan, total_ms, launches);
+}
+
+void mam_destroy(mam_problem* p) { delete p; }
+
+// ---- batches ---------------------------------------------------------------
+mam_status mam_batch_create(mam_batch** out, const mam_desc* descs, int32_t n) {
+  if (!out) return fail(MAM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!descs) return fail(MAM_EINVAL, "descs is NULL");
+  mam_batch* b = new (std::nothrow) mam_batch();
+  if (!b) return fail(MAM_ENOMEM, "host allocation failed");
+  b->plan.batch = true;
+  mam_status st = make_plan(&b->plan, descs, n);
+  if (st != MAM_OK) {
+    delete b;
+    return st;
   }
-  *total_ms = tot;
-  *launches = (int64_t)(p->ev_used / 2);
-  p->ev_used = 0;
+  *out = b;
   return MAM_OK;
 }
 
-void mam_destroy(mam_problem* p) {
-  if (!p) return;
-  for (hipEvent_t e : p->ev) hipEventDestroy(e);
-  delete p;
+int32_t mam_batch_groups(const mam_batch* b) { return b ? (int32_t)b->plan.G.size() : 0; }
+
+int32_t mam_batch_group_of(const mam_batch* b, int32_t i) {
+  if (!b || i < 0 || i >= (int32_t)b->plan.P.size()) return -1;
+  return b->plan.P[i].group;
 }
 
+mam_status mam_batch_set_schedule(mam_batch* b, int32_t group, const mam_schedule* s) {
+  if (!b || !s) return fail(MAM_EINVAL, "NULL argument");
+  if (group < 0 || group >= (int32_t)b->plan.G.size()) return fail(MAM_EINVAL, "no group %d", group);
+  return set_group_schedule(&b->plan, group, s);
+}
+
+mam_status mam_batch_get_schedule(const mam_batch* b, int32_t group, mam_schedule* s) {
+  if (!b || !s) return fail(MAM_EINVAL, "NULL argument");
+  if (group < 0 || group >= (int32_t)b->plan.G.size()) return fail(MAM_EINVAL, "no group %d", group);
+  get_group_schedule(&b->plan, group, s);
+  return MAM_OK;
+}
+
+size_t mam_batch_workspace_bytes(const mam_batch* b) { return b ? b->plan.lay.total : 0; }
+
+mam_status mam_batch_set_workspace(mam_batch* b, void* dev, size_t bytes) {
+  if (!b) return fail(MAM_EINVAL, "NULL handle");
+  return set_workspace(&b->plan, dev, bytes);
+}
+
+mam_status mam_batch_bind(mam_batch* b, int32_t i, void* theta, const void* cost, const int32_t* cost_col_index,
+                          const void* q) {
+  if (!b) return fail(MAM_EINVAL, "NULL handle");
+  if (i < 0 || i >= (int32_t)b->plan.P.size()) return fail(MAM_EINVAL, "no problem %d", i);
+  return bind(&b->plan, i, theta, cost, cost_col_index, q);
+}
+
+mam_status mam_batch_init(mam_batch* b, void* stream) {
+  if (!b) return fail(MAM_EINVAL, "NULL handle");
+  return plan_init(&b->plan, nullptr, static_cast<hipStream_t>(stream));
+}
+
+mam_status mam_batch_iterate(mam_batch* b, int64_t iters, void* stream) {
+  if (!b) return fail(MAM_EINVAL, "NULL handle");
+  return plan_iterate(&b->plan, iters, static_cast<hipStream_t>(stream));
+}
+
+mam_status mam_batch_graph(mam_batch* b, int64_t iters_per_launch) {
+  if (!b) return fail(MAM_EINVAL, "NULL handle");
+  return plan_graph(&b->plan, iters_per_launch);
+}
+
+mam_status mam_batch_barycenter(mam_batch* b, int32_t i, double* p_dev, void* stream) {
+  if (!b || !p_dev) return fail(MAM_EINVAL, "NULL argument");
+  if (i < 0 || i >= (int32_t)b->plan.P.size()) return fail(MAM_EINVAL, "no problem %d", i);
+  if (!b->plan.inited) return fail(MAM_ESTATE, "mam_batch_init has not run");
+  const Prob& pr = b->plan.P[i];
+  HIP_TRY(hipMemcpyAsync(p_dev, b->plan.ws + pr.o_p, pr.R * 8, hipMemcpyDeviceToDevice,
+                         static_cast<hipStream_t>(stream)));
+  return MAM_OK;
+}
+
+mam_status mam_batch_timing_enable(mam_batch* b, int32_t enable) {
+  if (!b) return fail(MAM_EINVAL, "NULL handle");
+  b->plan.timing = enable != 0;
+  b->plan.ev_used = 0;
+  return MAM_OK;
+}
+
+mam_status mam_batch_timing_read(mam_batch* b, double* total_ms, int64_t* launches) {
+  if (!b || !total_ms || !launches) return fail(MAM_EINVAL, "NULL argument");
+  return plan_timing_read(&b->plan, total_ms, launches);
+}
+
+void mam_batch_destroy(mam_batch* b) { delete b; }
+
+// ---- cost helper -----------------------------------------------------------
 mam_status mam_cost_sq_euclid(const double* xi, int64_t R, const double* zeta, int64_t S, int32_t dim,
                               int32_t normalize_max, void* out, int64_t out_ld, int32_t dtype, double* scratch,
                               void* stream) {

@@ -7,44 +7,70 @@
 
 namespace mam {
 
-// p^(m)_r = sum over the segments of measure m (in schedule order).
+// One problem as the marginal and average kernels see it.
+struct ProbAux {
+  double* pm;        // M x R
+  double* pm_prev;   // M x R, marginals before the last iteration (diagnostics)
+  double* p;         // R
+  double* p_prev;    // R
+  double* d2part;    // ceil(R/256) partial sums of d^2
+  const double* aw;  // averaging weights a_m
+  const double* Sd;  // S^m as double
+  int32_t R, M;
+  int32_t mbase;     // index of (this problem, measure 0) in the measure list
+  int32_t pad;
+};
+
+struct MargTask {
+  int32_t prob, m, r0, pad;
+};
+
+struct AvgTask {
+  int32_t prob, rb;
+};
+
+// p^(m)_r = sum over the segments of measure m, in schedule order.
 __global__ void __launch_bounds__(256)
-marginal_kernel(const double* __restrict__ partial, int R, const int32_t* __restrict__ mseg,
-                const int32_t* __restrict__ seg_idx, double* __restrict__ pm, double* __restrict__ pm_prev,
-                int save_prev) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  const int m = blockIdx.y;
-  if (r >= R) return;
+marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ probs,
+                const int32_t* __restrict__ mseg, const int32_t* __restrict__ seg_idx,
+                const int64_t* __restrict__ seg_poff, const double* __restrict__ partial, int save_prev) {
+  const MargTask tk = tasks[blockIdx.x];
+  const ProbAux& P = probs[tk.prob];
+  const int r = tk.r0 + threadIdx.x;
+  if (r >= P.R) return;
+  const int k = P.mbase + tk.m;
   double s = 0.0;
-  const int e = mseg[m + 1];
-  for (int i = mseg[m]; i < e; ++i) s += partial[(size_t)seg_idx[i] * R + r];
-  const size_t o = (size_t)m * R + r;
-  if (save_prev) pm_prev[o] = pm[o];
-  pm[o] = s;
+  const int e = mseg[k + 1];
+  for (int i = mseg[k]; i < e; ++i) s += partial[seg_poff[seg_idx[i]] + r];
+  const size_t o = (size_t)tk.m * P.R + r;
+  if (save_prev) P.pm_prev[o] = P.pm[o];
+  P.pm[o] = s;
 }
 
-// p_r = sum_m a_m p^(m)_r and per-block partials of sum_r sum_m (p_r - p^(m)_r)^2 / S^m.
+// p_r = sum_m a_m p^(m)_r, and the block's partial sum of
+// sum_r sum_m (p_r - p^(m)_r)^2 / S^m.
 __global__ void __launch_bounds__(256)
-average_kernel(const double* __restrict__ pm, int R, int M, const double* __restrict__ aw,
-               const double* __restrict__ Sd, double* __restrict__ p, double* __restrict__ p_prev,
-               int save_prev, double* __restrict__ d2part) {
+average_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ probs, int save_prev) {
   __shared__ double sh[4];
-  const int r = blockIdx.x * 256 + threadIdx.x;
+  const AvgTask tk = tasks[blockIdx.x];
+  const ProbAux& P = probs[tk.prob];
+  const int R = P.R, M = P.M;
+  const int r = tk.rb * 256 + threadIdx.x;
   double d2 = 0.0;
   if (r < R) {
     double pr = 0.0;
-    for (int m = 0; m < M; ++m) pr += aw[m] * pm[(size_t)m * R + r];
+    for (int m = 0; m < M; ++m) pr += P.aw[m] * P.pm[(size_t)m * R + r];
     for (int m = 0; m < M; ++m) {
-      const double e = pr - pm[(size_t)m * R + r];
-      d2 += e * e / Sd[m];
+      const double e = pr - P.pm[(size_t)m * R + r];
+      d2 += e * e / P.Sd[m];
     }
-    if (save_prev) p_prev[r] = p[r];
-    p[r] = pr;
+    if (save_prev) P.p_prev[r] = P.p[r];
+    P.p[r] = pr;
   }
   d2 = wave_sum(d2);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d2;
   __syncthreads();
-  if (threadIdx.x == 0) d2part[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  if (threadIdx.x == 0) P.d2part[tk.rb] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
 // theta^0_rs = q_s / R (Alg. 1 Step 0 with the library's default start).
@@ -70,18 +96,20 @@ copy_kernel(T* __restrict__ theta, int64_t ld, int R, const T* __restrict__ src,
   }
 }
 
-// Row sums of the plans into the segment partials (used by initialisation).
+// Row sums of the plans into the segment partials (initialisation).
 template <typename T>
 __global__ void __launch_bounds__(256)
-rowsum_kernel(const T* __restrict__ theta, int64_t ld, int R, const int64_t* __restrict__ seg_j0,
-              const int64_t* __restrict__ seg_j1, const int32_t* __restrict__ wg_seg,
+rowsum_kernel(const ProbDev<T>* __restrict__ probs, const int32_t* __restrict__ seg_p,
+              const int64_t* __restrict__ seg_j0, const int64_t* __restrict__ seg_j1,
+              const int64_t* __restrict__ seg_poff, const int32_t* __restrict__ wg_seg,
               double* __restrict__ partial) {
   const int wg = blockIdx.x;
   for (int si = wg_seg[wg]; si < wg_seg[wg + 1]; ++si) {
-    for (int r = threadIdx.x; r < R; r += 256) {
+    const ProbDev<T>& P = probs[seg_p[si]];
+    for (int r = threadIdx.x; r < P.R; r += 256) {
       double s = 0.0;
-      for (int64_t j = seg_j0[si]; j < seg_j1[si]; ++j) s += (double)theta[j * ld + r];
-      partial[(size_t)si * R + r] = s;
+      for (int64_t j = seg_j0[si]; j < seg_j1[si]; ++j) s += (double)P.theta[j * P.ld + r];
+      partial[seg_poff[si] + r] = s;
     }
   }
 }

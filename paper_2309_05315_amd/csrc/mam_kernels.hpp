@@ -176,29 +176,37 @@ __device__ __forceinline__ double wave_reduce(double v) {
 __device__ __forceinline__ double wave_sum(double v) { return wave_reduce<OpSum>(v); }
 __device__ __forceinline__ double wave_max(double v) { return wave_reduce<OpMax>(v); }
 
+// One problem as the column kernel sees it (a batch holds many).
 template <typename T>
-struct ColArgs {
+struct ProbDev {
   T* theta;
   const T* cost;
   const T* q;
   const int32_t* cidx;
   int64_t ld, cost_ld;
   int32_t R, cost_mode;
+  int32_t nb, warm;       // nb: d^2 partials; warm: use stored thresholds as starts
+  double rho, inv_rho, gamma;
   const double* pm;       // M x R marginals of the current plans
   const double* p;        // R, averaged marginal
   const double* d2part;   // nb partial sums of d^2
-  int32_t nb, warm;       // warm: use the stored thresholds as Newton starts
-  double rho, inv_rho, gamma;
-  const int64_t* col_off; // M+1
-  const double* Sd;       // S^m as double
-  const int32_t* seg_m;
-  const int64_t* seg_j0;
-  const int64_t* seg_j1;
-  const int32_t* wg_seg;  // nwg+1
-  double* partial;        // nseg x R
   double* lam;            // T thresholds of the last projection (NaN = none)
   double* t_out;          // 1
-  double* diag;           // nwg x DIAG_STRIDE
+  const int64_t* col_off; // M+1
+  const double* Sd;       // S^m as double
+};
+
+template <typename T>
+struct ColArgs {
+  const ProbDev<T>* probs;
+  const int32_t* seg_p;   // problem of each segment
+  const int32_t* seg_m;   // measure of each segment
+  const int64_t* seg_j0;  // first column
+  const int64_t* seg_j1;  // one past the last column
+  const int64_t* seg_poff;// offset of the segment's row-sum partial in 'partial'
+  const int32_t* wg_seg;  // segments of workgroup w: [wg_seg[w], wg_seg[w+1])
+  double* partial;
+  double* diag;           // nwg x DIAG_STRIDE (single-problem plans)
   int32_t nwg, xcd_remap;
 };
 
@@ -354,20 +362,7 @@ column_kernel(ColArgs<T> a) {
   const int tid = gtid % NT;
   const int lane = gtid & 63;
   const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int R = a.R;
   double* fix = lds_fix + (size_t)g * VPT * NT;
-
-  if (gtid == 0) {
-    double d2 = 0.0;
-    for (int i = 0; i < a.nb; ++i) d2 += a.d2part[i];
-    const double d = sqrt(d2);
-    const double t = (__builtin_isinf(a.gamma) || a.rho * d <= a.gamma) ? 1.0 : a.gamma / (a.rho * d);
-    sh_t = t;
-    if (blockIdx.x == 0) a.t_out[0] = t;
-  }
-  __syncthreads();
-  const double t = uniform_d(sh_t);
-  const double inv_rho = a.inv_rho;
 
   Rounds<NW, KC> rounds{red_d, red_f, red_i, 0};
   double dW = 0.0, dRes = 0.0, dTh = 0.0, dRounds = 0.0, dAct = 0.0, dCols = 0.0;
@@ -377,21 +372,41 @@ column_kernel(ColArgs<T> a) {
   // them constant); readfirstlane makes them scalar again
   const int sb = uniform_i(a.wg_seg[wg]), se = uniform_i(a.wg_seg[wg + 1]);
   for (int si = sb; si < se; ++si) {
+    const ProbDev<T>& P = a.probs[uniform_i(a.seg_p[si])];
+    T* const theta = (T*)uniform_l((int64_t)P.theta);
+    const T* const cost = (const T*)uniform_l((int64_t)P.cost);
+    const T* const qv = (const T*)uniform_l((int64_t)P.q);
+    const int32_t* const cidx = (const int32_t*)uniform_l((int64_t)P.cidx);
+    const int64_t ld = uniform_l(P.ld), cost_ld = uniform_l(P.cost_ld);
+    const int R = uniform_i(P.R), cost_mode = uniform_i(P.cost_mode), warm = uniform_i(P.warm);
+    const double inv_rho = uniform_d(P.inv_rho);
+    double* const lamv = (double*)uniform_l((int64_t)P.lam);
     const int m = uniform_i(a.seg_m[si]);
     const int64_t j0 = uniform_l(a.seg_j0[si]), j1 = uniform_l(a.seg_j1[si]);
-    const double Sm = uniform_d(a.Sd[m]);
-    const int64_t off_m = uniform_l(a.col_off[m]);
-    const double* __restrict__ pmm = a.pm + (size_t)m * R;
+    const double Sm = uniform_d(P.Sd[m]);
+    const int64_t off_m = uniform_l(P.col_off[m]);
+    const double* __restrict__ pmm = P.pm + (size_t)m * R;
+
+    // t^k of this problem from its d^2 partials (fixed order)
+    __syncthreads();  // previous segment's readers are done
+    if (gtid == 0) {
+      double d2 = 0.0;
+      for (int i = 0; i < P.nb; ++i) d2 += P.d2part[i];
+      const double d = sqrt(d2);
+      sh_t = (__builtin_isinf(P.gamma) || P.rho * d <= P.gamma) ? 1.0 : P.gamma / (P.rho * d);
+      if (j0 == 0) P.t_out[0] = sh_t;
+    }
+    __syncthreads();
+    const double t = uniform_d(sh_t);
 
     // b^(m) = t (p - p^(m)) / S^m for this thread's rows, kept in LDS
-    __syncthreads();  // previous segment's readers are done
     if (g == 0) {
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
           const int r = (c * NT + tid) * VEC + v;
-          lds_b[(c * VEC + v) * NT + tid] = (r < R) ? t * (a.p[r] - pmm[r]) / Sm : 0.0;
+          lds_b[(c * VEC + v) * NT + tid] = (r < R) ? t * (P.p[r] - pmm[r]) / Sm : 0.0;
         }
       }
     }
@@ -418,10 +433,10 @@ column_kernel(ColArgs<T> a) {
     };
     auto cost_col = [&](int64_t j) -> const T* {
       int64_t cc;
-      if (a.cost_mode == MAM_COST_INDEXED) cc = uniform_i(a.cidx[j]);
-      else if (a.cost_mode == MAM_COST_SHARED) cc = j - off_m;
+      if (cost_mode == MAM_COST_INDEXED) cc = uniform_i(cidx[j]);
+      else if (cost_mode == MAM_COST_SHARED) cc = j - off_m;
       else cc = j;
-      return a.cost + cc * a.cost_ld;
+      return cost + cc * cost_ld;
     };
     T rt[KC][VPT], rc[KC][VPT];  // raw theta and cost of the next step
     auto issue = [&](int64_t i) {
@@ -429,7 +444,7 @@ column_kernel(ColArgs<T> a) {
       for (int kc = 0; kc < KC; ++kc) {
         int64_t j;
         if (step_col(i, kc, j)) {
-          const T* __restrict__ thp = a.theta + j * a.ld;
+          const T* __restrict__ thp = theta + j * ld;
           const T* __restrict__ cp = cost_col(j);
 #pragma unroll
           for (int c = 0; c < NCH; ++c) {
@@ -474,9 +489,9 @@ column_kernel(ColArgs<T> a) {
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const int64_t j = jj[kc];
-        tau[kc] = valid[kc] ? uniform_d((double)a.q[j]) : 0.0;
+        tau[kc] = valid[kc] ? uniform_d((double)qv[j]) : 0.0;
         act[kc] = valid[kc] && tau[kc] > 0.0;
-        lam[kc] = (act[kc] && a.warm) ? uniform_d(a.lam[j]) : __builtin_nan("");
+        lam[kc] = (act[kc] && warm) ? uniform_d(lamv[j]) : __builtin_nan("");
         if (!act[kc]) lam[kc] = __builtin_huge_val();
         mask[kc] = 0;
         nrounds[kc] = 0;
@@ -563,9 +578,9 @@ column_kernel(ColArgs<T> a) {
       for (int kc = 0; kc < KC; ++kc) {
         if (!valid[kc]) continue;
         const int64_t j = jj[kc];
-        T* __restrict__ thp = a.theta + j * a.ld;
+        T* __restrict__ thp = theta + j * ld;
         double colsum = 0.0;
-        const T* __restrict__ cp = a.cost;
+        const T* __restrict__ cp = cost;
         if constexpr (DIAG) cp = cost_col(j);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -598,7 +613,7 @@ column_kernel(ColArgs<T> a) {
             }
           }
         }
-        if (tid == 0) a.lam[j] = lam[kc];
+        if (tid == 0) lamv[j] = lam[kc];
         if constexpr (DIAG) {
           colsum = wave_sum(colsum);
           if constexpr (NW > 1) {
@@ -630,7 +645,7 @@ column_kernel(ColArgs<T> a) {
         double f = lds_fix[i];
 #pragma unroll
         for (int gg = 1; gg < NG; ++gg) f += lds_fix[(size_t)gg * VPT * NT + i];
-        a.partial[(size_t)si * R + r] = ncols * (double)(T)(-lds_b[i]) + f;
+        a.partial[uniform_l(a.seg_poff[si]) + r] = ncols * (double)(T)(-lds_b[i]) + f;
       }
     }
   }

@@ -18,7 +18,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-__all__ = ["lib", "MAMError", "Solver", "solver_for", "cost_sq_euclid",
+__all__ = ["lib", "MAMError", "Solver", "Batch", "solver_for", "cost_sq_euclid",
            "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "FLAG_DIAG", "FLAG_COLD",
            "EXPORTED"]
 
@@ -34,7 +34,12 @@ EXPORTED = ["mam_abi_version", "mam_last_error", "mam_create", "mam_set_schedule
             "mam_get_schedule", "mam_workspace_bytes", "mam_set_workspace", "mam_bind",
             "mam_init", "mam_iterate", "mam_barycenter", "mam_barycenter_host",
             "mam_marginals", "mam_diagnostics", "mam_timing_enable", "mam_timing_read",
-            "mam_destroy", "mam_cost_sq_euclid"]
+            "mam_destroy", "mam_cost_sq_euclid", "mam_graph", "mam_batch_create",
+            "mam_batch_groups", "mam_batch_group_of", "mam_batch_set_schedule",
+            "mam_batch_get_schedule", "mam_batch_workspace_bytes", "mam_batch_set_workspace",
+            "mam_batch_bind", "mam_batch_init", "mam_batch_iterate", "mam_batch_graph",
+            "mam_batch_barycenter", "mam_batch_timing_enable", "mam_batch_timing_read",
+            "mam_batch_destroy"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmam.so")
 
@@ -105,6 +110,23 @@ def lib() -> ctypes.CDLL:
         "mam_cost_sq_euclid": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, ctypes.c_int64,
                                                 ctypes.c_int32, ctypes.c_int32, _vp,
                                                 ctypes.c_int64, ctypes.c_int32, _vp, _vp]),
+        "mam_graph": (ctypes.c_int32, [_vp, ctypes.c_int64]),
+        "mam_batch_create": (ctypes.c_int32, [ctypes.POINTER(_vp), ctypes.POINTER(Desc), ctypes.c_int32]),
+        "mam_batch_groups": (ctypes.c_int32, [_vp]),
+        "mam_batch_group_of": (ctypes.c_int32, [_vp, ctypes.c_int32]),
+        "mam_batch_set_schedule": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(Schedule)]),
+        "mam_batch_get_schedule": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(Schedule)]),
+        "mam_batch_workspace_bytes": (ctypes.c_size_t, [_vp]),
+        "mam_batch_set_workspace": (ctypes.c_int32, [_vp, _vp, ctypes.c_size_t]),
+        "mam_batch_bind": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp]),
+        "mam_batch_init": (ctypes.c_int32, [_vp, _vp]),
+        "mam_batch_iterate": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp]),
+        "mam_batch_graph": (ctypes.c_int32, [_vp, ctypes.c_int64]),
+        "mam_batch_barycenter": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp, _vp]),
+        "mam_batch_timing_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
+        "mam_batch_timing_read": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_double),
+                                                   ctypes.POINTER(ctypes.c_int64)]),
+        "mam_batch_destroy": (None, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -219,6 +241,10 @@ class Solver:
                "mam_diagnostics")
         return {k: getattr(d, k) for k, _ in Diag._fields_}
 
+    def graph(self, iters_per_launch: int) -> None:
+        """Replay iterations from a captured HIP graph (0 = off)."""
+        _check(lib().mam_graph(self._h, int(iters_per_launch)), "mam_graph")
+
     def timing(self, enable: bool) -> None:
         _check(lib().mam_timing_enable(self._h, int(enable)), "mam_timing_enable")
 
@@ -264,6 +290,121 @@ def solver_for(problem, device="cuda", diag: bool = False, cold: bool = False, *
         idx = torch.from_numpy(problem.col_index.astype(np.int32)).to(device)
     s.bind(theta, cost.to(device), torch.from_numpy(problem.q).to(dt).to(device), idx)
     return s
+
+
+def _dtype_of(problem):
+    return torch.float32 if problem.dtype == "f32" else torch.float64
+
+
+def _cost_mode_of(problem):
+    if problem.col_index is None:
+        return COST_SHARED
+    if np.array_equal(problem.col_index, np.arange(problem.T)):
+        return COST_PER_COLUMN
+    return COST_INDEXED
+
+
+def _device_buffers(problem, ld, cost_ld, dt, device):
+    """theta (zeros), cost and q (and the index for an indexed cost) on the device."""
+    mode = _cost_mode_of(problem)
+    ncols = problem.cost.shape[0]
+    cost = torch.zeros(ncols, cost_ld, dtype=dt)
+    cost[:, :problem.R] = torch.from_numpy(problem.cost).to(dt)
+    theta = torch.zeros(problem.T, ld, dtype=dt, device=device)
+    idx = None
+    if mode == COST_INDEXED:
+        idx = torch.from_numpy(problem.col_index.astype(np.int32)).to(device)
+    q = torch.from_numpy(problem.q).to(dt).to(device)
+    return theta, cost.to(device), q, idx
+
+
+class Batch:
+    """Many independent problems advanced together (one launch per shape
+    group per iteration, optionally replayed from a HIP graph)."""
+
+    def __init__(self, problems, device="cuda", schedules=None):
+        L = lib()
+        self.device = torch.device(device)
+        self.problems = list(problems)
+        dts = {p.dtype for p in self.problems}
+        if len(dts) != 1:
+            raise ValueError("all problems of a batch share one dtype")
+        self.dtype = _dtype_of(self.problems[0])
+        vec = 4 if self.dtype == torch.float32 else 2
+        descs = (Desc * len(self.problems))()
+        self._S = []
+        self.lds = []
+        for i, p in enumerate(self.problems):
+            S = (ctypes.c_int64 * p.M)(*p.S)
+            self._S.append(S)
+            ld = _round_up(p.R, vec)
+            self.lds.append(ld)
+            descs[i] = Desc(dtype=F32 if self.dtype == torch.float32 else F64, cost_mode=_cost_mode_of(p),
+                            R=p.R, M=p.M, S=S, ld=ld, cost_ld=ld, cost_ncols=p.cost.shape[0],
+                            rho=float(p.rho), gamma=float(p.gamma), flags=0)
+        h = _vp()
+        _check(L.mam_batch_create(ctypes.byref(h), descs, len(self.problems)), "mam_batch_create")
+        self._h = h
+        for g, sc in (schedules or {}).items():
+            s = Schedule(**sc)
+            _check(L.mam_batch_set_schedule(h, int(g), ctypes.byref(s)), "mam_batch_set_schedule")
+        nbytes = int(L.mam_batch_workspace_bytes(h))
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        _check(L.mam_batch_set_workspace(h, _ptr(self.workspace), nbytes), "mam_batch_set_workspace")
+        self.buffers = []
+        for i, p in enumerate(self.problems):
+            theta, cost, q, idx = _device_buffers(p, self.lds[i], self.lds[i], self.dtype, self.device)
+            self.buffers.append((theta, cost, q, idx))
+            _check(L.mam_batch_bind(h, i, _ptr(theta), _ptr(cost), _ptr(idx), _ptr(q)), "mam_batch_bind")
+
+    def groups(self) -> int:
+        return int(lib().mam_batch_groups(self._h))
+
+    def schedule(self, group: int) -> dict:
+        sc = Schedule()
+        _check(lib().mam_batch_get_schedule(self._h, int(group), ctypes.byref(sc)), "mam_batch_get_schedule")
+        return {k: getattr(sc, k) for k, _ in Schedule._fields_}
+
+    def init(self) -> None:
+        _check(lib().mam_batch_init(self._h, _stream(self.device)), "mam_batch_init")
+
+    def iterate(self, iters: int) -> None:
+        _check(lib().mam_batch_iterate(self._h, int(iters), _stream(self.device)), "mam_batch_iterate")
+
+    def graph(self, iters_per_launch: int) -> None:
+        _check(lib().mam_batch_graph(self._h, int(iters_per_launch)), "mam_batch_graph")
+
+    def barycenter(self, i: int) -> torch.Tensor:
+        out = torch.empty(self.problems[i].R, dtype=torch.float64, device=self.device)
+        _check(lib().mam_batch_barycenter(self._h, int(i), _ptr(out), _stream(self.device)),
+               "mam_batch_barycenter")
+        return out
+
+    def plans(self, i: int) -> list:
+        p = self.problems[i]
+        th = self.buffers[i][0][:, :p.R].double().cpu().numpy()
+        off = np.concatenate([[0], np.cumsum(p.S)])
+        return [th[off[m]:off[m + 1]].T.copy() for m in range(p.M)]
+
+    def timing(self, enable: bool) -> None:
+        _check(lib().mam_batch_timing_enable(self._h, int(enable)), "mam_batch_timing_enable")
+
+    def timing_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().mam_batch_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)),
+               "mam_batch_timing_read")
+        return ms.value, n.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().mam_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def cost_sq_euclid(xi: torch.Tensor, zeta: torch.Tensor, normalize_max: bool = False,

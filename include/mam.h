@@ -197,6 +197,54 @@ mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream);
 mam_status mam_timing_enable(mam_problem* p, int32_t enable);
 mam_status mam_timing_read(mam_problem* p, double* total_ms, int64_t* launches);
 
+/* ---- reverse mode ----------------------------------------------------------
+ * Gradients through the iteration of Alg. 1 (the paper does not treat
+ * differentiation; this is the exact derivative of the computed map away
+ * from the measure-zero set where an active set changes).  One balanced
+ * iteration is piecewise affine in (theta, q, c): on a column's active set A
+ * (w_r > lambda) the projection of Prop. 3 is w - lambda with
+ * lambda = (sum_A w - q_s)/|A|, so its Jacobian is D_A - 1_A 1_A^T/|A| and
+ * its derivative in q_s is 1_A/|A|.  The reverse sweep propagates
+ * dL/dtheta^k as a part supported on the active sets plus one R-vector per
+ * measure; it reads the active-set bit masks of the forward (R/8 bytes per
+ * column and iteration), never theta or c.
+ *
+ * Scope: single problems, balanced (gamma = INFINITY), started with the
+ * default theta^0 = q_s/R (mam_init with theta0 = NULL), any cost mode and
+ * dtype.  Gradients are accumulated in double and written in the problem's
+ * dtype.
+ *
+ * Memory: the adjoint workspace (caller-owned device memory, 256-byte
+ * aligned) holds the masks of one window of C = ckpt_every iterations
+ * (C+1 slots), a checkpoint of theta at the start of every later window,
+ * two R x T double arrays (the sparse adjoint and the cost adjoint per plan
+ * column) and O(M R + T + cost columns) more.  ckpt_every <= 0 or >= iters
+ * keeps every mask of the run (no recomputation).  The size depends on the
+ * schedule: query it after mam_set_schedule.  Returns 0 for a batch handle,
+ * a NULL handle or iters < 0. */
+size_t mam_adjoint_workspace_bytes(const mam_problem* p, int64_t iters, int64_t ckpt_every);
+
+/* Forward pass for the reverse mode: 'iters' iterations exactly as
+ * mam_iterate (same results), recording what mam_backward needs into
+ * 'adj_ws' ('bytes' long).  Must follow a mam_init with theta0 = NULL and
+ * no iteration since.  SYNCHRONIZES the stream once at the start (table
+ * upload); then asynchronous.  Errors: MAM_ESTATE (not freshly initialised
+ * with the default start), MAM_EUNSUPPORTED (batch or finite gamma),
+ * MAM_ENOMEM (workspace NULL or too small), MAM_EINVAL (misaligned, iters < 0). */
+mam_status mam_record(mam_problem* p, int64_t iters, int64_t ckpt_every, void* adj_ws, size_t bytes,
+                      void* stream);
+
+/* Reverse sweep of the last mam_record: given grad_p = dL/dp_bar (R
+ * doubles, device), writes grad_q = dL/dq (T elements of the dtype, device)
+ * and grad_cost = dL/dc (cost_ncols columns of R elements at stride
+ * cost_ld, device; columns no plan column reads get 0).  Reruns windows of
+ * the forward from their checkpoints where the mask ring does not hold
+ * them, so it may be called again (same results) while adj_ws, q and the
+ * cost are unchanged.  Leaves theta and the marginals at an intermediate
+ * iterate: mam_init is needed before further iterations.  Asynchronous.
+ * Errors: MAM_ESTATE (no mam_record), MAM_EINVAL (NULL gradient buffer). */
+mam_status mam_backward(mam_problem* p, const double* grad_p, void* grad_q, void* grad_cost, void* stream);
+
 /* Destroy a handle (NULL is allowed).  Device buffers stay with the caller. */
 void mam_destroy(mam_problem* p);
 

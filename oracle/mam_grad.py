@@ -16,9 +16,10 @@ from __future__ import annotations
 
 from typing import List
 
+import numpy as np
 import torch
 
-__all__ = ["proj_simplex_sort_t", "mam_pbar_t", "loss_and_grads"]
+__all__ = ["proj_simplex_sort_t", "mam_pbar_t", "loss_and_grads", "vjp"]
 
 
 def proj_simplex_sort_t(w: torch.Tensor, tau: torch.Tensor) -> torch.Tensor:
@@ -57,6 +58,11 @@ def mam_pbar_t(cost: List[torch.Tensor], q: List[torch.Tensor], rho: float, iter
     return (a.unsqueeze(1) * pm).sum(dim=0)
 
 
+def _grad(x: torch.Tensor):
+    """x.grad as numpy; zeros when x took no part (the cost with 0 iterations)."""
+    return np.zeros(tuple(x.shape)) if x.grad is None else x.grad.numpy().copy()
+
+
 def loss_and_grads(cost_np, q_np, rho, iters, target_np):
     """L = ||p-bar - target||^2 and its gradients with respect to every q^(m)
     and every c^(m) (lists of numpy arrays, float64)."""
@@ -65,5 +71,13 @@ def loss_and_grads(cost_np, q_np, rho, iters, target_np):
     pbar = mam_pbar_t(cost, q, rho, iters)
     loss = ((pbar - torch.tensor(target_np, dtype=torch.float64)) ** 2).sum()
     loss.backward()
-    return (float(loss), pbar.detach().numpy(), [v.grad.numpy().copy() for v in q],
-            [c.grad.numpy().copy() for c in cost])
+    return (float(loss.detach()), pbar.detach().numpy(), [_grad(v) for v in q], [_grad(c) for c in cost])
+
+
+def vjp(cost_np, q_np, rho, iters, u_np):
+    """p-bar and the vector-Jacobian products u^T dp-bar/dq^(m), u^T dp-bar/dc^(m)."""
+    cost = [torch.tensor(c, dtype=torch.float64, requires_grad=True) for c in cost_np]
+    q = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in q_np]
+    pbar = mam_pbar_t(cost, q, rho, iters)
+    pbar.backward(torch.tensor(u_np, dtype=torch.float64))
+    return pbar.detach().numpy(), [_grad(v) for v in q], [_grad(c) for c in cost]

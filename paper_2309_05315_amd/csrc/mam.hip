@@ -114,6 +114,19 @@ struct Layout {
   size_t total = 0;
 };
 
+// Reverse-mode state of a single-problem plan (mam_record / mam_backward).
+struct Adjoint {
+  bool valid = false;
+  int64_t K = 0, C = 1, nw = 0;  // iterations, window length, windows
+  int64_t resident = -1;         // window whose masks the ring holds
+  char* ws = nullptr;
+  size_t bytes = 0;
+  int64_t mld = 0;               // mask bytes per column
+  size_t ckpt_bytes = 0;         // one checkpoint of theta
+  size_t o_mask = 0, o_ckpt = 0, o_U = 0, o_cacc = 0, o_qacc = 0, o_V = 0, o_wold = 0, o_wnew = 0;
+  size_t o_cptr = 0, o_clist = 0, o_aux = 0, total = 0;
+};
+
 struct Plan {
   int dtype = MAM_F64;
   bool batch = false;
@@ -132,7 +145,9 @@ struct Plan {
   size_t ws_bytes = 0;
   bool tables_uploaded = false;
   bool inited = false;
+  bool default_start = false;
   int64_t iters_done = 0;
+  Adjoint adj;
   bool diag_valid = false;
   // graph of a fixed number of iterations
   int64_t graph_iters = 0;
@@ -635,7 +650,7 @@ mam_status upload_tables(Plan* pl, hipStream_t st) {
 // launches
 // ---------------------------------------------------------------------------
 template <typename T>
-mam_status launch_columns(Plan* pl, hipStream_t st, int diag) {
+mam_status launch_columns(Plan* pl, hipStream_t st, int diag, uint8_t* rec, int64_t rec_ld) {
   const Layout& L = pl->lay;
   for (const Group& g : pl->G) {
     mam::ColArgs<T> a;
@@ -648,6 +663,8 @@ mam_status launch_columns(Plan* pl, hipStream_t st, int diag) {
     a.wg_seg = at<int32_t>(pl, L.wg_seg) + g.wg_base;
     a.partial = at<double>(pl, L.partial);
     a.diag = at<double>(pl, L.diag) + (size_t)g.wg_base * mam::DIAG_STRIDE;
+    a.rec = rec;
+    a.rec_ld = rec_ld;
     a.nwg = g.nwg;
     a.xcd_remap = g.xcd_remap;
     const int kc = g.vec == 1 ? 1 : g.kc;
@@ -781,12 +798,15 @@ mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
   }
   TRY(pl->dtype == MAM_F32 ? launch_init<float>(pl, theta0, st) : launch_init<double>(pl, theta0, st));
   pl->inited = true;
+  pl->default_start = true;
+  for (size_t i = 0; i < pl->P.size(); ++i)
+    if (theta0 && theta0[i]) pl->default_start = false;
   pl->iters_done = 0;
   pl->diag_valid = false;
   return MAM_OK;
 }
 
-mam_status one_iteration(Plan* pl, hipStream_t st, int diag) {
+mam_status one_iteration(Plan* pl, hipStream_t st, int diag, uint8_t* rec = nullptr, int64_t rec_ld = 0) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (pl->timing) {
     e0 = next_event(pl);
@@ -794,7 +814,8 @@ mam_status one_iteration(Plan* pl, hipStream_t st, int diag) {
     if (!e0 || !e1) return fail(MAM_EHIP, "hipEventCreate failed");
     HIP_TRY(hipEventRecord(e0, st));
   }
-  TRY(pl->dtype == MAM_F32 ? launch_columns<float>(pl, st, diag) : launch_columns<double>(pl, st, diag));
+  TRY(pl->dtype == MAM_F32 ? launch_columns<float>(pl, st, diag, rec, rec_ld)
+                            : launch_columns<double>(pl, st, diag, rec, rec_ld));
   if (pl->timing) HIP_TRY(hipEventRecord(e1, st));
   return launch_marginals(pl, st, diag);
 }
@@ -869,6 +890,232 @@ mam_status plan_timing_read(Plan* pl, double* total_ms, int64_t* launches) {
   *total_ms = tot;
   *launches = (int64_t)(pl->ev_used / 2);
   pl->ev_used = 0;
+  return MAM_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// reverse mode
+//
+// mam_record runs K iterations from theta^0 = q/R, keeping theta at the
+// start of every window of C iterations but the first (theta^0 is rebuilt
+// from q) and the active-set masks of the last window.  mam_backward walks
+// the windows from the last: it rebuilds a window's masks (restore its
+// start, rerun its C iterations with recording) unless the ring holds them,
+// then takes the window's reverse steps from its last iteration down.  The
+// ring has C+1 slots (slot of iteration k = k mod (C+1)), so rerunning a
+// window never overwrites the first mask of the window after it, which its
+// last reverse step reads.
+// ---------------------------------------------------------------------------
+mam_status adjoint_layout(const Plan* pl, int64_t K, int64_t C, Adjoint* A) {
+  if (pl->batch) return fail(MAM_EUNSUPPORTED, "the reverse mode is available for single problems");
+  if (K < 0) return fail(MAM_EINVAL, "iters must be >= 0");
+  const Prob& p = pl->P[0];
+  const Group& g = pl->G[0];
+  A->K = K;
+  A->C = (C <= 0 || C > K) ? std::max<int64_t>(K, 1) : C;
+  A->nw = (K + A->C - 1) / A->C;
+  A->mld = (int64_t)g.nt * (g.vpt <= 8 ? 1 : 2);
+  A->ckpt_bytes = (size_t)p.ld * (size_t)p.T * elem_bytes(pl->dtype);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t a = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return a;
+  };
+  const size_t R = (size_t)p.R, M = (size_t)p.M, T = (size_t)p.T;
+  A->o_mask = take((size_t)(A->C + 1) * T * (size_t)A->mld);
+  A->o_ckpt = take((size_t)std::max<int64_t>(A->nw - 1, 0) * A->ckpt_bytes);
+  A->o_U = take(R * T * 8);
+  A->o_cacc = take(R * T * 8);
+  A->o_qacc = take(T * 8);
+  A->o_V = take(M * R * 8);
+  A->o_wold = take(M * R * 8);
+  A->o_wnew = take(M * R * 8);
+  A->o_cptr = take((size_t)(p.cost_ncols + 1) * 8);
+  A->o_clist = take(T * 4);
+  A->o_aux = take(sizeof(mam::ProbAux));
+  A->total = o;
+  return MAM_OK;
+}
+
+uint8_t* mask_slot(Plan* pl, int64_t k) {
+  Adjoint& A = pl->adj;
+  return reinterpret_cast<uint8_t*>(A.ws + A.o_mask) + (size_t)(k % (A.C + 1)) * (size_t)pl->P[0].T * (size_t)A.mld;
+}
+
+template <typename T>
+mam_status launch_copy(T* dst, const T* src, const Prob& p, hipStream_t st) {
+  const int blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (p.T * p.R + 255) / 256));
+  hipLaunchKernelGGL(mam::copy_kernel<T>, dim3(blocks), dim3(256), 0, st, dst, p.ld, (int)p.R, src, p.T);
+  LAUNCH_CHECK("copy_kernel");
+  return MAM_OK;
+}
+
+// Iterations [k0, k1) with the masks of those at or after 'rec_from'
+// recorded; theta is checkpointed at every window start k > 0 when 'ckpt'.
+mam_status record_range(Plan* pl, int64_t k0, int64_t k1, int64_t rec_from, bool ckpt, hipStream_t st) {
+  Adjoint& A = pl->adj;
+  const Prob& p = pl->P[0];
+  for (int64_t k = k0; k < k1; ++k) {
+    if (ckpt && k > 0 && k % A.C == 0) {
+      char* dst = A.ws + A.o_ckpt + (size_t)(k / A.C - 1) * A.ckpt_bytes;
+      if (pl->dtype == MAM_F32)
+        TRY(launch_copy<float>(reinterpret_cast<float*>(dst), static_cast<const float*>(p.theta), p, st));
+      else
+        TRY(launch_copy<double>(reinterpret_cast<double*>(dst), static_cast<const double*>(p.theta), p, st));
+    }
+    TRY(one_iteration(pl, st, 0, k >= rec_from ? mask_slot(pl, k) : nullptr, A.mld));
+  }
+  return MAM_OK;
+}
+
+mam_status plan_record(Plan* pl, int64_t K, int64_t C, void* ws, size_t bytes, hipStream_t st) {
+  Adjoint A;
+  TRY(adjoint_layout(pl, K, C, &A));
+  const Prob& p = pl->P[0];
+  if (!pl->inited) return fail(MAM_ESTATE, "mam_init has not run");
+  if (!pl->default_start || pl->iters_done != 0)
+    return fail(MAM_ESTATE, "mam_record needs a fresh mam_init with the default start (theta0 = NULL)");
+  if (!std::isinf(p.gamma)) return fail(MAM_EUNSUPPORTED, "the reverse mode covers balanced problems (gamma = inf)");
+  if (!ws) return fail(MAM_ENOMEM, "adjoint workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(MAM_EINVAL, "adjoint workspace must be 256-byte aligned");
+  if (bytes < A.total) return fail(MAM_ENOMEM, "adjoint workspace has %zu bytes, needs %zu", bytes, A.total);
+  A.ws = static_cast<char*>(ws);
+  A.bytes = bytes;
+  // cost-column -> plan-column lists (increasing plan column)
+  std::vector<int64_t> cptr(p.cost_ncols + 1, 0);
+  std::vector<int32_t> clist(p.T);
+  auto col_of = [&](int64_t j, int64_t m) -> int64_t {
+    if (p.cost_mode == MAM_COST_INDEXED) return p.idx[j];
+    if (p.cost_mode == MAM_COST_SHARED) return j - p.col_off[m];
+    return j;
+  };
+  for (int64_t m = 0; m < p.M; ++m)
+    for (int64_t j = p.col_off[m]; j < p.col_off[m + 1]; ++j) ++cptr[col_of(j, m) + 1];
+  for (int64_t c = 0; c < p.cost_ncols; ++c) cptr[c + 1] += cptr[c];
+  {
+    std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t m = 0; m < p.M; ++m)
+      for (int64_t j = p.col_off[m]; j < p.col_off[m + 1]; ++j) clist[fill[col_of(j, m)]++] = (int32_t)j;
+  }
+  mam::ProbAux aux = {reinterpret_cast<double*>(A.ws + A.o_wnew), nullptr, nullptr, nullptr, nullptr,
+                      at<double>(pl, p.o_aw), at<double>(pl, p.o_Sd), (int32_t)p.R, (int32_t)p.M, p.mbase, 0};
+  HIP_TRY(hipMemcpyAsync(A.ws + A.o_cptr, cptr.data(), cptr.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(A.ws + A.o_clist, clist.data(), clist.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(A.ws + A.o_aux, &aux, sizeof(aux), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  pl->adj = A;
+  pl->adj.valid = false;
+  TRY(record_range(pl, 0, K, (A.nw - 1) * A.C, true, st));
+  pl->iters_done += K;
+  pl->adj.resident = A.nw - 1;
+  pl->adj.valid = true;
+  return MAM_OK;
+}
+
+template <typename T>
+mam_status backward_finish(Plan* pl, void* gq, void* gc, hipStream_t st) {
+  Adjoint& A = pl->adj;
+  const Prob& p = pl->P[0];
+  hipLaunchKernelGGL(mam::grad_q_kernel<T>, dim3((unsigned)p.M), dim3(256), 0, st,
+                     reinterpret_cast<const double*>(A.ws + A.o_V), reinterpret_cast<const double*>(A.ws + A.o_qacc),
+                     at<int64_t>(pl, p.o_coloff), static_cast<T*>(gq), (int)p.R);
+  LAUNCH_CHECK("grad_q_kernel");
+  hipLaunchKernelGGL(mam::grad_cost_kernel<T>, dim3((unsigned)std::min<int64_t>(p.cost_ncols, 16384)), dim3(256), 0, st,
+                     reinterpret_cast<const double*>(A.ws + A.o_cacc), reinterpret_cast<const int64_t*>(A.ws + A.o_cptr),
+                     reinterpret_cast<const int32_t*>(A.ws + A.o_clist), p.cost_ncols, (int)p.R, 1.0 / p.rho,
+                     static_cast<T*>(gc), p.cost_ld);
+  LAUNCH_CHECK("grad_cost_kernel");
+  return MAM_OK;
+}
+
+mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStream_t st) {
+  Adjoint& A = pl->adj;
+  if (!A.valid) return fail(MAM_ESTATE, "mam_record has not run");
+  if (!gp || !gq || !gc) return fail(MAM_EINVAL, "grad_p, grad_q and grad_cost must be non-NULL");
+  const Prob& p = pl->P[0];
+  const Group& g = pl->G[0];
+  const Layout& L = pl->lay;
+  double* V = reinterpret_cast<double*>(A.ws + A.o_V);
+  double* wold = reinterpret_cast<double*>(A.ws + A.o_wold);
+  double* wnew = reinterpret_cast<double*>(A.ws + A.o_wnew);
+  const int64_t MR = p.M * p.R;
+  hipLaunchKernelGGL(mam::adjoint_start_kernel, dim3((unsigned)std::min<int64_t>(4096, (MR + 255) / 256)), dim3(256),
+                     0, st, gp, at<double>(pl, p.o_aw), V, wold, (int)p.R, (int)p.M);
+  LAUNCH_CHECK("adjoint_start_kernel");
+  const int64_t RT = p.R * p.T;
+  hipLaunchKernelGGL(mam::fill_value_kernel, dim3((unsigned)std::min<int64_t>(8192, (RT + 255) / 256)), dim3(256), 0,
+                     st, reinterpret_cast<double*>(A.ws + A.o_cacc), RT, 0.0);
+  LAUNCH_CHECK("fill_value_kernel");
+  hipLaunchKernelGGL(mam::fill_value_kernel, dim3((unsigned)std::min<int64_t>(4096, (p.T + 255) / 256)), dim3(256), 0,
+                     st, reinterpret_cast<double*>(A.ws + A.o_qacc), p.T, 0.0);
+  LAUNCH_CHECK("fill_value_kernel");
+
+  mam::AdjFn fn = mam::pick_adjoint(g.nt, g.vpt);
+  if (!fn) return fail(MAM_EUNSUPPORTED, "no reverse column kernel for nt=%d vpt=%d", g.nt, g.vpt);
+  const size_t shmem = (size_t)g.vpt * g.nt * 8 * (1 + g.ng);
+  if (shmem > 65536)
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shmem));
+  mam::AdjArgs a;
+  a.seg_m = at<int32_t>(pl, L.seg_m);
+  a.seg_j0 = at<int64_t>(pl, L.seg_j0);
+  a.seg_j1 = at<int64_t>(pl, L.seg_j1);
+  a.seg_poff = at<int64_t>(pl, L.seg_poff);
+  a.wg_seg = at<int32_t>(pl, L.wg_seg);
+  a.partial = at<double>(pl, L.partial);
+  a.mld = A.mld;
+  a.U = reinterpret_cast<double*>(A.ws + A.o_U);
+  a.cacc = reinterpret_cast<double*>(A.ws + A.o_cacc);
+  a.qacc = reinterpret_cast<double*>(A.ws + A.o_qacc);
+  a.V = V;
+  a.R = (int32_t)p.R;
+  a.vec_shift = g.vec == 4 ? 2 : (g.vec == 2 ? 1 : 0);
+  a.nwg = g.nwg;
+  a.xcd_remap = g.xcd_remap;
+  const int wgsize = g.nt == 64 ? 256 : g.nt;
+
+  const bool timing = pl->timing;
+  for (int64_t w = A.nw - 1; w >= 0; --w) {
+    const int64_t k0 = w * A.C, k1 = std::min(A.K, k0 + A.C);
+    if (A.resident != w) {
+      // rebuild the window's masks from its start
+      const void* start = w == 0 ? nullptr : A.ws + A.o_ckpt + (size_t)(w - 1) * A.ckpt_bytes;
+      const void* t0[1] = {start};
+      TRY(pl->dtype == MAM_F32 ? launch_init<float>(pl, t0, st) : launch_init<double>(pl, t0, st));
+      pl->timing = false;
+      const mam_status s = record_range(pl, k0, k1, k0, false, st);
+      pl->timing = timing;
+      TRY(s);
+      A.resident = w;
+    }
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      a.mk = mask_slot(pl, k);
+      a.mk1 = k + 1 < A.K ? mask_slot(pl, k + 1) : nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timing) {
+        e0 = next_event(pl);
+        e1 = next_event(pl);
+        if (!e0 || !e1) return fail(MAM_EHIP, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(e0, st));
+      }
+      hipLaunchKernelGGL(fn, dim3(g.nwg), dim3(wgsize), shmem, st, a);
+      LAUNCH_CHECK("adjoint_kernel");
+      if (timing) HIP_TRY(hipEventRecord(e1, st));
+      hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
+                         at<mam::MargTask>(pl, L.mtasks), reinterpret_cast<const mam::ProbAux*>(A.ws + A.o_aux),
+                         at<int32_t>(pl, L.mseg), at<int32_t>(pl, L.seg_idx), at<int64_t>(pl, L.seg_poff),
+                         at<double>(pl, L.partial), 0);
+      LAUNCH_CHECK("marginal_kernel");
+      hipLaunchKernelGGL(mam::adjoint_average_kernel, dim3((unsigned)((p.R + 255) / 256)), dim3(256), 0, st, wnew, wold,
+                         V, at<double>(pl, p.o_Sd), at<double>(pl, p.o_aw), (int)p.R, (int)p.M);
+      LAUNCH_CHECK("adjoint_average_kernel");
+    }
+  }
+  TRY(pl->dtype == MAM_F32 ? backward_finish<float>(pl, gq, gc, st) : backward_finish<double>(pl, gq, gc, st));
+  // the plans now hold an intermediate iterate
+  pl->inited = false;
   return MAM_OK;
 }
 
@@ -1044,6 +1291,25 @@ mam_status mam_timing_enable(mam_problem* p, int32_t enable) {
 mam_status mam_timing_read(mam_problem* p, double* total_ms, int64_t* launches) {
   if (!p || !total_ms || !launches) return fail(MAM_EINVAL, "NULL argument");
   return plan_timing_read(&p->plan, total_ms, launches);
+}
+
+// ---- reverse mode ----------------------------------------------------------
+size_t mam_adjoint_workspace_bytes(const mam_problem* p, int64_t iters, int64_t ckpt_every) {
+  if (!p) return 0;
+  Adjoint A;
+  if (adjoint_layout(&p->plan, iters, ckpt_every, &A) != MAM_OK) return 0;
+  return A.total;
+}
+
+mam_status mam_record(mam_problem* p, int64_t iters, int64_t ckpt_every, void* adj_ws, size_t bytes,
+                      void* stream) {
+  if (!p) return fail(MAM_EINVAL, "NULL handle");
+  return plan_record(&p->plan, iters, ckpt_every, adj_ws, bytes, static_cast<hipStream_t>(stream));
+}
+
+mam_status mam_backward(mam_problem* p, const double* grad_p, void* grad_q, void* grad_cost, void* stream) {
+  if (!p) return fail(MAM_EINVAL, "NULL handle");
+  return plan_backward(&p->plan, grad_p, grad_q, grad_cost, static_cast<hipStream_t>(stream));
 }
 
 void mam_destroy(mam_problem* p) { delete p; }

@@ -3,6 +3,7 @@
 // checks and the cost helper.  Included only by the host translation unit.
 #pragma once
 
+#include "mam_adjoint.hpp"
 #include "mam_kernels.hpp"
 
 namespace mam {
@@ -211,6 +212,77 @@ fill_value_kernel(double* __restrict__ p, int64_t n, double v) {
 __global__ void zero_kernel(double* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
+}
+
+// ---- reverse mode (see mam_adjoint.hpp for the step) ----
+
+// Transposed averaging of one reverse step, per row r:
+//   bbar_m = 2 W_new - W_old - S^m V_m,  pbar = sum_m bbar_m / S^m,
+//   V_m <- -bbar_m / S^m + a_m pbar,  W_old <- W_new.
+__global__ void __launch_bounds__(256)
+adjoint_average_kernel(const double* __restrict__ wnew, double* __restrict__ wold, double* __restrict__ V,
+                       const double* __restrict__ Sd, const double* __restrict__ aw, int R, int M) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= R) return;
+  double pbar = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const size_t o = (size_t)m * R + r;
+    const double bb = 2.0 * wnew[o] - wold[o] - Sd[m] * V[o];
+    pbar += bb / Sd[m];
+  }
+  for (int m = 0; m < M; ++m) {
+    const size_t o = (size_t)m * R + r;
+    const double wn = wnew[o];
+    const double bb = 2.0 * wn - wold[o] - Sd[m] * V[o];
+    V[o] = -bb / Sd[m] + aw[m] * pbar;
+    wold[o] = wn;
+  }
+}
+
+// Start of the reverse sweep: V_m = a_m * dL/dp_bar, W_old = 0.
+__global__ void __launch_bounds__(256)
+adjoint_start_kernel(const double* __restrict__ gp, const double* __restrict__ aw, double* __restrict__ V,
+                     double* __restrict__ wold, int R, int M) {
+  const int64_t n = (int64_t)R * M;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int m = (int)(i / R);
+    const int r = (int)(i - (int64_t)m * R);
+    V[i] = aw[m] * gp[r];
+    wold[i] = 0.0;
+  }
+}
+
+// qbar_s = qacc_s + (sum_r V^0_m,r) / R for the columns of measure m (one
+// block per measure; the row sum in a fixed order).
+template <typename T>
+__global__ void __launch_bounds__(256)
+grad_q_kernel(const double* __restrict__ V, const double* __restrict__ qacc, const int64_t* __restrict__ col_off,
+              T* __restrict__ gq, int R) {
+  __shared__ double sh[4];
+  const int m = blockIdx.x;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < R; r += 256) s += V[(size_t)m * R + r];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double add = (((sh[0] + sh[1]) + sh[2]) + sh[3]) / (double)R;
+  for (int64_t j = col_off[m] + threadIdx.x; j < col_off[m + 1]; j += 256) gq[j] = (T)(qacc[j] + add);
+}
+
+// cbar of cost column c = -(1/rho) * sum of cacc over the plan columns that
+// read column c (list in increasing order: fixed summation order).
+template <typename T>
+__global__ void __launch_bounds__(256)
+grad_cost_kernel(const double* __restrict__ cacc, const int64_t* __restrict__ cptr, const int32_t* __restrict__ clist,
+                 int64_t ncols, int R, double inv_rho, T* __restrict__ gc, int64_t cost_ld) {
+  for (int64_t c = blockIdx.x; c < ncols; c += gridDim.x) {
+    const int64_t b = cptr[c], e = cptr[c + 1];
+    for (int r = threadIdx.x; r < R; r += 256) {
+      double s = 0.0;
+      for (int64_t i = b; i < e; ++i) s += cacc[(int64_t)clist[i] * R + r];
+      gc[c * cost_ld + r] = (T)(-s * inv_rho);
+    }
+  }
 }
 
 }  // namespace mam

@@ -31,6 +31,11 @@ inline ColFn<T> pick_column(int nt, int vpt, int vec, int kc, int diag) {
   }
 }
 
+// Reverse-mode column kernel for (threads per column, values per thread).
+struct AdjArgs;
+using AdjFn = void (*)(AdjArgs);
+AdjFn pick_adjoint(int nt, int vpt);
+
 extern template ColFn<float> pick_column_kc<float, 1>(int, int, int);
 extern template ColFn<float> pick_column_kc<float, 2>(int, int, int);
 extern template ColFn<float> pick_column_kc<float, 4>(int, int, int);

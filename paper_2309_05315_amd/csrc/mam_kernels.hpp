@@ -207,6 +207,9 @@ struct ColArgs {
   const int32_t* wg_seg;  // segments of workgroup w: [wg_seg[w], wg_seg[w+1])
   double* partial;
   double* diag;           // nwg x DIAG_STRIDE (single-problem plans)
+  uint8_t* rec;           // null, or: per column j, the threads' active-set
+                          // mask words at rec + j*rec_ld (single-problem plans)
+  int64_t rec_ld;
   int32_t nwg, xcd_remap;
 };
 
@@ -225,6 +228,13 @@ __device__ __forceinline__ int logical_block(int bid, int nblocks, int remap) {
   const int base = (x < full) ? x * per : full * per + (x - full) * (per - 1);
   return base + k;
 }
+
+// Active-set mask word of one thread (bit k = slot k): 8 or 16 bits.
+template <int VPT> struct MaskWord { using type = uint16_t; };
+template <> struct MaskWord<1> { using type = uint8_t; };
+template <> struct MaskWord<2> { using type = uint8_t; };
+template <> struct MaskWord<4> { using type = uint8_t; };
+template <> struct MaskWord<8> { using type = uint8_t; };
 
 constexpr int KB = 4;  // column block a group owns at a time (multiple of every KC)
 
@@ -614,6 +624,11 @@ column_kernel(ColArgs<T> a) {
           }
         }
         if (tid == 0) lamv[j] = lam[kc];
+        if (a.rec) {
+          // the exact active set, one bit per slot, for the reverse mode
+          using W = typename MaskWord<VPT>::type;
+          reinterpret_cast<W*>(a.rec + j * a.rec_ld)[tid] = (W)mask[kc];
+        }
         if constexpr (DIAG) {
           colsum = wave_sum(colsum);
           if constexpr (NW > 1) {

@@ -39,7 +39,7 @@ EXPORTED = ["mam_abi_version", "mam_last_error", "mam_create", "mam_set_schedule
             "mam_batch_get_schedule", "mam_batch_workspace_bytes", "mam_batch_set_workspace",
             "mam_batch_bind", "mam_batch_init", "mam_batch_iterate", "mam_batch_graph",
             "mam_batch_barycenter", "mam_batch_timing_enable", "mam_batch_timing_read",
-            "mam_batch_destroy"]
+            "mam_batch_destroy", "mam_adjoint_workspace_bytes", "mam_record", "mam_backward"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmam.so")
 
@@ -127,6 +127,9 @@ def lib() -> ctypes.CDLL:
         "mam_batch_timing_read": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_double),
                                                    ctypes.POINTER(ctypes.c_int64)]),
         "mam_batch_destroy": (None, [_vp]),
+        "mam_adjoint_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int64, ctypes.c_int64]),
+        "mam_record": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_size_t, _vp]),
+        "mam_backward": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -252,6 +255,27 @@ class Solver:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(lib().mam_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)), "mam_timing_read")
         return ms.value, n.value
+
+    # -- reverse mode --------------------------------------------------------
+    def record(self, iters: int, ckpt_every: int = 0) -> None:
+        """Run 'iters' iterations (after a default init) keeping what backward() needs."""
+        n = int(lib().mam_adjoint_workspace_bytes(self._h, int(iters), int(ckpt_every)))
+        if n == 0:
+            raise MAMError(-1, "mam_adjoint_workspace_bytes", "no reverse mode for these arguments")
+        self.adj_workspace = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib().mam_record(self._h, int(iters), int(ckpt_every), _ptr(self.adj_workspace), n,
+                                _stream(self.device)), "mam_record")
+
+    def backward(self, grad_p: torch.Tensor):
+        """dL/dq (T,) and dL/dcost (cost_ncols, cost_ld) for dL/dp_bar = grad_p."""
+        gp = grad_p.detach().to(device=self.device, dtype=torch.float64).contiguous()
+        if gp.shape != (self.R,):
+            raise ValueError(f"grad_p must have shape {(self.R,)}")
+        gq = torch.empty(self.T, dtype=self.dtype, device=self.device)
+        gc = torch.zeros(self.cost_ncols, self.cost_ld, dtype=self.dtype, device=self.device)
+        _check(lib().mam_backward(self._h, _ptr(gp), _ptr(gq), _ptr(gc), _stream(self.device)),
+               "mam_backward")
+        return gq, gc
 
     def plans(self) -> list:
         """theta^(m) as R x S^m float64 numpy arrays (copies, for checking)."""

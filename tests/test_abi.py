@@ -124,3 +124,23 @@ def test_cost_helper_validation():
     assert L.mam_cost_sq_euclid(fake, 4, fake, 4, 2, 0, fake, 3, 1, None, None) == -1
     assert L.mam_cost_sq_euclid(fake, 4, fake, 4, 2, 1, fake, 4, 1, None, None) == -1
     assert L.mam_cost_sq_euclid(fake, 4, fake, 4, 2, 0, fake, 4, 5, None, None) == -1
+
+
+def test_reverse_mode_validation():
+    L = mam.lib()
+    assert L.mam_adjoint_workspace_bytes(None, 10, 0) == 0
+    rc, h = create(R=300, S=[40, 1, 17])
+    assert rc == 0
+    assert L.mam_adjoint_workspace_bytes(h, -1, 0) == 0
+    full = L.mam_adjoint_workspace_bytes(h, 10, 0)
+    assert full > 0 and full % 256 == 0
+    # ckpt_every beyond the run keeps every mask, like 0
+    assert L.mam_adjoint_workspace_bytes(h, 10, 50) == full
+    # windows of 3 iterations: 4 mask slots instead of 11, plus 3 checkpoints of theta
+    assert L.mam_adjoint_workspace_bytes(h, 10, 3) != full
+    fake = ctypes.c_void_p(0x100000)
+    assert L.mam_record(None, 10, 0, fake, full, None) == -1
+    assert L.mam_record(h, 10, 0, fake, full, None) == -7       # no init yet
+    assert L.mam_backward(None, fake, fake, fake, None) == -1
+    assert L.mam_backward(h, fake, fake, fake, None) == -7      # no record yet
+    L.mam_destroy(h)

@@ -59,3 +59,46 @@ def test_gradients_match_central_differences(seed):
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (which, fd, an)
             checked += 1
     assert checked >= 8
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_vjp_is_the_adjoint_of_the_jvp(seed):
+    """<J^T u, v> = <u, J v> with J v by central differences of the numpy
+    oracle (exact for a piecewise-affine map away from kinks)."""
+    p = inputs.tiny_problem(20 + seed, R=5, S=[4, 3, 5], zero_frac=0.0)
+    cost, q = blocks(p)
+    rho, iters = 1.1, 7
+    rng = np.random.default_rng(200 + seed)
+    u = rng.normal(size=5)
+    pbar, gq, gc = G.vjp(cost, q, rho, iters, u)
+    np.testing.assert_allclose(pbar, O.mam(cost, q, rho, iters=iters)["p_bar"], atol=1e-14)
+    h = 1e-7
+    dq = [rng.normal(size=x.shape) for x in q]
+    dq = [d - d.mean() for d in dq]
+    dc = [rng.normal(size=c.shape) for c in cost]
+    fplus = O.mam([c + h * d for c, d in zip(cost, dc)], [x + h * d for x, d in zip(q, dq)], rho, iters=iters)["p_bar"]
+    fminus = O.mam([c - h * d for c, d in zip(cost, dc)], [x - h * d for x, d in zip(q, dq)], rho, iters=iters)["p_bar"]
+    jv = (fplus - fminus) / (2 * h)
+    lhs = sum(float((g * d).sum()) for g, d in zip(gq, dq)) + sum(float((g * d).sum()) for g, d in zip(gc, dc))
+    rhs = float(u @ jv)
+    assert abs(lhs - rhs) <= 1e-6 * max(1.0, abs(rhs)), (lhs, rhs)
+
+
+def test_vjp_of_the_loss_gradient():
+    p = inputs.tiny_problem(31, R=6, S=[5, 5])
+    cost, q = blocks(p)
+    tgt = np.full(6, 1 / 6)
+    L, pbar, gq, gc = G.loss_and_grads(cost, q, 1.0, 9, tgt)
+    _, gq2, gc2 = G.vjp(cost, q, 1.0, 9, 2 * (pbar - tgt))
+    for a, b in zip(gq + gc, gq2 + gc2):
+        np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-16)
+
+
+def test_cost_gradient_columns_sum_to_zero():
+    """Adding a constant to one cost column shifts w uniformly in that column
+    and leaves its projection unchanged, so every column of dL/dc sums to 0."""
+    p = inputs.tiny_problem(41, R=8, S=[6, 7])
+    cost, q = blocks(p)
+    _, _, _, gc = G.loss_and_grads(cost, q, 0.9, 10, np.random.default_rng(3).dirichlet(np.ones(8)))
+    for g in gc:
+        assert np.abs(g.sum(axis=0)).max() <= 1e-14 * max(1.0, np.abs(g).max())

@@ -44,8 +44,9 @@ marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ 
   const int e = mseg[k + 1];
   for (int i = mseg[k]; i < e; ++i) s += partial[seg_poff[seg_idx[i]] + r];
   const size_t o = (size_t)tk.m * P.R + r;
-  if (save_prev) P.pm_prev[o] = P.pm[o];
-  P.pm[o] = s;
+  double* const pm = gptr(P.pm);
+  if (save_prev) gptr(P.pm_prev)[o] = pm[o];
+  pm[o] = s;
 }
 
 // p_r = sum_m a_m p^(m)_r, and the block's partial sum of
@@ -57,21 +58,25 @@ average_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ pr
   const ProbAux& P = probs[tk.prob];
   const int R = P.R, M = P.M;
   const int r = tk.rb * 256 + threadIdx.x;
+  const double* const pm = gptr(P.pm);
+  const double* const aw = gptr(P.aw);
+  const double* const Sd = gptr(P.Sd);
+  double* const p = gptr(P.p);
   double d2 = 0.0;
   if (r < R) {
     double pr = 0.0;
-    for (int m = 0; m < M; ++m) pr += P.aw[m] * P.pm[(size_t)m * R + r];
+    for (int m = 0; m < M; ++m) pr += aw[m] * pm[(size_t)m * R + r];
     for (int m = 0; m < M; ++m) {
-      const double e = pr - P.pm[(size_t)m * R + r];
-      d2 += e * e / P.Sd[m];
+      const double e = pr - pm[(size_t)m * R + r];
+      d2 += e * e / Sd[m];
     }
-    if (save_prev) P.p_prev[r] = P.p[r];
-    P.p[r] = pr;
+    if (save_prev) gptr(P.p_prev)[r] = p[r];
+    p[r] = pr;
   }
   d2 = wave_sum(d2);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d2;
   __syncthreads();
-  if (threadIdx.x == 0) P.d2part[tk.rb] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  if (threadIdx.x == 0) gptr(P.d2part)[tk.rb] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
 // theta^0_rs = q_s / R (Alg. 1 Step 0 with the library's default start).
@@ -107,9 +112,10 @@ rowsum_kernel(const ProbDev<T>* __restrict__ probs, const int32_t* __restrict__ 
   const int wg = blockIdx.x;
   for (int si = wg_seg[wg]; si < wg_seg[wg + 1]; ++si) {
     const ProbDev<T>& P = probs[seg_p[si]];
+    const T* const theta = gptr((const T*)P.theta);
     for (int r = threadIdx.x; r < P.R; r += 256) {
       double s = 0.0;
-      for (int64_t j = seg_j0[si]; j < seg_j1[si]; ++j) s += (double)P.theta[j * P.ld + r];
+      for (int64_t j = seg_j0[si]; j < seg_j1[si]; ++j) s += (double)theta[j * P.ld + r];
       partial[seg_poff[si] + r] = s;
     }
   }

@@ -173,6 +173,16 @@ __device__ __forceinline__ double wave_reduce(double v) {
   return read_lane63(v);
 }
 
+// Pointers read from device tables are generic to the compiler, which then
+// emits flat memory instructions; those also count against the LDS wait
+// counter and so serialise LDS traffic behind HBM loads.  Every buffer the
+// kernels touch through a table is global memory: the cast says so.
+template <typename T>
+__device__ __forceinline__ T* gptr(T* p) {
+  const uint64_t bits = (uint64_t)p;
+  return (T*)(__attribute__((address_space(1))) T*)bits;
+}
+
 __device__ __forceinline__ double wave_sum(double v) { return wave_reduce<OpSum>(v); }
 __device__ __forceinline__ double wave_max(double v) { return wave_reduce<OpMax>(v); }
 
@@ -359,7 +369,6 @@ column_kernel(ColArgs<T> a) {
   __shared__ double red_d[NW > 1 ? 2 * KC * 2 * NW : 1];
   __shared__ float red_f[NW > 1 ? 2 * KC * 2 * NW : 1];
   __shared__ int red_i[NW > 1 ? 2 * KC * NW : 1];
-  __shared__ double sh_t;
   __shared__ double sh_diag[WG / 64][6];
   extern __shared__ double lds_dyn[];
   double* lds_b = lds_dyn;                // [VPT][NT]
@@ -383,49 +392,20 @@ column_kernel(ColArgs<T> a) {
   const int sb = uniform_i(a.wg_seg[wg]), se = uniform_i(a.wg_seg[wg + 1]);
   for (int si = sb; si < se; ++si) {
     const ProbDev<T>& P = a.probs[uniform_i(a.seg_p[si])];
-    T* const theta = (T*)uniform_l((int64_t)P.theta);
-    const T* const cost = (const T*)uniform_l((int64_t)P.cost);
-    const T* const qv = (const T*)uniform_l((int64_t)P.q);
-    const int32_t* const cidx = (const int32_t*)uniform_l((int64_t)P.cidx);
+    T* const theta = gptr((T*)uniform_l((int64_t)P.theta));
+    const T* const cost = gptr((const T*)uniform_l((int64_t)P.cost));
+    const T* const qv = gptr((const T*)uniform_l((int64_t)P.q));
+    const int32_t* const cidx = gptr((const int32_t*)uniform_l((int64_t)P.cidx));
     const int64_t ld = uniform_l(P.ld), cost_ld = uniform_l(P.cost_ld);
     const int R = uniform_i(P.R), cost_mode = uniform_i(P.cost_mode), warm = uniform_i(P.warm);
     const double inv_rho = uniform_d(P.inv_rho);
-    double* const lamv = (double*)uniform_l((int64_t)P.lam);
+    double* const lamv = gptr((double*)uniform_l((int64_t)P.lam));
     const int m = uniform_i(a.seg_m[si]);
     const int64_t j0 = uniform_l(a.seg_j0[si]), j1 = uniform_l(a.seg_j1[si]);
-    const double Sm = uniform_d(P.Sd[m]);
-    const int64_t off_m = uniform_l(P.col_off[m]);
-    const double* __restrict__ pmm = P.pm + (size_t)m * R;
-
-    // t^k of this problem from its d^2 partials (fixed order)
-    __syncthreads();  // previous segment's readers are done
-    if (gtid == 0) {
-      double d2 = 0.0;
-      for (int i = 0; i < P.nb; ++i) d2 += P.d2part[i];
-      const double d = sqrt(d2);
-      sh_t = (__builtin_isinf(P.gamma) || P.rho * d <= P.gamma) ? 1.0 : P.gamma / (P.rho * d);
-      if (j0 == 0) P.t_out[0] = sh_t;
-    }
-    __syncthreads();
-    const double t = uniform_d(sh_t);
-
-    // b^(m) = t (p - p^(m)) / S^m for this thread's rows, kept in LDS
-    if (g == 0) {
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const int r = (c * NT + tid) * VEC + v;
-          lds_b[(c * VEC + v) * NT + tid] = (r < R) ? t * (P.p[r] - pmm[r]) / Sm : 0.0;
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < VPT; ++k) fix[k * NT + tid] = 0.0;
-    __syncthreads();
-    T nb[VPT];  // -b^(m) rounded to the storage type: every inactive entry's new value
-#pragma unroll
-    for (int k = 0; k < VPT; ++k) nb[k] = (T)(-lds_b[k * NT + tid]);
+    const double Sm = uniform_d(gptr(P.Sd)[m]);
+    const int64_t off_m = uniform_l(gptr(P.col_off)[m]);
+    const double* __restrict__ pmm = gptr(P.pm) + (size_t)m * R;
+    const double* __restrict__ pv = gptr(P.p);
 
     // Column steps of this group: blocks of KB columns taken in turn by the
     // NG groups, each walked KC columns at a time.  The raw loads of the
@@ -472,7 +452,36 @@ column_kernel(ColArgs<T> a) {
         }
       }
     };
-    if (step_exists(0)) issue(0);
+    if (step_exists(0)) issue(0);  // the first raw loads overlap the set-up below
+
+    // t^k of this problem from its d^2 partials: every wave sums them in a
+    // fixed order (one partial per lane), so t is wave-uniform without LDS
+    const int nbp = uniform_i(P.nb);
+    double d2 = lane < nbp ? gptr(P.d2part)[lane] : 0.0;
+    d2 = wave_sum(d2);
+    const double rho = uniform_d(P.rho), gam = uniform_d(P.gamma);
+    const double t = (__builtin_isinf(gam) || rho * sqrt(d2) <= gam) ? 1.0 : gam / (rho * sqrt(d2));
+    if (gtid == 0 && j0 == 0) gptr(P.t_out)[0] = t;
+
+    // b^(m) = t (p - p^(m)) / S^m for this thread's rows, kept in LDS
+    __syncthreads();  // previous segment's readers are done
+    if (g == 0) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const int r = (c * NT + tid) * VEC + v;
+          lds_b[(c * VEC + v) * NT + tid] = (r < R) ? t * (pv[r] - pmm[r]) / Sm : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) fix[k * NT + tid] = 0.0;
+    __syncthreads();
+    T nb[VPT];  // -b^(m) rounded to the storage type: every inactive entry's new value
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) nb[k] = (T)(-lds_b[k * NT + tid]);
+
     for (int64_t step = 0; step_exists(step); ++step) {
       // ---- reflect the step's columns: w = theta + 2b - c/rho (double) ----
       double w[KC][VPT];

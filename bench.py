@@ -8,7 +8,9 @@ density above 1e-3 (S^m uneven, T ~ 9.8e4 columns), squared Euclidean grid
 cost gathered by pixel index, rho = 1, plans in FP32 (thresholds, marginals
 and barycenter in FP64).  The default run times the 500 iterations that
 problem is quoted at, then the same 500 iterations with FP64 plans, and
-reports the FP32-vs-FP64 barycenter difference.
+reports the FP32-vs-FP64 barycenter difference.  Shorter runs of the other
+workloads (balanced FP64 with graph replay, unbalanced, a batch of 256
+problems, the reverse mode) are reported under "extras".
 
 Prints one JSON line:  metric, value (plan-entry updates per second), the
 roofline of the dominant kernel (the column kernel, timed with HIP events on
@@ -93,6 +95,108 @@ def cpu_baseline(p, n_measures):
                       f"({entries:.3e} plan entries, {dt:.1f} s, single thread)"}
 
 
+def extra_workloads(torch, mam, inputs, log):
+    """The other workloads of the hot path, timed briefly (informational)."""
+    import numpy as np
+    out = {}
+    sync = torch.cuda.synchronize
+
+    def timed(fn):
+        sync()
+        t0 = time.perf_counter()
+        fn()
+        sync()
+        return time.perf_counter() - t0
+
+    # balanced, FP64, 16x16 grid, 4 measures: launch-bound; eager vs graph replay
+    p1 = inputs.balanced_plain()
+    s = mam.solver_for(p1)
+    s.init()
+    s.iterate(10)
+    eager = timed(lambda: s.iterate(p1.iters)) / p1.iters
+    s.graph(50)
+    s.init()
+    s.iterate(50)
+    graph = timed(lambda: s.iterate(p1.iters)) / p1.iters
+    s.close()
+    out["balanced_plain_K16_M4_f64"] = {"iterations": p1.iters, "ms_per_iter_eager": eager * 1e3,
+                                        "ms_per_iter_graph": graph * 1e3}
+    log(f"balanced plain: {eager * 1e3:.4f} ms/iter eager, {graph * 1e3:.4f} ms/iter graph")
+
+    # unbalanced, FP32, 32x32 grid, 50 measures, gamma = 0.01
+    p3 = inputs.unbalanced_dense()
+    s = mam.solver_for(p3)
+    s.init()
+    s.iterate(10)
+    dt = timed(lambda: s.iterate(p3.iters)) / p3.iters
+    s.timing(True)
+    s.iterate(100)
+    col, n = s.timing_read()
+    s.close()
+    ab = algorithmic_bytes(p3)
+    out["unbalanced_K32_M50_f32"] = {"iterations": p3.iters, "ms_per_iter": dt * 1e3,
+                                     "column_kernel_ms": col / n,
+                                     "column_kernel_GBs": ab / (col / n * 1e-3) / 1e9}
+    log(f"unbalanced: {dt * 1e3:.4f} ms/iter, column kernel {col / n:.4f} ms")
+
+    # 256 independent problems (R = k^2, k in 8..32, M in 2..8), FP32, graph replay
+    probs = inputs.batched_problems()
+    b = mam.Batch(probs)
+    b.graph(25)
+    b.init()
+    b.iterate(25)
+    iters4 = probs[0].iters
+    dt = timed(lambda: b.iterate(iters4)) / iters4
+    b.graph(0)
+    b.timing(True)
+    b.iterate(50)
+    col, n = b.timing_read()
+    b.close()
+    ab = sum(algorithmic_bytes(p) for p in probs)
+    out["batch_256_f32"] = {"problems": len(probs), "iterations": iters4, "ms_per_iter_graph": dt * 1e3,
+                            "column_kernels_ms": col / n, "column_kernels_GBs": ab / (col / n * 1e-3) / 1e9,
+                            "plan_entries": int(sum(p.R * p.T for p in probs))}
+    log(f"batch of {len(probs)}: {dt * 1e3:.4f} ms/iter (graph), column kernels {col / n:.4f} ms")
+
+    # reverse mode: 64x64 grid, 8 measures, 100 iterations, FP32, loss ||p_bar - target||^2
+    p5, tgt = inputs.adjoint_problem()
+    tg = torch.as_tensor(tgt, device="cuda:0")
+    res = {"iterations": p5.iters}
+    for ck in (10, 0):
+        s = mam.solver_for(p5)
+        s.init()
+        rec = timed(lambda: s.record(p5.iters, ck))
+        g = 2.0 * (s.barycenter() - tg)
+        s.backward(g)
+        s.timing(True)
+        bwd = timed(lambda: s.backward(g))
+        ak, n = s.timing_read()
+        sc = s.schedule()
+        ws = s.adj_workspace.numel()
+        s.close()
+        res[f"ckpt_every_{ck}"] = {"record_ms": rec * 1e3, "backward_ms": bwd * 1e3,
+                                   "adjoint_kernel_us": ak / n * 1e3, "adjoint_workspace_GB": ws / 1e9}
+        log(f"adjoint ckpt_every={ck}: record {rec * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms, "
+            f"adjoint kernel {ak / n * 1e3:.1f} us")
+    # algorithmic bytes of one reverse column step: the active-set masks of
+    # two iterations, q's adjoint (read and write), and for every active
+    # entry the sparse adjoint (read, write) and the cost adjoint (read, write)
+    s = mam.solver_for(p5, diag=True)
+    s.init()
+    s.iterate(p5.iters)
+    act = s.diagnostics()["active_per_column"]
+    s.close()
+    mld = sc["threads_per_column"] * (1 if sc["values_per_thread"] <= 8 else 2)
+    abytes = 2 * p5.T * mld + 16 * p5.T + 32 * act * p5.T
+    us = res["ckpt_every_0"]["adjoint_kernel_us"]
+    res["adjoint_kernel_roofline"] = {"bound": "hbm", "algorithmic_bytes_per_launch": abytes,
+                                      "active_entries_per_column": act,
+                                      "achieved": abytes / (us * 1e-6) / 1e9, "peak": PEAK_HBM_GBS,
+                                      "unit": "GB/s", "frac": abytes / (us * 1e-6) / 1e9 / PEAK_HBM_GBS}
+    out["adjoint_K64_M8_f32"] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +205,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--cpu-measures", type=int, default=12)
+    ap.add_argument("--no-extras", action="store_true", help="skip the other workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -161,6 +266,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: 3 x {4 * n} bytes copied")
 
+    extras = None if args.no_extras else extra_workloads(torch, mam, inputs, log)
+
     cpu = None if args.no_cpu else cpu_baseline(p32, args.cpu_measures)
 
     out = {
@@ -186,6 +293,7 @@ def main():
                      "avg_launch_ms": col_ms32, "launches_timed": ncol},
         "fp64": fp64,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -365,6 +365,10 @@ column_kernel(ColArgs<T> a) {
   static_assert(VPT % VEC == 0, "VPT must be a multiple of VEC");
   static_assert(VPT <= 32, "the active mask is one 32-bit word");
   static_assert(NG == 1 || NW == 1, "multi-wave groups fill the workgroup");
+  // column steps whose raw loads are in flight at once: two for float plans
+  // with vector loads and at most 512 threads per group, where the extra
+  // buffer still fits the register budget without spills
+  constexpr int PF = (sizeof(T) == 4 && KC == 1 && VEC > 1 && NT <= 512) ? 2 : 1;
 
   __shared__ double red_d[NW > 1 ? 2 * KC * 2 * NW : 1];
   __shared__ float red_f[NW > 1 ? 2 * KC * 2 * NW : 1];
@@ -428,8 +432,9 @@ column_kernel(ColArgs<T> a) {
       else cc = j;
       return cost + cc * cost_ld;
     };
-    T rt[KC][VPT], rc[KC][VPT];  // raw theta and cost of the next step
-    auto issue = [&](int64_t i) {
+    // raw theta and cost of the next PF steps, one buffer per step in flight
+    T rt[PF][KC][VPT], rc[PF][KC][VPT];
+    auto issue = [&](int64_t i, T (&bt)[KC][VPT], T (&bc)[KC][VPT]) {
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         int64_t j;
@@ -445,14 +450,17 @@ column_kernel(ColArgs<T> a) {
             load_vec<T, VEC>(cp + r0, cv);
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-              rt[kc][c * VEC + v] = tv[v];
-              rc[kc][c * VEC + v] = cv[v];
+              bt[kc][c * VEC + v] = tv[v];
+              bc[kc][c * VEC + v] = cv[v];
             }
           }
         }
       }
     };
-    if (step_exists(0)) issue(0);  // the first raw loads overlap the set-up below
+    // the first raw loads overlap the set-up below
+#pragma unroll
+    for (int b = 0; b < PF; ++b)
+      if (step_exists(b)) issue(b, rt[b], rc[b]);
 
     // t^k of this problem from its d^2 partials: every wave sums them in a
     // fixed order (one partial per lane), so t is wave-uniform without LDS
@@ -482,7 +490,7 @@ column_kernel(ColArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < VPT; ++k) nb[k] = (T)(-lds_b[k * NT + tid]);
 
-    for (int64_t step = 0; step_exists(step); ++step) {
+    auto body = [&](int64_t step, T (&bt)[KC][VPT], T (&bc)[KC][VPT]) {
       // ---- reflect the step's columns: w = theta + 2b - c/rho (double) ----
       double w[KC][VPT];
       T told[DIAG ? KC : 1][DIAG ? VPT : 1];
@@ -494,12 +502,12 @@ column_kernel(ColArgs<T> a) {
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
           const int r = ((k / VEC) * NT + tid) * VEC + (k % VEC);
-          const double x = ((double)rt[kc][k] + 2.0 * lds_b[k * NT + tid]) - (double)rc[kc][k] * inv_rho;
+          const double x = ((double)bt[kc][k] + 2.0 * lds_b[k * NT + tid]) - (double)bc[kc][k] * inv_rho;
           w[kc][k] = (valid[kc] && r < R) ? x : -__builtin_huge_val();
-          if constexpr (DIAG) told[kc][k] = rt[kc][k];
+          if constexpr (DIAG) told[kc][k] = bt[kc][k];
         }
       }
-      if (step_exists(step + 1)) issue(step + 1);
+      if (step_exists(step + PF)) issue(step + PF, bt, bc);
 
       // ---- thresholds ----
       double tau[KC], lam[KC];
@@ -656,6 +664,14 @@ column_kernel(ColArgs<T> a) {
             dCols += 1.0;
           }
         }
+      }
+    };
+    // steps in turn, PF of them in flight: unrolled so every buffer index is static
+    for (int64_t step = 0; step_exists(step); step += PF) {
+      body(step, rt[0], rc[0]);
+      if constexpr (PF > 1) {
+        if (!step_exists(step + 1)) break;
+        body(step + 1, rt[1], rc[1]);
       }
     }
 

@@ -139,9 +139,14 @@ def extra_workloads(torch, mam, inputs, log):
                                      "column_kernel_GBs": ab / (col / n * 1e-3) / 1e9}
     log(f"unbalanced: {dt * 1e3:.4f} ms/iter, column kernel {col / n:.4f} ms")
 
-    # 256 independent problems (R = k^2, k in 8..32, M in 2..8), FP32, graph replay
+    # 256 independent problems (R = k^2, k in 8..32, M in 2..8), FP32, autotuned
+    # schedules per shape group, graph replay
+    from paper_2309_05315_amd import autotune
     probs = inputs.batched_problems()
-    b = mam.Batch(probs)
+    t0 = time.perf_counter()
+    scheds = autotune.tune_batch(probs)
+    tune_s = time.perf_counter() - t0
+    b = mam.Batch(probs, schedules=scheds)
     b.graph(25)
     b.init()
     b.iterate(25)
@@ -154,6 +159,7 @@ def extra_workloads(torch, mam, inputs, log):
     b.close()
     ab = sum(algorithmic_bytes(p) for p in probs)
     out["batch_256_f32"] = {"problems": len(probs), "iterations": iters4, "ms_per_iter_graph": dt * 1e3,
+                            "autotune_s": tune_s, "schedules": {str(g): v for g, v in scheds.items()},
                             "column_kernels_ms": col / n, "column_kernels_GBs": ab / (col / n * 1e-3) / 1e9,
                             "plan_entries": int(sum(p.R * p.T for p in probs))}
     log(f"batch of {len(probs)}: {dt * 1e3:.4f} ms/iter (graph), column kernels {col / n:.4f} ms")
@@ -250,6 +256,23 @@ def main():
         log(f"fp64: {fp64['ms_per_step']:.4f} ms/iter; fp32/fp64 barycenter rel L1 "
             f"{fp64['barycenter_rel_l1_fp32_vs_fp64']:.3e}")
 
+    # a plain device copy of 1 GiB: the measured stream bandwidth next to the nominal peak
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    bb = torch.empty_like(a)
+    for _ in range(3):
+        bb.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        bb.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 4 * n / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    del a, bb
+    torch.cuda.empty_cache()
+    log(f"device copy: {copy_gbs:.0f} GB/s")
+
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -290,6 +313,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "column_kernel", "algorithmic_bytes_per_launch": ab,
+                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
                      "avg_launch_ms": col_ms32, "launches_timed": ncol},
         "fp64": fp64,
         "cpu_baseline": cpu,

@@ -381,6 +381,10 @@ class Batch:
             self.buffers.append((theta, cost, q, idx))
             _check(L.mam_batch_bind(h, i, _ptr(theta), _ptr(cost), _ptr(idx), _ptr(q)), "mam_batch_bind")
 
+    def group_of(self, i: int) -> int:
+        """Shape group of problem i."""
+        return int(lib().mam_batch_group_of(self._h, int(i)))
+
     def groups(self) -> int:
         return int(lib().mam_batch_groups(self._h))
 

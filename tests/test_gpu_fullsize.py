@@ -1,0 +1,68 @@
+"""Parity at full size, in the benchmark's launch configuration: the
+balanced sparse workload (64x64 grid, 32 measures, T = 97,894 columns) with
+the default schedule.  The oracle cannot run whole iterations at this size
+in a test, but one iteration's columns are independent given the marginals
+(Alg. 1 Step 2), so sampled columns of theta^{k+1} are recomputed by the
+oracle from the GPU's theta^k; the marginals are checked against a plain
+FP64 sum of theta^k, and the mass invariant over all columns."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mam_oracle as O
+from paper_2309_05315_amd import inputs
+from paper_2309_05315_amd import mam
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_balanced_sparse_full_size_sampled_columns(dtype):
+    p = inputs.balanced_sparse(dtype=dtype)
+    say(f"{p.name} {dtype}: R={p.R} M={p.M} T={p.T}")
+    s = mam.solver_for(p)
+    say(f"schedule {s.schedule()}")
+    s.init()
+    s.iterate(5)
+    torch.cuda.synchronize()
+    th5 = s.theta[:, :p.R].cpu().numpy()              # theta^5, row j = plan column j
+    pm_gpu = s.marginals().cpu().numpy()
+    off = p.offsets
+    pm = np.stack([th5[off[m]:off[m + 1]].sum(axis=0, dtype=np.float64) for m in range(p.M)])
+    e_pm = np.abs(pm_gpu - pm).max() / np.abs(pm).max()
+    say(f"marginals of theta^5: max rel {e_pm:.2e}")
+    assert e_pm <= 1e-12
+    s.iterate(1)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1234)
+    cols = np.sort(np.concatenate([rng.choice(np.arange(off[m], off[m + 1]), size=3, replace=False)
+                                   for m in range(p.M)]))
+    meas = np.searchsorted(off, cols, side="right") - 1
+    new, _, t = O.mam_step_columns(th5[cols].T.astype(np.float64), meas, pm,
+                                   p.cost[p.col_index[cols]].T.astype(np.float64),
+                                   p.q[cols].astype(np.float64), p.S, p.rho, p.gamma)
+    got = s.theta[torch.as_tensor(cols, device=s.theta.device), :p.R].double().cpu().numpy().T
+    # FP32: the GPU rounds theta' once to float after FP64 arithmetic, so each
+    # entry is within 2 float ulps.  FP64: the inactive entries are -b =
+    # -(p - p^(m))/S^m, a difference of nearly equal marginals whose summation
+    # order differs, so entries are compared relative to the column's largest.
+    err = np.abs(got - new)
+    if dtype == "f32":
+        rel_e = np.max(err / np.maximum(np.abs(new), 1e-300))
+        say(f"{len(cols)} sampled columns: max |diff| / |value| = {rel_e:.2e}")
+        assert np.all(err <= 2.0 ** -23 * np.abs(new))
+    else:
+        rel_c = np.max(err.max(axis=0) / np.abs(new).max(axis=0))
+        say(f"{len(cols)} sampled columns: max over columns of ||diff||_inf / ||column||_inf = {rel_c:.2e}")
+        assert rel_c <= 1e-12
+    # mass invariant over every column of theta^6: each p^(m) keeps the mass 1
+    pm6 = s.marginals().cpu().numpy()
+    drift = np.abs(pm6.sum(axis=1) - 1.0).max()
+    say(f"mass drift after 6 iterations: {drift:.2e}")
+    assert drift <= (1e-5 if dtype == "f32" else 1e-12)

@@ -1054,7 +1054,7 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
 
   mam::AdjFn fn = mam::pick_adjoint(g.nt, g.vpt);
   if (!fn) return fail(MAM_EUNSUPPORTED, "no reverse column kernel for nt=%d vpt=%d", g.nt, g.vpt);
-  const size_t shmem = (size_t)g.vpt * g.nt * 8 * (1 + g.ng);
+  const size_t shmem = (size_t)g.vpt * g.nt * 8 * g.ng;  // row-sum accumulators only
   if (shmem > 65536)
     HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)shmem));

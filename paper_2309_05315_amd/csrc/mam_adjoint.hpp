@@ -49,8 +49,20 @@ struct AdjArgs {
 // Reverse column step.  Same column layout, groups and segments as the
 // forward column kernel whose masks it reads: thread tid of a group holds
 // bit k of a column's mask word for row ((k >> vs)*NT + tid) << vs | (k & (2^vs - 1)).
-// Dynamic LDS: VPT*NT doubles of V^(m), then NG*VPT*NT doubles of row-sum
-// accumulators (each row owned by one thread of a group: no atomics).
+//
+// A column has a handful of active entries (often one), spread over the
+// group, so a thread usually holds none and rarely more than one.  The fast
+// path keeps at most two active entries per thread in registers; a wave in
+// which some thread has more takes a slow path that walks the bits (same
+// summation order, so results do not depend on the path).  The work of a
+// column is a dependent chain (mask -> gathers -> group sum -> writes), so
+// columns are pipelined: masks are loaded two columns ahead and the V, U,
+// cost-adjoint and q-adjoint entries gathered one column ahead, so no
+// read-modify-write waits on memory inside a column step.  V is read from global memory (it is a few
+// tens of KB per measure and stays in L2).
+//
+// Dynamic LDS: NG*VPT*NT doubles of row-sum accumulators (each row owned by
+// one thread of a group: no atomics).
 template <int NT, int VPT>
 __global__ void __launch_bounds__(GroupShape<NT>::WG)
 adjoint_kernel(AdjArgs a) {
@@ -60,11 +72,8 @@ adjoint_kernel(AdjArgs a) {
   constexpr int NW = NT / 64;
   static_assert(VPT <= 16, "mask words hold at most 16 bits");
 
-  __shared__ double red_s[2][NW > 1 ? NW : 1];
-  __shared__ double red_n[2][NW > 1 ? NW : 1];
   extern __shared__ double lds_dyn[];
-  double* lds_v = lds_dyn;                // [VPT][NT]
-  double* lds_fix = lds_dyn + VPT * NT;   // [NG][VPT][NT]
+  double* lds_fix = lds_dyn;  // [NG][VPT][NT]
 
   const int gtid = threadIdx.x;
   const int g = NG == 1 ? 0 : __builtin_amdgcn_readfirstlane(gtid / NT);
@@ -75,49 +84,89 @@ adjoint_kernel(AdjArgs a) {
   const int R = a.R, vs = a.vec_shift;
   auto row = [&](int k) { return (((k >> vs) * NT + tid) << vs) | (k & ((1 << vs) - 1)); };
 
+  // one column in flight: its masks, up to two active slots and their X values
+  struct Col {
+    unsigned bk, bk1;
+    int k0, k1;      // active slots (-1: none)
+    double x0, x1;   // X = V + U at those slots (U only where also active at k+1)
+    double c0, c1;   // the cost adjoint there, read ahead for its update
+    double qa;       // q's adjoint of the column (thread 0), read ahead likewise
+  };
+  __shared__ double red_s[2][NW > 1 ? NW : 1];
+  __shared__ double red_n[2][NW > 1 ? NW : 1];
+
   int par = 0;
   const int wg = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
   const int sb = uniform_i(a.wg_seg[wg]), se = uniform_i(a.wg_seg[wg + 1]);
   for (int si = sb; si < se; ++si) {
     const int m = uniform_i(a.seg_m[si]);
     const int64_t j0 = uniform_l(a.seg_j0[si]), j1 = uniform_l(a.seg_j1[si]);
+    const double* __restrict__ Vm = a.V + (size_t)m * R;
     __syncthreads();  // previous segment's readers are done
-    if (g == 0) {
-#pragma unroll
-      for (int k = 0; k < VPT; ++k) {
-        const int r = row(k);
-        lds_v[k * NT + tid] = r < R ? a.V[(size_t)m * R + r] : 0.0;
-      }
-    }
 #pragma unroll
     for (int k = 0; k < VPT; ++k) fix[k * NT + tid] = 0.0;
     __syncthreads();
 
-    // masks of the next column are loaded one column ahead
-    W nk = 0, nk1 = 0;
-    auto load_masks = [&](int64_t j) {
-      nk = reinterpret_cast<const W*>(a.mk + j * a.mld)[tid];
-      nk1 = a.mk1 ? reinterpret_cast<const W*>(a.mk1 + j * a.mld)[tid] : (W)0;
+    auto colj = [&](int64_t t) { return j0 + g + (int64_t)NG * t; };
+    auto load_masks = [&](int64_t j, unsigned& bk, unsigned& bk1) {
+      bk = 0u;
+      bk1 = 0u;
+      if (j < j1) {
+        bk = reinterpret_cast<const W*>(a.mk + j * a.mld)[tid];
+        if (a.mk1) bk1 = reinterpret_cast<const W*>(a.mk1 + j * a.mld)[tid];
+      }
     };
-    if (j0 + g < j1) load_masks(j0 + g);
-    for (int64_t j = j0 + g; j < j1; j += NG) {
-      const unsigned bk = nk, bk1 = nk1;
-      if (j + NG < j1) load_masks(j + NG);
-      double* __restrict__ Uc = a.U + j * (int64_t)R;
-      double x[VPT];
-      double s = 0.0;
-      const bool wave_any = __ballot(bk != 0u) != 0ull;
-      if (wave_any) {
-#pragma unroll
-        for (int k = 0; k < VPT; ++k) {
-          x[k] = 0.0;
-          if ((bk >> k) & 1u) {
-            double v = lds_v[k * NT + tid];
-            if ((bk1 >> k) & 1u) v += Uc[row(k)];
-            x[k] = v;
-            s += v;
-          }
+    // gathers of a column whose masks are known (fast path: <= 2 active slots)
+    auto gather = [&](int64_t j, Col& c) {
+      c.k0 = c.k1 = -1;
+      c.x0 = c.x1 = 0.0;
+      c.c0 = c.c1 = 0.0;
+      c.qa = (tid == 0 && j < j1) ? a.qacc[j] : 0.0;
+      unsigned b = c.bk;
+      if (b) {
+        const double* __restrict__ Uc = a.U + j * (int64_t)R;
+        const double* __restrict__ Cc = a.cacc + j * (int64_t)R;
+        c.k0 = __builtin_ctz(b);
+        const int r0 = row(c.k0);
+        c.x0 = Vm[r0];
+        c.c0 = Cc[r0];
+        if ((c.bk1 >> c.k0) & 1u) c.x0 += Uc[r0];
+        b &= b - 1;
+        if (b) {
+          c.k1 = __builtin_ctz(b);
+          const int r1 = row(c.k1);
+          c.x1 = Vm[r1];
+          c.c1 = Cc[r1];
+          if ((c.bk1 >> c.k1) & 1u) c.x1 += Uc[r1];
         }
+      }
+    };
+
+    // column t is gathered, column t+1 gathered ahead, masks of t+2 in flight
+    Col cur, nxt;
+    unsigned mb, mb1;
+    load_masks(colj(0), cur.bk, cur.bk1);
+    load_masks(colj(1), nxt.bk, nxt.bk1);
+    gather(colj(0), cur);
+    for (int64_t t = 0; colj(t) < j1; ++t) {
+      load_masks(colj(t + 2), mb, mb1);
+      gather(colj(t + 1), nxt);
+
+      const int64_t j = colj(t);
+      double* __restrict__ Uc = a.U + j * (int64_t)R;
+      const unsigned bk = cur.bk, bk1 = cur.bk1;
+      const bool wave_any = __ballot(bk != 0u) != 0ull;
+      const bool wave_slow = __ballot(__popc(bk) > 2) != 0ull;
+      double s = 0.0;
+      if (wave_slow) {
+        for (unsigned b = bk; b; b &= b - 1) {
+          const int r = row(__builtin_ctz(b));
+          double v = Vm[r];
+          if ((bk1 >> __builtin_ctz(b)) & 1u) v += Uc[r];
+          s += v;
+        }
+      } else {
+        s = cur.x0 + cur.x1;  // slot order, as the slow path
       }
       double n = (double)__popc(bk);
       // group sums of X over A and of |A| (fixed order)
@@ -144,22 +193,44 @@ adjoint_kernel(AdjArgs a) {
         n = uniform_d(nn);
         par ^= 1;
       }
-      if (n == 0.0) continue;  // tau = 0 or an empty projection: no active entry
-      const double mean = s / n;
-      if (tid == 0) a.qacc[j] += mean;
-      if (wave_any) {
-        double* __restrict__ Cc = a.cacc + j * (int64_t)R;
-#pragma unroll
-        for (int k = 0; k < VPT; ++k) {
-          if ((bk >> k) & 1u) {
-            const int r = row(k);
-            const double wb = x[k] - mean;
-            Uc[r] = wb;
-            Cc[r] += wb;
-            fix[k * NT + tid] += wb;
+      if (n != 0.0) {  // n = 0: tau = 0 or an empty projection, nothing active
+        const double mean = s / n;
+        if (tid == 0) a.qacc[j] = cur.qa + mean;
+        if (wave_any) {
+          double* __restrict__ Cc = a.cacc + j * (int64_t)R;
+          if (wave_slow) {
+            // X is re-read: this column's U is written only below, entry by entry
+            for (unsigned b = bk; b; b &= b - 1) {
+              const int k = __builtin_ctz(b);
+              const int r = row(k);
+              double v = Vm[r];
+              if ((bk1 >> k) & 1u) v += Uc[r];
+              const double wb = v - mean;
+              Uc[r] = wb;
+              Cc[r] += wb;
+              fix[k * NT + tid] += wb;
+            }
+          } else {
+            if (cur.k0 >= 0) {
+              const int r = row(cur.k0);
+              const double wb = cur.x0 - mean;
+              Uc[r] = wb;
+              Cc[r] = cur.c0 + wb;
+              fix[cur.k0 * NT + tid] += wb;
+            }
+            if (cur.k1 >= 0) {
+              const int r = row(cur.k1);
+              const double wb = cur.x1 - mean;
+              Uc[r] = wb;
+              Cc[r] = cur.c1 + wb;
+              fix[cur.k1 * NT + tid] += wb;
+            }
           }
         }
       }
+      cur = nxt;
+      nxt.bk = mb;
+      nxt.bk1 = mb1;
     }
 
     // the segment's row sums of wbar, groups in order

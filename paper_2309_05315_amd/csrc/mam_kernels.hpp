@@ -432,13 +432,17 @@ column_kernel(ColArgs<T> a) {
       else cc = j;
       return cost + cc * cost_ld;
     };
-    // raw theta and cost of the next PF steps, one buffer per step in flight
-    T rt[PF][KC][VPT], rc[PF][KC][VPT];
-    auto issue = [&](int64_t i, T (&bt)[KC][VPT], T (&bc)[KC][VPT]) {
+    // raw theta and cost of the next PF steps, one buffer per step in flight,
+    // with each column's weight q_s and stored threshold (the warm start)
+    T rt[PF][KC][VPT], rc[PF][KC][VPT], rq[PF][KC];
+    double rl[PF][KC];
+    auto issue = [&](int64_t i, T (&bt)[KC][VPT], T (&bc)[KC][VPT], T (&bq)[KC], double (&bl)[KC]) {
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         int64_t j;
         if (step_col(i, kc, j)) {
+          bq[kc] = qv[j];
+          bl[kc] = lamv[j];
           const T* __restrict__ thp = theta + j * ld;
           const T* __restrict__ cp = cost_col(j);
 #pragma unroll
@@ -460,7 +464,7 @@ column_kernel(ColArgs<T> a) {
     // the first raw loads overlap the set-up below
 #pragma unroll
     for (int b = 0; b < PF; ++b)
-      if (step_exists(b)) issue(b, rt[b], rc[b]);
+      if (step_exists(b)) issue(b, rt[b], rc[b], rq[b], rl[b]);
 
     // t^k of this problem from its d^2 partials: every wave sums them in a
     // fixed order (one partial per lane), so t is wave-uniform without LDS
@@ -490,7 +494,7 @@ column_kernel(ColArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < VPT; ++k) nb[k] = (T)(-lds_b[k * NT + tid]);
 
-    auto body = [&](int64_t step, T (&bt)[KC][VPT], T (&bc)[KC][VPT]) {
+    auto body = [&](int64_t step, T (&bt)[KC][VPT], T (&bc)[KC][VPT], T (&bq)[KC], double (&bl)[KC]) {
       // ---- reflect the step's columns: w = theta + 2b - c/rho (double) ----
       double w[KC][VPT];
       T told[DIAG ? KC : 1][DIAG ? VPT : 1];
@@ -507,7 +511,14 @@ column_kernel(ColArgs<T> a) {
           if constexpr (DIAG) told[kc][k] = bt[kc][k];
         }
       }
-      if (step_exists(step + PF)) issue(step + PF, bt, bc);
+      // this step's q_s and stored threshold, taken before the buffer is refilled
+      double qcol[KC], lcol[KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        qcol[kc] = (double)bq[kc];
+        lcol[kc] = bl[kc];
+      }
+      if (step_exists(step + PF)) issue(step + PF, bt, bc, bq, bl);
 
       // ---- thresholds ----
       double tau[KC], lam[KC];
@@ -515,10 +526,9 @@ column_kernel(ColArgs<T> a) {
       int mask[KC], nrounds[KC], nact[KC], nprev[KC];
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
-        const int64_t j = jj[kc];
-        tau[kc] = valid[kc] ? uniform_d((double)qv[j]) : 0.0;
+        tau[kc] = valid[kc] ? uniform_d(qcol[kc]) : 0.0;
         act[kc] = valid[kc] && tau[kc] > 0.0;
-        lam[kc] = (act[kc] && warm) ? uniform_d(lamv[j]) : __builtin_nan("");
+        lam[kc] = (act[kc] && warm) ? uniform_d(lcol[kc]) : __builtin_nan("");
         if (!act[kc]) lam[kc] = __builtin_huge_val();
         mask[kc] = 0;
         nrounds[kc] = 0;
@@ -668,10 +678,10 @@ column_kernel(ColArgs<T> a) {
     };
     // steps in turn, PF of them in flight: unrolled so every buffer index is static
     for (int64_t step = 0; step_exists(step); step += PF) {
-      body(step, rt[0], rc[0]);
+      body(step, rt[0], rc[0], rq[0], rl[0]);
       if constexpr (PF > 1) {
         if (!step_exists(step + 1)) break;
-        body(step + 1, rt[1], rc[1]);
+        body(step + 1, rt[1], rc[1], rq[1], rl[1]);
       }
     }
 

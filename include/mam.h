@@ -119,7 +119,9 @@ typedef struct mam_schedule {
   int32_t values_per_thread;  /* rows held per thread (out)                     */
   int32_t columns_in_flight;  /* columns a group advances together: 1, 2 or 4   */
   int32_t workgroups;         /* workgroups per iteration, each owning a
-                                 contiguous run of columns                       */
+                                 contiguous run of columns; 0 automatic: as
+                                 many as the device holds at once for the
+                                 kernel (known after mam_init; at most 1024)     */
   int32_t xcd_remap;          /* consecutive runs on one XCD (shared L2): 1 on,
                                  -1 off, 0 automatic (on when the columns are
                                  ordered cost-block-major)                        */
@@ -128,6 +130,13 @@ typedef struct mam_schedule {
                                  (columns sharing cost columns close in time;
                                  shared costs, or indexed costs sorted within
                                  each measure), 0 automatic                       */
+  int32_t streaming;          /* plans loaded and stored with the non-temporal
+                                 (streaming) cache policy, so they do not evict
+                                 the cost from the caches: 1 on, -1 off, 0
+                                 automatic (on when the group's plans exceed
+                                 256 MiB, i.e. do not stay in the 256 MB
+                                 Infinity Cache between iterations).  Applies to
+                                 the vector-load, one-column-in-flight kernels. */
 } mam_schedule;
 
 /* ABI version of this header (1). */

@@ -101,8 +101,9 @@ struct Prob {
 
 struct Group {
   int nt = 64, vpt = 1, ng = 4, kc = 1, vec = 1;
-  int nt_req = 0, kc_req = 0, nwg_req = 0, xcd_req = 0, order_req = 0;
-  int nwg = 1, wg_base = 0, xcd_remap = 0;
+  int nt_req = 0, kc_req = 0, nwg_req = 0, xcd_req = 0, order_req = 0, stream_req = 0;
+  int nwg = 1, wg_base = 0, xcd_remap = 0, stream = 0;
+  int nwg_auto = 0;  // workgroups the device holds at once (set at init), 0 = unknown
   int64_t Rmax = 0;
   bool blocked = false;
   std::vector<int> probs;
@@ -329,10 +330,12 @@ std::vector<Task> task_order(int dtype, const Prob& p, int order_req, bool* is_b
   return tasks;
 }
 
-int default_nwg(int64_t T, int ng, int req) {
+// Default workgroup count: as many as the device holds at once for this
+// kernel (one wave of workgroups, equal shares, no tail), at most 1024.
+int default_nwg(int64_t T, int ng, int req, int resident) {
   int nwg = req;
   if (nwg <= 0) {
-    const int64_t cap = 1024;
+    const int64_t cap = resident > 0 ? std::min(resident, 1024) : 1024;
     const int64_t cpw = std::max<int64_t>(1, (T + ng * cap - 1) / (ng * cap));
     nwg = (int)std::min<int64_t>(cap, (T + ng * cpw - 1) / (ng * cpw));
   }
@@ -354,7 +357,7 @@ void build_schedule(Plan* pl) {
   for (Group& g : pl->G) {
     int64_t Tg = 0;
     for (int pi : g.probs) Tg += pl->P[pi].T;
-    g.nwg = default_nwg(Tg, g.ng, g.nwg_req);
+    g.nwg = default_nwg(Tg, g.ng, g.nwg_req, g.nwg_auto);
     g.wg_base = wg_base;
     // concatenated task order of the group's problems
     std::vector<std::pair<int, Task>> tasks;
@@ -370,6 +373,11 @@ void build_schedule(Plan* pl) {
     cap_part += (size_t)g.nwg * (size_t)g.Rmax;
     g.blocked = all_blocked;
     g.xcd_remap = g.xcd_req > 0 ? 1 : (g.xcd_req < 0 ? 0 : (g.blocked ? 1 : 0));
+    // stream the plans past the caches when they cannot stay in the 256 MB
+    // Infinity Cache from one iteration to the next anyway
+    size_t plan_bytes = 0;
+    for (int pi : g.probs) plan_bytes += (size_t)pl->P[pi].ld * (size_t)pl->P[pi].T * elem_bytes(pl->dtype);
+    g.stream = g.stream_req > 0 ? 1 : (g.stream_req < 0 ? 0 : (plan_bytes > ((size_t)256 << 20) ? 1 : 0));
     size_t ti = 0;
     int64_t tpos = 0;
     for (int w = 0; w < g.nwg; ++w) {
@@ -501,6 +509,8 @@ mam_status make_plan(Plan* pl, const mam_desc* descs, int n) {
 mam_status set_group_schedule(Plan* pl, int gi, const mam_schedule* s) {
   if (pl->ws) return fail(MAM_ESTATE, "schedule must be set before the workspace");
   if (s->order < 0 || s->order > 2) return fail(MAM_EINVAL, "order must be 0, 1 or 2 (got %d)", s->order);
+  if (s->streaming < -1 || s->streaming > 1)
+    return fail(MAM_EINVAL, "streaming must be -1, 0 or 1 (got %d)", s->streaming);
   Group& g = pl->G[gi];
   const Group saved = g;
   g.nt_req = s->threads_per_column;
@@ -513,6 +523,7 @@ mam_status set_group_schedule(Plan* pl, int gi, const mam_schedule* s) {
   g.nwg_req = s->workgroups;
   g.xcd_req = s->xcd_remap;
   g.order_req = s->order;
+  g.stream_req = s->streaming;
   build_schedule(pl);
   build_layout(pl);
   return MAM_OK;
@@ -527,6 +538,7 @@ void get_group_schedule(const Plan* pl, int gi, mam_schedule* s) {
   s->xcd_remap = g.xcd_remap;
   s->vector_width = g.vec;
   s->order = g.blocked ? 2 : 1;
+  s->streaming = g.stream ? 1 : -1;
 }
 
 mam_status set_workspace(Plan* pl, void* dev, size_t bytes) {
@@ -668,7 +680,7 @@ mam_status launch_columns(Plan* pl, hipStream_t st, int diag, uint8_t* rec, int6
     a.nwg = g.nwg;
     a.xcd_remap = g.xcd_remap;
     const int kc = g.vec == 1 ? 1 : g.kc;
-    mam::ColFn<T> fn = mam::pick_column<T>(g.nt, g.vpt, g.vec, kc, diag);
+    mam::ColFn<T> fn = mam::pick_column<T>(g.nt, g.vpt, g.vec, kc, diag, g.stream);
     if (!fn) return fail(MAM_EUNSUPPORTED, "no column kernel for nt=%d vpt=%d vec=%d kc=%d", g.nt, g.vpt, g.vec, kc);
     const int wgsize = g.nt == 64 ? 256 : g.nt;
     const size_t shmem = (size_t)g.vpt * g.nt * 8 * (1 + g.ng);
@@ -755,6 +767,33 @@ hipEvent_t next_event(Plan* pl) {
 // ---------------------------------------------------------------------------
 // plan operations shared by single problems and batches
 // ---------------------------------------------------------------------------
+// Workgroups of each group's column kernel that the current device holds at
+// once (occupancy of that instance times the compute units).
+template <typename T>
+mam_status resident_workgroups(Plan* pl, bool* changed) {
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  for (Group& g : pl->G) {
+    const int kc = g.vec == 1 ? 1 : g.kc;
+    mam::ColFn<T> fn = mam::pick_column<T>(g.nt, g.vpt, g.vec, kc, 0, g.stream);
+    if (!fn) continue;
+    const int wgsize = g.nt == 64 ? 256 : g.nt;
+    const size_t shmem = (size_t)g.vpt * g.nt * 8 * (1 + g.ng);
+    if (shmem > 65536)
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)shmem));
+    int blocks = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(fn), wgsize, shmem));
+    const int res = std::max(1, blocks) * std::max(1, cus);
+    if (res != g.nwg_auto) {
+      g.nwg_auto = res;
+      *changed = true;
+    }
+  }
+  return MAM_OK;
+}
+
 mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
   if (!pl->ws) return fail(MAM_ESTATE, "no workspace");
   for (size_t i = 0; i < pl->P.size(); ++i)
@@ -771,6 +810,7 @@ mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
         return fail(MAM_ENONFINITE, "cost_col_index[%lld] = %d is out of range", (long long)j, p.idx[j]);
     rebuilt = true;
   }
+  TRY(pl->dtype == MAM_F32 ? resident_workgroups<float>(pl, &rebuilt) : resident_workgroups<double>(pl, &rebuilt));
   if (rebuilt) build_schedule(pl);
   if (pl->gexec) {
     hipGraphExecDestroy(pl->gexec);

@@ -16,17 +16,17 @@ using ColFn = void (*)(ColArgs<T>);
 // 4-16; columns in flight 1, 2, 4 for vector loads without diagnostics,
 // otherwise 1.
 template <typename T, int KC>
-ColFn<T> pick_column_kc(int nt, int vpt, int vec);
+ColFn<T> pick_column_kc(int nt, int vpt, int vec, int stream);
 template <typename T>
 ColFn<T> pick_column_diag(int nt, int vpt, int vec);
 
 template <typename T>
-inline ColFn<T> pick_column(int nt, int vpt, int vec, int kc, int diag) {
+inline ColFn<T> pick_column(int nt, int vpt, int vec, int kc, int diag, int stream) {
   if (diag) return pick_column_diag<T>(nt, vpt, vec);
   switch (kc) {
-    case 1: return pick_column_kc<T, 1>(nt, vpt, vec);
-    case 2: return pick_column_kc<T, 2>(nt, vpt, vec);
-    case 4: return pick_column_kc<T, 4>(nt, vpt, vec);
+    case 1: return pick_column_kc<T, 1>(nt, vpt, vec, stream);
+    case 2: return pick_column_kc<T, 2>(nt, vpt, vec, stream);
+    case 4: return pick_column_kc<T, 4>(nt, vpt, vec, stream);
     default: return nullptr;
   }
 }
@@ -36,12 +36,12 @@ struct AdjArgs;
 using AdjFn = void (*)(AdjArgs);
 AdjFn pick_adjoint(int nt, int vpt);
 
-extern template ColFn<float> pick_column_kc<float, 1>(int, int, int);
-extern template ColFn<float> pick_column_kc<float, 2>(int, int, int);
-extern template ColFn<float> pick_column_kc<float, 4>(int, int, int);
-extern template ColFn<double> pick_column_kc<double, 1>(int, int, int);
-extern template ColFn<double> pick_column_kc<double, 2>(int, int, int);
-extern template ColFn<double> pick_column_kc<double, 4>(int, int, int);
+extern template ColFn<float> pick_column_kc<float, 1>(int, int, int, int);
+extern template ColFn<float> pick_column_kc<float, 2>(int, int, int, int);
+extern template ColFn<float> pick_column_kc<float, 4>(int, int, int, int);
+extern template ColFn<double> pick_column_kc<double, 1>(int, int, int, int);
+extern template ColFn<double> pick_column_kc<double, 2>(int, int, int, int);
+extern template ColFn<double> pick_column_kc<double, 4>(int, int, int, int);
 extern template ColFn<float> pick_column_diag<float>(int, int, int);
 extern template ColFn<double> pick_column_diag<double>(int, int, int);
 

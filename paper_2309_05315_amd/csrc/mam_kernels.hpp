@@ -44,6 +44,37 @@ template <typename T> struct VecOf;
 template <> struct VecOf<float>  { static constexpr int N = 4; using type = float4; };
 template <> struct VecOf<double> { static constexpr int N = 2; using type = double2; };
 
+// Non-temporal forms for the plans: the stream of theta passes through the
+// caches without displacing the cost columns that are reused.
+typedef float f4nt __attribute__((ext_vector_type(4)));
+typedef double d2nt __attribute__((ext_vector_type(2)));
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec_nt(const T* __restrict__ src, T (&v)[VEC]) {
+  if constexpr (VEC == 1) {
+    v[0] = __builtin_nontemporal_load(src);
+  } else if constexpr (sizeof(T) == 4) {
+    const f4nt x = __builtin_nontemporal_load(reinterpret_cast<const f4nt*>(src));
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else {
+    const d2nt x = __builtin_nontemporal_load(reinterpret_cast<const d2nt*>(src));
+    v[0] = x.x; v[1] = x.y;
+  }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec_nt(T* __restrict__ dst, const T (&v)[VEC]) {
+  if constexpr (VEC == 1) {
+    __builtin_nontemporal_store(v[0], dst);
+  } else if constexpr (sizeof(T) == 4) {
+    f4nt x = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(x, reinterpret_cast<f4nt*>(dst));
+  } else {
+    d2nt x = {v[0], v[1]};
+    __builtin_nontemporal_store(x, reinterpret_cast<d2nt*>(dst));
+  }
+}
+
 template <typename T, int VEC>
 __device__ __forceinline__ void load_vec(const T* __restrict__ src, T (&v)[VEC]) {
   if constexpr (VEC == 1) {
@@ -355,7 +386,7 @@ struct Rounds {
 //
 // Dynamic LDS: VPT*NT doubles of b^(m) (each thread reads only its own
 // slots), then NG*VPT*NT doubles of row-sum patches, one block per group.
-template <typename T, int NT, int VPT, int VEC, int KC, bool DIAG>
+template <typename T, int NT, int VPT, int VEC, int KC, bool DIAG, bool STREAM = false>
 __global__ void __launch_bounds__(GroupShape<NT>::WG)
 column_kernel(ColArgs<T> a) {
   constexpr int WG = GroupShape<NT>::WG;
@@ -450,7 +481,8 @@ column_kernel(ColArgs<T> a) {
             // rows past R read the column's first vector (in bounds) and are masked later
             const int r0 = (c * NT + tid) * VEC < R ? (c * NT + tid) * VEC : 0;
             T tv[VEC], cv[VEC];
-            load_vec<T, VEC>(thp + r0, tv);
+            if constexpr (STREAM) load_vec_nt<T, VEC>(thp + r0, tv);
+            else load_vec<T, VEC>(thp + r0, tv);
             load_vec<T, VEC>(cp + r0, cv);
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
@@ -642,7 +674,8 @@ column_kernel(ColArgs<T> a) {
               }
             }
             if (r0 + VEC <= R) {
-              store_vec<T, VEC>(thp + r0, out);
+              if constexpr (STREAM) store_vec_nt<T, VEC>(thp + r0, out);
+              else store_vec<T, VEC>(thp + r0, out);
             } else {
 #pragma unroll
               for (int v = 0; v < VEC; ++v)

@@ -100,6 +100,18 @@ def test_schedule_override_validation():
     L.mam_get_schedule(h, ctypes.byref(sc))
     assert (sc.threads_per_column, sc.values_per_thread, sc.columns_in_flight, sc.workgroups,
             sc.xcd_remap) == (1024, 4, 4, 37, 0)
+    assert sc.streaming == -1                       # 100 columns of 4096 doubles stay cached
+    bad_stream = mam.Schedule(streaming=2)
+    assert L.mam_set_schedule(h, ctypes.byref(bad_stream)) == -1
+    on = mam.Schedule(streaming=1)
+    assert L.mam_set_schedule(h, ctypes.byref(on)) == 0
+    L.mam_get_schedule(h, ctypes.byref(sc))
+    assert sc.streaming == 1
+    L.mam_destroy(h)
+    # plans of 4096 x 10,000 doubles (328 MB) are streamed by default
+    rc, h = create(R=4096, S=[5000, 5000])
+    L.mam_get_schedule(h, ctypes.byref(sc))
+    assert sc.streaming == 1
     L.mam_destroy(h)
 
 

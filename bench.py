@@ -40,10 +40,13 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the column kernel's device sources (its template, instances and
+    dispatch); the launch schedule is compared separately."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2309_05315_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
+        if name in ("mam_kernels.hpp", "mam_instances.hpp", "mam_dispatch.hpp") or \
+                (name.startswith(("col_f32", "col_f64")) and name.endswith(".hip")):
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(name.encode())
                 h.update(f.read())
@@ -277,7 +280,8 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("kernel_source_hash") == kernel_source_hash():
+        # counters apply only to the same kernel source launched the same way
+        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("schedule") == sched:
             traffic = tr.get("bytes_per_launch")
 
     if args.copy_probe:

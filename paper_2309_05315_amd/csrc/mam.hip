@@ -126,6 +126,13 @@ struct Adjoint {
   size_t ckpt_bytes = 0;         // one checkpoint of theta
   size_t o_mask = 0, o_ckpt = 0, o_U = 0, o_cacc = 0, o_qacc = 0, o_V = 0, o_wold = 0, o_wnew = 0;
   size_t o_cptr = 0, o_clist = 0, o_aux = 0, total = 0;
+  // the reverse kernel's own segments (more workgroups than the forward's:
+  // its columns are latency-bound chains)
+  static constexpr int kMaxWg = 2048;
+  int nwg = 0;
+  size_t nseg_cap = 0;
+  size_t o_seg_m = 0, o_seg_j0 = 0, o_seg_j1 = 0, o_seg_poff = 0, o_wg_seg = 0, o_mseg = 0, o_seg_idx = 0,
+         o_partial = 0;
 };
 
 struct Plan {
@@ -975,6 +982,16 @@ mam_status adjoint_layout(const Plan* pl, int64_t K, int64_t C, Adjoint* A) {
   A->o_cptr = take((size_t)(p.cost_ncols + 1) * 8);
   A->o_clist = take(T * 4);
   A->o_aux = take(sizeof(mam::ProbAux));
+  // reverse schedule: at most kMaxWg workgroups, each run split at measure boundaries
+  A->nseg_cap = (size_t)Adjoint::kMaxWg + (size_t)M;
+  A->o_seg_m = take(A->nseg_cap * 4);
+  A->o_seg_j0 = take(A->nseg_cap * 8);
+  A->o_seg_j1 = take(A->nseg_cap * 8);
+  A->o_seg_poff = take(A->nseg_cap * 8);
+  A->o_wg_seg = take(((size_t)Adjoint::kMaxWg + 1) * 4);
+  A->o_mseg = take((M + 1) * 4);
+  A->o_seg_idx = take(A->nseg_cap * 4);
+  A->o_partial = take(A->nseg_cap * R * 8);
   A->total = o;
   return MAM_OK;
 }
@@ -1007,6 +1024,75 @@ mam_status record_range(Plan* pl, int64_t k0, int64_t k1, int64_t rec_from, bool
     }
     TRY(one_iteration(pl, st, 0, k >= rec_from ? mask_slot(pl, k) : nullptr, A.mld));
   }
+  return MAM_OK;
+}
+
+// Segments of the reverse kernel: nwg workgroups take equal runs of the
+// measure-major column order, split at measure boundaries; each measure's
+// segments in schedule order for the marginal kernel.  Uploaded into the
+// adjoint workspace (synchronous).
+mam_status upload_adjoint_tables(Plan* pl, int nwg, hipStream_t st) {
+  Adjoint& A = pl->adj;
+  const Prob& p = pl->P[0];
+  std::vector<int32_t> seg_m, wg_seg, mseg(p.M + 1, 0), seg_idx;
+  std::vector<int64_t> seg_j0, seg_j1, seg_poff;
+  for (int w = 0; w < nwg; ++w) {
+    wg_seg.push_back((int32_t)seg_m.size());
+    int64_t lo = p.T * w / nwg, hi = p.T * (w + 1) / nwg;
+    while (lo < hi) {
+      const int64_t m = std::upper_bound(p.col_off.begin(), p.col_off.end(), lo) - p.col_off.begin() - 1;
+      const int64_t e = std::min(hi, p.col_off[m + 1]);
+      seg_m.push_back((int32_t)m);
+      seg_j0.push_back(lo);
+      seg_j1.push_back(e);
+      seg_poff.push_back((int64_t)(seg_m.size() - 1) * p.R);
+      lo = e;
+    }
+  }
+  wg_seg.push_back((int32_t)seg_m.size());
+  if (seg_m.size() > A.nseg_cap) return fail(MAM_EHIP, "reverse schedule exceeds its capacity");
+  for (size_t k = 0; k < seg_m.size(); ++k) ++mseg[seg_m[k] + 1];
+  for (int64_t m = 0; m < p.M; ++m) mseg[m + 1] += mseg[m];
+  seg_idx.assign(seg_m.size(), 0);
+  {
+    std::vector<int32_t> fill(mseg.begin(), mseg.end() - 1);
+    for (size_t k = 0; k < seg_m.size(); ++k) seg_idx[fill[seg_m[k]]++] = (int32_t)k;
+  }
+  auto put = [&](size_t off, const void* src, size_t n) -> mam_status {
+    if (n) HIP_TRY(hipMemcpyAsync(A.ws + off, src, n, hipMemcpyHostToDevice, st));
+    return MAM_OK;
+  };
+  TRY(put(A.o_seg_m, seg_m.data(), seg_m.size() * 4));
+  TRY(put(A.o_seg_j0, seg_j0.data(), seg_j0.size() * 8));
+  TRY(put(A.o_seg_j1, seg_j1.data(), seg_j1.size() * 8));
+  TRY(put(A.o_seg_poff, seg_poff.data(), seg_poff.size() * 8));
+  TRY(put(A.o_wg_seg, wg_seg.data(), wg_seg.size() * 4));
+  TRY(put(A.o_mseg, mseg.data(), mseg.size() * 4));
+  TRY(put(A.o_seg_idx, seg_idx.data(), seg_idx.size() * 4));
+  HIP_TRY(hipStreamSynchronize(st));
+  A.nwg = nwg;
+  return MAM_OK;
+}
+
+// Workgroups of the reverse kernel the device holds at once (at most kMaxWg).
+mam_status adjoint_resident(const Plan* pl, int* out) {
+  const Group& g = pl->G[0];
+  mam::AdjFn fn = mam::pick_adjoint(g.nt, g.vpt);
+  if (!fn) return fail(MAM_EUNSUPPORTED, "no reverse column kernel for nt=%d vpt=%d", g.nt, g.vpt);
+  int dev = 0, cus = 0, blocks = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const size_t shmem = (size_t)g.vpt * g.nt * 8 * g.ng;
+  if (shmem > 65536)
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shmem));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(fn),
+                                                       g.nt == 64 ? 256 : g.nt, shmem));
+  const int64_t cols_per_group = g.ng;
+  int64_t n = (int64_t)std::max(1, blocks) * std::max(1, cus);
+  n = std::min<int64_t>(n, Adjoint::kMaxWg);
+  n = std::min<int64_t>(n, std::max<int64_t>(1, pl->P[0].T / cols_per_group));
+  *out = (int)std::max<int64_t>(1, n);
   return MAM_OK;
 }
 
@@ -1047,6 +1133,9 @@ mam_status plan_record(Plan* pl, int64_t K, int64_t C, void* ws, size_t bytes, h
   HIP_TRY(hipStreamSynchronize(st));
   pl->adj = A;
   pl->adj.valid = false;
+  int nwg_adj = 1;
+  TRY(adjoint_resident(pl, &nwg_adj));
+  TRY(upload_adjoint_tables(pl, nwg_adj, st));
   TRY(record_range(pl, 0, K, (A.nw - 1) * A.C, true, st));
   pl->iters_done += K;
   pl->adj.resident = A.nw - 1;
@@ -1099,12 +1188,12 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
     HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)shmem));
   mam::AdjArgs a;
-  a.seg_m = at<int32_t>(pl, L.seg_m);
-  a.seg_j0 = at<int64_t>(pl, L.seg_j0);
-  a.seg_j1 = at<int64_t>(pl, L.seg_j1);
-  a.seg_poff = at<int64_t>(pl, L.seg_poff);
-  a.wg_seg = at<int32_t>(pl, L.wg_seg);
-  a.partial = at<double>(pl, L.partial);
+  a.seg_m = reinterpret_cast<const int32_t*>(A.ws + A.o_seg_m);
+  a.seg_j0 = reinterpret_cast<const int64_t*>(A.ws + A.o_seg_j0);
+  a.seg_j1 = reinterpret_cast<const int64_t*>(A.ws + A.o_seg_j1);
+  a.seg_poff = reinterpret_cast<const int64_t*>(A.ws + A.o_seg_poff);
+  a.wg_seg = reinterpret_cast<const int32_t*>(A.ws + A.o_wg_seg);
+  a.partial = reinterpret_cast<double*>(A.ws + A.o_partial);
   a.mld = A.mld;
   a.U = reinterpret_cast<double*>(A.ws + A.o_U);
   a.cacc = reinterpret_cast<double*>(A.ws + A.o_cacc);
@@ -1112,8 +1201,8 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
   a.V = V;
   a.R = (int32_t)p.R;
   a.vec_shift = g.vec == 4 ? 2 : (g.vec == 2 ? 1 : 0);
-  a.nwg = g.nwg;
-  a.xcd_remap = g.xcd_remap;
+  a.nwg = A.nwg;
+  a.xcd_remap = 0;
   const int wgsize = g.nt == 64 ? 256 : g.nt;
 
   const bool timing = pl->timing;
@@ -1140,13 +1229,15 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
         if (!e0 || !e1) return fail(MAM_EHIP, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(e0, st));
       }
-      hipLaunchKernelGGL(fn, dim3(g.nwg), dim3(wgsize), shmem, st, a);
+      hipLaunchKernelGGL(fn, dim3(A.nwg), dim3(wgsize), shmem, st, a);
       LAUNCH_CHECK("adjoint_kernel");
       if (timing) HIP_TRY(hipEventRecord(e1, st));
       hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
                          at<mam::MargTask>(pl, L.mtasks), reinterpret_cast<const mam::ProbAux*>(A.ws + A.o_aux),
-                         at<int32_t>(pl, L.mseg), at<int32_t>(pl, L.seg_idx), at<int64_t>(pl, L.seg_poff),
-                         at<double>(pl, L.partial), 0);
+                         reinterpret_cast<const int32_t*>(A.ws + A.o_mseg),
+                         reinterpret_cast<const int32_t*>(A.ws + A.o_seg_idx),
+                         reinterpret_cast<const int64_t*>(A.ws + A.o_seg_poff),
+                         reinterpret_cast<const double*>(A.ws + A.o_partial), 0);
       LAUNCH_CHECK("marginal_kernel");
       hipLaunchKernelGGL(mam::adjoint_average_kernel, dim3((unsigned)((p.R + 255) / 256)), dim3(256), 0, st, wnew, wold,
                          V, at<double>(pl, p.o_Sd), at<double>(pl, p.o_aw), (int)p.R, (int)p.M);

@@ -268,8 +268,11 @@ mam_status mam_graph(mam_problem* p, int64_t iters_per_launch);
  * Many independent problems (same dtype; any R <= 8192, M, S^m, cost mode,
  * rho, gamma) advanced together: each iteration is one column-kernel launch
  * per shape group (problems whose columns need the same threads per column
- * and values per thread), then one marginal and one averaging launch for
- * all problems; mam_batch_graph captures whole iterations as one graph.
+ * and values per thread; inside a captured graph the groups run
+ * concurrently on streams of the library's own, default priority, forked
+ * from and joined back into the capturing stream), then one marginal and
+ * one averaging launch for all
+ * problems; mam_batch_graph captures whole iterations as one graph.
  * Diagnostics (MAM_FLAG_DIAG) are not computed for batches. */
 typedef struct mam_batch mam_batch;
 

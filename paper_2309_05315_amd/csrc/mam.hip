@@ -165,9 +165,18 @@ struct Plan {
   bool timing = false;
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
+  // several shape groups run concurrently: one stream per group (default
+  // priority), forked from and joined back into the caller's stream
+  std::vector<hipStream_t> gstream;
+  std::vector<hipEvent_t> gjoin;
+  hipEvent_t gfork = nullptr;
+  bool capturing = false;  // forks are worth their event calls only inside a graph
 
   ~Plan() {
     for (hipEvent_t e : ev) hipEventDestroy(e);
+    for (hipEvent_t e : gjoin) hipEventDestroy(e);
+    if (gfork) hipEventDestroy(gfork);
+    for (hipStream_t s : gstream) hipStreamDestroy(s);
     if (gexec) hipGraphExecDestroy(gexec);
     if (capture_stream) hipStreamDestroy(capture_stream);
   }
@@ -668,10 +677,31 @@ mam_status upload_tables(Plan* pl, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
+mam_status group_streams(Plan* pl) {
+  while (pl->gstream.size() < pl->G.size()) {
+    hipStream_t s = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    pl->gstream.push_back(s);
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    pl->gjoin.push_back(e);
+  }
+  if (!pl->gfork) HIP_TRY(hipEventCreateWithFlags(&pl->gfork, hipEventDisableTiming));
+  return MAM_OK;
+}
+
 template <typename T>
 mam_status launch_columns(Plan* pl, hipStream_t st, int diag, uint8_t* rec, int64_t rec_ld) {
   const Layout& L = pl->lay;
-  for (const Group& g : pl->G) {
+  const bool fork = pl->G.size() > 1 && pl->capturing;
+  if (fork) {
+    TRY(group_streams(pl));
+    HIP_TRY(hipEventRecord(pl->gfork, st));
+  }
+  for (size_t gi = 0; gi < pl->G.size(); ++gi) {
+    const Group& g = pl->G[gi];
+    hipStream_t gs = fork ? pl->gstream[gi] : st;
+    if (fork) HIP_TRY(hipStreamWaitEvent(gs, pl->gfork, 0));
     mam::ColArgs<T> a;
     a.probs = at<mam::ProbDev<T>>(pl, L.probdev);
     a.seg_p = at<int32_t>(pl, L.seg_p);
@@ -696,9 +726,12 @@ mam_status launch_columns(Plan* pl, hipStream_t st, int diag, uint8_t* rec, int6
       HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)shmem));
     }
-    hipLaunchKernelGGL(fn, dim3(g.nwg), dim3(wgsize), shmem, st, a);
+    hipLaunchKernelGGL(fn, dim3(g.nwg), dim3(wgsize), shmem, gs, a);
     LAUNCH_CHECK("column_kernel");
+    if (fork) HIP_TRY(hipEventRecord(pl->gjoin[gi], gs));
   }
+  if (fork)
+    for (size_t gi = 0; gi < pl->G.size(); ++gi) HIP_TRY(hipStreamWaitEvent(st, pl->gjoin[gi], 0));
   return MAM_OK;
 }
 
@@ -874,7 +907,9 @@ mam_status capture_graph(Plan* pl) {
   if (!pl->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(pl->capture_stream, hipStreamCaptureModeThreadLocal));
   mam_status s = MAM_OK;
+  pl->capturing = true;
   for (int64_t k = 0; k < pl->graph_iters && s == MAM_OK; ++k) s = one_iteration(pl, pl->capture_stream, 0);
+  pl->capturing = false;
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(pl->capture_stream, &graph);
   if (s != MAM_OK) {

@@ -247,3 +247,20 @@ def test_reverse_mode_errors():
     s.backward(torch.ones(p.R, dtype=torch.float64))
     with pytest.raises(mam.MAMError, match="MAM_ESTATE"):
         s.iterate(1)   # the reverse sweep leaves an intermediate iterate
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gradients_large_rho(dtype):
+    """Large active sets: most threads hold more than two active entries, so
+    the reverse kernel's general path does the work."""
+    p = inputs.balanced_plain(K=10, M=3, dtype=dtype)
+    p.rho = float(p.R * np.mean(p.S))
+    iters = 15
+    tgt = np.random.default_rng(6).dirichlet(np.ones(p.R))
+    cost, q = blocks(p)
+    _, _, gq_o, gc_o = G.loss_and_grads(cost, q, p.rho, iters, tgt)
+    _, gq, gc, _ = gpu_grads(p, iters, target=tgt)
+    eq, ec = rel(gq, np.concatenate(gq_o)), rel(gc, fold_cost(p, gc_o))
+    say(f"large rho {dtype}: rel L1 q {eq:.2e} cost {ec:.2e}")
+    tol = 1e-9 if dtype == "f64" else 1e-4
+    assert eq <= tol and ec <= tol

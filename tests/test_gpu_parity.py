@@ -251,3 +251,19 @@ def test_columns_in_flight_and_warm_start(nt, kc):
     cost, q = blocks(p)
     ora = O.mam(cost, q, p.rho, p.gamma, 25)
     assert rel(got["p_bar"], ora["p_bar"]) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_large_rho_regime(dtype):
+    """rho = R * mean(S): c/rho is tiny, most entries of a column are active
+    and the threshold search takes many rounds (the opposite regime of the
+    benchmark workloads, where a column has one or two active entries)."""
+    p = inputs.balanced_plain(K=12, M=3, dtype=dtype)
+    p.rho = float(p.R * np.mean(p.S))
+    g, _ = check(p, 25)
+    s = mam.solver_for(p, diag=True)
+    s.init()
+    s.iterate(25)
+    d = s.diagnostics()
+    say(f"  rho={p.rho:.0f}: rounds/column {d['rounds_per_column']:.2f}, active/column {d['active_per_column']:.1f}")
+    assert d["active_per_column"] > 10

@@ -101,27 +101,6 @@ __device__ __forceinline__ void store_vec(T* __restrict__ dst, const T (&v)[VEC]
   }
 }
 
-// Row-sum accumulator: plain double for FP64 plans; compensated (Kahan)
-// float pairs for FP32 plans, finished in double.
-template <typename T> struct RowAcc;
-template <> struct RowAcc<double> {
-  double s;
-  __device__ __forceinline__ void zero() { s = 0.0; }
-  __device__ __forceinline__ void add(double x) { s += x; }
-  __device__ __forceinline__ double value() const { return s; }
-};
-template <> struct RowAcc<float> {
-  float s, c;  // running sum and the negated low part lost so far
-  __device__ __forceinline__ void zero() { s = 0.0f; c = 0.0f; }
-  __device__ __forceinline__ void add(float x) {
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-  }
-  __device__ __forceinline__ double value() const { return (double)s - (double)c; }
-};
-
 // ---------------------------------------------------------------------------
 // Wave reductions with DPP (data-parallel primitives): butterfly steps inside
 // rows of 16 lanes, then row broadcasts; the total lands in lane 63 and is
@@ -467,7 +446,22 @@ column_kernel(ColArgs<T> a) {
     // with each column's weight q_s and stored threshold (the warm start)
     T rt[PF][KC][VPT], rc[PF][KC][VPT], rq[PF][KC];
     double rl[PF][KC];
+    // an indexed cost's column numbers are read one issued step ahead, so
+    // forming a cost address never waits on memory
+    int32_t cnext[KC];
+    auto load_index = [&](int64_t i) {
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        int64_t j;
+        cnext[kc] = (cost_mode == MAM_COST_INDEXED && step_col(i, kc, j)) ? cidx[j] : 0;
+      }
+    };
+    if (cost_mode == MAM_COST_INDEXED) load_index(0);
     auto issue = [&](int64_t i, T (&bt)[KC][VPT], T (&bc)[KC][VPT], T (&bq)[KC], double (&bl)[KC]) {
+      int32_t cthis[KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) cthis[kc] = cnext[kc];
+      if (cost_mode == MAM_COST_INDEXED) load_index(i + 1);
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         int64_t j;
@@ -475,7 +469,11 @@ column_kernel(ColArgs<T> a) {
           bq[kc] = qv[j];
           bl[kc] = lamv[j];
           const T* __restrict__ thp = theta + j * ld;
-          const T* __restrict__ cp = cost_col(j);
+          int64_t cc;
+          if (cost_mode == MAM_COST_INDEXED) cc = uniform_i(cthis[kc]);
+          else if (cost_mode == MAM_COST_SHARED) cc = j - off_m;
+          else cc = j;
+          const T* __restrict__ cp = cost + cc * cost_ld;
 #pragma unroll
           for (int c = 0; c < NCH; ++c) {
             // rows past R read the column's first vector (in bounds) and are masked later

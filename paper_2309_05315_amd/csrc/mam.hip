@@ -142,6 +142,7 @@ struct Plan {
   std::vector<Group> G;
   // schedule tables
   std::vector<int32_t> seg_p, seg_m, wg_seg, mseg, seg_idx;
+  std::vector<int64_t> mpoff;  // partial offsets of every measure's segments, in schedule order
   std::vector<int64_t> seg_j0, seg_j1, seg_poff;
   std::vector<mam::MargTask> mtasks;
   std::vector<mam::AvgTask> atasks;
@@ -436,6 +437,8 @@ void build_schedule(Plan* pl) {
     for (size_t k = 0; k < pl->seg_p.size(); ++k)
       pl->seg_idx[fill[pl->P[pl->seg_p[k]].mbase + pl->seg_m[k]]++] = (int32_t)k;
   }
+  pl->mpoff.resize(pl->seg_idx.size());
+  for (size_t i = 0; i < pl->seg_idx.size(); ++i) pl->mpoff[i] = pl->seg_poff[pl->seg_idx[i]];
   pl->mtasks.clear();
   pl->atasks.clear();
   for (size_t pi = 0; pi < pl->P.size(); ++pi) {
@@ -467,7 +470,7 @@ void build_layout(Plan* pl) {
   L.seg_j0 = take(ns * 8);
   L.seg_j1 = take(ns * 8);
   L.seg_poff = take(ns * 8);
-  L.seg_idx = take(ns * 4);
+  L.seg_idx = take(ns * 8);  // holds mpoff
   L.wg_seg = take((size_t)(pl->nwg_total + 1) * 4);
   size_t nmeas = 0;
   for (const Prob& p : pl->P) nmeas += (size_t)p.M;
@@ -644,7 +647,7 @@ mam_status upload_tables(Plan* pl, hipStream_t st) {
   TRY(put(L.seg_j0, pl->seg_j0.data(), pl->seg_j0.size() * 8));
   TRY(put(L.seg_j1, pl->seg_j1.data(), pl->seg_j1.size() * 8));
   TRY(put(L.seg_poff, pl->seg_poff.data(), pl->seg_poff.size() * 8));
-  TRY(put(L.seg_idx, pl->seg_idx.data(), pl->seg_idx.size() * 4));
+  TRY(put(L.seg_idx, pl->mpoff.data(), pl->mpoff.size() * 8));
   TRY(put(L.wg_seg, pl->wg_seg.data(), pl->wg_seg.size() * 4));
   TRY(put(L.mseg, pl->mseg.data(), pl->mseg.size() * 4));
   TRY(put(L.mtasks, pl->mtasks.data(), pl->mtasks.size() * sizeof(mam::MargTask)));
@@ -739,8 +742,7 @@ mam_status launch_marginals(Plan* pl, hipStream_t st, int save_prev) {
   const Layout& L = pl->lay;
   hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
                      at<mam::MargTask>(pl, L.mtasks), at<mam::ProbAux>(pl, L.probaux), at<int32_t>(pl, L.mseg),
-                     at<int32_t>(pl, L.seg_idx), at<int64_t>(pl, L.seg_poff), at<double>(pl, L.partial),
-                     save_prev);
+                     at<int64_t>(pl, L.seg_idx), at<double>(pl, L.partial), save_prev);
   LAUNCH_CHECK("marginal_kernel");
   hipLaunchKernelGGL(mam::average_kernel, dim3((unsigned)pl->atasks.size()), dim3(256), 0, st,
                      at<mam::AvgTask>(pl, L.atasks), at<mam::ProbAux>(pl, L.probaux), save_prev);
@@ -1025,7 +1027,7 @@ mam_status adjoint_layout(const Plan* pl, int64_t K, int64_t C, Adjoint* A) {
   A->o_seg_poff = take(A->nseg_cap * 8);
   A->o_wg_seg = take(((size_t)Adjoint::kMaxWg + 1) * 4);
   A->o_mseg = take((M + 1) * 4);
-  A->o_seg_idx = take(A->nseg_cap * 4);
+  A->o_seg_idx = take(A->nseg_cap * 8);  // holds the partial offsets in measure order
   A->o_partial = take(A->nseg_cap * R * 8);
   A->total = o;
   return MAM_OK;
@@ -1093,6 +1095,8 @@ mam_status upload_adjoint_tables(Plan* pl, int nwg, hipStream_t st) {
     std::vector<int32_t> fill(mseg.begin(), mseg.end() - 1);
     for (size_t k = 0; k < seg_m.size(); ++k) seg_idx[fill[seg_m[k]]++] = (int32_t)k;
   }
+  std::vector<int64_t> mpoff(seg_idx.size());
+  for (size_t i = 0; i < seg_idx.size(); ++i) mpoff[i] = seg_poff[seg_idx[i]];
   auto put = [&](size_t off, const void* src, size_t n) -> mam_status {
     if (n) HIP_TRY(hipMemcpyAsync(A.ws + off, src, n, hipMemcpyHostToDevice, st));
     return MAM_OK;
@@ -1103,7 +1107,7 @@ mam_status upload_adjoint_tables(Plan* pl, int nwg, hipStream_t st) {
   TRY(put(A.o_seg_poff, seg_poff.data(), seg_poff.size() * 8));
   TRY(put(A.o_wg_seg, wg_seg.data(), wg_seg.size() * 4));
   TRY(put(A.o_mseg, mseg.data(), mseg.size() * 4));
-  TRY(put(A.o_seg_idx, seg_idx.data(), seg_idx.size() * 4));
+  TRY(put(A.o_seg_idx, mpoff.data(), mpoff.size() * 8));
   HIP_TRY(hipStreamSynchronize(st));
   A.nwg = nwg;
   return MAM_OK;
@@ -1270,8 +1274,7 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
       hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
                          at<mam::MargTask>(pl, L.mtasks), reinterpret_cast<const mam::ProbAux*>(A.ws + A.o_aux),
                          reinterpret_cast<const int32_t*>(A.ws + A.o_mseg),
-                         reinterpret_cast<const int32_t*>(A.ws + A.o_seg_idx),
-                         reinterpret_cast<const int64_t*>(A.ws + A.o_seg_poff),
+                         reinterpret_cast<const int64_t*>(A.ws + A.o_seg_idx),
                          reinterpret_cast<const double*>(A.ws + A.o_partial), 0);
       LAUNCH_CHECK("marginal_kernel");
       hipLaunchKernelGGL(mam::adjoint_average_kernel, dim3((unsigned)((p.R + 255) / 256)), dim3(256), 0, st, wnew, wold,

@@ -30,20 +30,37 @@ struct AvgTask {
   int32_t prob, rb;
 };
 
-// p^(m)_r = sum over the segments of measure m, in schedule order.
+// p^(m)_r = sum over the segments of measure m, in schedule order.  The
+// partials' offsets come as one list per measure (mpoff[mseg[k] .. mseg[k+1]));
+// they are wave-uniform, and the partial loads are issued eight at a time so
+// the loop is not a chain of dependent loads.  The additions keep the list
+// order.
 __global__ void __launch_bounds__(256)
 marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ probs,
-                const int32_t* __restrict__ mseg, const int32_t* __restrict__ seg_idx,
-                const int64_t* __restrict__ seg_poff, const double* __restrict__ partial, int save_prev) {
+                const int32_t* __restrict__ mseg, const int64_t* __restrict__ mpoff,
+                const double* __restrict__ partial, int save_prev) {
   const MargTask tk = tasks[blockIdx.x];
   const ProbAux& P = probs[tk.prob];
+  const int R = uniform_i(P.R);
   const int r = tk.r0 + threadIdx.x;
-  if (r >= P.R) return;
-  const int k = P.mbase + tk.m;
+  const int k = uniform_i(P.mbase) + tk.m;
+  const int b = uniform_i(mseg[k]), e = uniform_i(mseg[k + 1]);
+  constexpr int U = 8;
   double s = 0.0;
-  const int e = mseg[k + 1];
-  for (int i = mseg[k]; i < e; ++i) s += partial[seg_poff[seg_idx[i]] + r];
-  const size_t o = (size_t)tk.m * P.R + r;
+  const int rr = r < R ? r : 0;  // rows past R read row 0 (in bounds) and store nothing
+  for (int i = b; i < e; i += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t off = i + u < e ? uniform_l(mpoff[i + u]) : -1;
+      v[u] = off >= 0 ? partial[off + rr] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i + u < e) s += v[u];
+  }
+  if (r >= R) return;
+  const size_t o = (size_t)tk.m * R + r;
   double* const pm = gptr(P.pm);
   if (save_prev) gptr(P.pm_prev)[o] = pm[o];
   pm[o] = s;
@@ -64,11 +81,28 @@ average_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ pr
   double* const p = gptr(P.p);
   double d2 = 0.0;
   if (r < R) {
+    // eight measures' loads in flight at a time; the sums keep the order m = 0, 1, ...
+    constexpr int U = 8;
     double pr = 0.0;
-    for (int m = 0; m < M; ++m) pr += aw[m] * pm[(size_t)m * R + r];
-    for (int m = 0; m < M; ++m) {
-      const double e = pr - pm[(size_t)m * R + r];
-      d2 += e * e / Sd[m];
+    for (int m0 = 0; m0 < M; m0 += U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = m0 + u < M ? pm[(size_t)(m0 + u) * R + r] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (m0 + u < M) pr += aw[m0 + u] * v[u];
+    }
+    for (int m0 = 0; m0 < M; m0 += U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = m0 + u < M ? pm[(size_t)(m0 + u) * R + r] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (m0 + u < M) {
+          const double e = pr - v[u];
+          d2 += e * e / Sd[m0 + u];
+        }
+      }
     }
     if (save_prev) gptr(P.p_prev)[r] = p[r];
     p[r] = pr;

@@ -66,3 +66,62 @@ def test_balanced_sparse_full_size_sampled_columns(dtype):
     drift = np.abs(pm6.sum(axis=1) - 1.0).max()
     say(f"mass drift after 6 iterations: {drift:.2e}")
     assert drift <= (1e-5 if dtype == "f32" else 1e-12)
+
+
+def test_unbalanced_full_size_sampled_columns():
+    """32x32 grid, 50 dense measures with masses in [0.5, 1.5], gamma = 0.01,
+    FP32, default schedule: theta^6 columns from the GPU's theta^5 through
+    the oracle's step (including the damping t^k < 1)."""
+    p = inputs.unbalanced_dense()
+    say(f"{p.name}: R={p.R} M={p.M} T={p.T} gamma={p.gamma}")
+    s = mam.solver_for(p)
+    say(f"schedule {s.schedule()}")
+    s.init()
+    s.iterate(5)
+    torch.cuda.synchronize()
+    th5 = s.theta[:, :p.R].cpu().numpy()
+    off = p.offsets
+    pm = np.stack([th5[off[m]:off[m + 1]].sum(axis=0, dtype=np.float64) for m in range(p.M)])
+    e_pm = np.abs(s.marginals().cpu().numpy() - pm).max() / np.abs(pm).max()
+    say(f"marginals of theta^5: max rel {e_pm:.2e}")
+    assert e_pm <= 1e-12
+    s.iterate(1)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(99)
+    cols = np.sort(np.concatenate([rng.choice(np.arange(off[m], off[m + 1]), size=2, replace=False)
+                                   for m in range(p.M)]))
+    meas = np.searchsorted(off, cols, side="right") - 1
+    cost_cols = np.stack([p.cost[c - off[m]] for c, m in zip(cols, meas)], axis=1).astype(np.float64)
+    new, _, t = O.mam_step_columns(th5[cols].T.astype(np.float64), meas, pm, cost_cols,
+                                   p.q[cols].astype(np.float64), p.S, p.rho, p.gamma)
+    got = s.theta[torch.as_tensor(cols, device=s.theta.device), :p.R].double().cpu().numpy().T
+    err = np.abs(got - new)
+    say(f"t^5 = {t:.6f}; {len(cols)} sampled columns: max |diff| / |value| = "
+        f"{np.max(err / np.maximum(np.abs(new), 1e-300)):.2e}")
+    assert t < 1.0
+    assert np.all(err <= 2.0 ** -23 * np.abs(new))
+
+
+def test_batch_of_256_full_size_sampled_problems():
+    """All 256 problems of the batched workload with the benchmark's launch
+    configuration (autotuned schedules, graph replay); four problems (the
+    smallest, the largest and two drawn at random) against the oracle."""
+    from paper_2309_05315_amd import autotune
+    probs = inputs.batched_problems(iters=12)
+    scheds = autotune.tune_batch(probs, use_cache=False)
+    b = mam.Batch(probs, schedules=scheds)
+    b.graph(6)
+    b.init()
+    b.iterate(12)
+    torch.cuda.synchronize()
+    sizes = [p.R * p.T for p in probs]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))} |
+                  set(np.random.default_rng(7).choice(len(probs), 2, replace=False).tolist()))
+    for i in pick:
+        p = probs[i]
+        ref = O.mam([p.cost_block(m) for m in range(p.M)], [p.q_block(m) for m in range(p.M)],
+                    p.rho, p.gamma, 12)["p_bar"]
+        got = b.barycenter(i).cpu().numpy()
+        e = np.abs(got - ref).sum() / np.abs(ref).sum()
+        say(f"problem {i} {p.name}: rel L1 {e:.2e}")
+        assert e <= 1e-5

@@ -1,6 +1,6 @@
 """FP64 CPU oracle of gradients through the MAM iteration (TEST INFRASTRUCTURE ONLY).
 
-Alg. 1 (balanced, deterministic) written with torch CPU float64 tensors so
+Alg. 1 (deterministic, balanced or unbalanced) written with torch CPU float64 tensors so
 that autograd differentiates the unrolled iteration: theta^0 = q/R, K
 iterations of Step 1 (average the marginals), Step 2 (reflect, project every
 column onto Delta_R(q_s) by the sort-based exact formula of Prop. 3) and
@@ -14,6 +14,7 @@ central finite differences of it (derivatives).
 """
 from __future__ import annotations
 
+import math
 from typing import List
 
 import numpy as np
@@ -38,8 +39,12 @@ def proj_simplex_sort_t(w: torch.Tensor, tau: torch.Tensor) -> torch.Tensor:
     return torch.where(tau.unsqueeze(0) > 0, out, torch.zeros_like(out))
 
 
-def mam_pbar_t(cost: List[torch.Tensor], q: List[torch.Tensor], rho: float, iters: int) -> torch.Tensor:
-    """Barycenter after 'iters' balanced MAM iterations from theta^0 = q/R."""
+def mam_pbar_t(cost: List[torch.Tensor], q: List[torch.Tensor], rho: float, iters: int,
+               gamma: float = math.inf) -> torch.Tensor:
+    """Barycenter after 'iters' MAM iterations from theta^0 = q/R.  With a
+    finite gamma, Step 1's damping t^k = min(1, gamma / (rho d^k)), d^k =
+    sqrt(sum_m ||p - p^(m)||^2 / S^m) (eq. (Unbalanced-prox)), scales the
+    correction b^(m) = t^k (p - p^(m)) / S^m and is differentiated like the rest."""
     R = cost[0].shape[0]
     S = [c.shape[1] for c in cost]
     inv = torch.tensor([1.0 / s for s in S], dtype=torch.float64)
@@ -48,9 +53,14 @@ def mam_pbar_t(cost: List[torch.Tensor], q: List[torch.Tensor], rho: float, iter
     pm = torch.stack([th.sum(dim=1) for th in theta])
     for _ in range(iters):
         p = (a.unsqueeze(1) * pm).sum(dim=0)
+        t = torch.ones((), dtype=torch.float64)
+        if not math.isinf(gamma):
+            d = torch.sqrt(sum(((p - pm[m]) ** 2).sum() / S[m] for m in range(len(S))))
+            if float(rho * d) > gamma:
+                t = gamma / (rho * d)
         new = []
         for m in range(len(S)):
-            corr = (p - pm[m]) / S[m]
+            corr = t * (p - pm[m]) / S[m]
             w = theta[m] + 2.0 * corr.unsqueeze(1) - cost[m] / rho
             new.append(proj_simplex_sort_t(w, q[m]) - corr.unsqueeze(1))
         theta = new
@@ -63,21 +73,21 @@ def _grad(x: torch.Tensor):
     return np.zeros(tuple(x.shape)) if x.grad is None else x.grad.numpy().copy()
 
 
-def loss_and_grads(cost_np, q_np, rho, iters, target_np):
+def loss_and_grads(cost_np, q_np, rho, iters, target_np, gamma=math.inf):
     """L = ||p-bar - target||^2 and its gradients with respect to every q^(m)
     and every c^(m) (lists of numpy arrays, float64)."""
     cost = [torch.tensor(c, dtype=torch.float64, requires_grad=True) for c in cost_np]
     q = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in q_np]
-    pbar = mam_pbar_t(cost, q, rho, iters)
+    pbar = mam_pbar_t(cost, q, rho, iters, gamma)
     loss = ((pbar - torch.tensor(target_np, dtype=torch.float64)) ** 2).sum()
     loss.backward()
     return (float(loss.detach()), pbar.detach().numpy(), [_grad(v) for v in q], [_grad(c) for c in cost])
 
 
-def vjp(cost_np, q_np, rho, iters, u_np):
+def vjp(cost_np, q_np, rho, iters, u_np, gamma=math.inf):
     """p-bar and the vector-Jacobian products u^T dp-bar/dq^(m), u^T dp-bar/dc^(m)."""
     cost = [torch.tensor(c, dtype=torch.float64, requires_grad=True) for c in cost_np]
     q = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in q_np]
-    pbar = mam_pbar_t(cost, q, rho, iters)
+    pbar = mam_pbar_t(cost, q, rho, iters, gamma)
     pbar.backward(torch.tensor(u_np, dtype=torch.float64))
     return pbar.detach().numpy(), [_grad(v) for v in q], [_grad(c) for c in cost]

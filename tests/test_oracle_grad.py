@@ -102,3 +102,30 @@ def test_cost_gradient_columns_sum_to_zero():
     _, _, _, gc = G.loss_and_grads(cost, q, 0.9, 10, np.random.default_rng(3).dirichlet(np.ones(8)))
     for g in gc:
         assert np.abs(g.sum(axis=0)).max() <= 1e-14 * max(1.0, np.abs(g).max())
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_unbalanced_forward_and_gradients(seed):
+    """Finite gamma with the damping active (t < 1): forward equals the numpy
+    oracle; gradients equal central differences (q moves freely: the masses
+    need not stay equal)."""
+    p = inputs.tiny_problem(50 + seed, R=6, S=[5, 4], masses=[0.7, 1.3], gamma=0.02)
+    cost, q = blocks(p)
+    rho, iters, gamma = 1.0, 8, p.gamma
+    tgt = np.random.default_rng(seed).dirichlet(np.ones(6))
+    ora = O.mam(cost, q, rho, gamma, iters, record=True)
+    assert min(ora["hist"]["t"]) < 1.0
+    _, pbar, gq, gc = G.loss_and_grads(cost, q, rho, iters, tgt, gamma)
+    np.testing.assert_allclose(pbar, ora["p_bar"], atol=1e-14)
+    rng = np.random.default_rng(300 + seed)
+    h = 1e-7
+    lossf = lambda c, qq: float(((O.mam(c, qq, rho, gamma, iters)["p_bar"] - tgt) ** 2).sum())
+    for _ in range(3):
+        du = [rng.normal(size=x.shape) * x for x in q]
+        dc = [rng.normal(size=c.shape) for c in cost]
+        fd = (lossf(cost, [x + h * d for x, d in zip(q, du)]) - lossf(cost, [x - h * d for x, d in zip(q, du)])) / (2 * h)
+        an = sum(float((g * d).sum()) for g, d in zip(gq, du))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+        fd = (lossf([c + h * d for c, d in zip(cost, dc)], q) - lossf([c - h * d for c, d in zip(cost, dc)], q)) / (2 * h)
+        an = sum(float((g * d).sum()) for g, d in zip(gc, dc))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)

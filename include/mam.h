@@ -218,10 +218,13 @@ mam_status mam_timing_read(mam_problem* p, double* total_ms, int64_t* launches);
  * measure; it reads the active-set bit masks of the forward (R/8 bytes per
  * column and iteration), never theta or c.
  *
- * Scope: single problems, balanced (gamma = INFINITY), started with the
- * default theta^0 = q_s/R (mam_init with theta0 = NULL), any cost mode and
- * dtype.  Gradients are accumulated in double and written in the problem's
- * dtype.
+ * Scope: single problems, balanced or unbalanced, started with the default
+ * theta^0 = q_s/R (mam_init with theta0 = NULL), any cost mode and dtype.
+ * With a finite gamma, Step 1's damping t = gamma/(rho d) (eq.
+ * (Unbalanced-prox)) depends on the plans through d; its derivative adds a
+ * rank-one term to the transposed averaging, for which the forward also
+ * keeps p, p^(m) and d of every recorded iteration (O(M R) per iteration).
+ * Gradients are accumulated in double and written in the problem's dtype.
  *
  * Memory: the adjoint workspace (caller-owned device memory, 256-byte
  * aligned) holds the masks of one window of C = ckpt_every iterations
@@ -238,7 +241,7 @@ size_t mam_adjoint_workspace_bytes(const mam_problem* p, int64_t iters, int64_t 
  * 'adj_ws' ('bytes' long).  Must follow a mam_init with theta0 = NULL and
  * no iteration since.  SYNCHRONIZES the stream once at the start (table
  * upload); then asynchronous.  Errors: MAM_ESTATE (not freshly initialised
- * with the default start), MAM_EUNSUPPORTED (batch or finite gamma),
+ * with the default start), MAM_EUNSUPPORTED (batch),
  * MAM_ENOMEM (workspace NULL or too small), MAM_EINVAL (misaligned, iters < 0). */
 mam_status mam_record(mam_problem* p, int64_t iters, int64_t ckpt_every, void* adj_ws, size_t bytes,
                       void* stream);

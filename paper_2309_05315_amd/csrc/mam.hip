@@ -133,6 +133,10 @@ struct Adjoint {
   size_t nseg_cap = 0;
   size_t o_seg_m = 0, o_seg_j0 = 0, o_seg_j1 = 0, o_seg_poff = 0, o_wg_seg = 0, o_mseg = 0, o_seg_idx = 0,
          o_partial = 0;
+  // unbalanced problems: p, p^(m) and the d^2 partials of every recorded
+  // iteration (same slot ring as the masks), and the two-pass buffers
+  bool unbal = false;
+  size_t o_pm_rec = 0, o_p_rec = 0, o_d2_rec = 0, o_bbar = 0, o_tpart = 0;
 };
 
 struct Plan {
@@ -1029,6 +1033,15 @@ mam_status adjoint_layout(const Plan* pl, int64_t K, int64_t C, Adjoint* A) {
   A->o_mseg = take((M + 1) * 4);
   A->o_seg_idx = take(A->nseg_cap * 8);  // holds the partial offsets in measure order
   A->o_partial = take(A->nseg_cap * R * 8);
+  A->unbal = !std::isinf(p.gamma);
+  if (A->unbal) {
+    const size_t slots = (size_t)(A->C + 1);
+    A->o_pm_rec = take(slots * M * R * 8);
+    A->o_p_rec = take(slots * R * 8);
+    A->o_d2_rec = take(slots * (size_t)p.nb * 8);
+    A->o_bbar = take(M * R * 8);
+    A->o_tpart = take(((R + 255) / 256) * 8);
+  }
   A->total = o;
   return MAM_OK;
 }
@@ -1058,6 +1071,16 @@ mam_status record_range(Plan* pl, int64_t k0, int64_t k1, int64_t rec_from, bool
         TRY(launch_copy<float>(reinterpret_cast<float*>(dst), static_cast<const float*>(p.theta), p, st));
       else
         TRY(launch_copy<double>(reinterpret_cast<double*>(dst), static_cast<const double*>(p.theta), p, st));
+    }
+    if (A.unbal && k >= rec_from) {
+      // the iteration's p^(m), p and d^2 partials, as its column kernel reads them
+      const size_t sl = (size_t)(k % (A.C + 1));
+      const size_t MR = (size_t)p.M * (size_t)p.R;
+      HIP_TRY(hipMemcpyAsync(A.ws + A.o_pm_rec + sl * MR * 8, pl->ws + p.o_pm, MR * 8, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(A.ws + A.o_p_rec + sl * (size_t)p.R * 8, pl->ws + p.o_p, (size_t)p.R * 8,
+                             hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(A.ws + A.o_d2_rec + sl * (size_t)p.nb * 8, pl->ws + p.o_d2, (size_t)p.nb * 8,
+                             hipMemcpyDeviceToDevice, st));
     }
     TRY(one_iteration(pl, st, 0, k >= rec_from ? mask_slot(pl, k) : nullptr, A.mld));
   }
@@ -1142,7 +1165,6 @@ mam_status plan_record(Plan* pl, int64_t K, int64_t C, void* ws, size_t bytes, h
   if (!pl->inited) return fail(MAM_ESTATE, "mam_init has not run");
   if (!pl->default_start || pl->iters_done != 0)
     return fail(MAM_ESTATE, "mam_record needs a fresh mam_init with the default start (theta0 = NULL)");
-  if (!std::isinf(p.gamma)) return fail(MAM_EUNSUPPORTED, "the reverse mode covers balanced problems (gamma = inf)");
   if (!ws) return fail(MAM_ENOMEM, "adjoint workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(MAM_EINVAL, "adjoint workspace must be 256-byte aligned");
   if (bytes < A.total) return fail(MAM_ENOMEM, "adjoint workspace has %zu bytes, needs %zu", bytes, A.total);
@@ -1277,9 +1299,27 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
                          reinterpret_cast<const int64_t*>(A.ws + A.o_seg_idx),
                          reinterpret_cast<const double*>(A.ws + A.o_partial), 0);
       LAUNCH_CHECK("marginal_kernel");
-      hipLaunchKernelGGL(mam::adjoint_average_kernel, dim3((unsigned)((p.R + 255) / 256)), dim3(256), 0, st, wnew, wold,
-                         V, at<double>(pl, p.o_Sd), at<double>(pl, p.o_aw), (int)p.R, (int)p.M);
-      LAUNCH_CHECK("adjoint_average_kernel");
+      const unsigned nbr = (unsigned)((p.R + 255) / 256);
+      if (!A.unbal) {
+        hipLaunchKernelGGL(mam::adjoint_average_kernel, dim3(nbr), dim3(256), 0, st, wnew, wold, V,
+                           at<double>(pl, p.o_Sd), at<double>(pl, p.o_aw), (int)p.R, (int)p.M);
+        LAUNCH_CHECK("adjoint_average_kernel");
+      } else {
+        const size_t sl = (size_t)(k % (A.C + 1));
+        const size_t MR = (size_t)p.M * (size_t)p.R;
+        const double* pmk = reinterpret_cast<const double*>(A.ws + A.o_pm_rec) + sl * MR;
+        const double* pk = reinterpret_cast<const double*>(A.ws + A.o_p_rec) + sl * (size_t)p.R;
+        const double* d2k = reinterpret_cast<const double*>(A.ws + A.o_d2_rec) + sl * (size_t)p.nb;
+        double* bbar = reinterpret_cast<double*>(A.ws + A.o_bbar);
+        double* tpart = reinterpret_cast<double*>(A.ws + A.o_tpart);
+        hipLaunchKernelGGL(mam::adjoint_unbal1_kernel, dim3(nbr), dim3(256), 0, st, wnew, wold, V,
+                           at<double>(pl, p.o_Sd), pmk, pk, bbar, tpart, (int)p.R, (int)p.M);
+        LAUNCH_CHECK("adjoint_unbal1_kernel");
+        hipLaunchKernelGGL(mam::adjoint_unbal2_kernel, dim3(nbr), dim3(256), 0, st, bbar, wnew, wold, V, pmk, pk,
+                           d2k, p.nb, tpart, (int)nbr, at<double>(pl, p.o_Sd), at<double>(pl, p.o_aw), p.rho,
+                           p.gamma, (int)p.R, (int)p.M);
+        LAUNCH_CHECK("adjoint_unbal2_kernel");
+      }
     }
   }
   TRY(pl->dtype == MAM_F32 ? backward_finish<float>(pl, gq, gc, st) : backward_finish<double>(pl, gq, gc, st));

@@ -279,6 +279,67 @@ adjoint_average_kernel(const double* __restrict__ wnew, double* __restrict__ wol
   }
 }
 
+// Transposed averaging with the unbalanced damping.  Step 1 of Alg. 1 scales
+// the correction by t = gamma / (rho d) when rho d > gamma (eq.
+// (Unbalanced-prox)), so b^(m) = t e_m / S^m with e_m = p - p^(m) and t
+// depends on every e_m through d^2 = sum_m ||e_m||^2 / S^m.  Given
+// bbar_m = 2 W_new - W_old - S^m V_m, the adjoint of e_m is
+//   ebar_m = t bbar_m / S^m - tbar t e_m / (S^m d^2),  tbar = sum_m <bbar_m, e_m> / S^m
+// (second term only while t < 1), and V_m <- a_m sum_j ebar_j - ebar_m.
+// First pass: bbar and the per-block partials of tbar (fixed order).
+__global__ void __launch_bounds__(256)
+adjoint_unbal1_kernel(const double* __restrict__ wnew, const double* __restrict__ wold,
+                      const double* __restrict__ V, const double* __restrict__ Sd,
+                      const double* __restrict__ pm_k, const double* __restrict__ p_k,
+                      double* __restrict__ bbar, double* __restrict__ tpart, int R, int M) {
+  __shared__ double sh[4];
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  double acc = 0.0;
+  if (r < R) {
+    for (int m = 0; m < M; ++m) {
+      const size_t o = (size_t)m * R + r;
+      const double bb = 2.0 * wnew[o] - wold[o] - Sd[m] * V[o];
+      bbar[o] = bb;
+      acc += bb * (p_k[r] - pm_k[o]) / Sd[m];
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) tpart[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// Second pass: tbar, d and t of the iteration (from its recorded d^2
+// partials), then ebar, V and W_old <- W_new per row.
+__global__ void __launch_bounds__(256)
+adjoint_unbal2_kernel(const double* __restrict__ bbar, const double* __restrict__ wnew,
+                      double* __restrict__ wold, double* __restrict__ V,
+                      const double* __restrict__ pm_k, const double* __restrict__ p_k,
+                      const double* __restrict__ d2_k, int nd2, const double* __restrict__ tpart, int ntp,
+                      const double* __restrict__ Sd, const double* __restrict__ aw, double rho, double gamma,
+                      int R, int M) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= R) return;
+  double tb = 0.0, d2 = 0.0;
+  for (int i = 0; i < ntp; ++i) tb += tpart[i];
+  for (int i = 0; i < nd2; ++i) d2 += d2_k[i];
+  const double d = sqrt(d2);
+  const bool damped = !__builtin_isinf(gamma) && rho * d > gamma;
+  const double t = damped ? gamma / (rho * d) : 1.0;
+  const double c = damped ? tb * t / d2 : 0.0;
+  double pbar = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const size_t o = (size_t)m * R + r;
+    pbar += (t * bbar[o] - c * (p_k[r] - pm_k[o])) / Sd[m];
+  }
+  for (int m = 0; m < M; ++m) {
+    const size_t o = (size_t)m * R + r;
+    const double eb = (t * bbar[o] - c * (p_k[r] - pm_k[o])) / Sd[m];
+    V[o] = aw[m] * pbar - eb;
+    wold[o] = wnew[o];
+  }
+}
+
 // Start of the reverse sweep: V_m = a_m * dL/dp_bar, W_old = 0.
 __global__ void __launch_bounds__(256)
 adjoint_start_kernel(const double* __restrict__ gp, const double* __restrict__ aw, double* __restrict__ V,

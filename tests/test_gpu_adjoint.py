@@ -226,11 +226,6 @@ def test_adjoint_problem_full_size_vs_finite_differences():
 
 
 def test_reverse_mode_errors():
-    p = inputs.tiny_problem(14, R=20, S=[5, 6], masses=[1.0, 1.0], gamma=0.5)
-    s = mam.solver_for(p)
-    s.init()
-    with pytest.raises(mam.MAMError, match="MAM_EUNSUPPORTED"):
-        s.record(5)
     p = inputs.tiny_problem(15, R=20, S=[5, 6])
     s = mam.solver_for(p)
     s.init(torch.full_like(s.theta, 0.01))
@@ -264,3 +259,39 @@ def test_gradients_large_rho(dtype):
     say(f"large rho {dtype}: rel L1 q {eq:.2e} cost {ec:.2e}")
     tol = 1e-9 if dtype == "f64" else 1e-4
     assert eq <= tol and ec <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ckpt", [0, 4])
+def test_unbalanced_gradients_match_oracle(dtype, ckpt):
+    """Finite gamma with the damping active (t < 1 from the second iteration
+    on): the rank-one term of the transposed averaging, against the gradient
+    oracle."""
+    p = inputs.tiny_problem(16, R=90, S=[30, 45, 20], dtype=dtype, masses=[0.6, 1.0, 1.5], gamma=0.02)
+    iters = 12
+    cost, q = blocks(p)
+    ora = O.mam(cost, q, p.rho, p.gamma, iters, record=True)
+    assert max(ora["hist"]["t"][1:]) < 1.0
+    tgt = np.random.default_rng(8).dirichlet(np.ones(p.R))
+    _, _, gq_o, gc_o = G.loss_and_grads(cost, q, p.rho, iters, tgt, p.gamma)
+    _, gq, gc, _ = gpu_grads(p, iters, target=tgt, ckpt_every=ckpt)
+    eq, ec = rel(gq, np.concatenate(gq_o)), rel(gc, fold_cost(p, gc_o))
+    say(f"unbalanced {dtype} ckpt={ckpt}: rel L1 q {eq:.2e} cost {ec:.2e}")
+    tol = 1e-9 if dtype == "f64" else 1e-4
+    assert eq <= tol and ec <= tol
+
+
+def test_unbalanced_gradients_mixed_damping():
+    """gamma between the damped and undamped regimes: t = 1 at some
+    iterations and t < 1 at others."""
+    p = inputs.tiny_problem(17, R=50, S=[20, 25], masses=[0.9, 1.1], gamma=0.2)
+    iters = 15
+    cost, q = blocks(p)
+    ts = O.mam(cost, q, p.rho, p.gamma, iters, record=True)["hist"]["t"]
+    say(f"t history: min {min(ts):.3f} max {max(ts):.3f}")
+    assert min(ts) < 1.0 and max(ts) == 1.0
+    u = np.random.default_rng(9).normal(size=p.R)
+    _, gq_o, gc_o = G.vjp(cost, q, p.rho, iters, u, p.gamma)
+    _, gq, gc, _ = gpu_grads(p, iters, grad_p=u)
+    assert rel(gq, np.concatenate(gq_o)) <= 1e-9
+    assert rel(gc, fold_cost(p, gc_o)) <= 1e-9

@@ -158,8 +158,11 @@ def damping(p: np.ndarray, pm: np.ndarray, S: Sequence[int], rho: float, gamma: 
 # Alg. 1 (deterministic MAM)
 # ---------------------------------------------------------------------------
 def mam_step(theta: List[np.ndarray], pm: np.ndarray, cost: List[np.ndarray],
-             q: List[np.ndarray], rho: float, gamma: float):
-    """One pass of Alg. 1's loop body with M^k = {1, ..., M}.
+             q: List[np.ndarray], rho: float, gamma: float, chosen: Optional[Sequence[int]] = None):
+    """One pass of Alg. 1's loop body with M^k = {1, ..., M}, or with
+    M^k = ``chosen`` (the randomized variant, eq. (DR-random)): Step 1 still
+    averages every marginal, Steps 2 and 3 run only for the chosen measures,
+    and every other plan and marginal is left as it was.
 
     Step 1: p^k = sum_m a_m p^(m); t^k from the damping rule.
     Step 2 (every m, every column s, all with the marginal p^(m) of theta^k):
@@ -176,14 +179,21 @@ def mam_step(theta: List[np.ndarray], pm: np.ndarray, cost: List[np.ndarray],
     a = averaging_weights(S)
     p = (a[:, None] * pm).sum(axis=0)                    # Step 1
     t, d = damping(p, pm, S, rho, gamma)
+    active = set(range(M)) if chosen is None else set(int(m) for m in chosen)
     new_theta, pi_hat = [], []
     for m in range(M):                                    # Step 2
+        if m not in active:
+            pi_hat.append(None)
+            new_theta.append(theta[m])
+            continue
         corr = t * (p - pm[m]) / S[m]
         w = theta[m] + 2.0 * corr[:, None] - cost[m] / rho
         ph, _ = proj_simplex_sort(w, q[m])
         pi_hat.append(ph)
         new_theta.append(ph - corr[:, None])
-    pm_new = marginals(new_theta)                         # Step 3
+    pm_new = pm.copy()                                    # Step 3
+    for m in active:
+        pm_new[m] = new_theta[m].sum(axis=1)
     return new_theta, pm_new, {"p": p, "t": t, "d": d, "pi_hat": pi_hat}
 
 
@@ -213,8 +223,13 @@ def mam_step_columns(theta_cols: np.ndarray, measure_of_col: Sequence[int], pm: 
 
 def mam(cost: List[np.ndarray], q: List[np.ndarray], rho: float,
         gamma: float = math.inf, iters: int = 1,
-        theta0: Optional[List[np.ndarray]] = None, record: bool = False) -> Dict:
+        theta0: Optional[List[np.ndarray]] = None, record: bool = False,
+        bundles: Optional[Sequence[Sequence[int]]] = None, seq: Optional[Sequence[int]] = None) -> Dict:
     """Run Alg. 1 for ``iters`` iterations from theta^0.
+
+    Randomized variant: with ``bundles`` (a partition of the measures, as in
+    the remark on bundles) and ``seq`` (the bundle drawn at each iteration,
+    supplied by the caller), iteration k uses M^k = bundles[seq[k]].
 
     cost[m]: R x S^m cost matrix c^(m) (taken as given, Sec. 4 eq. (fm));
     q[m]: weights q^(m) (length S^m); rho > 0; gamma in [0, inf].
@@ -235,8 +250,9 @@ def mam(cost: List[np.ndarray], q: List[np.ndarray], rho: float,
     pm = marginals(theta)                                 # Step 0
     hist = {"t": [], "d": [], "p": []}
     info = {"pi_hat": None, "t": None, "p": None}
-    for _ in range(iters):
-        theta, pm_new, info = mam_step(theta, pm, cost, q, rho, gamma)
+    for k in range(iters):
+        chosen = None if bundles is None else bundles[int(seq[k])]
+        theta, pm_new, info = mam_step(theta, pm, cost, q, rho, gamma, chosen)
         if record:
             hist["t"].append(info["t"])
             hist["d"].append(info["d"])

@@ -298,3 +298,14 @@ def tiny_problem(seed: int, R: int, S: List[int], dtype: str = "f64",
         name=f"tiny_R{R}_M{M}", R=R, S=list(S), cost=_round(np.ascontiguousarray(cost), dtype),
         q=_round(np.concatenate(qs), dtype), col_index=col_index, rho=rho,
         gamma=gamma, iters=iters, dtype=dtype, meta={"seed": seed})
+
+
+def bundle_sequence(bundles, iters: int, seed: int = 0, alpha=None) -> np.ndarray:
+    """Seeded draws for the randomized variant: iteration k takes bundle i
+    with probability beta_i = sum of alpha_m over the bundle's measures
+    (alpha uniform by default).  Returns ``iters`` bundle indices (int32)."""
+    M = sum(len(b) for b in bundles)
+    a = np.full(M, 1.0 / M) if alpha is None else np.asarray(alpha, dtype=np.float64)
+    beta = np.array([a[list(b)].sum() for b in bundles])
+    rng = np.random.default_rng([6, seed])
+    return rng.choice(len(bundles), size=iters, p=beta / beta.sum()).astype(np.int32)

@@ -245,3 +245,45 @@ def test_sampled_columns_match_full_step():
     got, _, _ = O.mam_step_columns(cols, [m for m, _ in picks], pm, ccols, qcols, p.S, 1.7, 0.05)
     for k, (m, s) in enumerate(picks):
         np.testing.assert_array_equal(got[:, k], full[m][:, s])
+
+
+def test_randomized_with_one_bundle_is_deterministic():
+    p = inputs.tiny_problem(21, R=7, S=[4, 6, 5])
+    cost, q = blocks(p)
+    a = O.mam(cost, q, 1.0, iters=30)
+    b = O.mam(cost, q, 1.0, iters=30, bundles=[[0, 1, 2]], seq=[0] * 30)
+    assert np.array_equal(a["p_bar"], b["p_bar"])
+    for x, y in zip(a["theta"], b["theta"]):
+        assert np.array_equal(x, y)
+
+
+def test_randomized_step_leaves_other_measures_alone():
+    """A step with M^k = {1}: measures 0 and 2 keep their plans and marginals
+    bitwise; measure 1 gets exactly the deterministic step's plan."""
+    p = inputs.tiny_problem(22, R=6, S=[3, 5, 4], masses=[0.8, 1.0, 1.2], gamma=0.1)
+    cost, q = blocks(p)
+    r = O.mam(cost, q, 1.0, p.gamma, iters=3)
+    th, pm = r["theta"], r["pm"]
+    det, pm_det, _ = O.mam_step(th, pm, cost, q, 1.0, p.gamma)
+    ran, pm_ran, _ = O.mam_step(th, pm, cost, q, 1.0, p.gamma, chosen=[1])
+    assert np.array_equal(ran[0], th[0]) and np.array_equal(ran[2], th[2])
+    assert np.array_equal(pm_ran[0], pm[0]) and np.array_equal(pm_ran[2], pm[2])
+    assert np.array_equal(ran[1], det[1]) and np.array_equal(pm_ran[1], pm_det[1])
+
+
+def test_randomized_converges_to_lp_optimum():
+    """Randomized MAM with single-measure bundles drawn with probability
+    alpha_m = 1/M (Theorem on convergence, part b): the objective reaches the
+    LP optimum of (HugeLP)."""
+    p = inputs.tiny_problem(2, R=9, S=[5, 7, 6])
+    cost, q = blocks(p)
+    f_lp, _, _ = lp.wb_lp(cost, q)
+    bundles = [[0], [1], [2]]
+    seq = inputs.bundle_sequence(bundles, 12000, seed=1)
+    r = O.mam(cost, q, 1.0, iters=12000, bundles=bundles, seq=seq)
+    th = r["theta"]
+    # pi_hat of the last full step from the final plans (every measure)
+    _, _, info = O.mam_step(th, r["pm"], cost, q, 1.0, math.inf)
+    d = O.diagnostics(cost, q, info["pi_hat"], th, th)
+    assert abs(d["W_hat"] - f_lp) <= 1e-6 * max(1.0, abs(f_lp))
+    assert abs(r["p_bar"].sum() - 1.0) < 1e-10

@@ -257,6 +257,35 @@ mam_status mam_record(mam_problem* p, int64_t iters, int64_t ckpt_every, void* a
  * Errors: MAM_ESTATE (no mam_record), MAM_EINVAL (NULL gradient buffer). */
 mam_status mam_backward(mam_problem* p, const double* grad_p, void* grad_q, void* grad_cost, void* stream);
 
+/* ---- randomized variant ----------------------------------------------------
+ * Alg. 1 with M^k a subset of the measures (eq. (DR-random), and the remark
+ * on bundles after the algorithm): the measures are partitioned into nb
+ * bundles, and an iteration that draws bundle i updates the plans and
+ * marginals of bundle i only (Steps 2 and 3), while Step 1 still averages
+ * every marginal.  The draws are the caller's: seq[k] is the bundle of
+ * iteration k, so a run can be replayed exactly.  Single problems only; no
+ * diagnostics, no graph replay for these iterations.
+ *
+ * bundle_of: host array of M bundle indices in [0, nb), every bundle
+ * non-empty.  The bundle workspace (caller-owned device memory, 256-byte
+ * aligned) holds each bundle's column schedule; its size depends on the
+ * device (query after mam_init).  mam_bundle_workspace_bytes returns 0 for
+ * an invalid partition, a batch or a NULL handle. */
+size_t mam_bundle_workspace_bytes(const mam_problem* p, const int32_t* bundle_of, int32_t nb);
+
+/* Build and upload the bundles' schedules (SYNCHRONIZES the stream).  Must
+ * follow mam_init.  Errors: MAM_EINVAL (partition, alignment), MAM_ENOMEM
+ * (workspace NULL or too small), MAM_ESTATE (no mam_init), MAM_EUNSUPPORTED
+ * (batch). */
+mam_status mam_set_bundles(mam_problem* p, const int32_t* bundle_of, int32_t nb, void* bundle_ws, size_t bytes,
+                           void* stream);
+
+/* 'iters' randomized iterations; iteration k updates bundle seq[k] (host
+ * array of iters entries, each in [0, nb)).  Asynchronous after the host
+ * check of seq.  Errors: MAM_EINVAL (seq NULL or out of range), MAM_ESTATE
+ * (no mam_init or no mam_set_bundles). */
+mam_status mam_iterate_bundles(mam_problem* p, int64_t iters, const int32_t* seq, void* stream);
+
 /* Destroy a handle (NULL is allowed).  Device buffers stay with the caller. */
 void mam_destroy(mam_problem* p);
 

@@ -139,6 +139,23 @@ struct Adjoint {
   size_t o_pm_rec = 0, o_p_rec = 0, o_d2_rec = 0, o_bbar = 0, o_tpart = 0;
 };
 
+// Randomized variant: a partition of a single problem's measures into
+// bundles, each with its own segment schedule (tables in a caller-provided
+// bundle workspace; partials in the plan's buffer).
+struct BundleSched {
+  int nwg = 0;
+  size_t nseg = 0;
+  size_t o_seg_p = 0, o_seg_m = 0, o_seg_j0 = 0, o_seg_j1 = 0, o_seg_poff = 0, o_wg_seg = 0, o_mseg = 0,
+         o_mpoff = 0, o_mtasks = 0;
+  size_t nmtasks = 0;
+};
+
+struct Bundles {
+  int nb = 0;
+  char* ws = nullptr;
+  std::vector<BundleSched> b;
+};
+
 struct Plan {
   int dtype = MAM_F64;
   bool batch = false;
@@ -161,6 +178,7 @@ struct Plan {
   bool default_start = false;
   int64_t iters_done = 0;
   Adjoint adj;
+  Bundles bund;
   bool diag_valid = false;
   // graph of a fixed number of iterations
   int64_t graph_iters = 0;
@@ -1328,6 +1346,216 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
   return MAM_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// randomized variant (bundles)
+// ---------------------------------------------------------------------------
+// Per bundle: workgroups take equal runs of the bundle's columns (its
+// measures' column ranges, in measure order), split at measure boundaries.
+struct BundleHost {
+  std::vector<int32_t> seg_p, seg_m, wg_seg, mseg;
+  std::vector<int64_t> seg_j0, seg_j1, seg_poff, mpoff;
+  std::vector<mam::MargTask> mtasks;
+};
+
+mam_status bundle_check(const Plan* pl, const int32_t* bundle_of, int32_t nb) {
+  if (pl->batch) return fail(MAM_EUNSUPPORTED, "bundles are available for single problems");
+  if (!bundle_of) return fail(MAM_EINVAL, "bundle_of is NULL");
+  const Prob& p = pl->P[0];
+  if (nb < 1 || nb > p.M) return fail(MAM_EINVAL, "nb must be in [1, M] (got %d)", nb);
+  std::vector<int> cnt(nb, 0);
+  for (int64_t m = 0; m < p.M; ++m) {
+    if (bundle_of[m] < 0 || bundle_of[m] >= nb)
+      return fail(MAM_EINVAL, "bundle_of[%lld] = %d is outside [0, %d)", (long long)m, bundle_of[m], nb);
+    ++cnt[bundle_of[m]];
+  }
+  for (int i = 0; i < nb; ++i)
+    if (!cnt[i]) return fail(MAM_EINVAL, "bundle %d has no measure", i);
+  return MAM_OK;
+}
+
+void bundle_build(const Plan* pl, const int32_t* bundle_of, int bi, BundleHost* h, int* nwg_out) {
+  const Prob& p = pl->P[0];
+  const Group& g = pl->G[0];
+  std::vector<int64_t> ms;
+  int64_t Tb = 0;
+  for (int64_t m = 0; m < p.M; ++m)
+    if (bundle_of[m] == bi) {
+      ms.push_back(m);
+      Tb += p.S[m];
+    }
+  const int nwg = default_nwg(Tb, g.ng, g.nwg_req, g.nwg_auto);
+  // the bundle's columns as a list of (measure, first, end) runs
+  std::vector<int64_t> starts(ms.size() + 1, 0);
+  for (size_t i = 0; i < ms.size(); ++i) starts[i + 1] = starts[i] + p.S[ms[i]];
+  for (int w = 0; w < nwg; ++w) {
+    h->wg_seg.push_back((int32_t)h->seg_m.size());
+    int64_t lo = Tb * w / nwg, hi = Tb * (w + 1) / nwg;
+    while (lo < hi) {
+      const size_t i = std::upper_bound(starts.begin(), starts.end(), lo) - starts.begin() - 1;
+      const int64_t m = ms[i];
+      const int64_t e = std::min(hi, starts[i + 1]);
+      h->seg_p.push_back(0);
+      h->seg_m.push_back((int32_t)m);
+      h->seg_j0.push_back(p.col_off[m] + (lo - starts[i]));
+      h->seg_j1.push_back(p.col_off[m] + (e - starts[i]));
+      h->seg_poff.push_back((int64_t)(h->seg_m.size() - 1) * p.R);
+      lo = e;
+    }
+  }
+  h->wg_seg.push_back((int32_t)h->seg_m.size());
+  h->mseg.assign(p.M + 1, 0);
+  for (size_t k = 0; k < h->seg_m.size(); ++k) ++h->mseg[h->seg_m[k] + 1];
+  for (int64_t m = 0; m < p.M; ++m) h->mseg[m + 1] += h->mseg[m];
+  h->mpoff.assign(h->seg_m.size(), 0);
+  {
+    std::vector<int32_t> fill(h->mseg.begin(), h->mseg.end() - 1);
+    for (size_t k = 0; k < h->seg_m.size(); ++k) h->mpoff[fill[h->seg_m[k]]++] = h->seg_poff[k];
+  }
+  for (int64_t m : ms)
+    for (int64_t r0 = 0; r0 < p.R; r0 += 256) h->mtasks.push_back({0, (int32_t)m, (int32_t)r0, 0});
+  *nwg_out = nwg;
+}
+
+// Bytes of the bundle workspace, and the offsets of every bundle's tables.
+size_t bundle_layout(const Plan* pl, const int32_t* bundle_of, int32_t nb, Bundles* out) {
+  const Prob& p = pl->P[0];
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t a = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return a;
+  };
+  Bundles B;
+  B.nb = nb;
+  B.b.resize(nb);
+  for (int i = 0; i < nb; ++i) {
+    BundleHost h;
+    int nwg = 0;
+    bundle_build(pl, bundle_of, i, &h, &nwg);
+    BundleSched& bs = B.b[i];
+    bs.nwg = nwg;
+    bs.nseg = h.seg_m.size();
+    bs.nmtasks = h.mtasks.size();
+    bs.o_seg_p = take(bs.nseg * 4);
+    bs.o_seg_m = take(bs.nseg * 4);
+    bs.o_seg_j0 = take(bs.nseg * 8);
+    bs.o_seg_j1 = take(bs.nseg * 8);
+    bs.o_seg_poff = take(bs.nseg * 8);
+    bs.o_wg_seg = take(((size_t)nwg + 1) * 4);
+    bs.o_mseg = take(((size_t)p.M + 1) * 4);
+    bs.o_mpoff = take(bs.nseg * 8);
+    bs.o_mtasks = take(bs.nmtasks * sizeof(mam::MargTask));
+  }
+  if (out) *out = B;
+  return o;
+}
+
+mam_status plan_set_bundles(Plan* pl, const int32_t* bundle_of, int32_t nb, void* ws, size_t bytes, hipStream_t st) {
+  TRY(bundle_check(pl, bundle_of, nb));
+  if (!pl->inited) return fail(MAM_ESTATE, "mam_init has not run");
+  if (!ws) return fail(MAM_ENOMEM, "bundle workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(MAM_EINVAL, "bundle workspace must be 256-byte aligned");
+  Bundles B;
+  const size_t need = bundle_layout(pl, bundle_of, nb, &B);
+  if (bytes < need) return fail(MAM_ENOMEM, "bundle workspace has %zu bytes, needs %zu", bytes, need);
+  const Prob& p = pl->P[0];
+  for (int i = 0; i < nb; ++i) {
+    // a bundle's partials fit in the plan's partial buffer
+    if (B.b[i].nseg * (size_t)p.R > pl->partial_cap) return fail(MAM_EUNSUPPORTED, "bundle %d has too many segments", i);
+  }
+  B.ws = static_cast<char*>(ws);
+  for (int i = 0; i < nb; ++i) {
+    BundleHost h;
+    int nwg = 0;
+    bundle_build(pl, bundle_of, i, &h, &nwg);
+    const BundleSched& bs = B.b[i];
+    auto put = [&](size_t off, const void* src, size_t n) -> mam_status {
+      if (n) HIP_TRY(hipMemcpyAsync(B.ws + off, src, n, hipMemcpyHostToDevice, st));
+      return MAM_OK;
+    };
+    TRY(put(bs.o_seg_p, h.seg_p.data(), h.seg_p.size() * 4));
+    TRY(put(bs.o_seg_m, h.seg_m.data(), h.seg_m.size() * 4));
+    TRY(put(bs.o_seg_j0, h.seg_j0.data(), h.seg_j0.size() * 8));
+    TRY(put(bs.o_seg_j1, h.seg_j1.data(), h.seg_j1.size() * 8));
+    TRY(put(bs.o_seg_poff, h.seg_poff.data(), h.seg_poff.size() * 8));
+    TRY(put(bs.o_wg_seg, h.wg_seg.data(), h.wg_seg.size() * 4));
+    TRY(put(bs.o_mseg, h.mseg.data(), h.mseg.size() * 4));
+    TRY(put(bs.o_mpoff, h.mpoff.data(), h.mpoff.size() * 8));
+    TRY(put(bs.o_mtasks, h.mtasks.data(), h.mtasks.size() * sizeof(mam::MargTask)));
+    HIP_TRY(hipStreamSynchronize(st));  // host staging is released at the end of this loop body
+  }
+  pl->bund = B;
+  return MAM_OK;
+}
+
+template <typename T>
+mam_status launch_bundle_columns(Plan* pl, const BundleSched& bs, hipStream_t st) {
+  const Layout& L = pl->lay;
+  const Group& g = pl->G[0];
+  char* bw = pl->bund.ws;
+  mam::ColArgs<T> a;
+  a.probs = at<mam::ProbDev<T>>(pl, L.probdev);
+  a.seg_p = reinterpret_cast<const int32_t*>(bw + bs.o_seg_p);
+  a.seg_m = reinterpret_cast<const int32_t*>(bw + bs.o_seg_m);
+  a.seg_j0 = reinterpret_cast<const int64_t*>(bw + bs.o_seg_j0);
+  a.seg_j1 = reinterpret_cast<const int64_t*>(bw + bs.o_seg_j1);
+  a.seg_poff = reinterpret_cast<const int64_t*>(bw + bs.o_seg_poff);
+  a.wg_seg = reinterpret_cast<const int32_t*>(bw + bs.o_wg_seg);
+  a.partial = at<double>(pl, L.partial);
+  a.diag = at<double>(pl, L.diag);
+  a.rec = nullptr;
+  a.rec_ld = 0;
+  a.nwg = bs.nwg;
+  a.xcd_remap = 0;
+  const int kc = g.vec == 1 ? 1 : g.kc;
+  mam::ColFn<T> fn = mam::pick_column<T>(g.nt, g.vpt, g.vec, kc, 0, g.stream);
+  if (!fn) return fail(MAM_EUNSUPPORTED, "no column kernel for nt=%d vpt=%d vec=%d kc=%d", g.nt, g.vpt, g.vec, kc);
+  const int wgsize = g.nt == 64 ? 256 : g.nt;
+  const size_t shmem = (size_t)g.vpt * g.nt * 8 * (1 + g.ng);
+  if (shmem > 65536)
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shmem));
+  hipLaunchKernelGGL(fn, dim3(bs.nwg), dim3(wgsize), shmem, st, a);
+  LAUNCH_CHECK("column_kernel");
+  return MAM_OK;
+}
+
+mam_status plan_iterate_bundles(Plan* pl, int64_t iters, const int32_t* seq, hipStream_t st) {
+  if (iters < 0) return fail(MAM_EINVAL, "iters must be >= 0");
+  if (!pl->inited) return fail(MAM_ESTATE, "mam_init has not run");
+  if (!pl->bund.nb) return fail(MAM_ESTATE, "mam_set_bundles has not run");
+  if (iters > 0 && !seq) return fail(MAM_EINVAL, "seq is NULL");
+  for (int64_t k = 0; k < iters; ++k)
+    if (seq[k] < 0 || seq[k] >= pl->bund.nb)
+      return fail(MAM_EINVAL, "seq[%lld] = %d is not a bundle", (long long)k, seq[k]);
+  const Layout& L = pl->lay;
+  for (int64_t k = 0; k < iters; ++k) {
+    const BundleSched& bs = pl->bund.b[seq[k]];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (pl->timing) {
+      e0 = next_event(pl);
+      e1 = next_event(pl);
+      if (!e0 || !e1) return fail(MAM_EHIP, "hipEventCreate failed");
+      HIP_TRY(hipEventRecord(e0, st));
+    }
+    TRY(pl->dtype == MAM_F32 ? launch_bundle_columns<float>(pl, bs, st) : launch_bundle_columns<double>(pl, bs, st));
+    if (pl->timing) HIP_TRY(hipEventRecord(e1, st));
+    // new marginals of the bundle's measures only, then the average of all
+    hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)bs.nmtasks), dim3(256), 0, st,
+                       reinterpret_cast<const mam::MargTask*>(pl->bund.ws + bs.o_mtasks),
+                       at<mam::ProbAux>(pl, L.probaux), reinterpret_cast<const int32_t*>(pl->bund.ws + bs.o_mseg),
+                       reinterpret_cast<const int64_t*>(pl->bund.ws + bs.o_mpoff), at<double>(pl, L.partial), 0);
+    LAUNCH_CHECK("marginal_kernel");
+    hipLaunchKernelGGL(mam::average_kernel, dim3((unsigned)pl->atasks.size()), dim3(256), 0, st,
+                       at<mam::AvgTask>(pl, L.atasks), at<mam::ProbAux>(pl, L.probaux), 0);
+    LAUNCH_CHECK("average_kernel");
+  }
+  pl->iters_done += iters;
+  pl->diag_valid = false;
+  return MAM_OK;
+}
+
 }  // namespace
 
 struct mam_problem {
@@ -1519,6 +1747,23 @@ mam_status mam_record(mam_problem* p, int64_t iters, int64_t ckpt_every, void* a
 mam_status mam_backward(mam_problem* p, const double* grad_p, void* grad_q, void* grad_cost, void* stream) {
   if (!p) return fail(MAM_EINVAL, "NULL handle");
   return plan_backward(&p->plan, grad_p, grad_q, grad_cost, static_cast<hipStream_t>(stream));
+}
+
+// ---- randomized variant ----------------------------------------------------
+size_t mam_bundle_workspace_bytes(const mam_problem* p, const int32_t* bundle_of, int32_t nb) {
+  if (!p || bundle_check(&p->plan, bundle_of, nb) != MAM_OK) return 0;
+  return bundle_layout(&p->plan, bundle_of, nb, nullptr);
+}
+
+mam_status mam_set_bundles(mam_problem* p, const int32_t* bundle_of, int32_t nb, void* bundle_ws, size_t bytes,
+                           void* stream) {
+  if (!p) return fail(MAM_EINVAL, "NULL handle");
+  return plan_set_bundles(&p->plan, bundle_of, nb, bundle_ws, bytes, static_cast<hipStream_t>(stream));
+}
+
+mam_status mam_iterate_bundles(mam_problem* p, int64_t iters, const int32_t* seq, void* stream) {
+  if (!p) return fail(MAM_EINVAL, "NULL handle");
+  return plan_iterate_bundles(&p->plan, iters, seq, static_cast<hipStream_t>(stream));
 }
 
 void mam_destroy(mam_problem* p) { delete p; }

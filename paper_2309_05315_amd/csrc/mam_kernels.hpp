@@ -24,10 +24,11 @@
 // step on f is lambda_{k+1} = (sum_{w > lambda_k} w - tau) / |{w > lambda_k}|;
 // it increases monotonically and stops on the exact root as soon as the
 // active set no longer shrinks, so the loop ends after at most R+1 passes
-// (in practice 2-3) with the same lambda as the sort-based formula, up to
-// summation order.  The column stays in registers (held as w in double) for
-// all passes; each pass is one compare/select/add per value plus a group
-// reduction.
+// (2-3 from this cold start) with the same lambda as the sort-based formula,
+// up to summation order.  Started from the column's threshold of the previous
+// iteration, one pass usually both moves to and certifies the root.  The
+// column stays in registers (held as w in double) for all passes; each pass
+// is one compare/select/add per value plus a group reduction.
 //
 // All reductions have a fixed order, so results are bitwise reproducible
 // run to run; there are no floating-point atomics.
@@ -362,6 +363,12 @@ struct Rounds {
 // equal counts mean equal sets) or when min_A w >= lam' >= max_{not A} w;
 // then lam' is the root itself, so one round usually both moves and
 // verifies.  Entries equal to lam' contribute 0 either way.
+//
+// Loads ahead.  Everything a column step needs (raw theta and c, q_s, the
+// stored threshold, and for an indexed cost the cost column number one step
+// earlier still) is requested PF steps before the step runs, so no load
+// waits inside a step.  STREAM instances load and store theta with the
+// non-temporal policy (plans larger than the Infinity Cache).
 //
 // Dynamic LDS: VPT*NT doubles of b^(m) (each thread reads only its own
 // slots), then NG*VPT*NT doubles of row-sum patches, one block per group.

@@ -39,7 +39,8 @@ EXPORTED = ["mam_abi_version", "mam_last_error", "mam_create", "mam_set_schedule
             "mam_batch_get_schedule", "mam_batch_workspace_bytes", "mam_batch_set_workspace",
             "mam_batch_bind", "mam_batch_init", "mam_batch_iterate", "mam_batch_graph",
             "mam_batch_barycenter", "mam_batch_timing_enable", "mam_batch_timing_read",
-            "mam_batch_destroy", "mam_adjoint_workspace_bytes", "mam_record", "mam_backward"]
+            "mam_batch_destroy", "mam_adjoint_workspace_bytes", "mam_record", "mam_backward",
+            "mam_bundle_workspace_bytes", "mam_set_bundles", "mam_iterate_bundles"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmam.so")
 
@@ -130,6 +131,9 @@ def lib() -> ctypes.CDLL:
         "mam_adjoint_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int64, ctypes.c_int64]),
         "mam_record": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_size_t, _vp]),
         "mam_backward": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+        "mam_bundle_workspace_bytes": (ctypes.c_size_t, [_vp, _vp, ctypes.c_int32]),
+        "mam_set_bundles": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
+        "mam_iterate_bundles": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -256,6 +260,24 @@ class Solver:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(lib().mam_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)), "mam_timing_read")
         return ms.value, n.value
+
+    # -- randomized variant --------------------------------------------------
+    def set_bundles(self, bundle_of: Sequence[int]) -> None:
+        """Partition the measures into bundles (bundle_of[m] = bundle of measure m)."""
+        arr = (ctypes.c_int32 * self.M)(*[int(b) for b in bundle_of])
+        nb = max(int(b) for b in bundle_of) + 1
+        n = int(lib().mam_bundle_workspace_bytes(self._h, arr, nb))
+        if n == 0:
+            raise MAMError(-1, "mam_bundle_workspace_bytes", "invalid partition")
+        self.bundle_workspace = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib().mam_set_bundles(self._h, arr, nb, _ptr(self.bundle_workspace), n, _stream(self.device)),
+               "mam_set_bundles")
+
+    def iterate_bundles(self, seq: Sequence[int]) -> None:
+        """One randomized iteration per entry of seq (the bundle it updates)."""
+        s = np.ascontiguousarray(np.asarray(seq, dtype=np.int32))
+        _check(lib().mam_iterate_bundles(self._h, int(s.size), s.ctypes.data_as(_vp), _stream(self.device)),
+               "mam_iterate_bundles")
 
     # -- reverse mode --------------------------------------------------------
     def record(self, iters: int, ckpt_every: int = 0) -> None:

@@ -156,3 +156,19 @@ def test_reverse_mode_validation():
     assert L.mam_backward(None, fake, fake, fake, None) == -1
     assert L.mam_backward(h, fake, fake, fake, None) == -7      # no record yet
     L.mam_destroy(h)
+
+
+def test_bundle_validation():
+    L = mam.lib()
+    rc, h = create(R=50, S=[10, 20, 30])
+    assert rc == 0
+    B3 = ctypes.c_int32 * 3
+    assert L.mam_bundle_workspace_bytes(None, B3(0, 1, 2), 3) == 0
+    assert L.mam_bundle_workspace_bytes(h, B3(0, 3, 1), 3) == 0        # index out of range
+    assert L.mam_bundle_workspace_bytes(h, B3(0, 0, 2), 3) == 0        # bundle 1 is empty
+    assert L.mam_bundle_workspace_bytes(h, B3(0, 1, 0), 2) > 0
+    fake = ctypes.c_void_p(0x100000)
+    assert L.mam_set_bundles(None, B3(0, 1, 0), 2, fake, 1 << 20, None) == -1
+    assert L.mam_set_bundles(h, B3(0, 1, 0), 2, fake, 1 << 20, None) == -7   # no init yet
+    assert L.mam_iterate_bundles(h, 1, None, None) == -7
+    L.mam_destroy(h)

@@ -10,7 +10,7 @@ and barycenter in FP64).  The default run times the 500 iterations that
 problem is quoted at, then the same 500 iterations with FP64 plans, and
 reports the FP32-vs-FP64 barycenter difference.  Shorter runs of the other
 workloads (balanced FP64 with graph replay, unbalanced, a batch of 256
-problems, the reverse mode) are reported under "extras".
+problems, the randomized variant, the reverse mode) are reported under "extras".
 
 Prints one JSON line:  metric, value (plan-entry updates per second), the
 roofline of the dominant kernel (the column kernel, timed with HIP events on
@@ -166,6 +166,26 @@ def extra_workloads(torch, mam, inputs, log):
                             "column_kernels_ms": col / n, "column_kernels_GBs": ab / (col / n * 1e-3) / 1e9,
                             "plan_entries": int(sum(p.R * p.T for p in probs))}
     log(f"batch of {len(probs)}: {dt * 1e3:.4f} ms/iter (graph), column kernels {col / n:.4f} ms")
+
+    # randomized variant on the benchmark workload: 4 bundles of 8 measures,
+    # drawn with probability proportional to alpha_m = 1/M (the same seeded draws
+    # for every run)
+    p2 = inputs.balanced_sparse(dtype="f32")
+    bundles = [list(range(i, p2.M, 4)) for i in range(4)]
+    bundle_of = [m % 4 for m in range(p2.M)]
+    seq = inputs.bundle_sequence(bundles, 200, seed=0)
+    s = mam.solver_for(p2)
+    s.init()
+    s.set_bundles(bundle_of)
+    s.iterate_bundles(seq[:20])
+    dt = timed(lambda: s.iterate_bundles(seq[20:]))
+    n_it = len(seq) - 20
+    ent = sum(p2.R * sum(p2.S[m] for m in bundles[b]) for b in seq[20:])
+    s.close()
+    out["randomized_4_bundles_K64_M32_f32"] = {
+        "iterations": n_it, "ms_per_iter": dt / n_it * 1e3, "plan_entry_updates_per_s": ent / dt,
+        "entries_per_iter": ent / n_it}
+    log(f"randomized, 4 bundles: {dt / n_it * 1e3:.4f} ms/iter, {ent / dt:.3e} entries/s")
 
     # reverse mode: 64x64 grid, 8 measures, 100 iterations, FP32, loss ||p_bar - target||^2
     p5, tgt = inputs.adjoint_problem()

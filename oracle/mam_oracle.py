@@ -24,6 +24,8 @@ Functions and the passage each follows:
   since the columns are independent given the marginals, Prop. 3).
 * ``diagnostics``  the stopping quantities of Sec. 5 (Stopping criteria) and
   the objective/feasibility figures used in Sec. 6.3.
+* ``mam_until``  Alg. 1 with one of the stopping tests of Sec. 5 (Stopping
+  criteria) evaluated every few iterations in place of "while not converged".
 
 Readings where the paper is silent or loose (each is listed in the design doc):
 
@@ -54,6 +56,8 @@ __all__ = [
     "mam_step_columns",
     "mam",
     "diagnostics",
+    "mam_until",
+    "STOP_TESTS",
     "sq_euclid_cost",
 ]
 
@@ -284,6 +288,58 @@ def diagnostics(cost: List[np.ndarray], q: List[np.ndarray], pi_hat: List[np.nda
     res = max(float(np.abs(ph.sum(axis=0) - qm).max()) for ph, qm in zip(pi_hat, q))
     dth = max(float(np.abs(a - b).max()) for a, b in zip(theta_new, theta_old))
     return {"W_hat": W, "dist_L": dist_L(pi_hat), "meas_resid": res, "dtheta_inf": dth}
+
+
+STOP_TESTS = ("dtheta", "dp", "dist")
+
+
+def mam_until(cost: List[np.ndarray], q: List[np.ndarray], rho: float, max_iters: int,
+              test: str, tol: float, check_every: int = 1, gamma: float = math.inf) -> Dict:
+    """Alg. 1 run until a stopping test of Sec. 5 holds, at most ``max_iters``
+    iterations.  After iteration j (j = 1, 2, ...) with j a multiple of
+    ``check_every`` the test is evaluated on that iteration, and the run stops
+    as soon as its value is <= tol:
+
+    * "dtheta": ||theta^{k+1} - theta^k||_inf over every plan entry;
+    * "dp":     ||p^{k+1} - p^k||_2, p^k = sum_m a_m p^(m) of theta^k;
+    * "dist":   dist_L(pi_hat^k), the distance of the projected plans to the
+      balanced set (the test the paper calls heuristic).
+
+    Returns a dict with ``iters`` (iterations run), ``converged``, ``values``
+    (the test's value at every check, in order), ``p_bar``, ``theta``, ``pm``.
+    """
+    if test not in STOP_TESTS:
+        raise ValueError(f"unknown stopping test {test!r}")
+    if check_every < 1:
+        raise ValueError("check_every must be >= 1")
+    cost = [np.asarray(c, dtype=np.float64) for c in cost]
+    q = [np.asarray(v, dtype=np.float64) for v in q]
+    R = cost[0].shape[0]
+    S = [c.shape[1] for c in cost]
+    a = averaging_weights(S)
+    theta = [np.repeat((qm / R)[None, :], R, axis=0) for qm in q]
+    pm = marginals(theta)
+    values: List[float] = []
+    converged = False
+    j = 0
+    while j < max_iters:
+        theta_new, pm_new, info = mam_step(theta, pm, cost, q, rho, gamma)
+        j += 1
+        if j % check_every == 0:
+            if test == "dtheta":
+                v = max(float(np.abs(tn - to).max()) for tn, to in zip(theta_new, theta))
+            elif test == "dp":
+                p_new = (a[:, None] * pm_new).sum(axis=0)
+                v = float(np.sqrt(((p_new - info["p"]) ** 2).sum()))
+            else:
+                v = dist_L(info["pi_hat"])
+            values.append(v)
+            converged = v <= tol
+        theta, pm = theta_new, pm_new
+        if converged:
+            break
+    p_bar = (a[:, None] * pm).sum(axis=0)
+    return {"iters": j, "converged": converged, "values": values, "p_bar": p_bar, "theta": theta, "pm": pm}
 
 
 def sq_euclid_cost(xi: np.ndarray, zeta: np.ndarray, normalize_max: bool = False) -> np.ndarray:

@@ -39,6 +39,7 @@ __all__ = [
     "adjoint_problem",
     "batched_problems",
     "tiny_problem",
+    "line_problem",
 ]
 
 
@@ -298,6 +299,25 @@ def tiny_problem(seed: int, R: int, S: List[int], dtype: str = "f64",
         name=f"tiny_R{R}_M{M}", R=R, S=list(S), cost=_round(np.ascontiguousarray(cost), dtype),
         q=_round(np.concatenate(qs), dtype), col_index=col_index, rho=rho,
         gamma=gamma, iters=iters, dtype=dtype, meta={"seed": seed})
+
+
+def line_problem(seed: int, R: int, M: int, dtype: str = "f64", rho: float = 1.0,
+                 gamma: float = float("inf"), iters: int = 10) -> Problem:
+    """M measures on the barycenter's own support, R points 0, 1, ..., R-1 on
+    a line, with the unscaled cost c_rs = (r - s)^2 (zero diagonal, gaps of
+    at least 1 off it) shared by every measure.  Weights uniform in (0, 1],
+    normalised to mass 1."""
+    rng = np.random.default_rng([8, seed])
+    x = np.arange(R, dtype=np.float64)
+    cost = (x[:, None] - x[None, :]) ** 2
+    qs = []
+    for _ in range(M):
+        w = rng.uniform(0, 1, size=R) + 1e-3
+        qs.append(w / w.sum())
+    return Problem(
+        name=f"line_R{R}_M{M}", R=R, S=[R] * M, cost=_round(cost, dtype),
+        q=_round(np.concatenate(qs), dtype), col_index=None, rho=rho, gamma=gamma,
+        iters=iters, dtype=dtype, meta={"seed": seed})
 
 
 def bundle_sequence(bundles, iters: int, seed: int = 0, alpha=None) -> np.ndarray:

@@ -185,6 +185,45 @@ mam_status mam_init(mam_problem* p, const void* theta0, void* stream);
  * Alg. 1).  Asynchronous.  Errors: MAM_ESTATE before mam_init. */
 mam_status mam_iterate(mam_problem* p, int64_t iters, void* stream);
 
+/* ---- stopping tests ----------------------------------------------------------
+ * Alg. 1 with "while not converged" made concrete by one of the stopping
+ * tests of Sec. 5 (Stopping criteria), evaluated on the device.  After every
+ * check_every-th iteration of the run (iterations j = check_every,
+ * 2 check_every, ... counted from the call) the test's value is computed for
+ * that iteration; when value <= tol the run stops there: the plans and
+ * marginals stay at that iterate, and every launch the library had already
+ * enqueued for the run returns at once (a flag in the workspace gates
+ * them).  A NaN value never stops the run.
+ *   MAM_STOP_DTHETA: ||theta^{k+1} - theta^k||_inf over all plan entries, in
+ *                    the stored precision (the check iteration computes the
+ *                    diagnostics of mam_diag);
+ *   MAM_STOP_DP:     ||p^{k+1} - p^k||_2 of the averaged marginals;
+ *   MAM_STOP_DIST:   dist_L(pi_hat^k), distance of the projected plans to
+ *                    the balanced set (a heuristic test, Sec. 5). */
+#define MAM_STOP_DTHETA 0
+#define MAM_STOP_DP     1
+#define MAM_STOP_DIST   2
+
+typedef struct mam_stop_result {
+  int64_t iterations;   /* iterations run by the call                           */
+  int64_t checks;       /* tests evaluated                                      */
+  int32_t converged;    /* 1 if the test held (the run stopped on it)           */
+  double value;         /* value at the last check (NaN if no check ran)        */
+} mam_stop_result;
+
+/* Run at most max_iters >= 0 iterations with stopping test 'test' (MAM_STOP_*)
+ * and tolerance tol (not NaN) evaluated every check_every >= 1 iterations;
+ * iterations past the last multiple of check_every run without a test.
+ * Single problems.  Periods of check_every iterations run from a captured
+ * HIP graph when mam_graph has turned graphs on (and timing is off), else as
+ * plain launches; at most max(2, ceil(32/check_every)) periods are in flight.
+ * SYNCHRONIZES the stream (it returns when the run has ended) and fills
+ * *out.  mam_diagnostics afterwards describes the last iteration when it was
+ * a MAM_STOP_DTHETA check.  Errors: MAM_EINVAL (arguments), MAM_ESTATE
+ * (before mam_init), MAM_EUNSUPPORTED (batch). */
+mam_status mam_iterate_until(mam_problem* p, int64_t max_iters, int32_t test, double tol, int64_t check_every,
+                             mam_stop_result* out, void* stream);
+
 /* Barycenter p-bar = sum_m a_m p^(m) of the current plans: R doubles into
  * the device buffer p_dev (asynchronous) or the host buffer p_host
  * (synchronizes). */

@@ -112,6 +112,7 @@ struct Group {
 struct Layout {
   size_t partial = 0, diag = 0, seg_p = 0, seg_m = 0, seg_j0 = 0, seg_j1 = 0, seg_poff = 0, seg_idx = 0;
   size_t wg_seg = 0, mseg = 0, probdev = 0, probaux = 0, mtasks = 0, atasks = 0;
+  size_t stop = 0, stop_part = 0;  // stopping-test state and row-block partials
   size_t total = 0;
 };
 
@@ -194,8 +195,20 @@ struct Plan {
   std::vector<hipEvent_t> gjoin;
   hipEvent_t gfork = nullptr;
   bool capturing = false;  // forks are worth their event calls only inside a graph
+  // runs with an on-device stopping test: the gate flag every launch of such
+  // a run checks (null otherwise), a host-visible copy of it, the graph of
+  // one check period and the events that bound the periods in flight
+  const int32_t* gate = nullptr;
+  int32_t* host_flag = nullptr;
+  hipGraphExec_t uexec = nullptr;
+  int utest = -1;
+  int64_t uevery = 0;
+  std::vector<hipEvent_t> uev;
 
   ~Plan() {
+    for (hipEvent_t e : uev) hipEventDestroy(e);
+    if (uexec) hipGraphExecDestroy(uexec);
+    if (host_flag) hipHostFree(host_flag);
     for (hipEvent_t e : ev) hipEventDestroy(e);
     for (hipEvent_t e : gjoin) hipEventDestroy(e);
     if (gfork) hipEventDestroy(gfork);
@@ -501,6 +514,8 @@ void build_layout(Plan* pl) {
   L.probaux = take(pl->P.size() * sizeof(mam::ProbAux));
   L.mtasks = take(pl->mtasks.size() * sizeof(mam::MargTask));
   L.atasks = take(pl->atasks.size() * sizeof(mam::AvgTask));
+  L.stop = take(sizeof(mam::StopState));
+  L.stop_part = take((size_t)pl->P[0].nb * 8);
   for (Prob& p : pl->P) {
     const size_t R = (size_t)p.R, M = (size_t)p.M;
     p.o_pm = take(M * R * 8);
@@ -582,6 +597,17 @@ void get_group_schedule(const Plan* pl, int gi, mam_schedule* s) {
   s->streaming = g.stream ? 1 : -1;
 }
 
+void drop_graphs(Plan* pl) {
+  if (pl->gexec) {
+    hipGraphExecDestroy(pl->gexec);
+    pl->gexec = nullptr;
+  }
+  if (pl->uexec) {
+    hipGraphExecDestroy(pl->uexec);
+    pl->uexec = nullptr;
+  }
+}
+
 mam_status set_workspace(Plan* pl, void* dev, size_t bytes) {
   if (!dev) return fail(MAM_ENOMEM, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(dev) % kAlign) return fail(MAM_EINVAL, "workspace must be 256-byte aligned");
@@ -616,10 +642,7 @@ mam_status bind(Plan* pl, int i, void* theta, const void* cost, const int32_t* c
   g.vec = (all && g.vpt >= vn) ? vn : 1;
   pl->inited = false;
   pl->tables_uploaded = false;
-  if (pl->gexec) {  // a captured graph holds the old buffers
-    hipGraphExecDestroy(pl->gexec);
-    pl->gexec = nullptr;
-  }
+  drop_graphs(pl);  // a captured graph holds the old buffers
   return MAM_OK;
 }
 
@@ -739,6 +762,7 @@ mam_status launch_columns(Plan* pl, hipStream_t st, int diag, uint8_t* rec, int6
     a.diag = at<double>(pl, L.diag) + (size_t)g.wg_base * mam::DIAG_STRIDE;
     a.rec = rec;
     a.rec_ld = rec_ld;
+    a.stop = pl->gate;
     a.nwg = g.nwg;
     a.xcd_remap = g.xcd_remap;
     const int kc = g.vec == 1 ? 1 : g.kc;
@@ -764,10 +788,10 @@ mam_status launch_marginals(Plan* pl, hipStream_t st, int save_prev) {
   const Layout& L = pl->lay;
   hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
                      at<mam::MargTask>(pl, L.mtasks), at<mam::ProbAux>(pl, L.probaux), at<int32_t>(pl, L.mseg),
-                     at<int64_t>(pl, L.seg_idx), at<double>(pl, L.partial), save_prev);
+                     at<int64_t>(pl, L.seg_idx), at<double>(pl, L.partial), save_prev, pl->gate);
   LAUNCH_CHECK("marginal_kernel");
   hipLaunchKernelGGL(mam::average_kernel, dim3((unsigned)pl->atasks.size()), dim3(256), 0, st,
-                     at<mam::AvgTask>(pl, L.atasks), at<mam::ProbAux>(pl, L.probaux), save_prev);
+                     at<mam::AvgTask>(pl, L.atasks), at<mam::ProbAux>(pl, L.probaux), save_prev, pl->gate);
   LAUNCH_CHECK("average_kernel");
   return MAM_OK;
 }
@@ -876,10 +900,7 @@ mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
   }
   TRY(pl->dtype == MAM_F32 ? resident_workgroups<float>(pl, &rebuilt) : resident_workgroups<double>(pl, &rebuilt));
   if (rebuilt) build_schedule(pl);
-  if (pl->gexec) {
-    hipGraphExecDestroy(pl->gexec);
-    pl->gexec = nullptr;
-  }
+  drop_graphs(pl);
   TRY(upload_tables(pl, st));
   TRY(pl->dtype == MAM_F32 ? launch_checks<float>(pl, st) : launch_checks<double>(pl, st));
   for (size_t i = 0; i < pl->P.size(); ++i) {
@@ -910,7 +931,9 @@ mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
   return MAM_OK;
 }
 
-mam_status one_iteration(Plan* pl, hipStream_t st, int diag, uint8_t* rec = nullptr, int64_t rec_ld = 0) {
+// save_prev < 0: keep the previous marginals when computing diagnostics
+mam_status one_iteration(Plan* pl, hipStream_t st, int diag, uint8_t* rec = nullptr, int64_t rec_ld = 0,
+                         int save_prev = -1) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (pl->timing) {
     e0 = next_event(pl);
@@ -921,7 +944,7 @@ mam_status one_iteration(Plan* pl, hipStream_t st, int diag, uint8_t* rec = null
   TRY(pl->dtype == MAM_F32 ? launch_columns<float>(pl, st, diag, rec, rec_ld)
                             : launch_columns<double>(pl, st, diag, rec, rec_ld));
   if (pl->timing) HIP_TRY(hipEventRecord(e1, st));
-  return launch_marginals(pl, st, diag);
+  return launch_marginals(pl, st, save_prev < 0 ? diag : save_prev);
 }
 
 // Capture graph_iters iterations once on a stream of the library's own (a
@@ -983,6 +1006,134 @@ mam_status plan_graph(Plan* pl, int64_t iters) {
   }
   pl->graph_iters = iters;
   return MAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// runs with an on-device stopping test (Sec. 5, stopping criteria)
+// ---------------------------------------------------------------------------
+static_assert(offsetof(mam::StopState, stop) == 0, "the gate flag is the state's first word");
+static_assert(MAM_STOP_DTHETA == mam::STOP_DTHETA && MAM_STOP_DP == mam::STOP_DP &&
+                  MAM_STOP_DIST == mam::STOP_DIST,
+              "stopping-test codes");
+
+// One check period: every-1 plain iterations, then the check iteration
+// (diagnostics of the column kernel for the theta test, previous marginals
+// kept for the others) and the test itself, all gated by the stop flag.
+mam_status until_period(Plan* pl, hipStream_t st, int test, int64_t every) {
+  const Layout& L = pl->lay;
+  for (int64_t k = 0; k + 1 < every; ++k) TRY(one_iteration(pl, st, 0));
+  TRY(one_iteration(pl, st, test == MAM_STOP_DTHETA ? 1 : 0, nullptr, 0, 1));
+  mam::StopState* ss = at<mam::StopState>(pl, L.stop);
+  const Prob& pr = pl->P[0];
+  if (test != MAM_STOP_DTHETA) {
+    hipLaunchKernelGGL(mam::stop_partial_kernel, dim3((unsigned)pr.nb), dim3(256), 0, st,
+                       at<mam::ProbAux>(pl, L.probaux), at<double>(pl, pr.o_t), test, at<double>(pl, L.stop_part),
+                       ss);
+    LAUNCH_CHECK("stop_partial_kernel");
+  }
+  hipLaunchKernelGGL(mam::stop_final_kernel, dim3(1), dim3(256), 0, st, ss, test, at<double>(pl, L.stop_part),
+                     pr.nb, at<double>(pl, L.diag), pl->nwg_total, pl->host_flag);
+  LAUNCH_CHECK("stop_final_kernel");
+  return MAM_OK;
+}
+
+mam_status capture_until(Plan* pl, int test, int64_t every) {
+  if (!pl->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&pl->capture_stream, hipStreamNonBlocking));
+  if (pl->uexec) {
+    hipGraphExecDestroy(pl->uexec);
+    pl->uexec = nullptr;
+  }
+  HIP_TRY(hipStreamBeginCapture(pl->capture_stream, hipStreamCaptureModeThreadLocal));
+  pl->capturing = true;
+  const mam_status s = until_period(pl, pl->capture_stream, test, every);
+  pl->capturing = false;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(pl->capture_stream, &graph);
+  if (s != MAM_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(MAM_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  const hipError_t e2 = hipGraphInstantiate(&pl->uexec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e2 != hipSuccess) {
+    pl->uexec = nullptr;
+    return fail(MAM_EHIP, "graph instantiation failed: %s", hipGetErrorString(e2));
+  }
+  pl->utest = test;
+  pl->uevery = every;
+  return MAM_OK;
+}
+
+// Periods are enqueued with a bounded number in flight: before enqueuing
+// period i the host waits for period i - ahead and reads the host-visible
+// stop flag, so after the stop at most 'ahead' periods of gated (empty)
+// launches follow.  The gate makes the iterate exact whatever was enqueued.
+mam_status until_run(Plan* pl, int64_t max_iters, int test, double tol, int64_t every, hipStream_t st,
+                     mam_stop_result* out) {
+  const Layout& L = pl->lay;
+  if (!pl->host_flag) {
+    void* h = nullptr;
+    HIP_TRY(hipHostMalloc(&h, 256, hipHostMallocCoherent));
+    pl->host_flag = static_cast<int32_t*>(h);
+  }
+  *reinterpret_cast<volatile int32_t*>(pl->host_flag) = 0;
+  mam::StopState* ss = at<mam::StopState>(pl, L.stop);
+  hipLaunchKernelGGL(mam::stop_reset_kernel, dim3(1), dim3(64), 0, st, ss, tol);
+  LAUNCH_CHECK("stop_reset_kernel");
+  const int64_t periods = max_iters / every, tail = max_iters % every;
+  const bool graph = pl->graph_iters > 0 && !pl->timing;
+  if (graph && periods > 0 && (!pl->uexec || pl->utest != test || pl->uevery != every))
+    TRY(capture_until(pl, test, every));
+  const int64_t ahead = std::max<int64_t>(2, (32 + every - 1) / every);
+  while ((int64_t)pl->uev.size() < ahead) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    pl->uev.push_back(e);
+  }
+  bool seen_stop = false;
+  for (int64_t i = 0; i < periods; ++i) {
+    if (i >= ahead) {
+      HIP_TRY(hipEventSynchronize(pl->uev[(i - ahead) % ahead]));
+      if (*reinterpret_cast<volatile int32_t*>(pl->host_flag) != 0) {
+        seen_stop = true;
+        break;
+      }
+    }
+    if (graph) HIP_TRY(hipGraphLaunch(pl->uexec, st));
+    else TRY(until_period(pl, st, test, every));
+    HIP_TRY(hipEventRecord(pl->uev[i % ahead], st));
+  }
+  if (!seen_stop)
+    for (int64_t k = 0; k < tail; ++k) TRY(one_iteration(pl, st, 0));
+  mam::StopState hs{};
+  HIP_TRY(hipMemcpyAsync(&hs, ss, sizeof(hs), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  out->converged = hs.stop != 0;
+  out->checks = hs.checks;
+  out->value = hs.value;
+  out->iterations = hs.stop ? hs.checks * every : max_iters;
+  pl->iters_done += out->iterations;
+  // diagnostics stay valid when the last iteration run was a theta check
+  pl->diag_valid = test == MAM_STOP_DTHETA && out->iterations > 0 && (hs.stop || (tail == 0 && periods > 0));
+  return MAM_OK;
+}
+
+mam_status plan_iterate_until(Plan* pl, int64_t max_iters, int test, double tol, int64_t every,
+                              mam_stop_result* out, hipStream_t st) {
+  if (!out) return fail(MAM_EINVAL, "out is NULL");
+  *out = mam_stop_result{0, 0, 0, (double)NAN};
+  if (pl->batch) return fail(MAM_EUNSUPPORTED, "stopping tests run on single problems");
+  if (!pl->inited) return fail(MAM_ESTATE, "mam_init has not run");
+  if (max_iters < 0) return fail(MAM_EINVAL, "max_iters must be >= 0");
+  if (every < 1) return fail(MAM_EINVAL, "check_every must be >= 1");
+  if (test != MAM_STOP_DTHETA && test != MAM_STOP_DP && test != MAM_STOP_DIST)
+    return fail(MAM_EINVAL, "unknown stopping test %d", test);
+  if (std::isnan(tol)) return fail(MAM_EINVAL, "tol is NaN");
+  pl->gate = at<int32_t>(pl, pl->lay.stop);  // StopState.stop is its first member
+  const mam_status s = until_run(pl, max_iters, test, tol, every, st, out);
+  pl->gate = nullptr;
+  return s;
 }
 
 mam_status plan_timing_read(Plan* pl, double* total_ms, int64_t* launches) {
@@ -1315,7 +1466,7 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
                          at<mam::MargTask>(pl, L.mtasks), reinterpret_cast<const mam::ProbAux*>(A.ws + A.o_aux),
                          reinterpret_cast<const int32_t*>(A.ws + A.o_mseg),
                          reinterpret_cast<const int64_t*>(A.ws + A.o_seg_idx),
-                         reinterpret_cast<const double*>(A.ws + A.o_partial), 0);
+                         reinterpret_cast<const double*>(A.ws + A.o_partial), 0, nullptr);
       LAUNCH_CHECK("marginal_kernel");
       const unsigned nbr = (unsigned)((p.R + 255) / 256);
       if (!A.unbal) {
@@ -1506,6 +1657,7 @@ mam_status launch_bundle_columns(Plan* pl, const BundleSched& bs, hipStream_t st
   a.diag = at<double>(pl, L.diag);
   a.rec = nullptr;
   a.rec_ld = 0;
+  a.stop = nullptr;
   a.nwg = bs.nwg;
   a.xcd_remap = 0;
   const int kc = g.vec == 1 ? 1 : g.kc;
@@ -1545,10 +1697,11 @@ mam_status plan_iterate_bundles(Plan* pl, int64_t iters, const int32_t* seq, hip
     hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)bs.nmtasks), dim3(256), 0, st,
                        reinterpret_cast<const mam::MargTask*>(pl->bund.ws + bs.o_mtasks),
                        at<mam::ProbAux>(pl, L.probaux), reinterpret_cast<const int32_t*>(pl->bund.ws + bs.o_mseg),
-                       reinterpret_cast<const int64_t*>(pl->bund.ws + bs.o_mpoff), at<double>(pl, L.partial), 0);
+                       reinterpret_cast<const int64_t*>(pl->bund.ws + bs.o_mpoff), at<double>(pl, L.partial), 0,
+                       nullptr);
     LAUNCH_CHECK("marginal_kernel");
     hipLaunchKernelGGL(mam::average_kernel, dim3((unsigned)pl->atasks.size()), dim3(256), 0, st,
-                       at<mam::AvgTask>(pl, L.atasks), at<mam::ProbAux>(pl, L.probaux), 0);
+                       at<mam::AvgTask>(pl, L.atasks), at<mam::ProbAux>(pl, L.probaux), 0, nullptr);
     LAUNCH_CHECK("average_kernel");
   }
   pl->iters_done += iters;
@@ -1622,6 +1775,12 @@ mam_status mam_init(mam_problem* p, const void* theta0, void* stream) {
 mam_status mam_iterate(mam_problem* p, int64_t iters, void* stream) {
   if (!p) return fail(MAM_EINVAL, "NULL handle");
   return plan_iterate(&p->plan, iters, static_cast<hipStream_t>(stream));
+}
+
+mam_status mam_iterate_until(mam_problem* p, int64_t max_iters, int32_t test, double tol, int64_t check_every,
+                             mam_stop_result* out, void* stream) {
+  if (!p) return fail(MAM_EINVAL, "NULL handle");
+  return plan_iterate_until(&p->plan, max_iters, test, tol, check_every, out, static_cast<hipStream_t>(stream));
 }
 
 mam_status mam_graph(mam_problem* p, int64_t iters_per_launch) {

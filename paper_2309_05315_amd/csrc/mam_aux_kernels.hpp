@@ -38,7 +38,8 @@ struct AvgTask {
 __global__ void __launch_bounds__(256)
 marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ probs,
                 const int32_t* __restrict__ mseg, const int64_t* __restrict__ mpoff,
-                const double* __restrict__ partial, int save_prev) {
+                const double* __restrict__ partial, int save_prev, const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;  // early exit: the run has stopped
   const MargTask tk = tasks[blockIdx.x];
   const ProbAux& P = probs[tk.prob];
   const int R = uniform_i(P.R);
@@ -69,7 +70,9 @@ marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ 
 // p_r = sum_m a_m p^(m)_r, and the block's partial sum of
 // sum_r sum_m (p_r - p^(m)_r)^2 / S^m.
 __global__ void __launch_bounds__(256)
-average_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ probs, int save_prev) {
+average_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ probs, int save_prev,
+               const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;  // early exit: the run has stopped
   __shared__ double sh[4];
   const AvgTask tk = tasks[blockIdx.x];
   const ProbAux& P = probs[tk.prob];
@@ -111,6 +114,106 @@ average_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ pr
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d2;
   __syncthreads();
   if (threadIdx.x == 0) gptr(P.d2part)[tk.rb] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// ---------------------------------------------------------------------------
+// On-device stopping tests (Sec. 5, stopping criteria).  A run evaluates one
+// test after every check iteration; once it holds, the stop flag is set and
+// every later gated launch of the run (column, marginal, average and these
+// kernels) returns at once, so the plans stay at the iterate that passed.
+// ---------------------------------------------------------------------------
+constexpr int STOP_DTHETA = 0;  // ||theta^{k+1} - theta^k||_inf (the column kernel's diagnostics)
+constexpr int STOP_DP = 1;      // ||p^{k+1} - p^k||_2
+constexpr int STOP_DIST = 2;    // dist_L(pi_hat^k)
+
+struct StopState {
+  int32_t stop;    // 1 once the test held
+  int32_t pad;
+  int64_t checks;  // checks evaluated since the reset
+  double value;    // the test's value at the last check (NaN before any)
+  double tol;
+};
+
+__global__ void stop_reset_kernel(StopState* __restrict__ st, double tol) {
+  if (threadIdx.x == 0) {
+    st->stop = 0;
+    st->pad = 0;
+    st->checks = 0;
+    st->value = __builtin_nan("");
+    st->tol = tol;
+  }
+}
+
+// Per-block partial sums (256 rows a block) of the squared value of a test
+// that the marginals decide.  After a check iteration p and p^(m) hold the
+// new values, p_prev and pm_prev the ones the iteration started from, and
+// t_out its damping.
+//   STOP_DP:   sum_r (p_r - p_prev_r)^2
+//   STOP_DIST: the row sums of pi_hat^(m) are ph^(m) = p^(m) + t (p_prev - pm_prev^(m))
+//              (Step 2 subtracts t b^(m) from every column), and
+//              dist_L(pi_hat)^2 = sum_m ||ph - ph^(m)||^2 / S^m, ph = sum_m a_m ph^(m).
+__global__ void __launch_bounds__(256)
+stop_partial_kernel(const ProbAux* __restrict__ probs, const double* __restrict__ t_out, int test,
+                    double* __restrict__ part, const StopState* __restrict__ st) {
+  if (st->stop != 0) return;
+  __shared__ double sh[4];
+  const ProbAux& P = probs[0];
+  const int R = P.R, M = P.M;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (r < R) {
+    const double* const pm = gptr(P.pm);
+    const double* const pmp = gptr(P.pm_prev);
+    const double pr = gptr(P.p)[r], pp = gptr(P.p_prev)[r];
+    if (test == STOP_DP) {
+      v = (pr - pp) * (pr - pp);
+    } else {
+      const double t = *t_out;
+      double ph = 0.0;
+      for (int m = 0; m < M; ++m)
+        ph += P.aw[m] * (pm[(size_t)m * R + r] + t * (pp - pmp[(size_t)m * R + r]));
+      for (int m = 0; m < M; ++m) {
+        const double e = ph - (pm[(size_t)m * R + r] + t * (pp - pmp[(size_t)m * R + r]));
+        v += e * e / P.Sd[m];
+      }
+    }
+  }
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// Finish a check (one workgroup of 256): the test's value from the
+// partials (fixed order) or from the column kernel's per-workgroup maxima
+// of |theta^{k+1} - theta^k|; count the check; set the flag when
+// value <= tol (a NaN value never stops), also in the host-visible word.
+__global__ void __launch_bounds__(256)
+stop_final_kernel(StopState* __restrict__ st, int test, const double* __restrict__ part, int nparts,
+                  const double* __restrict__ diag, int nwg, int32_t* __restrict__ host_flag) {
+  __shared__ double sh[4];
+  if (st->stop != 0) return;
+  double v;
+  if (test == STOP_DTHETA) {
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < nwg; i += 256) mx = fmax(mx, diag[(size_t)i * DIAG_STRIDE + 2]);
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    v = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  } else {
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += part[i];
+    v = sqrt(s);
+  }
+  if (threadIdx.x == 0) {
+    st->checks += 1;
+    st->value = v;
+    if (v <= st->tol) {
+      st->stop = 1;
+      if (host_flag) *reinterpret_cast<volatile int32_t*>(host_flag) = 1;
+    }
+  }
 }
 
 // theta^0_rs = q_s / R (Alg. 1 Step 0 with the library's default start).

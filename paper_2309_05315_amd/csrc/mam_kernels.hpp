@@ -231,6 +231,8 @@ struct ColArgs {
   uint8_t* rec;           // null, or: per column j, the threads' active-set
                           // mask words at rec + j*rec_ld (single-problem plans)
   int64_t rec_ld;
+  const int32_t* stop;    // null, or a flag: nonzero once a stopping test
+                          // held, and then the launch does nothing
   int32_t nwg, xcd_remap;
 };
 
@@ -403,6 +405,8 @@ column_kernel(ColArgs<T> a) {
   const int lane = gtid & 63;
   const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
   double* fix = lds_fix + (size_t)g * VPT * NT;
+
+  if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;  // early exit: the run has stopped
 
   Rounds<NW, KC> rounds{red_d, red_f, red_i, 0};
   double dW = 0.0, dRes = 0.0, dTh = 0.0, dRounds = 0.0, dAct = 0.0, dCols = 0.0;

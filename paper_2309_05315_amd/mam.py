@@ -20,11 +20,13 @@ import torch
 
 __all__ = ["lib", "MAMError", "Solver", "Batch", "solver_for", "cost_sq_euclid",
            "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "FLAG_DIAG", "FLAG_COLD",
-           "EXPORTED"]
+           "STOP_TESTS", "EXPORTED"]
 
 F32, F64 = 0, 1
 COST_PER_COLUMN, COST_SHARED, COST_INDEXED = 0, 1, 2
 FLAG_DIAG, FLAG_COLD = 1, 2
+# stopping tests of Sec. 5 (MAM_STOP_*)
+STOP_TESTS = {"dtheta": 0, "dp": 1, "dist": 2}
 
 STATUS = {0: "MAM_OK", -1: "MAM_EINVAL", -2: "MAM_ENOMEM", -3: "MAM_EHIP",
           -4: "MAM_ENOTBALANCED", -5: "MAM_ENONFINITE", -6: "MAM_EUNSUPPORTED",
@@ -40,7 +42,8 @@ EXPORTED = ["mam_abi_version", "mam_last_error", "mam_create", "mam_set_schedule
             "mam_batch_bind", "mam_batch_init", "mam_batch_iterate", "mam_batch_graph",
             "mam_batch_barycenter", "mam_batch_timing_enable", "mam_batch_timing_read",
             "mam_batch_destroy", "mam_adjoint_workspace_bytes", "mam_record", "mam_backward",
-            "mam_bundle_workspace_bytes", "mam_set_bundles", "mam_iterate_bundles"]
+            "mam_bundle_workspace_bytes", "mam_set_bundles", "mam_iterate_bundles",
+            "mam_iterate_until"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmam.so")
 
@@ -67,6 +70,11 @@ class Schedule(ctypes.Structure):
                 ("columns_in_flight", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("vector_width", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("streaming", ctypes.c_int32)]
+
+
+class StopResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("checks", ctypes.c_int64),
+                ("converged", ctypes.c_int32), ("value", ctypes.c_double)]
 
 
 class MAMError(RuntimeError):
@@ -134,6 +142,8 @@ def lib() -> ctypes.CDLL:
         "mam_bundle_workspace_bytes": (ctypes.c_size_t, [_vp, _vp, ctypes.c_int32]),
         "mam_set_bundles": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
         "mam_iterate_bundles": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp]),
+        "mam_iterate_until": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                               ctypes.c_int64, ctypes.POINTER(StopResult), _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -232,6 +242,20 @@ class Solver:
 
     def iterate(self, iters: int) -> None:
         _check(lib().mam_iterate(self._h, int(iters), _stream(self.device)), "mam_iterate")
+
+    def iterate_until(self, max_iters: int, test: str = "dtheta", tol: float = 1e-8,
+                      check_every: int = 1) -> dict:
+        """Iterate until a stopping test of Sec. 5 holds ("dtheta", "dp" or
+        "dist", evaluated on the device every check_every iterations), at
+        most max_iters iterations.  Blocks until the run ends; returns
+        {"iterations", "checks", "converged", "value"}."""
+        if test not in STOP_TESTS:
+            raise ValueError(f"unknown stopping test {test!r}; one of {sorted(STOP_TESTS)}")
+        r = StopResult()
+        _check(lib().mam_iterate_until(self._h, int(max_iters), STOP_TESTS[test], float(tol), int(check_every),
+                                       ctypes.byref(r), _stream(self.device)), "mam_iterate_until")
+        return {"iterations": r.iterations, "checks": r.checks, "converged": bool(r.converged),
+                "value": r.value}
 
     def barycenter(self) -> torch.Tensor:
         out = torch.empty(self.R, dtype=torch.float64, device=self.device)

@@ -172,3 +172,15 @@ def test_bundle_validation():
     assert L.mam_set_bundles(h, B3(0, 1, 0), 2, fake, 1 << 20, None) == -7   # no init yet
     assert L.mam_iterate_bundles(h, 1, None, None) == -7
     L.mam_destroy(h)
+
+
+def test_stopping_test_validation():
+    L = mam.lib()
+    rc, h = create(R=40, S=[10, 20])
+    assert rc == 0
+    r = mam.StopResult()
+    assert L.mam_iterate_until(None, 5, 0, 1e-3, 1, ctypes.byref(r), None) == -1
+    assert L.mam_iterate_until(h, 5, 0, 1e-3, 1, None, None) == -1           # no result struct
+    assert L.mam_iterate_until(h, 5, 0, 1e-3, 1, ctypes.byref(r), None) == -7  # no init yet
+    assert r.iterations == 0 and r.checks == 0 and r.converged == 0 and math.isnan(r.value)
+    L.mam_destroy(h)

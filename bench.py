@@ -10,7 +10,8 @@ and barycenter in FP64).  The default run times the 500 iterations that
 problem is quoted at, then the same 500 iterations with FP64 plans, and
 reports the FP32-vs-FP64 barycenter difference.  Shorter runs of the other
 workloads (balanced FP64 with graph replay, unbalanced, a batch of 256
-problems, the randomized variant, the reverse mode) are reported under "extras".
+problems, the randomized variant, on-device stopping tests, the reverse mode)
+are reported under "extras".
 
 Prints one JSON line:  metric, value (plan-entry updates per second), the
 roofline of the dominant kernel (the column kernel, timed with HIP events on
@@ -186,6 +187,33 @@ def extra_workloads(torch, mam, inputs, log):
         "iterations": n_it, "ms_per_iter": dt / n_it * 1e3, "plan_entry_updates_per_s": ent / dt,
         "entries_per_iter": ent / n_it}
     log(f"randomized, 4 bundles: {dt / n_it * 1e3:.4f} ms/iter, {ent / dt:.3e} entries/s")
+
+    # stopping tests on the device (Sec. 5): the cost of a check every 10
+    # iterations against plain iterations (graph replay in both), on the
+    # benchmark workload and on the launch-bound 16x16 problem, and the time a
+    # run of at most 20000 iterations takes when its first check stops it
+    res = {}
+    for name, prob in (("K64_M32_f32", p2), ("K16_M4_f64", p1)):
+        s = mam.solver_for(prob)
+        s.graph(10)
+        s.init()
+        s.iterate(20)
+        r_ = {"plain_ms_per_iter": timed(lambda: s.iterate(200)) / 200 * 1e3}
+        for test in ("dp", "dist", "dtheta"):
+            s.init()
+            s.iterate_until(20, test, -1.0, 10)
+            r_[f"{test}_every_10_ms_per_iter"] = timed(lambda: s.iterate_until(200, test, -1.0, 10)) / 200 * 1e3
+        s.init()
+        got = {}
+        r_["stop_at_first_check_ms"] = timed(lambda: got.update(s.iterate_until(20000, "dp", float("inf"), 10))) * 1e3
+        r_["stop_at_first_check_iterations"] = got["iterations"]
+        s.close()
+        res[name] = r_
+        log(f"stopping tests {name}: plain {r_['plain_ms_per_iter']:.4f} ms/iter, with checks every 10: "
+            f"dp {r_['dp_every_10_ms_per_iter']:.4f}, dist {r_['dist_every_10_ms_per_iter']:.4f}, "
+            f"dtheta {r_['dtheta_every_10_ms_per_iter']:.4f}; stop at the first check of 20000: "
+            f"{r_['stop_at_first_check_ms']:.2f} ms")
+    out["stopping_tests"] = res
 
     # reverse mode: 64x64 grid, 8 measures, 100 iterations, FP32, loss ||p_bar - target||^2
     p5, tgt = inputs.adjoint_problem()

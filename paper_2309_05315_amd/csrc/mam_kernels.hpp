@@ -386,8 +386,9 @@ column_kernel(ColArgs<T> a) {
   static_assert(NG == 1 || NW == 1, "multi-wave groups fill the workgroup");
   // column steps whose raw loads are in flight at once: two for float plans
   // with vector loads and at most 512 threads per group, where the extra
-  // buffer still fits the register budget without spills
-  constexpr int PF = (sizeof(T) == 4 && KC == 1 && VEC > 1 && NT <= 512) ? 2 : 1;
+  // buffer still fits the register budget without spills (not with the
+  // diagnostics' extra state, which would halve the occupancy)
+  constexpr int PF = (sizeof(T) == 4 && KC == 1 && VEC > 1 && NT <= 512 && !DIAG) ? 2 : 1;
 
   __shared__ double red_d[NW > 1 ? 2 * KC * 2 * NW : 1];
   __shared__ float red_f[NW > 1 ? 2 * KC * 2 * NW : 1];

@@ -137,6 +137,16 @@ typedef struct mam_schedule {
                                  256 MiB, i.e. do not stay in the 256 MB
                                  Infinity Cache between iterations).  Applies to
                                  the vector-load, one-column-in-flight kernels. */
+  int32_t rows_per_tile;      /* long-column path (single problems): rows of a
+                                 column tile, 1024, 2048 or 4096.  0 automatic:
+                                 the path is taken when R > 8192, with 4096
+                                 (float) or 2048 (double) rows.  A value > 0
+                                 forces the path at any R.                      */
+  int32_t candidates_per_column; /* long-column path: capacity of a column's
+                                 candidate list (0 automatic: min(R, 4096)).
+                                 A column with more candidates in an iteration
+                                 is handled from theta and c directly (same
+                                 result, slower).                               */
 } mam_schedule;
 
 /* ABI version of this header (1). */

@@ -60,6 +60,8 @@ mam_status fail(mam_status code, const char* fmt, ...) {
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxLds = 160 * 1024;  // LDS per compute unit on gfx950
+constexpr int64_t kShortMaxR = 8192;      // longest column one workgroup holds in registers
+constexpr int64_t kLongMaxR = 1 << 28;    // row indices of the long-column path are int32
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int vec_width(int dtype) { return dtype == MAM_F32 ? 4 : 2; }
@@ -157,6 +159,20 @@ struct Bundles {
   std::vector<BundleSched> b;
 };
 
+// Long-column path (single problems with R beyond kShortMaxR, or forced by
+// the schedule): work items (row tile, measure, column range) split evenly
+// over the workgroups, candidate lists per column.
+struct LongPlan {
+  bool on = false;
+  int vpt = 16, rows = 4096, nrb = 0, cap = 0, vec = 1;
+  int nwg = 1, nwg_req = 0, nwg_auto = 0, rows_req = 0, cap_req = 0;
+  std::vector<int32_t> it_rb, it_m, wg_it;
+  std::vector<int64_t> it_j0, it_j1, it_poff;
+  size_t items_cap = 0;
+  size_t o_it_rb = 0, o_it_m = 0, o_it_j0 = 0, o_it_j1 = 0, o_it_poff = 0, o_wg_it = 0;
+  size_t o_cnt = 0, o_crow = 0, o_cw = 0, o_sub_off = 0, o_sub_cnt = 0;
+};
+
 struct Plan {
   int dtype = MAM_F64;
   bool batch = false;
@@ -180,6 +196,7 @@ struct Plan {
   int64_t iters_done = 0;
   Adjoint adj;
   Bundles bund;
+  LongPlan lg;
   bool diag_valid = false;
   // graph of a fixed number of iterations
   int64_t graph_iters = 0;
@@ -234,7 +251,7 @@ mam_status read_desc(const mam_desc* d, int index, Prob* out) {
   if (!d->S) return fail(MAM_EINVAL, "S is NULL");
   if (!(d->rho > 0.0) || !std::isfinite(d->rho)) return fail(MAM_EINVAL, "rho must be finite and > 0");
   if (!(d->gamma >= 0.0)) return fail(MAM_EINVAL, "gamma must be >= 0 (INFINITY = balanced)");
-  if (d->R > 8192) return fail(MAM_EUNSUPPORTED, "R = %lld exceeds 8192", (long long)d->R);
+  if (d->R > kLongMaxR) return fail(MAM_EUNSUPPORTED, "R = %lld exceeds %lld", (long long)d->R, (long long)kLongMaxR);
   if (d->M > 65535) return fail(MAM_EUNSUPPORTED, "M = %lld exceeds 65535", (long long)d->M);
   const int64_t ld = d->ld ? d->ld : d->R;
   const int64_t cld = d->cost_ld ? d->cost_ld : d->R;
@@ -397,7 +414,13 @@ int default_nwg(int64_t T, int ng, int req, int resident) {
 // Build the tables of every group.  The workspace capacity depends only on
 // the problem sizes and workgroup counts (not on an indexed cost's index),
 // so rebuilding after the index is known never grows it.
+void build_long_schedule(Plan* pl);
+
 void build_schedule(Plan* pl) {
+  if (pl->lg.on) {
+    build_long_schedule(pl);
+    return;
+  }
   pl->seg_p.clear();
   pl->seg_m.clear();
   pl->seg_j0.clear();
@@ -479,12 +502,92 @@ void build_schedule(Plan* pl) {
   for (size_t pi = 0; pi < pl->P.size(); ++pi) {
     const Prob& p = pl->P[pi];
     for (int64_t m = 0; m < p.M; ++m)
-      for (int64_t r0 = 0; r0 < p.R; r0 += 256) pl->mtasks.push_back({(int32_t)pi, (int32_t)m, (int32_t)r0, 0});
+      for (int64_t r0 = 0; r0 < p.R; r0 += 256)
+        pl->mtasks.push_back({(int32_t)pi, (int32_t)m, (int32_t)r0, (int32_t)m});
     for (int rb = 0; rb < p.nb; ++rb) pl->atasks.push_back({(int32_t)pi, rb});
   }
   if (!pl->ws) {
     pl->nseg_cap = cap_segs;
     pl->partial_cap = cap_part;
+  }
+  pl->tables_uploaded = false;
+}
+
+// Long-column schedule.  Units (row tile rb, column j) in the order
+// rb-major, then measure, then column are split into equal contiguous
+// shares, one per workgroup; each piece inside one (rb, measure) is an item
+// with its own RB-row partial.  The marginal kernel sums, for a row of tile
+// rb, the items of (measure, rb): list index m*nrb + rb.
+void build_long_schedule(Plan* pl) {
+  LongPlan& lg = pl->lg;
+  const Prob& p = pl->P[0];
+  const int vn = vec_width(pl->dtype);
+  lg.vpt = lg.rows_req ? lg.rows_req / 256 : (pl->dtype == MAM_F32 ? 16 : 8);
+  lg.rows = 256 * lg.vpt;
+  lg.nrb = (int)((p.R + lg.rows - 1) / lg.rows);
+  lg.cap = lg.cap_req ? lg.cap_req : (int)std::min<int64_t>(p.R, 4096);
+  if (!p.theta) lg.vec = vn;  // until binding checks the alignment
+  const int64_t units = (int64_t)lg.nrb * p.T;
+  const int64_t cap_wg = lg.nwg_auto > 0 ? std::min(lg.nwg_auto, 1024) : 1024;
+  lg.nwg = (int)std::max<int64_t>(1, std::min<int64_t>(lg.nwg_req > 0 ? lg.nwg_req : cap_wg, units));
+  lg.it_rb.clear();
+  lg.it_m.clear();
+  lg.it_j0.clear();
+  lg.it_j1.clear();
+  lg.it_poff.clear();
+  lg.wg_it.clear();
+  int rb = 0, m = 0;
+  int64_t pos = 0;  // columns of (rb, m) already given out
+  for (int w = 0; w < lg.nwg; ++w) {
+    int64_t need = units * (w + 1) / lg.nwg - units * w / lg.nwg;
+    lg.wg_it.push_back((int32_t)lg.it_rb.size());
+    while (need > 0 && rb < lg.nrb) {
+      const int64_t take = std::min(need, p.S[m] - pos);
+      lg.it_rb.push_back(rb);
+      lg.it_m.push_back(m);
+      lg.it_j0.push_back(p.col_off[m] + pos);
+      lg.it_j1.push_back(p.col_off[m] + pos + take);
+      lg.it_poff.push_back((int64_t)lg.it_rb.size() - 1);  // scaled below
+      need -= take;
+      pos += take;
+      if (pos == p.S[m]) {
+        pos = 0;
+        if (++m == p.M) {
+          m = 0;
+          ++rb;
+        }
+      }
+    }
+  }
+  lg.wg_it.push_back((int32_t)lg.it_rb.size());
+  for (auto& o : lg.it_poff) o *= lg.rows;
+  const int nl = (int)p.M * lg.nrb;
+  pl->mseg.assign(nl + 1, 0);
+  for (size_t i = 0; i < lg.it_rb.size(); ++i) ++pl->mseg[lg.it_m[i] * lg.nrb + lg.it_rb[i] + 1];
+  for (int k = 0; k < nl; ++k) pl->mseg[k + 1] += pl->mseg[k];
+  pl->mpoff.assign(lg.it_rb.size(), 0);
+  {
+    std::vector<int32_t> fill(pl->mseg.begin(), pl->mseg.end() - 1);
+    for (size_t i = 0; i < lg.it_rb.size(); ++i)
+      pl->mpoff[fill[lg.it_m[i] * lg.nrb + lg.it_rb[i]]++] = lg.it_poff[i] - (int64_t)lg.it_rb[i] * lg.rows;
+  }
+  pl->mtasks.clear();
+  pl->atasks.clear();
+  for (int64_t mm = 0; mm < p.M; ++mm)
+    for (int64_t r0 = 0; r0 < p.R; r0 += 256)
+      pl->mtasks.push_back({0, (int32_t)mm, (int32_t)r0, (int32_t)(mm * lg.nrb + r0 / lg.rows)});
+  for (int b = 0; b < p.nb; ++b) pl->atasks.push_back({0, b});
+  pl->seg_p.clear();
+  pl->seg_m.clear();
+  pl->seg_j0.clear();
+  pl->seg_j1.clear();
+  pl->seg_poff.clear();
+  pl->wg_seg.assign(2, 0);
+  pl->nwg_total = 1;
+  if (!pl->ws) {
+    lg.items_cap = (size_t)lg.nrb * (size_t)p.M + (size_t)std::max(lg.nwg, 1024);
+    pl->nseg_cap = 1;
+    pl->partial_cap = lg.items_cap * (size_t)lg.rows;
   }
   pl->tables_uploaded = false;
 }
@@ -509,6 +612,10 @@ void build_layout(Plan* pl) {
   L.wg_seg = take((size_t)(pl->nwg_total + 1) * 4);
   size_t nmeas = 0;
   for (const Prob& p : pl->P) nmeas += (size_t)p.M;
+  if (pl->lg.on) {
+    nmeas *= (size_t)pl->lg.nrb;  // one partial list per (measure, row tile)
+    L.seg_idx = take(pl->lg.items_cap * 8);
+  }
   L.mseg = take((nmeas + 1) * 4);
   L.probdev = take(pl->P.size() * std::max(sizeof(mam::ProbDev<float>), sizeof(mam::ProbDev<double>)));
   L.probaux = take(pl->P.size() * sizeof(mam::ProbAux));
@@ -516,6 +623,21 @@ void build_layout(Plan* pl) {
   L.atasks = take(pl->atasks.size() * sizeof(mam::AvgTask));
   L.stop = take(sizeof(mam::StopState));
   L.stop_part = take((size_t)pl->P[0].nb * 8);
+  if (pl->lg.on) {
+    LongPlan& lg = pl->lg;
+    const size_t T = (size_t)pl->P[0].T, ni = lg.items_cap;
+    lg.o_it_rb = take(ni * 4);
+    lg.o_it_m = take(ni * 4);
+    lg.o_it_j0 = take(ni * 8);
+    lg.o_it_j1 = take(ni * 8);
+    lg.o_it_poff = take(ni * 8);
+    lg.o_wg_it = take(((size_t)std::max(lg.nwg, 1024) + 1) * 4);
+    lg.o_cnt = take(T * 4);
+    lg.o_crow = take(T * (size_t)lg.cap * 4);
+    lg.o_cw = take(T * (size_t)lg.cap * 8);
+    lg.o_sub_off = take(T * (size_t)lg.nrb * 4 * 4);
+    lg.o_sub_cnt = take(T * (size_t)lg.nrb * 4 * 4);
+  }
   for (Prob& p : pl->P) {
     const size_t R = (size_t)p.R, M = (size_t)p.M;
     p.o_pm = take(M * R * 8);
@@ -542,6 +664,16 @@ mam_status make_plan(Plan* pl, const mam_desc* descs, int n) {
     if (descs[i].dtype != descs[0].dtype) return fail(MAM_EINVAL, "all problems of a batch share one dtype");
   }
   pl->dtype = descs[0].dtype;
+  for (int i = 0; i < n; ++i)
+    if (pl->P[i].R > kShortMaxR && pl->batch)
+      return fail(MAM_EUNSUPPORTED, "problem %d: R = %lld exceeds %lld in a batch", i, (long long)pl->P[i].R,
+                  (long long)kShortMaxR);
+  if (pl->P[0].R > kShortMaxR) {
+    pl->lg.on = true;
+    build_schedule(pl);
+    build_layout(pl);
+    return MAM_OK;
+  }
   std::map<std::pair<int, int>, int> by_shape;
   for (int i = 0; i < n; ++i) {
     int nt = 0, vpt = 0;
@@ -564,6 +696,21 @@ mam_status make_plan(Plan* pl, const mam_desc* descs, int n) {
 
 mam_status set_group_schedule(Plan* pl, int gi, const mam_schedule* s) {
   if (pl->ws) return fail(MAM_ESTATE, "schedule must be set before the workspace");
+  if (s->rows_per_tile != 0 && s->rows_per_tile != 1024 && s->rows_per_tile != 2048 && s->rows_per_tile != 4096)
+    return fail(MAM_EINVAL, "rows_per_tile must be 0, 1024, 2048 or 4096 (got %d)", s->rows_per_tile);
+  if (s->candidates_per_column < 0) return fail(MAM_EINVAL, "candidates_per_column must be >= 0");
+  if (s->rows_per_tile && pl->batch) return fail(MAM_EINVAL, "long-column tiles are for single problems");
+  if (!pl->batch && (s->rows_per_tile > 0 || pl->P[0].R > kShortMaxR)) {
+    if (s->workgroups < 0) return fail(MAM_EINVAL, "workgroups must be >= 0");
+    pl->lg.on = true;
+    pl->lg.rows_req = s->rows_per_tile;
+    pl->lg.cap_req = s->candidates_per_column;
+    pl->lg.nwg_req = s->workgroups;
+    build_schedule(pl);
+    build_layout(pl);
+    return MAM_OK;
+  }
+  pl->lg.on = false;
   if (s->order < 0 || s->order > 2) return fail(MAM_EINVAL, "order must be 0, 1 or 2 (got %d)", s->order);
   if (s->streaming < -1 || s->streaming > 1)
     return fail(MAM_EINVAL, "streaming must be -1, 0 or 1 (got %d)", s->streaming);
@@ -586,6 +733,20 @@ mam_status set_group_schedule(Plan* pl, int gi, const mam_schedule* s) {
 }
 
 void get_group_schedule(const Plan* pl, int gi, mam_schedule* s) {
+  *s = mam_schedule{};
+  if (pl->lg.on) {
+    s->threads_per_column = 256;
+    s->values_per_thread = pl->lg.vpt;
+    s->columns_in_flight = 1;
+    s->workgroups = pl->lg.nwg;
+    s->xcd_remap = -1;
+    s->vector_width = pl->lg.vec;
+    s->order = 1;
+    s->streaming = 1;
+    s->rows_per_tile = pl->lg.rows;
+    s->candidates_per_column = pl->lg.cap;
+    return;
+  }
   const Group& g = pl->G[gi];
   s->threads_per_column = g.nt;
   s->values_per_thread = g.vpt;
@@ -636,10 +797,14 @@ mam_status bind(Plan* pl, int i, void* theta, const void* cost, const int32_t* c
   const int vn = vec_width(pl->dtype);
   p.aligned = reinterpret_cast<uintptr_t>(theta) % 16 == 0 && reinterpret_cast<uintptr_t>(cost) % 16 == 0 &&
               p.ld % vn == 0 && p.cost_ld % vn == 0;
-  Group& g = pl->G[p.group];
-  bool all = true;
-  for (int pi : g.probs) all = all && pl->P[pi].aligned;
-  g.vec = (all && g.vpt >= vn) ? vn : 1;
+  if (pl->lg.on) {
+    pl->lg.vec = p.aligned ? vn : 1;
+  } else {
+    Group& g = pl->G[p.group];
+    bool all = true;
+    for (int pi : g.probs) all = all && pl->P[pi].aligned;
+    g.vec = (all && g.vpt >= vn) ? vn : 1;
+  }
   pl->inited = false;
   pl->tables_uploaded = false;
   drop_graphs(pl);  // a captured graph holds the old buffers
@@ -708,6 +873,15 @@ mam_status upload_tables(Plan* pl, hipStream_t st) {
     TRY(put(p.o_aw, p.aw.data(), p.aw.size() * 8));
   }
   TRY(put(L.probaux, aux.data(), aux.size() * sizeof(mam::ProbAux)));
+  if (pl->lg.on) {
+    const LongPlan& lg = pl->lg;
+    TRY(put(lg.o_it_rb, lg.it_rb.data(), lg.it_rb.size() * 4));
+    TRY(put(lg.o_it_m, lg.it_m.data(), lg.it_m.size() * 4));
+    TRY(put(lg.o_it_j0, lg.it_j0.data(), lg.it_j0.size() * 8));
+    TRY(put(lg.o_it_j1, lg.it_j1.data(), lg.it_j1.size() * 8));
+    TRY(put(lg.o_it_poff, lg.it_poff.data(), lg.it_poff.size() * 8));
+    TRY(put(lg.o_wg_it, lg.wg_it.data(), lg.wg_it.size() * 4));
+  }
   std::vector<mam::ProbDev<float>> pdf;
   std::vector<mam::ProbDev<double>> pdd;
   if (pl->dtype == MAM_F32) {
@@ -784,6 +958,103 @@ mam_status launch_columns(Plan* pl, hipStream_t st, int diag, uint8_t* rec, int6
   return MAM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// long-column iterations
+// ---------------------------------------------------------------------------
+template <typename T>
+mam::LongArgs<T> long_args(Plan* pl) {
+  const Prob& p = pl->P[0];
+  const LongPlan& lg = pl->lg;
+  mam::LongArgs<T> a{};
+  a.theta = static_cast<T*>(p.theta);
+  a.cost = static_cast<const T*>(p.cost);
+  a.q = static_cast<const T*>(p.q);
+  a.cidx = p.cidx;
+  a.ld = p.ld;
+  a.cost_ld = p.cost_ld;
+  a.R = (int32_t)p.R;
+  a.cost_mode = p.cost_mode;
+  a.M = (int32_t)p.M;
+  a.nrb = lg.nrb;
+  a.cap = lg.cap;
+  a.warm = (p.flags & MAM_FLAG_COLD) ? 0 : 1;
+  a.rho = p.rho;
+  a.inv_rho = 1.0 / p.rho;
+  a.gamma = p.gamma;
+  a.t = at<double>(pl, p.o_t);
+  a.p = at<double>(pl, p.o_p);
+  a.pm = at<double>(pl, p.o_pm);
+  a.d2part = at<double>(pl, p.o_d2);
+  a.nb = p.nb;
+  a.Sd = at<double>(pl, p.o_Sd);
+  a.col_off = at<int64_t>(pl, p.o_coloff);
+  a.it_rb = at<int32_t>(pl, lg.o_it_rb);
+  a.it_m = at<int32_t>(pl, lg.o_it_m);
+  a.it_j0 = at<int64_t>(pl, lg.o_it_j0);
+  a.it_j1 = at<int64_t>(pl, lg.o_it_j1);
+  a.it_poff = at<int64_t>(pl, lg.o_it_poff);
+  a.wg_it = at<int32_t>(pl, lg.o_wg_it);
+  a.cnt = at<int32_t>(pl, lg.o_cnt);
+  a.crow = at<int32_t>(pl, lg.o_crow);
+  a.cw = at<double>(pl, lg.o_cw);
+  a.sub_off = at<int32_t>(pl, lg.o_sub_off);
+  a.sub_cnt = at<int32_t>(pl, lg.o_sub_cnt);
+  a.lam = at<double>(pl, p.o_lam);
+  a.partial = at<double>(pl, pl->lay.partial);
+  a.stop = pl->gate;
+  a.T_cols = p.T;
+  return a;
+}
+
+// t^k, cleared candidate counts, then scan, threshold and write.
+template <typename T>
+mam_status launch_long_columns(Plan* pl, hipStream_t st) {
+  const Prob& p = pl->P[0];
+  const LongPlan& lg = pl->lg;
+  mam::LongFns<T> fn = mam::pick_long<T>(lg.vpt, lg.vec);
+  if (!fn.scan) return fail(MAM_EUNSUPPORTED, "no long-column kernels for vpt=%d vec=%d", lg.vpt, lg.vec);
+  mam::LongArgs<T> a = long_args<T>(pl);
+  hipLaunchKernelGGL(mam::damping_kernel, dim3(1), dim3(256), 0, st, a.d2part, p.nb, p.rho, p.gamma, a.t, a.stop);
+  LAUNCH_CHECK("damping_kernel");
+  hipLaunchKernelGGL(mam::fill_i32_kernel, dim3((unsigned)std::min<int64_t>(1024, (p.T + 255) / 256)), dim3(256), 0,
+                     st, a.cnt, p.T, 0, a.stop);
+  LAUNCH_CHECK("fill_i32_kernel");
+  hipLaunchKernelGGL(fn.scan, dim3(lg.nwg), dim3(mam::LNT), 0, st, a);
+  LAUNCH_CHECK("long_scan_kernel");
+  hipLaunchKernelGGL(fn.thresh, dim3((unsigned)((p.T + 3) / 4)), dim3(256), 0, st, a);
+  LAUNCH_CHECK("long_threshold_kernel");
+  hipLaunchKernelGGL(fn.write, dim3(lg.nwg), dim3(mam::LNT), (size_t)lg.vpt * mam::LNT * 8, st, a);
+  LAUNCH_CHECK("long_write_kernel");
+  return MAM_OK;
+}
+
+template <typename T>
+mam_status launch_long_rowsum(Plan* pl, hipStream_t st) {
+  const LongPlan& lg = pl->lg;
+  mam::LongFns<T> fn = mam::pick_long<T>(lg.vpt, lg.vec);
+  if (!fn.rowsum) return fail(MAM_EUNSUPPORTED, "no long-column kernels for vpt=%d vec=%d", lg.vpt, lg.vec);
+  hipLaunchKernelGGL(fn.rowsum, dim3(lg.nwg), dim3(256), 0, st, long_args<T>(pl), lg.rows);
+  LAUNCH_CHECK("long_rowsum_kernel");
+  return MAM_OK;
+}
+
+// Workgroups of the scan kernel the device holds at once.
+template <typename T>
+mam_status long_resident(Plan* pl, bool* changed) {
+  mam::LongFns<T> fn = mam::pick_long<T>(pl->lg.vpt, pl->lg.vec);
+  if (!fn.scan) return MAM_OK;
+  int dev = 0, cus = 0, blocks = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(fn.scan), mam::LNT, 0));
+  const int res = std::max(1, blocks) * std::max(1, cus);
+  if (res != pl->lg.nwg_auto) {
+    pl->lg.nwg_auto = res;
+    *changed = true;
+  }
+  return MAM_OK;
+}
+
 mam_status launch_marginals(Plan* pl, hipStream_t st, int save_prev) {
   const Layout& L = pl->lay;
   hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
@@ -814,6 +1085,10 @@ mam_status launch_init(Plan* pl, const void* const* theta0, hipStream_t st) {
     hipLaunchKernelGGL(mam::fill_value_kernel, dim3((unsigned)std::min<int64_t>(4096, (p.T + 255) / 256)), dim3(256),
                        0, st, at<double>(pl, p.o_lam), p.T, (double)NAN);
     LAUNCH_CHECK("fill_value_kernel");
+  }
+  if (pl->lg.on) {
+    TRY(launch_long_rowsum<T>(pl, st));
+    return launch_marginals(pl, st, 0);
   }
   for (const Group& g : pl->G) {
     hipLaunchKernelGGL(mam::rowsum_kernel<T>, dim3(g.nwg), dim3(256), 0, st, at<mam::ProbDev<T>>(pl, L.probdev),
@@ -898,7 +1173,10 @@ mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
         return fail(MAM_ENONFINITE, "cost_col_index[%lld] = %d is out of range", (long long)j, p.idx[j]);
     rebuilt = true;
   }
-  TRY(pl->dtype == MAM_F32 ? resident_workgroups<float>(pl, &rebuilt) : resident_workgroups<double>(pl, &rebuilt));
+  if (pl->lg.on)
+    TRY(pl->dtype == MAM_F32 ? long_resident<float>(pl, &rebuilt) : long_resident<double>(pl, &rebuilt));
+  else
+    TRY(pl->dtype == MAM_F32 ? resident_workgroups<float>(pl, &rebuilt) : resident_workgroups<double>(pl, &rebuilt));
   if (rebuilt) build_schedule(pl);
   drop_graphs(pl);
   TRY(upload_tables(pl, st));
@@ -941,8 +1219,13 @@ mam_status one_iteration(Plan* pl, hipStream_t st, int diag, uint8_t* rec = null
     if (!e0 || !e1) return fail(MAM_EHIP, "hipEventCreate failed");
     HIP_TRY(hipEventRecord(e0, st));
   }
-  TRY(pl->dtype == MAM_F32 ? launch_columns<float>(pl, st, diag, rec, rec_ld)
-                            : launch_columns<double>(pl, st, diag, rec, rec_ld));
+  if (pl->lg.on) {
+    if (diag || rec) return fail(MAM_EUNSUPPORTED, "diagnostics and the reverse mode are not available for long columns");
+    TRY(pl->dtype == MAM_F32 ? launch_long_columns<float>(pl, st) : launch_long_columns<double>(pl, st));
+  } else {
+    TRY(pl->dtype == MAM_F32 ? launch_columns<float>(pl, st, diag, rec, rec_ld)
+                              : launch_columns<double>(pl, st, diag, rec, rec_ld));
+  }
   if (pl->timing) HIP_TRY(hipEventRecord(e1, st));
   return launch_marginals(pl, st, save_prev < 0 ? diag : save_prev);
 }
@@ -977,6 +1260,7 @@ mam_status plan_iterate(Plan* pl, int64_t iters, hipStream_t st) {
   if (iters < 0) return fail(MAM_EINVAL, "iters must be >= 0");
   if (!pl->inited) return fail(MAM_ESTATE, "mam_init has not run");
   const bool want_diag = !pl->batch && (pl->P[0].flags & MAM_FLAG_DIAG);
+  if (want_diag && pl->lg.on) return fail(MAM_EUNSUPPORTED, "diagnostics are not computed for long columns");
   int64_t k = 0;
   if (pl->graph_iters > 0 && !pl->timing) {
     // keep the last iteration outside the graph when it computes diagnostics
@@ -1166,6 +1450,7 @@ mam_status plan_timing_read(Plan* pl, double* total_ms, int64_t* launches) {
 // ---------------------------------------------------------------------------
 mam_status adjoint_layout(const Plan* pl, int64_t K, int64_t C, Adjoint* A) {
   if (pl->batch) return fail(MAM_EUNSUPPORTED, "the reverse mode is available for single problems");
+  if (pl->lg.on) return fail(MAM_EUNSUPPORTED, "the reverse mode is not available for long columns");
   if (K < 0) return fail(MAM_EINVAL, "iters must be >= 0");
   const Prob& p = pl->P[0];
   const Group& g = pl->G[0];
@@ -1603,6 +1888,7 @@ size_t bundle_layout(const Plan* pl, const int32_t* bundle_of, int32_t nb, Bundl
 }
 
 mam_status plan_set_bundles(Plan* pl, const int32_t* bundle_of, int32_t nb, void* ws, size_t bytes, hipStream_t st) {
+  if (pl->lg.on) return fail(MAM_EUNSUPPORTED, "the randomized variant is not available for long columns");
   TRY(bundle_check(pl, bundle_of, nb));
   if (!pl->inited) return fail(MAM_ESTATE, "mam_init has not run");
   if (!ws) return fail(MAM_ENOMEM, "bundle workspace is NULL");
@@ -1910,7 +2196,7 @@ mam_status mam_backward(mam_problem* p, const double* grad_p, void* grad_q, void
 
 // ---- randomized variant ----------------------------------------------------
 size_t mam_bundle_workspace_bytes(const mam_problem* p, const int32_t* bundle_of, int32_t nb) {
-  if (!p || bundle_check(&p->plan, bundle_of, nb) != MAM_OK) return 0;
+  if (!p || p->plan.lg.on || bundle_check(&p->plan, bundle_of, nb) != MAM_OK) return 0;
   return bundle_layout(&p->plan, bundle_of, nb, nullptr);
 }
 

@@ -5,6 +5,7 @@
 
 #include "mam_adjoint.hpp"
 #include "mam_kernels.hpp"
+#include "mam_long.hpp"
 
 namespace mam {
 
@@ -23,7 +24,8 @@ struct ProbAux {
 };
 
 struct MargTask {
-  int32_t prob, m, r0, pad;
+  int32_t prob, m, r0;
+  int32_t list;  // partial-offset list: the measure's, or (long columns) its row tile's
 };
 
 struct AvgTask {
@@ -31,7 +33,8 @@ struct AvgTask {
 };
 
 // p^(m)_r = sum over the segments of measure m, in schedule order.  The
-// partials' offsets come as one list per measure (mpoff[mseg[k] .. mseg[k+1]));
+// partials' offsets come as one list per measure, or per (measure, row tile)
+// for long columns (mpoff[mseg[k] .. mseg[k+1]), k = the task's list);
 // they are wave-uniform, and the partial loads are issued eight at a time so
 // the loop is not a chain of dependent loads.  The additions keep the list
 // order.
@@ -44,11 +47,11 @@ marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ 
   const ProbAux& P = probs[tk.prob];
   const int R = uniform_i(P.R);
   const int r = tk.r0 + threadIdx.x;
-  const int k = uniform_i(P.mbase) + tk.m;
+  const int k = uniform_i(P.mbase) + tk.list;
   const int b = uniform_i(mseg[k]), e = uniform_i(mseg[k + 1]);
   constexpr int U = 8;
   double s = 0.0;
-  const int rr = r < R ? r : 0;  // rows past R read row 0 (in bounds) and store nothing
+  const int rr = r < R ? r : tk.r0;  // rows past R read the task's first row (in bounds) and store nothing
   for (int i = b; i < e; i += U) {
     double v[U];
 #pragma unroll
@@ -214,6 +217,30 @@ stop_final_kernel(StopState* __restrict__ st, int test, const double* __restrict
       if (host_flag) *reinterpret_cast<volatile int32_t*>(host_flag) = 1;
     }
   }
+}
+
+// ---- long-column iterations (the tile kernels are in mam_long.hpp) ----
+// t^k from the d^2 partials (Alg. 1 Step 1), one workgroup, fixed order.
+__global__ void __launch_bounds__(256)
+damping_kernel(const double* __restrict__ d2part, int nb, double rho, double gamma, double* __restrict__ t_out,
+               const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += d2part[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double d2 = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    t_out[0] = (__builtin_isinf(gamma) || rho * sqrt(d2) <= gamma) ? 1.0 : gamma / (rho * sqrt(d2));
+  }
+}
+
+__global__ void __launch_bounds__(256) fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v,
+                                                       const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
 }
 
 // theta^0_rs = q_s / R (Alg. 1 Step 0 with the library's default start).

@@ -31,6 +31,21 @@ inline ColFn<T> pick_column(int nt, int vpt, int vec, int kc, int diag, int stre
   }
 }
 
+// Long-column tile kernels for (values per thread, vector width); null
+// members if no instance exists.
+template <typename T> struct LongArgs;
+template <typename T>
+struct LongFns {
+  void (*scan)(LongArgs<T>) = nullptr;
+  void (*thresh)(LongArgs<T>) = nullptr;
+  void (*write)(LongArgs<T>) = nullptr;
+  void (*rowsum)(LongArgs<T>, int) = nullptr;
+};
+template <typename T>
+LongFns<T> pick_long(int vpt, int vec);
+extern template LongFns<float> pick_long<float>(int, int);
+extern template LongFns<double> pick_long<double>(int, int);
+
 // Reverse-mode column kernel for (threads per column, values per thread).
 struct AdjArgs;
 using AdjFn = void (*)(AdjArgs);

@@ -69,7 +69,8 @@ class Schedule(ctypes.Structure):
     _fields_ = [("threads_per_column", ctypes.c_int32), ("values_per_thread", ctypes.c_int32),
                 ("columns_in_flight", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("vector_width", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("streaming", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("streaming", ctypes.c_int32),
+                ("rows_per_tile", ctypes.c_int32), ("candidates_per_column", ctypes.c_int32)]
 
 
 class StopResult(ctypes.Structure):
@@ -184,7 +185,7 @@ class Solver:
                  cost_ld: Optional[int] = None, diag: bool = False, cold: bool = False,
                  threads_per_column: int = 0, columns_in_flight: int = 0,
                  workgroups: int = 0, xcd_remap: int = 0, order: int = 0, streaming: int = 0,
-                 device="cuda"):
+                 rows_per_tile: int = 0, candidates_per_column: int = 0, device="cuda"):
         L = lib()
         self.device = torch.device(device)
         self.R, self.S = int(R), [int(s) for s in S]
@@ -205,9 +206,11 @@ class Solver:
         h = _vp()
         _check(L.mam_create(ctypes.byref(h), ctypes.byref(d)), "mam_create")
         self._h = h
-        if threads_per_column or columns_in_flight or workgroups or xcd_remap or order or streaming:
+        if (threads_per_column or columns_in_flight or workgroups or xcd_remap or order or streaming
+                or rows_per_tile or candidates_per_column):
             sc = Schedule(threads_per_column=threads_per_column, columns_in_flight=columns_in_flight,
-                          workgroups=workgroups, xcd_remap=xcd_remap, order=order, streaming=streaming)
+                          workgroups=workgroups, xcd_remap=xcd_remap, order=order, streaming=streaming,
+                          rows_per_tile=rows_per_tile, candidates_per_column=candidates_per_column)
             _check(L.mam_set_schedule(h, ctypes.byref(sc)), "mam_set_schedule")
         nbytes = int(L.mam_workspace_bytes(h))
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)

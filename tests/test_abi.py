@@ -52,7 +52,7 @@ def create(**kw):
     (dict(rho=math.inf), -1), (dict(gamma=-1.0), -1), (dict(gamma=math.nan), -1),
     (dict(dtype=7), -1), (dict(cost_mode=9), -1), (dict(ld=8), -1), (dict(cost_ld=3), -1),
     (dict(cost_mode=mam.COST_SHARED, cost_ncols=5), -1),
-    (dict(cost_ncols=3), -1), (dict(R=8193), -6),
+    (dict(cost_ncols=3), -1), (dict(R=(1 << 28) + 1), -6),
 ])
 def test_create_rejects(kw, code):
     rc, h = create(**kw)
@@ -184,3 +184,37 @@ def test_stopping_test_validation():
     assert L.mam_iterate_until(h, 5, 0, 1e-3, 1, ctypes.byref(r), None) == -7  # no init yet
     assert r.iterations == 0 and r.checks == 0 and r.converged == 0 and math.isnan(r.value)
     L.mam_destroy(h)
+
+
+def test_long_column_path_selection():
+    L = mam.lib()
+    sc = mam.Schedule()
+    # single problems with R > 8192 take the long-column path
+    rc, h = create(R=10000, S=[30, 20])
+    assert rc == 0
+    assert L.mam_get_schedule(h, ctypes.byref(sc)) == 0
+    assert sc.rows_per_tile == 2048 and sc.candidates_per_column == 4096   # double
+    assert L.mam_workspace_bytes(h) > 0
+    assert L.mam_adjoint_workspace_bytes(h, 10, 0) == 0                    # no reverse mode
+    B2 = ctypes.c_int32 * 2
+    assert L.mam_bundle_workspace_bytes(h, B2(0, 1), 2) == 0               # no randomized variant
+    bad = mam.Schedule(rows_per_tile=1000)
+    assert L.mam_set_schedule(h, ctypes.byref(bad)) == -1
+    ok = mam.Schedule(rows_per_tile=1024, candidates_per_column=64)
+    assert L.mam_set_schedule(h, ctypes.byref(ok)) == 0
+    assert L.mam_get_schedule(h, ctypes.byref(sc)) == 0
+    assert sc.rows_per_tile == 1024 and sc.values_per_thread == 4 and sc.candidates_per_column == 64
+    L.mam_destroy(h)
+    # forced on a short problem, and back
+    rc, h = create(R=300, S=[40, 17])
+    assert rc == 0
+    assert L.mam_set_schedule(h, ctypes.byref(mam.Schedule(rows_per_tile=1024))) == 0
+    assert L.mam_get_schedule(h, ctypes.byref(sc)) == 0 and sc.rows_per_tile == 1024
+    assert L.mam_set_schedule(h, ctypes.byref(mam.Schedule())) == 0
+    assert L.mam_get_schedule(h, ctypes.byref(sc)) == 0 and sc.rows_per_tile == 0
+    L.mam_destroy(h)
+    # batches keep R <= 8192
+    d, arr = desc(R=9000, S=[10])
+    ds = (mam.Desc * 1)(d)
+    b = ctypes.c_void_p()
+    assert L.mam_batch_create(ctypes.byref(b), ds, 1) == -6

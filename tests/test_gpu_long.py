@@ -1,0 +1,149 @@
+"""Long-column path (row tiles, candidate lists, per-column thresholds) vs
+the FP64 oracle, element by element (MI355X only).
+
+The path is forced on small problems (rows_per_tile = 1024 with R spanning
+several tiles and a ragged last tile) so the oracle runs the same iterations
+in seconds; R > 8192 takes it automatically.  A tiny candidate capacity
+forces the fallback that recomputes a column from theta and c.  Tolerances
+as for the short path: 1e-10 (FP64 plans) and 1e-5 (FP32 plans) relative.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mam_oracle as O
+from paper_2309_05315_amd import inputs
+from paper_2309_05315_amd import mam
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def blocks(p):
+    return [p.cost_block(m) for m in range(p.M)], [p.q_block(m) for m in range(p.M)]
+
+
+def rel(a, b, ord=1):
+    a, b = np.asarray(a, dtype=np.float64).ravel(), np.asarray(b, dtype=np.float64).ravel()
+    if ord == 1:
+        return float(np.abs(a - b).sum() / max(np.abs(b).sum(), 1e-300))
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def run(p, iters, graph=0, **sched):
+    s = mam.solver_for(p, **sched)
+    sc = s.schedule()
+    assert sc["rows_per_tile"] > 0, "the long-column path was not taken"
+    if graph:
+        s.graph(graph)
+    s.init()
+    s.iterate(iters)
+    return s
+
+
+def check(p, iters, **sched):
+    say(f"case {p.name} {p.dtype} R={p.R} S={p.S} gamma={p.gamma} iters={iters} sched={sched}")
+    cost, q = blocks(p)
+    ora = O.mam(cost, q, p.rho, p.gamma, iters)
+    s = run(p, iters, **sched)
+    pb = s.barycenter().cpu().numpy()
+    th = s.plans()
+    tol = TOL[p.dtype]
+    e1, einf = rel(pb, ora["p_bar"]), rel(pb, ora["p_bar"], np.inf)
+    eth = max(rel(a, b, np.inf) for a, b in zip(th, ora["theta"]))
+    say(f"  p_bar rel L1 {e1:.3e} max {einf:.3e}  theta rel max {eth:.3e}")
+    assert e1 <= tol and einf <= tol
+    if p.dtype == "f64":
+        assert eth <= tol
+    np.testing.assert_allclose(s.marginals().cpu().numpy(), ora["pm"], rtol=0,
+                               atol=tol * np.abs(ora["pm"]).max() * 10)
+    return s, ora
+
+
+@pytest.mark.parametrize("R,S,dtype,shared", [
+    (3000, [40, 25, 33], "f64", False),   # three tiles, ragged last one
+    (2049, [17, 30], "f32", False),       # one row past two tiles
+    (1024, [20, 20], "f64", True),        # exactly one tile, shared cost
+    (4100, [12, 12], "f32", True),
+    (2500, [7, 41, 3, 19], "f64", False),
+])
+def test_forced_long_path_matches_oracle(R, S, dtype, shared):
+    p = inputs.tiny_problem(11, R=R, S=S, dtype=dtype, rho=1.0, shared=shared)
+    check(p, 25, rows_per_tile=1024)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_unbalanced_long_path(dtype):
+    p = inputs.tiny_problem(12, R=2200, S=[30, 22, 15], dtype=dtype, masses=[0.6, 1.0, 1.5], gamma=0.02)
+    check(p, 30, rows_per_tile=1024)
+
+
+@pytest.mark.parametrize("rho", [1.0, 200.0])
+def test_candidate_overflow_falls_back_exactly(rho):
+    # a capacity of 4 entries overflows on most columns: those columns take
+    # their threshold and write pass from theta and c
+    p = inputs.tiny_problem(13, R=2600, S=[24, 18], rho=rho)
+    check(p, 20, rows_per_tile=1024, candidates_per_column=4)
+
+
+def test_large_rho_many_candidates():
+    # rho = R * mean(S): large active sets, long candidate lists
+    p = inputs.tiny_problem(14, R=2100, S=[16, 12], rho=2100.0 * 14)
+    check(p, 15, rows_per_tile=1024)
+
+
+def test_zero_weights_and_cold_start():
+    p = inputs.tiny_problem(15, R=1500, S=[30, 26], zero_frac=0.4)
+    check(p, 20, rows_per_tile=1024, cold=True)
+
+
+@pytest.mark.parametrize("R", [8193, 12000])
+def test_automatic_long_path_above_8192(R):
+    p = inputs.tiny_problem(16, R=R, S=[9, 14], dtype="f32")
+    s, _ = check(p, 12)
+    assert s.schedule()["rows_per_tile"] == 4096
+
+
+def test_bitwise_reproducible_and_graph_equals_eager():
+    p = inputs.tiny_problem(17, R=3100, S=[35, 28], dtype="f32")
+    a = run(p, 20, rows_per_tile=1024)
+    b = run(p, 20, rows_per_tile=1024)
+    g = run(p, 20, graph=5, rows_per_tile=1024)
+    for x, y, z in zip(a.plans(), b.plans(), g.plans()):
+        np.testing.assert_array_equal(x, y)
+        np.testing.assert_array_equal(x, z)
+    np.testing.assert_array_equal(a.barycenter().cpu().numpy(), g.barycenter().cpu().numpy())
+
+
+def test_stopping_test_on_long_columns():
+    p = inputs.tiny_problem(18, R=2300, S=[20, 31], rho=2.0)
+    cost, q = blocks(p)
+    s = mam.solver_for(p, rows_per_tile=1024)
+    s.init()
+    r = s.iterate_until(12, "dp", -1.0, 4)
+    assert r["iterations"] == 12 and r["checks"] == 3
+    ora = O.mam_until(cost, q, p.rho, 12, "dp", -1.0, 4)
+    assert r["value"] == pytest.approx(ora["values"][-1], rel=1e-6)
+    assert rel(s.barycenter().cpu().numpy(), ora["p_bar"]) <= 1e-10
+
+
+def test_unsupported_on_long_columns():
+    p = inputs.tiny_problem(19, R=1100, S=[10, 12])
+    s = mam.solver_for(p, rows_per_tile=1024, diag=True)
+    s.init()
+    with pytest.raises(mam.MAMError):
+        s.iterate(2)  # diagnostics are not computed on this path
+    s = mam.solver_for(p, rows_per_tile=1024)
+    s.init()
+    with pytest.raises(mam.MAMError):
+        s.record(3)
+    with pytest.raises(mam.MAMError):
+        s.set_bundles([0, 1])

@@ -6,7 +6,9 @@
   splitting of Sec. 4 eq. (fm)).
 * ``uwb_slsqp``: the unbalanced problem (UWB) -- transport cost plus
   gamma * dist_L over the product of the sets Pi^(m) -- minimised directly
-  with scipy's SLSQP on instances with a few dozen variables.
+  with scipy's SLSQP on instances with a few dozen variables; with
+  ``relaxed`` the column sums are only bounded by q^(m)_s (the full
+  unbalanced extension).
 
 Only the test suite may import this module.
 """
@@ -70,8 +72,9 @@ def uwb_objective(cost: List[np.ndarray], pis: List[np.ndarray], gamma: float) -
 
 
 def uwb_slsqp(cost: List[np.ndarray], q: List[np.ndarray], gamma: float, x0=None,
-              iters: int = 2000):
-    """Minimise problem (UWB) over pi^(m) in Pi^(m) with SLSQP (tiny sizes)."""
+              iters: int = 2000, relaxed: bool = False):
+    """Minimise problem (UWB) over pi^(m) in Pi^(m) with SLSQP (tiny sizes);
+    relaxed: over pi^(m) >= 0 with column sums <= q^(m)_s."""
     R = cost[0].shape[0]
     S = [c.shape[1] for c in cost]
     sizes = [R * s for s in S]
@@ -87,9 +90,14 @@ def uwb_slsqp(cost: List[np.ndarray], q: List[np.ndarray], gamma: float, x0=None
     for m in range(len(S)):
         for s in range(S[m]):
             idx = offs[m] + np.arange(R) * S[m] + s
-            cons.append({"type": "eq",
-                         "fun": (lambda x, idx=idx, v=q[m][s]: x[idx].sum() - v),
-                         "jac": (lambda x, idx=idx: _unit(x.size, idx))})
+            if relaxed:
+                cons.append({"type": "ineq",
+                             "fun": (lambda x, idx=idx, v=q[m][s]: v - x[idx].sum()),
+                             "jac": (lambda x, idx=idx: -_unit(x.size, idx))})
+            else:
+                cons.append({"type": "eq",
+                             "fun": (lambda x, idx=idx, v=q[m][s]: x[idx].sum() - v),
+                             "jac": (lambda x, idx=idx: _unit(x.size, idx))})
     if x0 is None:
         x0 = np.concatenate([np.repeat((qm / R)[None, :], R, axis=0).ravel() for qm in q])
     res = minimize(f, x0, method="SLSQP", constraints=cons,

@@ -15,6 +15,10 @@ Functions and the passage each follows:
 * ``proj_simplex_sort``  Prop. 3 (eq. (proj-s)) and the Remark on Delta_R(tau):
   exact Euclidean projection onto {u >= 0, sum u = tau}; the exact
   sort-based threshold method that the paper delegates to (Condat 2016).
+* ``proj_subsimplex``  the extension to the full unbalanced setting (the
+  section on relaxing the marginals of q^(m) as well, and its proposition):
+  projection onto {u >= 0, sum u <= tau} by clamping at 0 and, if the clamped
+  vector carries more than tau, the simplex projection.
 * ``marginals``, ``averaging_weights``, ``proj_L``  Prop. 2 (eqs. (pr), (row_sol)).
 * ``dist_L``  the reduction of dist_L to R-vectors stated after Alg. 1.
 * ``unbalanced_prox``  eq. (Unbalanced-prox).
@@ -46,6 +50,7 @@ import numpy as np
 
 __all__ = [
     "proj_simplex_sort",
+    "proj_subsimplex",
     "averaging_weights",
     "marginals",
     "proj_L",
@@ -106,6 +111,21 @@ def proj_simplex_sort(w: np.ndarray, tau) -> tuple:
 # ---------------------------------------------------------------------------
 # Prop. 2: projection onto the subspace L of balanced plans
 # ---------------------------------------------------------------------------
+def proj_subsimplex(w: np.ndarray, tau) -> np.ndarray:
+    """Project every column of ``w`` (R x n) onto {u >= 0, sum u <= tau_s}:
+    first u = max(w, 0); a column whose u sums to at most tau_s keeps it,
+    any other column is projected onto Delta_R(tau_s) (the full unbalanced
+    extension; tau_s = 0 gives 0)."""
+    w = np.asarray(w, dtype=np.float64)
+    tau = np.broadcast_to(np.asarray(tau, dtype=np.float64), (w.shape[1],))
+    out = np.maximum(w, 0.0)
+    over = out.sum(axis=0) > tau
+    if np.any(over):
+        ph, _ = proj_simplex_sort(w[:, over], tau[over])
+        out[:, over] = ph
+    return out
+
+
 def averaging_weights(S: Sequence[int]) -> np.ndarray:
     """a_m = (1/S^m) / sum_j (1/S^j), eq. (pr)."""
     inv = 1.0 / np.asarray(S, dtype=np.float64)
@@ -162,7 +182,8 @@ def damping(p: np.ndarray, pm: np.ndarray, S: Sequence[int], rho: float, gamma: 
 # Alg. 1 (deterministic MAM)
 # ---------------------------------------------------------------------------
 def mam_step(theta: List[np.ndarray], pm: np.ndarray, cost: List[np.ndarray],
-             q: List[np.ndarray], rho: float, gamma: float, chosen: Optional[Sequence[int]] = None):
+             q: List[np.ndarray], rho: float, gamma: float, chosen: Optional[Sequence[int]] = None,
+             relaxed: bool = False):
     """One pass of Alg. 1's loop body with M^k = {1, ..., M}, or with
     M^k = ``chosen`` (the randomized variant, eq. (DR-random)): Step 1 still
     averages every marginal, Steps 2 and 3 run only for the chosen measures,
@@ -174,6 +195,9 @@ def mam_step(theta: List[np.ndarray], pm: np.ndarray, cost: List[np.ndarray],
         pi_hat = Proj_{Delta_R(q_s)}(w)
         theta' = pi_hat - t^k (p^k - p^(m)) / S^m
     Step 3: p^(m) = row sums of the new theta^(m).
+    With ``relaxed`` the columns are projected onto {u >= 0, sum u <= q_s}
+    instead (the full unbalanced extension; the cost passed is then the
+    shifted d^(m) = c^(m) - eta).
 
     Returns (theta_new, pm_new, info) where info holds p^k, t^k, the
     distance d^k and the pi_hat blocks.
@@ -192,7 +216,7 @@ def mam_step(theta: List[np.ndarray], pm: np.ndarray, cost: List[np.ndarray],
             continue
         corr = t * (p - pm[m]) / S[m]
         w = theta[m] + 2.0 * corr[:, None] - cost[m] / rho
-        ph, _ = proj_simplex_sort(w, q[m])
+        ph = proj_subsimplex(w, q[m]) if relaxed else proj_simplex_sort(w, q[m])[0]
         pi_hat.append(ph)
         new_theta.append(ph - corr[:, None])
     pm_new = pm.copy()                                    # Step 3
@@ -228,7 +252,8 @@ def mam_step_columns(theta_cols: np.ndarray, measure_of_col: Sequence[int], pm: 
 def mam(cost: List[np.ndarray], q: List[np.ndarray], rho: float,
         gamma: float = math.inf, iters: int = 1,
         theta0: Optional[List[np.ndarray]] = None, record: bool = False,
-        bundles: Optional[Sequence[Sequence[int]]] = None, seq: Optional[Sequence[int]] = None) -> Dict:
+        bundles: Optional[Sequence[Sequence[int]]] = None, seq: Optional[Sequence[int]] = None,
+        relaxed: bool = False) -> Dict:
     """Run Alg. 1 for ``iters`` iterations from theta^0.
 
     Randomized variant: with ``bundles`` (a partition of the measures, as in
@@ -256,7 +281,7 @@ def mam(cost: List[np.ndarray], q: List[np.ndarray], rho: float,
     info = {"pi_hat": None, "t": None, "p": None}
     for k in range(iters):
         chosen = None if bundles is None else bundles[int(seq[k])]
-        theta, pm_new, info = mam_step(theta, pm, cost, q, rho, gamma, chosen)
+        theta, pm_new, info = mam_step(theta, pm, cost, q, rho, gamma, chosen, relaxed)
         if record:
             hist["t"].append(info["t"])
             hist["d"].append(info["d"])

@@ -10,8 +10,9 @@ and barycenter in FP64).  The default run times the 500 iterations that
 problem is quoted at, then the same 500 iterations with FP64 plans, and
 reports the FP32-vs-FP64 barycenter difference.  Shorter runs of the other
 workloads (balanced FP64 with graph replay, unbalanced, a batch of 256
-problems, the randomized variant, on-device stopping tests, the reverse mode)
-are reported under "extras".
+problems, the randomized variant, on-device stopping tests, the free-support
+workload on the long-column path, the reverse mode) are reported under
+"extras".
 
 Prints one JSON line:  metric, value (plan-entry updates per second), the
 roofline of the dominant kernel (the column kernel, timed with HIP events on
@@ -214,6 +215,33 @@ def extra_workloads(torch, mam, inputs, log):
             f"dtheta {r_['dtheta_every_10_ms_per_iter']:.4f}; stop at the first check of 20000: "
             f"{r_['stop_at_first_check_ms']:.2f} ms")
     out["stopping_tests"] = res
+
+    # free-support barycenter (Theorem c): 10 nested-ellipse 60x60 images,
+    # R = 349,281 support points, T = 36,000 columns, FP32 plans (50 GB):
+    # the long-column path (row tiles, candidate slots, per-column thresholds)
+    pf = inputs.free_support(dtype="f32")
+    s = mam.solver_for(pf)
+    sc = s.schedule()
+    s.init()
+    s.iterate(3)
+    n_it = 20
+    dt = timed(lambda: s.iterate(n_it)) / n_it
+    s.timing(True)
+    s.iterate(5)
+    col, n = s.timing_read()
+    ws = s.workspace.numel()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    abf = algorithmic_bytes(pf)
+    out["free_support_K60_M10_f32"] = {
+        "R": pf.R, "M": pf.M, "T": pf.T, "iterations": n_it, "ms_per_iter": dt * 1e3,
+        "plan_entry_updates_per_s": pf.R * pf.T / dt, "column_kernels_ms": col / n,
+        "algorithmic_bytes_per_iter": abf, "column_kernels_GBs": abf / (col / n * 1e-3) / 1e9,
+        "plans_GB": pf.T * pf.R * 4 / 1e9, "workspace_GB": ws / 1e9,
+        "rows_per_tile": sc["rows_per_tile"], "candidate_slots": sc["candidate_slots"]}
+    log(f"free support R={pf.R} T={pf.T}: {dt * 1e3:.2f} ms/iter, {pf.R * pf.T / dt:.3e} entries/s, "
+        f"column kernels {col / n:.2f} ms ({abf / (col / n * 1e-3) / 1e9:.0f} GB/s algorithmic)")
 
     # reverse mode: 64x64 grid, 8 measures, 100 iterations, FP32, loss ||p_bar - target||^2
     p5, tgt = inputs.adjoint_problem()

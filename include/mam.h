@@ -76,6 +76,17 @@ typedef int32_t mam_status;
 #define MAM_FLAG_COLD 2u       /* start every threshold search from w_max - q_s
                                   instead of the column's previous threshold
                                   (same results; for testing and timing) */
+#define MAM_FLAG_RELAXED 4u    /* the full unbalanced extension (the section
+                                  relaxing the marginals of q^(m) as well):
+                                  Step 2 projects every column onto
+                                  {u >= 0, sum_r u_r <= q_s} instead of
+                                  Delta_R(q_s), i.e. max(w - max(lambda, 0), 0)
+                                  with lambda the simplex threshold.  The
+                                  mismatch penalty alpha_m*eta of that problem
+                                  enters through the cost: pass c - eta.  The
+                                  balanced mass check is skipped; no reverse
+                                  mode; mam_diag.meas_resid reports the excess
+                                  max(sum_r pi_hat_rs - q_s, 0). */
 
 typedef struct mam_problem mam_problem;
 
@@ -142,11 +153,12 @@ typedef struct mam_schedule {
                                  the path is taken when R > 8192, with 4096
                                  (float) or 2048 (double) rows.  A value > 0
                                  forces the path at any R.                      */
-  int32_t candidates_per_column; /* long-column path: capacity of a column's
-                                 candidate list (0 automatic: min(R, 4096)).
-                                 A column with more candidates in an iteration
-                                 is handled from theta and c directly (same
-                                 result, slower).                               */
+  int32_t candidate_slots;    /* long-column path: candidates kept per
+                                 (column, wave sub-tile of 64*rows_per_tile/256
+                                 rows), 1..64; 0 automatic (32).  A sub-tile
+                                 with more candidates in an iteration is
+                                 recomputed from theta and c (same result,
+                                 slower).                                       */
 } mam_schedule;
 
 /* ABI version of this header (1). */

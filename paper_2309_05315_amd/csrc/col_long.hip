@@ -9,10 +9,10 @@ template <typename T, int VPT>
 LongFns<T> pick_long_vec(int vec) {
   constexpr int VN = VecOf<T>::N;
   if (vec == VN)
-    return {&long_scan_kernel<T, VPT, VN>, &long_threshold_kernel<T>, &long_write_kernel<T, VPT, VN>,
+    return {&long_scan_kernel<T, VPT, VN>, &long_threshold_kernel<T, VPT, VN>, &long_write_kernel<T, VPT, VN>,
             &long_rowsum_kernel<T>};
   if (vec == 1)
-    return {&long_scan_kernel<T, VPT, 1>, &long_threshold_kernel<T>, &long_write_kernel<T, VPT, 1>,
+    return {&long_scan_kernel<T, VPT, 1>, &long_threshold_kernel<T, VPT, 1>, &long_write_kernel<T, VPT, 1>,
             &long_rowsum_kernel<T>};
   return {};
 }

@@ -161,7 +161,8 @@ struct Bundles {
 
 // Long-column path (single problems with R beyond kShortMaxR, or forced by
 // the schedule): work items (row tile, measure, column range) split evenly
-// over the workgroups, candidate lists per column.
+// over the workgroups; per (column, wave sub-tile) a header (maximum of w,
+// candidate count) and 'cap' candidate slots.
 struct LongPlan {
   bool on = false;
   int vpt = 16, rows = 4096, nrb = 0, cap = 0, vec = 1;
@@ -170,7 +171,7 @@ struct LongPlan {
   std::vector<int64_t> it_j0, it_j1, it_poff;
   size_t items_cap = 0;
   size_t o_it_rb = 0, o_it_m = 0, o_it_j0 = 0, o_it_j1 = 0, o_it_poff = 0, o_wg_it = 0;
-  size_t o_cnt = 0, o_crow = 0, o_cw = 0, o_sub_off = 0, o_sub_cnt = 0;
+  size_t o_hmax = 0, o_hcnt = 0, o_crow = 0, o_cw = 0;
 };
 
 struct Plan {
@@ -525,7 +526,7 @@ void build_long_schedule(Plan* pl) {
   lg.vpt = lg.rows_req ? lg.rows_req / 256 : (pl->dtype == MAM_F32 ? 16 : 8);
   lg.rows = 256 * lg.vpt;
   lg.nrb = (int)((p.R + lg.rows - 1) / lg.rows);
-  lg.cap = lg.cap_req ? lg.cap_req : (int)std::min<int64_t>(p.R, 4096);
+  lg.cap = lg.cap_req ? lg.cap_req : 32;
   if (!p.theta) lg.vec = vn;  // until binding checks the alignment
   const int64_t units = (int64_t)lg.nrb * p.T;
   const int64_t cap_wg = lg.nwg_auto > 0 ? std::min(lg.nwg_auto, 1024) : 1024;
@@ -632,11 +633,11 @@ void build_layout(Plan* pl) {
     lg.o_it_j1 = take(ni * 8);
     lg.o_it_poff = take(ni * 8);
     lg.o_wg_it = take(((size_t)std::max(lg.nwg, 1024) + 1) * 4);
-    lg.o_cnt = take(T * 4);
-    lg.o_crow = take(T * (size_t)lg.cap * 4);
-    lg.o_cw = take(T * (size_t)lg.cap * 8);
-    lg.o_sub_off = take(T * (size_t)lg.nrb * 4 * 4);
-    lg.o_sub_cnt = take(T * (size_t)lg.nrb * 4 * 4);
+    const size_t nh = T * (size_t)lg.nrb * 4;  // (column, sub-tile) headers
+    lg.o_hmax = take(nh * 8);
+    lg.o_hcnt = take(nh * 4);
+    lg.o_crow = take(nh * (size_t)lg.cap * 4);
+    lg.o_cw = take(nh * (size_t)lg.cap * 8);
   }
   for (Prob& p : pl->P) {
     const size_t R = (size_t)p.R, M = (size_t)p.M;
@@ -698,13 +699,14 @@ mam_status set_group_schedule(Plan* pl, int gi, const mam_schedule* s) {
   if (pl->ws) return fail(MAM_ESTATE, "schedule must be set before the workspace");
   if (s->rows_per_tile != 0 && s->rows_per_tile != 1024 && s->rows_per_tile != 2048 && s->rows_per_tile != 4096)
     return fail(MAM_EINVAL, "rows_per_tile must be 0, 1024, 2048 or 4096 (got %d)", s->rows_per_tile);
-  if (s->candidates_per_column < 0) return fail(MAM_EINVAL, "candidates_per_column must be >= 0");
+  if (s->candidate_slots < 0 || s->candidate_slots > 64)
+    return fail(MAM_EINVAL, "candidate_slots must be in [0, 64] (got %d)", s->candidate_slots);
   if (s->rows_per_tile && pl->batch) return fail(MAM_EINVAL, "long-column tiles are for single problems");
   if (!pl->batch && (s->rows_per_tile > 0 || pl->P[0].R > kShortMaxR)) {
     if (s->workgroups < 0) return fail(MAM_EINVAL, "workgroups must be >= 0");
     pl->lg.on = true;
     pl->lg.rows_req = s->rows_per_tile;
-    pl->lg.cap_req = s->candidates_per_column;
+    pl->lg.cap_req = s->candidate_slots;
     pl->lg.nwg_req = s->workgroups;
     build_schedule(pl);
     build_layout(pl);
@@ -744,7 +746,7 @@ void get_group_schedule(const Plan* pl, int gi, mam_schedule* s) {
     s->order = 1;
     s->streaming = 1;
     s->rows_per_tile = pl->lg.rows;
-    s->candidates_per_column = pl->lg.cap;
+    s->candidate_slots = pl->lg.cap;
     return;
   }
   const Group& g = pl->G[gi];
@@ -830,6 +832,7 @@ void fill_probdev(Plan* pl, std::vector<mam::ProbDev<T>>& out) {
     d.cost_mode = p.cost_mode;
     d.nb = p.nb;
     d.warm = (p.flags & MAM_FLAG_COLD) ? 0 : 1;
+    d.relaxed = (p.flags & MAM_FLAG_RELAXED) ? 1 : 0;
     d.rho = p.rho;
     d.inv_rho = 1.0 / p.rho;
     d.gamma = p.gamma;
@@ -978,6 +981,7 @@ mam::LongArgs<T> long_args(Plan* pl) {
   a.nrb = lg.nrb;
   a.cap = lg.cap;
   a.warm = (p.flags & MAM_FLAG_COLD) ? 0 : 1;
+  a.relaxed = (p.flags & MAM_FLAG_RELAXED) ? 1 : 0;
   a.rho = p.rho;
   a.inv_rho = 1.0 / p.rho;
   a.gamma = p.gamma;
@@ -994,11 +998,10 @@ mam::LongArgs<T> long_args(Plan* pl) {
   a.it_j1 = at<int64_t>(pl, lg.o_it_j1);
   a.it_poff = at<int64_t>(pl, lg.o_it_poff);
   a.wg_it = at<int32_t>(pl, lg.o_wg_it);
-  a.cnt = at<int32_t>(pl, lg.o_cnt);
+  a.hmax = at<double>(pl, lg.o_hmax);
+  a.hcnt = at<int32_t>(pl, lg.o_hcnt);
   a.crow = at<int32_t>(pl, lg.o_crow);
   a.cw = at<double>(pl, lg.o_cw);
-  a.sub_off = at<int32_t>(pl, lg.o_sub_off);
-  a.sub_cnt = at<int32_t>(pl, lg.o_sub_cnt);
   a.lam = at<double>(pl, p.o_lam);
   a.partial = at<double>(pl, pl->lay.partial);
   a.stop = pl->gate;
@@ -1006,7 +1009,7 @@ mam::LongArgs<T> long_args(Plan* pl) {
   return a;
 }
 
-// t^k, cleared candidate counts, then scan, threshold and write.
+// t^k, then scan, threshold and write (the scan rewrites every header).
 template <typename T>
 mam_status launch_long_columns(Plan* pl, hipStream_t st) {
   const Prob& p = pl->P[0];
@@ -1016,9 +1019,6 @@ mam_status launch_long_columns(Plan* pl, hipStream_t st) {
   mam::LongArgs<T> a = long_args<T>(pl);
   hipLaunchKernelGGL(mam::damping_kernel, dim3(1), dim3(256), 0, st, a.d2part, p.nb, p.rho, p.gamma, a.t, a.stop);
   LAUNCH_CHECK("damping_kernel");
-  hipLaunchKernelGGL(mam::fill_i32_kernel, dim3((unsigned)std::min<int64_t>(1024, (p.T + 255) / 256)), dim3(256), 0,
-                     st, a.cnt, p.T, 0, a.stop);
-  LAUNCH_CHECK("fill_i32_kernel");
   hipLaunchKernelGGL(fn.scan, dim3(lg.nwg), dim3(mam::LNT), 0, st, a);
   LAUNCH_CHECK("long_scan_kernel");
   hipLaunchKernelGGL(fn.thresh, dim3((unsigned)((p.T + 3) / 4)), dim3(256), 0, st, a);
@@ -1188,7 +1188,7 @@ mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
     HIP_TRY(hipStreamSynchronize(st));
     if (chk[p.M] != 0.0) return fail(MAM_ENONFINITE, "problem %zu: q holds a negative or non-finite weight", i);
     if (chk[p.M + 1] != 0.0) return fail(MAM_ENONFINITE, "problem %zu: cost holds a non-finite entry", i);
-    if (std::isinf(p.gamma)) {
+    if (std::isinf(p.gamma) && !(p.flags & MAM_FLAG_RELAXED)) {
       const double tol = pl->dtype == MAM_F32 ? 1e-6 : 1e-12;
       double lo = chk[0], hi = chk[0];
       for (int64_t m = 1; m < p.M; ++m) {
@@ -1451,6 +1451,8 @@ mam_status plan_timing_read(Plan* pl, double* total_ms, int64_t* launches) {
 mam_status adjoint_layout(const Plan* pl, int64_t K, int64_t C, Adjoint* A) {
   if (pl->batch) return fail(MAM_EUNSUPPORTED, "the reverse mode is available for single problems");
   if (pl->lg.on) return fail(MAM_EUNSUPPORTED, "the reverse mode is not available for long columns");
+  if (pl->P[0].flags & MAM_FLAG_RELAXED)
+    return fail(MAM_EUNSUPPORTED, "the reverse mode is not available for relaxed measure constraints");
   if (K < 0) return fail(MAM_EINVAL, "iters must be >= 0");
   const Prob& p = pl->P[0];
   const Group& g = pl->G[0];
@@ -1849,7 +1851,7 @@ void bundle_build(const Plan* pl, const int32_t* bundle_of, int bi, BundleHost* 
     for (size_t k = 0; k < h->seg_m.size(); ++k) h->mpoff[fill[h->seg_m[k]]++] = h->seg_poff[k];
   }
   for (int64_t m : ms)
-    for (int64_t r0 = 0; r0 < p.R; r0 += 256) h->mtasks.push_back({0, (int32_t)m, (int32_t)r0, 0});
+    for (int64_t r0 = 0; r0 < p.R; r0 += 256) h->mtasks.push_back({0, (int32_t)m, (int32_t)r0, (int32_t)m});
   *nwg_out = nwg;
 }
 

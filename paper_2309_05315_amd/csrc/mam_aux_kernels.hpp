@@ -237,11 +237,6 @@ damping_kernel(const double* __restrict__ d2part, int nb, double rho, double gam
   }
 }
 
-__global__ void __launch_bounds__(256) fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v,
-                                                       const int32_t* __restrict__ stop) {
-  if (stop != nullptr && *stop != 0) return;
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
-}
 
 // theta^0_rs = q_s / R (Alg. 1 Step 0 with the library's default start).
 template <typename T>

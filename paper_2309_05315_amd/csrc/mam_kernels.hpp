@@ -207,6 +207,7 @@ struct ProbDev {
   int64_t ld, cost_ld;
   int32_t R, cost_mode;
   int32_t nb, warm;       // nb: d^2 partials; warm: use stored thresholds as starts
+  int32_t relaxed, pad;   // relaxed: columns projected onto {u >= 0, sum u <= q_s}
   double rho, inv_rho, gamma;
   const double* pm;       // M x R marginals of the current plans
   const double* p;        // R, averaged marginal
@@ -424,6 +425,7 @@ column_kernel(ColArgs<T> a) {
     const int32_t* const cidx = gptr((const int32_t*)uniform_l((int64_t)P.cidx));
     const int64_t ld = uniform_l(P.ld), cost_ld = uniform_l(P.cost_ld);
     const int R = uniform_i(P.R), cost_mode = uniform_i(P.cost_mode), warm = uniform_i(P.warm);
+    const bool relaxed = uniform_i(P.relaxed) != 0;
     const double inv_rho = uniform_d(P.inv_rho);
     double* const lamv = gptr((double*)uniform_l((int64_t)P.lam));
     const int m = uniform_i(a.seg_m[si]);
@@ -653,6 +655,13 @@ column_kernel(ColArgs<T> a) {
       }
 
       // ---- theta' = -b, patched at the active rows with max(w - lam, 0) - b ----
+      // With relaxed columns the projection onto {u >= 0, sum u <= q_s} is
+      // max(w - max(lam, 0), 0): the clamped column if it carries at most q_s
+      // (then the simplex threshold is <= 0), else the simplex projection.
+      // The stored warm start stays the simplex threshold.
+      double lout[KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) lout[kc] = relaxed ? fmax(lam[kc], 0.0) : lam[kc];
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         if (!valid[kc]) continue;
@@ -671,7 +680,7 @@ column_kernel(ColArgs<T> a) {
               const int k = c * VEC + v;
               out[v] = nb[k];
               if ((mask[kc] >> k) & 1) {
-                const double ph = fmax(w[kc][k] - lam[kc], 0.0);
+                const double ph = fmax(w[kc][k] - lout[kc], 0.0);
                 out[v] = (T)(ph - lds_b[k * NT + tid]);
                 fix[k * NT + tid] += (double)out[v] - (double)nb[k];
                 if constexpr (DIAG) {
@@ -710,7 +719,7 @@ column_kernel(ColArgs<T> a) {
             colsum = cs;
             rounds.par ^= 1;
           }
-          dRes = fmax(dRes, fabs(colsum - tau[kc]));
+          dRes = fmax(dRes, relaxed ? fmax(colsum - tau[kc], 0.0) : fabs(colsum - tau[kc]));
           if (tid == 0) {
             dRounds += nrounds[kc];
             dAct += nact[kc];

@@ -9,26 +9,27 @@
 // k < VPT.  One iteration of Alg. 1 is three kernels plus the marginal and
 // averaging kernels of the short path:
 //
-//   scan       per (sub-tile, column): w = theta + 2b - c/rho, the sub-tile's
-//              maximum w_loc, and every entry with w > w_loc - q_s appended
-//              as (row, w) to the column's candidate list.  An entry left out
-//              has w <= w_loc - q_s <= w_max - q_s <= lambda (one entry of a
+//   scan       per (column, sub-tile): w = theta + 2b - c/rho, the sub-tile's
+//              maximum w_loc, and the entries with w > w_loc - q_s (at most
+//              E of them kept, in fixed slots).  An entry left out has
+//              w <= w_loc - q_s <= w_max - q_s <= lambda (one entry of a
 //              projection onto Delta_R(q_s) carries at most q_s, Prop. 3), so
 //              it is inactive.
-//   threshold  per column: the exact threshold of Prop. 3 from the candidates
-//              alone.  Newton steps on the piecewise-linear root with an
-//              exactness certificate; every step is kept >= w_max - q_s, so
-//              the left-out entries stay below it.
-//   write      per (sub-tile, column): theta' = -b everywhere, patched with
-//              max(w - lambda, 0) - b at the candidates above lambda, and the
-//              row-sum partials of the tile (fixed order, no atomics).
+//   threshold  per column (one wave): the exact threshold of Prop. 3 from the
+//              kept entries of the sub-tiles with w_loc > w_max - q_s (no other
+//              sub-tile can hold an active entry).  Newton steps on the
+//              piecewise-linear root with an exactness certificate; every step
+//              is kept >= w_max - q_s, so the left-out entries stay below it.
+//   write      per (column, sub-tile): theta' = -b everywhere, patched with
+//              max(w - lambda, 0) - b at the kept entries above lambda (none
+//              unless w_loc > lambda), and the tile's row-sum partials (fixed
+//              order, no atomics).
 //
-// The candidate lists are the only cross-workgroup exchange: theta and c are
-// read once and theta written once per iteration.  A column whose candidates
-// exceed the list capacity is handled from theta and c directly: threshold
-// rounds over the whole column, and a write pass that recomputes w before
-// overwriting theta.  Summation orders are fixed: results are bitwise
-// reproducible.
+// The sub-tile headers and slots are the only cross-workgroup exchange: theta
+// and c are read once and theta written once per iteration.  A sub-tile with
+// more than E candidates is recomputed from theta and c where it is needed
+// (threshold rounds, and the write pass before theta is overwritten).  Every
+// sum has a fixed order: results are bitwise reproducible.
 #pragma once
 
 #include "mam_kernels.hpp"
@@ -45,7 +46,8 @@ struct LongArgs {
   const int32_t* cidx;
   int64_t ld, cost_ld;
   int32_t R, cost_mode, M, nrb;  // nrb: row tiles per column
-  int32_t cap, warm;             // candidate capacity per column; warm starts on
+  int32_t cap, warm;             // candidate slots per sub-tile; warm starts on
+  int32_t relaxed, pad0;         // columns projected onto {u >= 0, sum u <= q_s}
   double rho, inv_rho, gamma;
   double* t;                     // damping t^k of the iteration (set by damping_kernel)
   const double* p;               // R, averaged marginal
@@ -61,12 +63,11 @@ struct LongArgs {
   const int64_t* it_j1;
   const int64_t* it_poff;        // offset of the item's RB row-sum partials
   const int32_t* wg_it;          // items of workgroup w: [wg_it[w], wg_it[w+1])
-  // candidates
-  int32_t* cnt;                  // T: entries appended to column j this iteration
-  int32_t* crow;                 // T*cap rows
-  double* cw;                    // T*cap values of w
-  int32_t* sub_off;              // (j*nrb + rb)*4 + wave: first entry of the sub-tile
-  int32_t* sub_cnt;              //                        entries of the sub-tile
+  // per (column j, sub-tile s = rb*4 + wave), index h = j*nrb*4 + s
+  double* hmax;                  // the sub-tile's maximum of w
+  int32_t* hcnt;                 // its candidates (entries with w > hmax - q_s)
+  int32_t* crow;                 // h*cap + e: row of candidate e < min(hcnt, cap)
+  double* cw;                    //            its w
   double* lam;                   // T: threshold (previous one in, new one out)
   double* partial;
   const int32_t* stop;           // early-exit flag, or null
@@ -88,7 +89,7 @@ __device__ __forceinline__ double long_b(double t, const double* p, const double
   return t * (p[r] - pmm[r]) / Sm;
 }
 
-// ---- scan: w, sub-tile maxima, candidate lists ---------------------------
+// ---- scan: w, sub-tile maxima, candidates -------------------------------
 template <typename T, int VPT, int VEC>
 __global__ void __launch_bounds__(LNT)
 long_scan_kernel(LongArgs<T> a) {
@@ -97,11 +98,10 @@ long_scan_kernel(LongArgs<T> a) {
   if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = uniform_i(tid >> 6);
-  const int R = a.R, cap = a.cap, nrb = a.nrb;
+  const int R = a.R, cap = a.cap, nsub = a.nrb * 4;
   const double t = uniform_d(*gptr(a.t)), inv_rho = a.inv_rho;
   const T* const theta = gptr(a.theta);
   const T* const qv = gptr(a.q);
-  int32_t* const cnt = gptr(a.cnt);
   int32_t* const crow = gptr(a.crow);
   double* const cw = gptr(a.cw);
   const int ib = uniform_i(a.wg_it[blockIdx.x]), ie = uniform_i(a.wg_it[blockIdx.x + 1]);
@@ -158,48 +158,40 @@ long_scan_kernel(LongArgs<T> a) {
 #pragma unroll
         for (int k = 0; k < VPT; ++k) bits |= (int)(w[k] > thr) << k;
       }
-      // slot-major order inside the wave: position = entries of earlier
-      // slots + earlier lanes of this slot
-      unsigned long long bal[VPT];
+      // slots in slot-major order inside the wave: position = candidates of
+      // earlier slots + earlier lanes of this slot
+      const int64_t h = j * nsub + rb * 4 + wv;
       int n = 0;
 #pragma unroll
       for (int k = 0; k < VPT; ++k) {
-        bal[k] = __ballot((bits >> k) & 1);
-        n += __popcll(bal[k]);
-      }
-      int off = 0;
-      if (n > 0) {
-        if (lane == 0) off = atomicAdd(cnt + j, n);
-        off = __builtin_amdgcn_readlane(off, 0);
-        int base = off;
-#pragma unroll
-        for (int k = 0; k < VPT; ++k) {
-          if ((bits >> k) & 1) {
-            const int pos = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal[k] >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)bal[k], 0u));
-            if (pos < cap) {
-              crow[j * cap + pos] = row[k];
-              cw[j * cap + pos] = w[k];
-            }
+        const unsigned long long bal = __ballot((bits >> k) & 1);
+        if ((bits >> k) & 1) {
+          const int pos = n + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+          if (pos < cap) {
+            crow[h * cap + pos] = row[k];
+            cw[h * cap + pos] = w[k];
           }
-          base += __popcll(bal[k]);
         }
+        n += __popcll(bal);
       }
       if (lane == 0) {
-        const int64_t s = (j * nrb + rb) * 4 + wv;
-        gptr(a.sub_off)[s] = off;
-        gptr(a.sub_cnt)[s] = n;
+        gptr(a.hmax)[h] = mx;
+        gptr(a.hcnt)[h] = n;
       }
     }
   }
 }
 
 // ---- threshold: one wave per column -------------------------------------
-// Sums over the candidates in a fixed order: sub-tiles in order, and inside
-// a sub-tile lane l takes entries l, l+64, ...; then a fixed wave tree.
-template <typename T>
+// Only sub-tiles with w_loc > w_max - q_s are visited, in index order; inside
+// one, lane e takes kept entry e, or (more than E candidates) lane l
+// recomputes the VPT values of thread 64*wave + l of the tile.  The wave
+// sums in a fixed tree: the order is fixed.
+template <typename T, int VPT, int VEC>
 __global__ void __launch_bounds__(256)
 long_threshold_kernel(LongArgs<T> a) {
+  constexpr int RB = LNT * VPT;
   if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;
   const int lane = threadIdx.x & 63;
   const int64_t j = (int64_t)blockIdx.x * 4 + uniform_i(threadIdx.x >> 6);
@@ -211,16 +203,17 @@ long_threshold_kernel(LongArgs<T> a) {
     if (lane == 0) lamv[j] = __builtin_huge_val();  // q_s = 0: the column is 0
     return;
   }
-  const int ntot = uniform_i(gptr(a.cnt)[j]);
-  const bool listed = ntot <= cap;
-  const int32_t* __restrict__ so = gptr(a.sub_off) + j * nsub;
-  const int32_t* __restrict__ sc = gptr(a.sub_cnt) + j * nsub;
-  const double* __restrict__ cwj = gptr(a.cw) + j * cap;
-  // an unlisted column is recomputed from theta and c: its measure and b
+  const double* __restrict__ hm = gptr(a.hmax) + j * nsub;
+  const int32_t* __restrict__ hc = gptr(a.hcnt) + j * nsub;
+  const double* __restrict__ cwj = gptr(a.cw) + j * nsub * (int64_t)cap;
+  double wmx = -__builtin_huge_val();
+  for (int s = lane; s < nsub; s += 64) wmx = fmax(wmx, hm[s]);
+  wmx = wave_max(wmx);
+  const double lo = wmx - tau;  // the root is >= w_max - tau
+  // an overflowed sub-tile is recomputed from theta and c: the column's
+  // measure and b
   int m = 0;
-  if (!listed) {
-    while (m + 1 < a.M && gptr(a.col_off)[m + 1] <= j) ++m;
-  }
+  while (m + 1 < a.M && gptr(a.col_off)[m + 1] <= j) ++m;
   const double t = uniform_d(*gptr(a.t));
   const double Sm = gptr(a.Sd)[m];
   const int64_t off_m = gptr(a.col_off)[m];
@@ -228,22 +221,27 @@ long_threshold_kernel(LongArgs<T> a) {
   const double* __restrict__ pv = gptr(a.p);
   const T* __restrict__ thp = gptr(a.theta) + j * a.ld;
   const T* __restrict__ cp = long_cost_col(a, j, off_m);
-  // visit every entry of the column that can be active, in the fixed order
   auto visit = [&](auto&& f) {
-    if (listed) {
-      for (int s = 0; s < nsub; ++s) {
-        const int o = uniform_i(so[s]), c = uniform_i(sc[s]);
-        for (int e = lane; e < c; e += 64) f(cwj[o + e]);
+    for (int s0 = 0; s0 < nsub; s0 += 64) {
+      const int s = s0 + lane;
+      unsigned long long rel = __ballot(s < nsub && hm[s < nsub ? s : 0] > lo);
+      while (rel) {
+        const int si = s0 + __builtin_ctzll(rel);
+        rel &= rel - 1;
+        const int n = uniform_i(hc[si]);
+        if (n <= cap) {
+          if (lane < n) f(cwj[(int64_t)si * cap + lane]);
+        } else {
+          const int rbase = (si >> 2) * RB, tt = (si & 3) * 64 + lane;
+#pragma unroll
+          for (int k = 0; k < VPT; ++k) {
+            const int r = rbase + ((k / VEC) * LNT + tt) * VEC + (k % VEC);
+            if (r < R) f(((double)thp[r] + 2.0 * long_b(t, pv, pmm, r, Sm)) - (double)cp[r] * a.inv_rho);
+          }
+        }
       }
-    } else {
-      for (int r = lane; r < R; r += 64)
-        f(((double)thp[r] + 2.0 * long_b(t, pv, pmm, r, Sm)) - (double)cp[r] * a.inv_rho);
     }
   };
-  double wmx = -__builtin_huge_val();
-  visit([&](double x) { wmx = fmax(wmx, x); });
-  wmx = wave_max(wmx);
-  const double lo = wmx - tau;  // the root is >= w_max - tau
   const double lprev = lamv[j];
   double lam = (a.warm && lprev == lprev && lprev > lo) ? lprev : lo;
   int nprev = -1;
@@ -282,15 +280,19 @@ long_threshold_kernel(LongArgs<T> a) {
     nprev = n;
     lam = fmax(ln, lo);
   }
+  // relaxed columns: max(w - max(lam, 0), 0) is the projection onto
+  // {u >= 0, sum u <= q_s} (the write pass patches only entries above it)
+  if (a.relaxed) lam = fmax(lam, 0.0);
   if (lane == 0) lamv[j] = lam;
 }
 
 // ---- write: theta' and the tile's row-sum partials ----------------------
-// Every row is written once, by its owner thread: the active rows of the
-// column among the thread's slots are found first (from the wave's
-// candidates, or from w recomputed for an unlisted column), then the
-// thread's vectors are stored.  Dynamic LDS: VPT*256 doubles of row-sum
-// patches (each row owned by one thread: no atomics).
+// Every row is written once, by its owner thread: the active rows among the
+// thread's slots are found first (from the wave's kept entries, or from w
+// recomputed for an overflowed sub-tile), then the thread's vectors are
+// stored.  A column's threshold and this sub-tile's header are read one
+// column ahead.  Dynamic LDS: VPT*256 doubles of row-sum patches (each row
+// owned by one thread: no atomics).
 template <typename T, int VPT, int VEC>
 __global__ void __launch_bounds__(LNT)
 long_write_kernel(LongArgs<T> a) {
@@ -300,10 +302,11 @@ long_write_kernel(LongArgs<T> a) {
   double* fix = lds_dyn;  // [VPT][256]
   const int tid = threadIdx.x;
   const int wv = uniform_i(tid >> 6);
-  const int R = a.R, cap = a.cap, nrb = a.nrb;
+  const int R = a.R, cap = a.cap, nsub = a.nrb * 4;
   const double t = uniform_d(*gptr(a.t)), inv_rho = a.inv_rho;
   T* const theta = gptr(a.theta);
-  const int32_t* const cnt = gptr(a.cnt);
+  const double* const hm = gptr(a.hmax);
+  const int32_t* const hc = gptr(a.hcnt);
   const int32_t* const crow = gptr(a.crow);
   const double* const cw = gptr(a.cw);
   const double* const lamv = gptr(a.lam);
@@ -316,6 +319,7 @@ long_write_kernel(LongArgs<T> a) {
     const double* __restrict__ pmm = gptr(a.pm) + (size_t)m * R;
     const double* __restrict__ pv = gptr(a.p);
     const int rbase = rb * RB;
+    const int sub = rb * 4 + wv;
     int row[VPT];
     double b[VPT];
     T nb[VPT];  // -b rounded to the storage type: every inactive entry's new value
@@ -326,37 +330,49 @@ long_write_kernel(LongArgs<T> a) {
       nb[k] = (T)(-b[k]);
       fix[k * LNT + tid] = 0.0;  // each thread touches only its own slots
     }
+    // header of the next column, read ahead
+    double nlam = 0.0, nmax = 0.0;
+    int ncnt = 0;
+    auto ahead = [&](int64_t j) {
+      nlam = lamv[j];
+      nmax = hm[j * nsub + sub];
+      ncnt = hc[j * nsub + sub];
+    };
+    if (j0 < j1) ahead(j0);
     for (int64_t j = j0; j < j1; ++j) {
+      const double lam = uniform_d(nlam), lmax = uniform_d(nmax);
+      const int n = uniform_i(ncnt);
+      if (j + 1 < j1) ahead(j + 1);
       T* __restrict__ thp = theta + j * a.ld;
-      const double lam = uniform_d(lamv[j]);
       double w[VPT];
       int act = 0;  // bit k: slot k is active
 #pragma unroll
       for (int k = 0; k < VPT; ++k) w[k] = -__builtin_huge_val();
-      if (uniform_i(cnt[j]) <= cap) {
-        // this wave's candidates; the owner of each active row takes it
-        const int64_t s = (j * nrb + rb) * 4 + wv;
-        const int o = uniform_i(gptr(a.sub_off)[s]), c = uniform_i(gptr(a.sub_cnt)[s]);
-        for (int e = 0; e < c; ++e) {
-          const double x = uniform_d(cw[j * cap + o + e]);
-          if (!(x > lam)) continue;
-          const int rr = uniform_i(crow[j * cap + o + e]) - rbase;
-          if ((rr / VEC) % LNT == tid) {
-            const int ks = (rr / (VEC * LNT)) * VEC + rr % VEC;
+      if (lmax > lam) {  // some entry of this sub-tile is active
+        if (n <= cap) {
+          // the kept entries; the owner of each active row takes it
+          const int64_t h = j * nsub + sub;
+          for (int e = 0; e < n; ++e) {
+            const double x = uniform_d(cw[h * cap + e]);
+            if (!(x > lam)) continue;
+            const int rr = uniform_i(crow[h * cap + e]) - rbase;
+            if ((rr / VEC) % LNT == tid) {
+              const int ks = (rr / (VEC * LNT)) * VEC + rr % VEC;
 #pragma unroll
-            for (int k = 0; k < VPT; ++k)
-              if (k == ks) w[k] = x;
-            act |= 1 << ks;
+              for (int k = 0; k < VPT; ++k)
+                if (k == ks) w[k] = x;
+              act |= 1 << ks;
+            }
           }
-        }
-      } else {
-        // no candidate list: w from theta and c, read before theta is overwritten
-        const T* __restrict__ cp = long_cost_col(a, j, off_m);
+        } else {
+          // more candidates than slots: w from theta and c, read before theta is overwritten
+          const T* __restrict__ cp = long_cost_col(a, j, off_m);
 #pragma unroll
-        for (int k = 0; k < VPT; ++k) {
-          if (row[k] < R) {
-            w[k] = ((double)thp[row[k]] + 2.0 * b[k]) - (double)cp[row[k]] * inv_rho;
-            act |= (int)(w[k] > lam) << k;
+          for (int k = 0; k < VPT; ++k) {
+            if (row[k] < R) {
+              w[k] = ((double)thp[row[k]] + 2.0 * b[k]) - (double)cp[row[k]] * inv_rho;
+              act |= (int)(w[k] > lam) << k;
+            }
           }
         }
       }

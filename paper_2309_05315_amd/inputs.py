@@ -40,6 +40,9 @@ __all__ = [
     "batched_problems",
     "tiny_problem",
     "line_problem",
+    "free_support_grid",
+    "nested_ellipses",
+    "free_support",
 ]
 
 
@@ -58,6 +61,9 @@ class Problem:
     iters: int = 1
     dtype: str = "f64"            # storage precision of plans, cost, q
     meta: dict = field(default_factory=dict)
+    # support points instead of a stored cost (cost None): c_rs = ||xi_r - zeta_s||^2
+    xi: Optional[np.ndarray] = None      # (R, d) float64
+    zeta: Optional[np.ndarray] = None    # (ncols, d) float64
 
     @property
     def M(self) -> int:
@@ -84,7 +90,22 @@ class Problem:
 
     def cost_block(self, m: int) -> np.ndarray:
         """c^(m) as an R x S^m float64 matrix."""
+        if self.cost is None:
+            return np.stack([self.cost_column(int(c)) for c in self.cost_columns(m)], axis=1)
         return np.ascontiguousarray(self.cost[self.cost_columns(m)].T)
+
+    @property
+    def cost_ncols(self) -> int:
+        return int(self.zeta.shape[0] if self.cost is None else self.cost.shape[0])
+
+    def cost_column(self, c: int) -> np.ndarray:
+        """Cost column c (length R, float64, rounded to the storage precision)."""
+        if self.cost is not None:
+            return self.cost[c].copy()
+        d = np.zeros(self.R)
+        for k in range(self.xi.shape[1]):
+            d += (self.xi[:, k] - self.zeta[c, k]) ** 2
+        return _round(d, self.dtype)
 
     def q_block(self, m: int) -> np.ndarray:
         off = self.offsets
@@ -318,6 +339,56 @@ def line_problem(seed: int, R: int, M: int, dtype: str = "f64", rho: float = 1.0
         name=f"line_R{R}_M{M}", R=R, S=[R] * M, cost=_round(cost, dtype),
         q=_round(np.concatenate(qs), dtype), col_index=None, rho=rho, gamma=gamma,
         iters=iters, dtype=dtype, meta={"seed": seed})
+
+
+def free_support_grid(K: int, M: int, d: int = 2) -> np.ndarray:
+    """The set Xi of Theorem c: every average (1/M) sum_m zeta_m of M pixel
+    centres ((i + 1/2)/K per axis) of a K^d grid.  Per axis these are
+    (I + M/2)/(M K), I = 0, ..., M(K-1): a uniform grid of ((K-1)M+1)^d points
+    (row-major, last axis fastest)."""
+    v = (np.arange(M * (K - 1) + 1) + M / 2) / (M * K)
+    mesh = np.meshgrid(*([v] * d), indexing="ij")
+    return np.stack([g.ravel() for g in mesh], axis=1)
+
+
+def nested_ellipses(rng: np.random.Generator, K: int) -> np.ndarray:
+    """A K x K image of two or three concentric, equally rotated elliptic
+    rings (random centre, axes and angle), as a float64 histogram of mass 1
+    on the pixel centres (row-major)."""
+    c = (np.arange(K) + 0.5) / K
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    cx, cy = rng.uniform(0.35, 0.65, size=2)
+    a, b = rng.uniform(0.15, 0.3, size=2)
+    phi = rng.uniform(0, np.pi)
+    u = (X - cx) * np.cos(phi) + (Y - cy) * np.sin(phi)
+    v = -(X - cx) * np.sin(phi) + (Y - cy) * np.cos(phi)
+    rad = np.sqrt((u / a) ** 2 + (v / b) ** 2)  # 1 on the outer ellipse
+    nrings = int(rng.integers(2, 4))
+    scales = np.linspace(1.0, 0.3, nrings)
+    width = 1.5 / (K * min(a, b))             # about 1.5 pixels, in units of rad
+    h = sum(np.exp(-((rad - sc) ** 2) / (2 * width ** 2)) for sc in scales).ravel()
+    return h / h.sum()
+
+
+def free_support(seed: int = 0, K: int = 60, M: int = 10, dtype: str = "f32", rho: float = 1.0,
+                 iters: int = 100) -> Problem:
+    """Free-support barycenter of M nested-ellipse images on a K x K grid with
+    alpha_m = 1/M (Theorem c): support Xi of ((K-1)M+1)^2 points (349,281 for
+    K = 60, M = 10), S^m = K^2 pixels per measure (all kept; weights that
+    round to zero project to zero columns), squared Euclidean cost between
+    Xi and the pixel centres, not scaled.  The cost is given by its points
+    (xi, zeta): it is R x K^2 values per measure-independent column set."""
+    rng = np.random.default_rng([9, seed])
+    xi = free_support_grid(K, M)
+    c = (np.arange(K) + 0.5) / K
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    zeta = np.stack([X.ravel(), Y.ravel()], axis=1)
+    q = np.concatenate([nested_ellipses(rng, K) for _ in range(M)])
+    S = K * K
+    return Problem(
+        name=f"free_support_K{K}_M{M}", R=xi.shape[0], S=[S] * M, cost=None, q=_round(q, dtype),
+        col_index=None, rho=rho, iters=iters, dtype=dtype,
+        meta={"K": K, "M": M, "seed": seed}, xi=xi, zeta=zeta)
 
 
 def bundle_sequence(bundles, iters: int, seed: int = 0, alpha=None) -> np.ndarray:

@@ -19,12 +19,12 @@ import numpy as np
 import torch
 
 __all__ = ["lib", "MAMError", "Solver", "Batch", "solver_for", "cost_sq_euclid",
-           "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "FLAG_DIAG", "FLAG_COLD",
+           "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "FLAG_DIAG", "FLAG_COLD", "FLAG_RELAXED",
            "STOP_TESTS", "EXPORTED"]
 
 F32, F64 = 0, 1
 COST_PER_COLUMN, COST_SHARED, COST_INDEXED = 0, 1, 2
-FLAG_DIAG, FLAG_COLD = 1, 2
+FLAG_DIAG, FLAG_COLD, FLAG_RELAXED = 1, 2, 4
 # stopping tests of Sec. 5 (MAM_STOP_*)
 STOP_TESTS = {"dtheta": 0, "dp": 1, "dist": 2}
 
@@ -70,7 +70,7 @@ class Schedule(ctypes.Structure):
                 ("columns_in_flight", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("vector_width", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("streaming", ctypes.c_int32),
-                ("rows_per_tile", ctypes.c_int32), ("candidates_per_column", ctypes.c_int32)]
+                ("rows_per_tile", ctypes.c_int32), ("candidate_slots", ctypes.c_int32)]
 
 
 class StopResult(ctypes.Structure):
@@ -183,9 +183,10 @@ class Solver:
                  dtype: torch.dtype = torch.float32, cost_mode: int = COST_SHARED,
                  cost_ncols: Optional[int] = None, ld: Optional[int] = None,
                  cost_ld: Optional[int] = None, diag: bool = False, cold: bool = False,
+                 relaxed: bool = False,
                  threads_per_column: int = 0, columns_in_flight: int = 0,
                  workgroups: int = 0, xcd_remap: int = 0, order: int = 0, streaming: int = 0,
-                 rows_per_tile: int = 0, candidates_per_column: int = 0, device="cuda"):
+                 rows_per_tile: int = 0, candidate_slots: int = 0, device="cuda"):
         L = lib()
         self.device = torch.device(device)
         self.R, self.S = int(R), [int(s) for s in S]
@@ -202,15 +203,15 @@ class Solver:
         d = Desc(dtype=F32 if dtype == torch.float32 else F64, cost_mode=cost_mode,
                  R=self.R, M=self.M, S=self._S_arr, ld=self.ld, cost_ld=self.cost_ld,
                  cost_ncols=self.cost_ncols, rho=float(rho), gamma=float(gamma),
-                 flags=(FLAG_DIAG if diag else 0) | (FLAG_COLD if cold else 0))
+                 flags=(FLAG_DIAG if diag else 0) | (FLAG_COLD if cold else 0) | (FLAG_RELAXED if relaxed else 0))
         h = _vp()
         _check(L.mam_create(ctypes.byref(h), ctypes.byref(d)), "mam_create")
         self._h = h
         if (threads_per_column or columns_in_flight or workgroups or xcd_remap or order or streaming
-                or rows_per_tile or candidates_per_column):
+                or rows_per_tile or candidate_slots):
             sc = Schedule(threads_per_column=threads_per_column, columns_in_flight=columns_in_flight,
                           workgroups=workgroups, xcd_remap=xcd_remap, order=order, streaming=streaming,
-                          rows_per_tile=rows_per_tile, candidates_per_column=candidates_per_column)
+                          rows_per_tile=rows_per_tile, candidate_slots=candidate_slots)
             _check(L.mam_set_schedule(h, ctypes.byref(sc)), "mam_set_schedule")
         nbytes = int(L.mam_workspace_bytes(h))
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
@@ -345,24 +346,34 @@ class Solver:
             pass
 
 
-def solver_for(problem, device="cuda", diag: bool = False, cold: bool = False, **sched) -> Solver:
-    """Allocate device buffers for an ``inputs.Problem`` and bind them."""
+def solver_for(problem, device="cuda", diag: bool = False, cold: bool = False, relaxed: bool = False,
+               **sched) -> Solver:
+    """Allocate device buffers for an ``inputs.Problem`` and bind them
+    (relaxed: measure constraints sum_r pi_rs <= q_s, with the problem's
+    cost taken as the shifted c - eta)."""
     dt = torch.float32 if problem.dtype == "f32" else torch.float64
+    ncols = problem.cost_ncols
     if problem.col_index is None:
-        mode, ncols = COST_SHARED, problem.cost.shape[0]
+        mode = COST_SHARED
     elif np.array_equal(problem.col_index, np.arange(problem.T)):
-        mode, ncols = COST_PER_COLUMN, problem.cost.shape[0]
+        mode = COST_PER_COLUMN
     else:
-        mode, ncols = COST_INDEXED, problem.cost.shape[0]
+        mode = COST_INDEXED
     s = Solver(problem.R, problem.S, rho=problem.rho, gamma=problem.gamma, dtype=dt,
-               cost_mode=mode, cost_ncols=ncols, diag=diag, cold=cold, device=device, **sched)
-    cost = torch.zeros(ncols, s.cost_ld, dtype=dt)
-    cost[:, :problem.R] = torch.from_numpy(problem.cost).to(dt)
+               cost_mode=mode, cost_ncols=ncols, diag=diag, cold=cold, relaxed=relaxed, device=device, **sched)
+    if problem.cost is None:
+        # a cost given by its points is built on the device (rounded once to dt)
+        cost = cost_sq_euclid(torch.from_numpy(problem.xi).to(device), torch.from_numpy(problem.zeta).to(device),
+                              dtype=dt, ld=s.cost_ld)
+    else:
+        cost = torch.zeros(ncols, s.cost_ld, dtype=dt)
+        cost[:, :problem.R] = torch.from_numpy(problem.cost).to(dt)
+        cost = cost.to(device)
     theta = torch.zeros(problem.T, s.ld, dtype=dt, device=device)
     idx = None
     if mode == COST_INDEXED:
         idx = torch.from_numpy(problem.col_index.astype(np.int32)).to(device)
-    s.bind(theta, cost.to(device), torch.from_numpy(problem.q).to(dt).to(device), idx)
+    s.bind(theta, cost, torch.from_numpy(problem.q).to(dt).to(device), idx)
     return s
 
 

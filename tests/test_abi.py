@@ -193,17 +193,17 @@ def test_long_column_path_selection():
     rc, h = create(R=10000, S=[30, 20])
     assert rc == 0
     assert L.mam_get_schedule(h, ctypes.byref(sc)) == 0
-    assert sc.rows_per_tile == 2048 and sc.candidates_per_column == 4096   # double
+    assert sc.rows_per_tile == 2048 and sc.candidate_slots == 32   # double
     assert L.mam_workspace_bytes(h) > 0
     assert L.mam_adjoint_workspace_bytes(h, 10, 0) == 0                    # no reverse mode
     B2 = ctypes.c_int32 * 2
     assert L.mam_bundle_workspace_bytes(h, B2(0, 1), 2) == 0               # no randomized variant
     bad = mam.Schedule(rows_per_tile=1000)
     assert L.mam_set_schedule(h, ctypes.byref(bad)) == -1
-    ok = mam.Schedule(rows_per_tile=1024, candidates_per_column=64)
+    ok = mam.Schedule(rows_per_tile=1024, candidate_slots=8)
     assert L.mam_set_schedule(h, ctypes.byref(ok)) == 0
     assert L.mam_get_schedule(h, ctypes.byref(sc)) == 0
-    assert sc.rows_per_tile == 1024 and sc.values_per_thread == 4 and sc.candidates_per_column == 64
+    assert sc.rows_per_tile == 1024 and sc.values_per_thread == 4 and sc.candidate_slots == 8
     L.mam_destroy(h)
     # forced on a short problem, and back
     rc, h = create(R=300, S=[40, 17])

@@ -125,3 +125,54 @@ def test_batch_of_256_full_size_sampled_problems():
         e = np.abs(got - ref).sum() / np.abs(ref).sum()
         say(f"problem {i} {p.name}: rel L1 {e:.2e}")
         assert e <= 1e-5
+
+
+def test_free_support_full_size_sampled_columns():
+    """Free-support barycenter of 10 nested-ellipse 60x60 images: the R =
+    349,281 support points of Theorem c, T = 36,000 columns, 50 GB of FP32
+    plans, default long-column schedule.  theta^6 columns from the GPU's
+    theta^5 through the oracle's step with the oracle's own cost (built from
+    the points in FP64 and rounded once to float, as the device builds it;
+    the two may differ by one float ulp, and the projection moves at most
+    twice as far as w, which the tolerance allows).  The marginal of
+    measure 0 is checked against a plain FP64 sum of its 3,600 columns."""
+    p = inputs.free_support(dtype="f32")
+    say(f"{p.name}: R={p.R} M={p.M} T={p.T}")
+    s = mam.solver_for(p)
+    sc = s.schedule()
+    say(f"schedule {sc}")
+    assert sc["rows_per_tile"] > 0
+    s.init()
+    s.iterate(5)
+    torch.cuda.synchronize()
+    off = p.offsets
+    rng = np.random.default_rng(4321)
+    cols = np.sort(np.concatenate([rng.choice(np.arange(off[m], off[m + 1]), size=3, replace=False)
+                                   for m in range(p.M)]))
+    cols_t = torch.as_tensor(cols, device=s.theta.device)
+    th5 = s.theta[cols_t, :p.R].double().cpu().numpy()
+    pm5 = s.marginals().cpu().numpy()
+    pm0 = np.zeros(p.R)
+    for c0 in range(off[0], off[1], 360):
+        pm0 += s.theta[c0:min(c0 + 360, off[1]), :p.R].cpu().numpy().astype(np.float64).sum(axis=0)
+    e_pm = np.abs(pm5[0] - pm0).max() / np.abs(pm0).max()
+    say(f"marginal of measure 0 over theta^5: max rel {e_pm:.2e}")
+    assert e_pm <= 1e-9
+    s.iterate(1)
+    torch.cuda.synchronize()
+    meas = np.searchsorted(off, cols, side="right") - 1
+    cost_cols = np.stack([p.cost_column(int(c - off[m])) for c, m in zip(cols, meas)], axis=1)
+    new, _, t = O.mam_step_columns(th5.T, meas, pm5, cost_cols, p.q[cols].astype(np.float64), p.S, p.rho,
+                                   p.gamma)
+    got = s.theta[cols_t, :p.R].double().cpu().numpy().T
+    dc = np.abs(s.cost[torch.as_tensor(cols - off[meas], device=s.cost.device), :p.R].double().cpu().numpy().T
+                - cost_cols).max(axis=0)
+    say(f"device cost vs oracle cost on the sampled columns: max |diff| {dc.max():.2e}")
+    assert np.all(dc <= 2.0 ** -23 * np.abs(cost_cols).max(axis=0))
+    err = np.abs(got - new)
+    bound = 2.0 ** -23 * np.abs(new) + 2.0 * dc[None, :] / p.rho
+    say(f"{len(cols)} sampled columns: max |diff| / bound = {np.max(err / np.maximum(bound, 1e-300)):.3f}")
+    assert np.all(err <= bound)
+    drift = np.abs(s.marginals().cpu().numpy().sum(axis=1) - 1.0).max()
+    say(f"mass drift after 6 iterations: {drift:.2e}")
+    assert drift <= 1e-5

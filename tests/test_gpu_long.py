@@ -88,10 +88,10 @@ def test_unbalanced_long_path(dtype):
 
 @pytest.mark.parametrize("rho", [1.0, 200.0])
 def test_candidate_overflow_falls_back_exactly(rho):
-    # a capacity of 4 entries overflows on most columns: those columns take
-    # their threshold and write pass from theta and c
+    # one slot per sub-tile overflows near every active set: those sub-tiles
+    # are recomputed from theta and c in the threshold and write passes
     p = inputs.tiny_problem(13, R=2600, S=[24, 18], rho=rho)
-    check(p, 20, rows_per_tile=1024, candidates_per_column=4)
+    check(p, 20, rows_per_tile=1024, candidate_slots=1)
 
 
 def test_large_rho_many_candidates():

@@ -155,7 +155,7 @@ typedef struct mam_schedule {
                                  forces the path at any R.                      */
   int32_t candidate_slots;    /* long-column path: candidates kept per
                                  (column, wave sub-tile of 64*rows_per_tile/256
-                                 rows), 1..64; 0 automatic (32).  A sub-tile
+                                 rows), 1..64; 0 automatic (64).  A sub-tile
                                  with more candidates in an iteration is
                                  recomputed from theta and c (same result,
                                  slower).                                       */

@@ -164,7 +164,7 @@ struct Bundles {
 // over the workgroups; per (column, wave sub-tile) a header (maximum of w,
 // candidate count) and 'cap' candidate slots.
 struct LongPlan {
-  bool on = false;
+  bool on = false, sets = false;
   int vpt = 16, rows = 4096, nrb = 0, cap = 0, vec = 1;
   int nwg = 1, nwg_req = 0, nwg_auto = 0, rows_req = 0, cap_req = 0;
   std::vector<int32_t> it_rb, it_m, wg_it;
@@ -519,6 +519,12 @@ void build_schedule(Plan* pl) {
 // shares, one per workgroup; each piece inside one (rb, measure) is an item
 // with its own RB-row partial.  The marginal kernel sums, for a row of tile
 // rb, the items of (measure, rb): list index m*nrb + rb.
+//
+// Measure sets: with one cost shared by M measures of equal size, plan
+// column s of every measure reads cost column s.  The M workgroups of a set
+// then take the same (rb, s) units, one measure each, and sit on one XCD
+// (the hardware deals workgroup b to XCD b mod 8), so a cost tile fetched
+// by one of them is read by the others from that XCD's L2.
 void build_long_schedule(Plan* pl) {
   LongPlan& lg = pl->lg;
   const Prob& p = pl->P[0];
@@ -526,7 +532,7 @@ void build_long_schedule(Plan* pl) {
   lg.vpt = lg.rows_req ? lg.rows_req / 256 : (pl->dtype == MAM_F32 ? 16 : 8);
   lg.rows = 256 * lg.vpt;
   lg.nrb = (int)((p.R + lg.rows - 1) / lg.rows);
-  lg.cap = lg.cap_req ? lg.cap_req : 32;
+  lg.cap = lg.cap_req ? lg.cap_req : 64;
   if (!p.theta) lg.vec = vn;  // until binding checks the alignment
   const int64_t units = (int64_t)lg.nrb * p.T;
   const int64_t cap_wg = lg.nwg_auto > 0 ? std::min(lg.nwg_auto, 1024) : 1024;
@@ -537,9 +543,34 @@ void build_long_schedule(Plan* pl) {
   lg.it_j1.clear();
   lg.it_poff.clear();
   lg.wg_it.clear();
-  int rb = 0, m = 0;
+  bool equal_S = true;
+  for (int64_t k = 1; k < p.M; ++k) equal_S = equal_S && p.S[k] == p.S[0];
+  const int64_t sets_per_xcd = cap_wg / 8 / std::max<int64_t>(p.M, 1);
+  lg.sets = p.cost_mode == MAM_COST_SHARED && equal_S && p.M >= 2 && lg.nwg_req == 0 && sets_per_xcd >= 1 &&
+            (int64_t)lg.nrb * p.S[0] >= 8 * sets_per_xcd;
+  if (lg.sets) {
+    const int64_t G = 8 * sets_per_xcd, M = p.M, S = p.S[0], su = (int64_t)lg.nrb * S;
+    lg.nwg = (int)(G * M);
+    for (int b = 0; b < lg.nwg; ++b) {
+      // workgroup b: XCD b % 8, slot b / 8 = (set within the XCD) * M + measure
+      const int64_t x = b % 8, k = b / 8, mm = k % M, g = (k / M) * 8 + x;
+      lg.wg_it.push_back((int32_t)lg.it_rb.size());
+      int64_t u = su * g / G;
+      const int64_t u1 = su * (g + 1) / G;
+      while (u < u1) {
+        const int64_t rbu = u / S, s0 = u % S, take = std::min(u1 - u, S - s0);
+        lg.it_rb.push_back((int32_t)rbu);
+        lg.it_m.push_back((int32_t)mm);
+        lg.it_j0.push_back(p.col_off[mm] + s0);
+        lg.it_j1.push_back(p.col_off[mm] + s0 + take);
+        lg.it_poff.push_back((int64_t)lg.it_rb.size() - 1);
+        u += take;
+      }
+    }
+  }
+  int rb = lg.sets ? lg.nrb : 0, m = 0;
   int64_t pos = 0;  // columns of (rb, m) already given out
-  for (int w = 0; w < lg.nwg; ++w) {
+  for (int w = 0; w < lg.nwg && !lg.sets; ++w) {
     int64_t need = units * (w + 1) / lg.nwg - units * w / lg.nwg;
     lg.wg_it.push_back((int32_t)lg.it_rb.size());
     while (need > 0 && rb < lg.nrb) {

@@ -287,12 +287,15 @@ long_threshold_kernel(LongArgs<T> a) {
 }
 
 // ---- write: theta' and the tile's row-sum partials ----------------------
-// Every row is written once, by its owner thread: the active rows among the
-// thread's slots are found first (from the wave's kept entries, or from w
-// recomputed for an overflowed sub-tile), then the thread's vectors are
-// stored.  A column's threshold and this sub-tile's header are read one
-// column ahead.  Dynamic LDS: VPT*256 doubles of row-sum patches (each row
-// owned by one thread: no atomics).
+// Usually a column's sub-tile is stored as -b in whole vectors, and the few
+// kept entries above lambda are then patched by the thread that owns the
+// row (its own earlier store to the same address comes first).  An
+// overflowed sub-tile above lambda is done vector by vector instead: theta
+// and c are read, w formed, and the patched vector stored in one go.  The
+// thresholds and sub-tile headers of 256 columns at a time are loaded into
+// LDS together (one column per thread), so no column waits on memory for
+// them.  Dynamic LDS: VPT*256 doubles of row-sum patches (each row owned by
+// one thread: no atomics).
 template <typename T, int VPT, int VEC>
 __global__ void __launch_bounds__(LNT)
 long_write_kernel(LongArgs<T> a) {
@@ -300,6 +303,8 @@ long_write_kernel(LongArgs<T> a) {
   if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;
   extern __shared__ double lds_dyn[];
   double* fix = lds_dyn;  // [VPT][256]
+  __shared__ double s_lam[LNT], s_max[4][LNT];
+  __shared__ int s_cnt[4][LNT];
   const int tid = threadIdx.x;
   const int wv = uniform_i(tid >> 6);
   const int R = a.R, cap = a.cap, nsub = a.nrb * 4;
@@ -320,75 +325,71 @@ long_write_kernel(LongArgs<T> a) {
     const double* __restrict__ pv = gptr(a.p);
     const int rbase = rb * RB;
     const int sub = rb * 4 + wv;
-    int row[VPT];
-    double b[VPT];
+    auto row = [&](int k) { return rbase + ((k / VEC) * LNT + tid) * VEC + (k % VEC); };
     T nb[VPT];  // -b rounded to the storage type: every inactive entry's new value
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
-      row[k] = rbase + ((k / VEC) * LNT + tid) * VEC + (k % VEC);
-      b[k] = row[k] < R ? long_b(t, pv, pmm, row[k], Sm) : 0.0;
-      nb[k] = (T)(-b[k]);
+      nb[k] = (T)(-(row(k) < R ? long_b(t, pv, pmm, row(k), Sm) : 0.0));
       fix[k * LNT + tid] = 0.0;  // each thread touches only its own slots
     }
-    // header of the next column, read ahead
-    double nlam = 0.0, nmax = 0.0;
-    int ncnt = 0;
-    auto ahead = [&](int64_t j) {
-      nlam = lamv[j];
-      nmax = hm[j * nsub + sub];
-      ncnt = hc[j * nsub + sub];
-    };
-    if (j0 < j1) ahead(j0);
-    for (int64_t j = j0; j < j1; ++j) {
-      const double lam = uniform_d(nlam), lmax = uniform_d(nmax);
-      const int n = uniform_i(ncnt);
-      if (j + 1 < j1) ahead(j + 1);
+    for (int64_t jb = j0; jb < j1; jb += LNT) {
+      // thresholds and this tile's four sub-tile headers of 256 columns
+      __syncthreads();  // the previous block's readers are done
+      if (jb + tid < j1) {
+        const int64_t jj = jb + tid;
+        s_lam[tid] = lamv[jj];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          s_max[q][tid] = hm[jj * nsub + rb * 4 + q];
+          s_cnt[q][tid] = hc[jj * nsub + rb * 4 + q];
+        }
+      }
+      __syncthreads();
+      const int64_t je = jb + LNT < j1 ? jb + LNT : j1;
+    for (int64_t j = jb; j < je; ++j) {
+      const double lam = uniform_d(s_lam[j - jb]), lmax = uniform_d(s_max[wv][j - jb]);
+      const int n = uniform_i(s_cnt[wv][j - jb]);
       T* __restrict__ thp = theta + j * a.ld;
-      double w[VPT];
-      int act = 0;  // bit k: slot k is active
+      const bool some = lmax > lam;  // some entry of this sub-tile is active
+      if (some && n > cap) {
+        // more candidates than slots: vector by vector, w from theta and c
+        const T* __restrict__ cp = long_cost_col(a, j, off_m);
 #pragma unroll
-      for (int k = 0; k < VPT; ++k) w[k] = -__builtin_huge_val();
-      if (lmax > lam) {  // some entry of this sub-tile is active
-        if (n <= cap) {
-          // the kept entries; the owner of each active row takes it
-          const int64_t h = j * nsub + sub;
-          for (int e = 0; e < n; ++e) {
-            const double x = uniform_d(cw[h * cap + e]);
-            if (!(x > lam)) continue;
-            const int rr = uniform_i(crow[h * cap + e]) - rbase;
-            if ((rr / VEC) % LNT == tid) {
-              const int ks = (rr / (VEC * LNT)) * VEC + rr % VEC;
+        for (int c = 0; c < NCH; ++c) {
+          const int r0 = row(c * VEC);
+          const int rl = r0 < R ? r0 : rbase;  // rows past R read the tile's first (masked)
+          T tv[VEC], cv[VEC], out[VEC];
+          load_vec<T, VEC>(thp + rl, tv);
+          load_vec<T, VEC>(cp + rl, cv);
 #pragma unroll
-              for (int k = 0; k < VPT; ++k)
-                if (k == ks) w[k] = x;
-              act |= 1 << ks;
+          for (int v = 0; v < VEC; ++v) {
+            const int k = c * VEC + v;
+            out[v] = nb[k];
+            if (r0 + v < R) {
+              const double bk = long_b(t, pv, pmm, r0 + v, Sm);
+              const double w = ((double)tv[v] + 2.0 * bk) - (double)cv[v] * inv_rho;
+              if (w > lam) {
+                out[v] = (T)(fmax(w - lam, 0.0) - bk);
+                fix[k * LNT + tid] += (double)out[v] - (double)nb[k];
+              }
             }
           }
-        } else {
-          // more candidates than slots: w from theta and c, read before theta is overwritten
-          const T* __restrict__ cp = long_cost_col(a, j, off_m);
+          if (r0 + VEC <= R) {
+            store_vec_nt<T, VEC>(thp + r0, out);
+          } else {
 #pragma unroll
-          for (int k = 0; k < VPT; ++k) {
-            if (row[k] < R) {
-              w[k] = ((double)thp[row[k]] + 2.0 * b[k]) - (double)cp[row[k]] * inv_rho;
-              act |= (int)(w[k] > lam) << k;
-            }
+            for (int v = 0; v < VEC; ++v)
+              if (r0 + v < R) thp[r0 + v] = out[v];
           }
         }
+        continue;
       }
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
-        const int r0 = row[c * VEC];
+        const int r0 = row(c * VEC);
         T out[VEC];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const int k = c * VEC + v;
-          out[v] = nb[k];
-          if ((act >> k) & 1) {
-            out[v] = (T)(fmax(w[k] - lam, 0.0) - b[k]);
-            fix[k * LNT + tid] += (double)out[v] - (double)nb[k];
-          }
-        }
+        for (int v = 0; v < VEC; ++v) out[v] = nb[c * VEC + v];
         if (r0 + VEC <= R) {
           store_vec_nt<T, VEC>(thp + r0, out);
         } else {
@@ -397,13 +398,31 @@ long_write_kernel(LongArgs<T> a) {
             if (r0 + v < R) thp[r0 + v] = out[v];
         }
       }
+      if (some) {
+        // the kept entries above lambda; the owner of each row patches it
+        const int64_t h = j * nsub + sub;
+        for (int e = 0; e < n; ++e) {
+          const double x = uniform_d(cw[h * cap + e]);
+          if (!(x > lam)) continue;
+          const int r = uniform_i(crow[h * cap + e]);
+          const int rr = r - rbase;
+          if ((rr / VEC) % LNT == tid) {
+            const double bk = long_b(t, pv, pmm, r, Sm);
+            const T val = (T)(fmax(x - lam, 0.0) - bk);
+            thp[r] = val;
+            const int k = (rr / (VEC * LNT)) * VEC + rr % VEC;
+            fix[k * LNT + tid] += (double)val - (double)(T)(-bk);
+          }
+        }
+      }
+    }
     }
     // the item's row sums: (#columns) * (-b) plus the patches
     const double ncols = (double)(j1 - j0);
     double* __restrict__ part = gptr(a.partial) + uniform_l(a.it_poff[it]);
 #pragma unroll
     for (int k = 0; k < VPT; ++k)
-      if (row[k] < R) part[row[k] - rbase] = ncols * (double)nb[k] + fix[k * LNT + tid];
+      if (row(k) < R) part[row(k) - rbase] = ncols * (double)nb[k] + fix[k * LNT + tid];
   }
 }
 

@@ -193,7 +193,7 @@ def test_long_column_path_selection():
     rc, h = create(R=10000, S=[30, 20])
     assert rc == 0
     assert L.mam_get_schedule(h, ctypes.byref(sc)) == 0
-    assert sc.rows_per_tile == 2048 and sc.candidate_slots == 32   # double
+    assert sc.rows_per_tile == 2048 and sc.candidate_slots == 64   # double
     assert L.mam_workspace_bytes(h) > 0
     assert L.mam_adjoint_workspace_bytes(h, 10, 0) == 0                    # no reverse mode
     B2 = ctypes.c_int32 * 2

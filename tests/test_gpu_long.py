@@ -147,3 +147,13 @@ def test_unsupported_on_long_columns():
         s.record(3)
     with pytest.raises(mam.MAMError):
         s.set_bundles([0, 1])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_measure_sets_schedule_matches_oracle(dtype):
+    # one shared cost and equal S^m: the M workgroups of a set take the same
+    # (tile, column) units, one measure each, on one XCD
+    p = inputs.tiny_problem(20, R=3000, S=[400, 400, 400], dtype=dtype, shared=True, rho=2.0)
+    s, _ = check(p, 12, rows_per_tile=1024)
+    nwg = s.schedule()["workgroups"]
+    assert nwg % (8 * p.M) == 0, nwg

@@ -220,28 +220,32 @@ def extra_workloads(torch, mam, inputs, log):
     # R = 349,281 support points, T = 36,000 columns, FP32 plans (50 GB):
     # the long-column path (row tiles, candidate slots, per-column thresholds)
     pf = inputs.free_support(dtype="f32")
-    s = mam.solver_for(pf)
-    sc = s.schedule()
-    s.init()
-    s.iterate(3)
-    n_it = 20
-    dt = timed(lambda: s.iterate(n_it)) / n_it
-    s.timing(True)
-    s.iterate(5)
-    col, n = s.timing_read()
-    ws = s.workspace.numel()
-    s.close()
-    del s
-    torch.cuda.empty_cache()
-    abf = algorithmic_bytes(pf)
-    out["free_support_K60_M10_f32"] = {
-        "R": pf.R, "M": pf.M, "T": pf.T, "iterations": n_it, "ms_per_iter": dt * 1e3,
-        "plan_entry_updates_per_s": pf.R * pf.T / dt, "column_kernels_ms": col / n,
-        "algorithmic_bytes_per_iter": abf, "column_kernels_GBs": abf / (col / n * 1e-3) / 1e9,
-        "plans_GB": pf.T * pf.R * 4 / 1e9, "workspace_GB": ws / 1e9,
-        "rows_per_tile": sc["rows_per_tile"], "candidate_slots": sc["candidate_slots"]}
-    log(f"free support R={pf.R} T={pf.T}: {dt * 1e3:.2f} ms/iter, {pf.R * pf.T / dt:.3e} entries/s, "
-        f"column kernels {col / n:.2f} ms ({abf / (col / n * 1e-3) / 1e9:.0f} GB/s algorithmic)")
+    res = {"R": pf.R, "M": pf.M, "T": pf.T, "plans_GB": pf.T * pf.R * 4 / 1e9}
+    for mode, grid in (("stored_cost", False), ("grid_cost", True)):
+        s = mam.solver_for(pf, grid=grid)
+        sc = s.schedule()
+        s.init()
+        s.iterate(3)
+        n_it = 20
+        dt = timed(lambda: s.iterate(n_it)) / n_it
+        s.timing(True)
+        s.iterate(5)
+        col, n = s.timing_read()
+        ws = s.workspace.numel()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        # algorithmic bytes: theta read and written, the distinct cost read
+        # once (none when the kernels form it from the grid), q
+        abf = 4 * (2 * pf.R * pf.T + (0 if grid else pf.R * pf.distinct_cost_columns()) + pf.T)
+        res[mode] = {"iterations": n_it, "ms_per_iter": dt * 1e3, "plan_entry_updates_per_s": pf.R * pf.T / dt,
+                     "column_kernels_ms": col / n, "algorithmic_bytes_per_iter": abf,
+                     "column_kernels_GBs": abf / (col / n * 1e-3) / 1e9, "workspace_GB": ws / 1e9,
+                     "rows_per_tile": sc["rows_per_tile"], "candidate_slots": sc["candidate_slots"],
+                     "workgroups": sc["workgroups"]}
+        log(f"free support R={pf.R} T={pf.T} ({mode}): {dt * 1e3:.2f} ms/iter, {pf.R * pf.T / dt:.3e} entries/s, "
+            f"column kernels {col / n:.2f} ms ({abf / (col / n * 1e-3) / 1e9:.0f} GB/s algorithmic)")
+    out["free_support_K60_M10_f32"] = res
 
     # reverse mode: 64x64 grid, 8 measures, 100 iterations, FP32, loss ||p_bar - target||^2
     p5, tgt = inputs.adjoint_problem()

@@ -69,6 +69,12 @@ typedef int32_t mam_status;
 #define MAM_COST_SHARED     1  /* one R x S cost for every measure: column s of
                                   measure m uses cost column s (all S^m <= cost_ncols) */
 #define MAM_COST_INDEXED    2  /* plan column j uses cost column cost_col_index[j] */
+#define MAM_COST_GRID       3  /* the cost of (HugeLP) formed in the kernels from
+                                  points: the barycenter support is a regular grid
+                                  (mam_set_grid), column s of every measure is the
+                                  point cost[s*dim ..] (cost_ncols points of dim
+                                  doubles), c_rs = sum_k (x_rk - z_sk)^2 rounded to
+                                  the dtype.  Single problems, long-column path. */
 
 /* mam_desc.flags */
 #define MAM_FLAG_DIAG 1u       /* compute diagnostics on the last iteration of
@@ -206,6 +212,16 @@ mam_status mam_init(mam_problem* p, const void* theta0, void* stream);
 /* Run 'iters' >= 0 deterministic MAM iterations (M^k = all measures,
  * Alg. 1).  Asynchronous.  Errors: MAM_ESTATE before mam_init. */
 mam_status mam_iterate(mam_problem* p, int64_t iters, void* stream);
+
+/* Grid of a MAM_COST_GRID problem (Theorem c: with measures on one grid and
+ * alpha_m = 1/M the support Xi of a barycenter is itself a regular grid).
+ * Row r is the grid point of index (i_0, ..., i_{dim-1}), last axis fastest
+ * (r = i_0 * n[1] + i_1 for dim 2), with coordinates
+ * x_rk = origin[k] + i_k * spacing[k] (one product and one sum, each
+ * rounded).  Host arrays of dim values, dim 1 or 2; the point count must be
+ * R.  Must precede mam_init.  Errors: MAM_EINVAL (mode, sizes, non-finite
+ * values). */
+mam_status mam_set_grid(mam_problem* p, int32_t dim, const int64_t* n, const double* origin, const double* spacing);
 
 /* ---- stopping tests ----------------------------------------------------------
  * Alg. 1 with "while not converged" made concrete by one of the stopping

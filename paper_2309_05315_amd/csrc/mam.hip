@@ -93,6 +93,10 @@ struct Prob {
   const void* q = nullptr;
   bool aligned = true;
   std::vector<int32_t> idx;  // host copy of an indexed cost's column index
+  // grid cost: dimension (0 = not set), points per axis, origin, spacing
+  int gdim = 0;
+  int64_t gn[2] = {1, 1};
+  double go[2] = {0.0, 0.0}, gh[2] = {0.0, 0.0};
   // workspace offsets of the problem's own region
   size_t o_pm = 0, o_pm_prev = 0, o_p = 0, o_p_prev = 0, o_d2 = 0, o_t = 0, o_lam = 0, o_check = 0;
   size_t o_coloff = 0, o_Sd = 0, o_aw = 0;
@@ -245,7 +249,7 @@ U* at(Plan* pl, size_t off) { return reinterpret_cast<U*>(pl->ws + off); }
 mam_status read_desc(const mam_desc* d, int index, Prob* out) {
   if (!d) return fail(MAM_EINVAL, "desc %d is NULL", index);
   if (d->dtype != MAM_F32 && d->dtype != MAM_F64) return fail(MAM_EINVAL, "unknown dtype %d", d->dtype);
-  if (d->cost_mode < MAM_COST_PER_COLUMN || d->cost_mode > MAM_COST_INDEXED)
+  if (d->cost_mode < MAM_COST_PER_COLUMN || d->cost_mode > MAM_COST_GRID)
     return fail(MAM_EINVAL, "unknown cost_mode %d", d->cost_mode);
   if (d->R < 1) return fail(MAM_EINVAL, "R must be >= 1 (got %lld)", (long long)d->R);
   if (d->M < 1) return fail(MAM_EINVAL, "M must be >= 1 (got %lld)", (long long)d->M);
@@ -255,7 +259,8 @@ mam_status read_desc(const mam_desc* d, int index, Prob* out) {
   if (d->R > kLongMaxR) return fail(MAM_EUNSUPPORTED, "R = %lld exceeds %lld", (long long)d->R, (long long)kLongMaxR);
   if (d->M > 65535) return fail(MAM_EUNSUPPORTED, "M = %lld exceeds 65535", (long long)d->M);
   const int64_t ld = d->ld ? d->ld : d->R;
-  const int64_t cld = d->cost_ld ? d->cost_ld : d->R;
+  // a grid cost is formed in the kernels: its buffer holds points, no stride
+  const int64_t cld = (d->cost_ld && d->cost_mode != MAM_COST_GRID) ? d->cost_ld : d->R;
   if (ld < d->R) return fail(MAM_EINVAL, "ld (%lld) < R (%lld)", (long long)ld, (long long)d->R);
   if (cld < d->R) return fail(MAM_EINVAL, "cost_ld (%lld) < R (%lld)", (long long)cld, (long long)d->R);
   int64_t T = 0, smax = 0;
@@ -265,7 +270,7 @@ mam_status read_desc(const mam_desc* d, int index, Prob* out) {
     smax = std::max(smax, d->S[m]);
   }
   if (d->cost_ncols < 1) return fail(MAM_EINVAL, "cost_ncols must be >= 1");
-  if (d->cost_mode == MAM_COST_SHARED && smax > d->cost_ncols)
+  if ((d->cost_mode == MAM_COST_SHARED || d->cost_mode == MAM_COST_GRID) && smax > d->cost_ncols)
     return fail(MAM_EINVAL, "shared cost has %lld columns but a measure has %lld", (long long)d->cost_ncols,
                 (long long)smax);
   if (d->cost_mode == MAM_COST_PER_COLUMN && d->cost_ncols < T)
@@ -700,7 +705,10 @@ mam_status make_plan(Plan* pl, const mam_desc* descs, int n) {
     if (pl->P[i].R > kShortMaxR && pl->batch)
       return fail(MAM_EUNSUPPORTED, "problem %d: R = %lld exceeds %lld in a batch", i, (long long)pl->P[i].R,
                   (long long)kShortMaxR);
-  if (pl->P[0].R > kShortMaxR) {
+  for (int i = 0; i < n; ++i)
+    if (pl->P[i].cost_mode == MAM_COST_GRID && pl->batch)
+      return fail(MAM_EUNSUPPORTED, "problem %d: a grid cost is for single problems", i);
+  if (pl->P[0].R > kShortMaxR || pl->P[0].cost_mode == MAM_COST_GRID) {
     pl->lg.on = true;
     build_schedule(pl);
     build_layout(pl);
@@ -733,7 +741,7 @@ mam_status set_group_schedule(Plan* pl, int gi, const mam_schedule* s) {
   if (s->candidate_slots < 0 || s->candidate_slots > 64)
     return fail(MAM_EINVAL, "candidate_slots must be in [0, 64] (got %d)", s->candidate_slots);
   if (s->rows_per_tile && pl->batch) return fail(MAM_EINVAL, "long-column tiles are for single problems");
-  if (!pl->batch && (s->rows_per_tile > 0 || pl->P[0].R > kShortMaxR)) {
+  if (!pl->batch && (s->rows_per_tile > 0 || pl->P[0].R > kShortMaxR || pl->P[0].cost_mode == MAM_COST_GRID)) {
     if (s->workgroups < 0) return fail(MAM_EINVAL, "workgroups must be >= 0");
     pl->lg.on = true;
     pl->lg.rows_req = s->rows_per_tile;
@@ -820,7 +828,8 @@ mam_status bind(Plan* pl, int i, void* theta, const void* cost, const int32_t* c
   if (p.cost_mode != MAM_COST_INDEXED && cidx)
     return fail(MAM_EINVAL, "cost_col_index given but cost_mode is not MAM_COST_INDEXED");
   const size_t eb = elem_bytes(pl->dtype);
-  if (reinterpret_cast<uintptr_t>(theta) % eb || reinterpret_cast<uintptr_t>(cost) % eb ||
+  const bool grid = p.cost_mode == MAM_COST_GRID;  // cost = the measures' points, doubles
+  if (reinterpret_cast<uintptr_t>(theta) % eb || reinterpret_cast<uintptr_t>(cost) % (grid ? 8 : eb) ||
       reinterpret_cast<uintptr_t>(q) % eb)
     return fail(MAM_EINVAL, "buffers must be aligned to their element size");
   p.theta = theta;
@@ -828,8 +837,8 @@ mam_status bind(Plan* pl, int i, void* theta, const void* cost, const int32_t* c
   p.cidx = cidx;
   p.q = q;
   const int vn = vec_width(pl->dtype);
-  p.aligned = reinterpret_cast<uintptr_t>(theta) % 16 == 0 && reinterpret_cast<uintptr_t>(cost) % 16 == 0 &&
-              p.ld % vn == 0 && p.cost_ld % vn == 0;
+  p.aligned = reinterpret_cast<uintptr_t>(theta) % 16 == 0 && p.ld % vn == 0 &&
+              (grid || (reinterpret_cast<uintptr_t>(cost) % 16 == 0 && p.cost_ld % vn == 0));
   if (pl->lg.on) {
     pl->lg.vec = p.aligned ? vn : 1;
   } else {
@@ -1037,6 +1046,13 @@ mam::LongArgs<T> long_args(Plan* pl) {
   a.partial = at<double>(pl, pl->lay.partial);
   a.stop = pl->gate;
   a.T_cols = p.T;
+  a.gdim = p.cost_mode == MAM_COST_GRID ? p.gdim : 0;
+  a.gn1 = (int32_t)(p.gdim == 2 ? p.gn[1] : 1);
+  for (int k = 0; k < 2; ++k) {
+    a.go[k] = p.go[k];
+    a.gh[k] = p.gh[k];
+  }
+  a.gz = a.gdim ? static_cast<const double*>(p.cost) : nullptr;
   return a;
 }
 
@@ -1045,7 +1061,7 @@ template <typename T>
 mam_status launch_long_columns(Plan* pl, hipStream_t st) {
   const Prob& p = pl->P[0];
   const LongPlan& lg = pl->lg;
-  mam::LongFns<T> fn = mam::pick_long<T>(lg.vpt, lg.vec);
+  mam::LongFns<T> fn = mam::pick_long<T>(lg.vpt, lg.vec, pl->P[0].cost_mode == MAM_COST_GRID);
   if (!fn.scan) return fail(MAM_EUNSUPPORTED, "no long-column kernels for vpt=%d vec=%d", lg.vpt, lg.vec);
   mam::LongArgs<T> a = long_args<T>(pl);
   hipLaunchKernelGGL(mam::damping_kernel, dim3(1), dim3(256), 0, st, a.d2part, p.nb, p.rho, p.gamma, a.t, a.stop);
@@ -1062,7 +1078,7 @@ mam_status launch_long_columns(Plan* pl, hipStream_t st) {
 template <typename T>
 mam_status launch_long_rowsum(Plan* pl, hipStream_t st) {
   const LongPlan& lg = pl->lg;
-  mam::LongFns<T> fn = mam::pick_long<T>(lg.vpt, lg.vec);
+  mam::LongFns<T> fn = mam::pick_long<T>(lg.vpt, lg.vec, pl->P[0].cost_mode == MAM_COST_GRID);
   if (!fn.rowsum) return fail(MAM_EUNSUPPORTED, "no long-column kernels for vpt=%d vec=%d", lg.vpt, lg.vec);
   hipLaunchKernelGGL(fn.rowsum, dim3(lg.nwg), dim3(256), 0, st, long_args<T>(pl), lg.rows);
   LAUNCH_CHECK("long_rowsum_kernel");
@@ -1072,7 +1088,7 @@ mam_status launch_long_rowsum(Plan* pl, hipStream_t st) {
 // Workgroups of the scan kernel the device holds at once.
 template <typename T>
 mam_status long_resident(Plan* pl, bool* changed) {
-  mam::LongFns<T> fn = mam::pick_long<T>(pl->lg.vpt, pl->lg.vec);
+  mam::LongFns<T> fn = mam::pick_long<T>(pl->lg.vpt, pl->lg.vec, pl->P[0].cost_mode == MAM_COST_GRID);
   if (!fn.scan) return MAM_OK;
   int dev = 0, cus = 0, blocks = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -1141,9 +1157,16 @@ mam_status launch_checks(Plan* pl, hipStream_t st) {
     hipLaunchKernelGGL(mam::check_q_kernel<T>, dim3((unsigned)p.M), dim3(256), 0, st, static_cast<const T*>(p.q),
                        at<int64_t>(pl, p.o_coloff), chk, (int)p.M);
     LAUNCH_CHECK("check_q_kernel");
-    const int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (p.cost_ncols * p.R + 255) / 256));
-    hipLaunchKernelGGL(mam::check_cost_kernel<T>, dim3(blocks), dim3(256), 0, st, static_cast<const T*>(p.cost),
-                       p.cost_ld, (int)p.R, p.cost_ncols, chk + p.M + 1);
+    if (p.cost_mode == MAM_COST_GRID) {
+      // the measures' points: cost_ncols rows of gdim doubles
+      const int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (p.cost_ncols * p.gdim + 255) / 256));
+      hipLaunchKernelGGL(mam::check_cost_kernel<double>, dim3(blocks), dim3(256), 0, st,
+                         static_cast<const double*>(p.cost), (int64_t)p.gdim, p.gdim, p.cost_ncols, chk + p.M + 1);
+    } else {
+      const int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (p.cost_ncols * p.R + 255) / 256));
+      hipLaunchKernelGGL(mam::check_cost_kernel<T>, dim3(blocks), dim3(256), 0, st, static_cast<const T*>(p.cost),
+                         p.cost_ld, (int)p.R, p.cost_ncols, chk + p.M + 1);
+    }
     LAUNCH_CHECK("check_cost_kernel");
   }
   return MAM_OK;
@@ -1190,6 +1213,9 @@ mam_status resident_workgroups(Plan* pl, bool* changed) {
 
 mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
   if (!pl->ws) return fail(MAM_ESTATE, "no workspace");
+  for (size_t i = 0; i < pl->P.size(); ++i)
+    if (pl->P[i].cost_mode == MAM_COST_GRID && pl->P[i].gdim == 0)
+      return fail(MAM_ESTATE, "problem %zu: MAM_COST_GRID needs mam_set_grid", i);
   for (size_t i = 0; i < pl->P.size(); ++i)
     if (!pl->P[i].theta) return fail(MAM_ESTATE, "problem %zu has no buffers bound", i);
   // an indexed cost's column order depends on its index: read it once here
@@ -2094,6 +2120,30 @@ mam_status mam_init(mam_problem* p, const void* theta0, void* stream) {
 mam_status mam_iterate(mam_problem* p, int64_t iters, void* stream) {
   if (!p) return fail(MAM_EINVAL, "NULL handle");
   return plan_iterate(&p->plan, iters, static_cast<hipStream_t>(stream));
+}
+
+mam_status mam_set_grid(mam_problem* p, int32_t dim, const int64_t* n, const double* origin, const double* spacing) {
+  if (!p || !n || !origin || !spacing) return fail(MAM_EINVAL, "NULL argument");
+  Prob& pr = p->plan.P[0];
+  if (pr.cost_mode != MAM_COST_GRID) return fail(MAM_EINVAL, "cost_mode is not MAM_COST_GRID");
+  if (dim != 1 && dim != 2) return fail(MAM_EINVAL, "dim must be 1 or 2 (got %d)", dim);
+  int64_t npts = 1;
+  for (int k = 0; k < dim; ++k) {
+    if (n[k] < 1) return fail(MAM_EINVAL, "n[%d] must be >= 1", k);
+    if (!std::isfinite(origin[k]) || !std::isfinite(spacing[k]))
+      return fail(MAM_EINVAL, "origin and spacing must be finite");
+    npts *= n[k];
+  }
+  if (npts != pr.R) return fail(MAM_EINVAL, "the grid has %lld points but R = %lld", (long long)npts, (long long)pr.R);
+  pr.gdim = dim;
+  for (int k = 0; k < 2; ++k) {
+    pr.gn[k] = k < dim ? n[k] : 1;
+    pr.go[k] = k < dim ? origin[k] : 0.0;
+    pr.gh[k] = k < dim ? spacing[k] : 0.0;
+  }
+  p->plan.inited = false;
+  drop_graphs(&p->plan);
+  return MAM_OK;
 }
 
 mam_status mam_iterate_until(mam_problem* p, int64_t max_iters, int32_t test, double tol, int64_t check_every,

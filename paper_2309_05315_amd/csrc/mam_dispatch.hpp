@@ -31,8 +31,8 @@ inline ColFn<T> pick_column(int nt, int vpt, int vec, int kc, int diag, int stre
   }
 }
 
-// Long-column tile kernels for (values per thread, vector width); null
-// members if no instance exists.
+// Long-column tile kernels for (values per thread, vector width, grid
+// cost); null members if no instance exists.
 template <typename T> struct LongArgs;
 template <typename T>
 struct LongFns {
@@ -42,9 +42,9 @@ struct LongFns {
   void (*rowsum)(LongArgs<T>, int) = nullptr;
 };
 template <typename T>
-LongFns<T> pick_long(int vpt, int vec);
-extern template LongFns<float> pick_long<float>(int, int);
-extern template LongFns<double> pick_long<double>(int, int);
+LongFns<T> pick_long(int vpt, int vec, bool grid);
+extern template LongFns<float> pick_long<float>(int, int, bool);
+extern template LongFns<double> pick_long<double>(int, int, bool);
 
 // Reverse-mode column kernel for (threads per column, values per thread).
 struct AdjArgs;

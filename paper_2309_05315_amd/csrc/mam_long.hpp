@@ -72,7 +72,36 @@ struct LongArgs {
   double* partial;
   const int32_t* stop;           // early-exit flag, or null
   int64_t T_cols;
+  // grid cost (cost_mode MAM_COST_GRID): row r is point (i0, i1) of an
+  // n0 x n1 grid (last axis fastest; gdim 1: just i0 = r) with coordinates
+  // go[k] + i_k * gh[k], and cost column s is the point gz[s*gdim ..]:
+  // c_rs = sum_k (x_rk - z_sk)^2, rounded to the storage type
+  int32_t gdim, gn1;
+  double go[2], gh[2];
+  const double* gz;
 };
+
+// The grid cost of row index pair (i0, i1) and point z, evaluated in the
+// order of its definition (each product and sum rounded, no contraction),
+// then rounded to the storage type as a stored cost would be.
+template <typename T>
+__device__ __forceinline__ double grid_cost_at(const LongArgs<T>& a, int i0, int i1, const double* z) {
+  const double x0 = __dadd_rn(a.go[0], __dmul_rn((double)i0, a.gh[0]));
+  const double d0 = __dsub_rn(x0, z[0]);
+  double c = __dmul_rn(d0, d0);
+  if (a.gdim == 2) {
+    const double x1 = __dadd_rn(a.go[1], __dmul_rn((double)i1, a.gh[1]));
+    const double d1 = __dsub_rn(x1, z[1]);
+    c = __dadd_rn(c, __dmul_rn(d1, d1));
+  }
+  return (double)(T)c;
+}
+
+template <typename T>
+__device__ __forceinline__ double grid_cost(const LongArgs<T>& a, int r, const double* z) {
+  const int i0 = a.gdim == 2 ? r / a.gn1 : r;
+  return grid_cost_at(a, i0, r - i0 * a.gn1, z);
+}
 
 template <typename T>
 __device__ __forceinline__ const T* long_cost_col(const LongArgs<T>& a, int64_t j, int64_t off_m) {
@@ -90,7 +119,9 @@ __device__ __forceinline__ double long_b(double t, const double* p, const double
 }
 
 // ---- scan: w, sub-tile maxima, candidates -------------------------------
-template <typename T, int VPT, int VEC>
+// GRID: the cost is formed from the row's grid point and the column's point
+// instead of being read (only theta is streamed).
+template <typename T, int VPT, int VEC, bool GRID>
 __global__ void __launch_bounds__(LNT)
 long_scan_kernel(LongArgs<T> a) {
   constexpr int NCH = VPT / VEC, RB = LNT * VPT;
@@ -115,27 +146,40 @@ long_scan_kernel(LongArgs<T> a) {
     const int rbase = rb * RB;
     int row[VPT];
     double b[VPT];
+    int gi0[GRID ? VPT : 1], gi1[GRID ? VPT : 1];  // grid indices of the rows
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       row[k] = rbase + ((k / VEC) * LNT + tid) * VEC + (k % VEC);
       b[k] = row[k] < R ? long_b(t, pv, pmm, row[k], Sm) : 0.0;
+      if constexpr (GRID) {
+        gi0[k] = a.gdim == 2 ? row[k] / a.gn1 : row[k];
+        gi1[k] = row[k] - gi0[k] * a.gn1;
+      }
     }
-    // raw theta and c of the next column in flight while this one is scanned
-    T rt[VPT], rc[VPT], rq;
+    // raw theta and c (or the column's point) of the next column in flight
+    // while this one is scanned
+    T rt[VPT], rc[GRID ? 1 : VPT], rq;
+    double rz[2];
     auto issue = [&](int64_t j) {
       const T* __restrict__ thp = theta + j * a.ld;
-      const T* __restrict__ cp = long_cost_col(a, j, off_m);
       rq = qv[j];
+      if constexpr (GRID) {
+        const double* z = gptr(a.gz) + (j - off_m) * a.gdim;
+        rz[0] = z[0];
+        rz[1] = a.gdim == 2 ? z[1] : 0.0;
+      }
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
         const int r0 = row[c * VEC] < R ? row[c * VEC] : rbase;  // rows past R read the tile's first (masked)
-        T tv[VEC], cv[VEC];
+        T tv[VEC];
         load_vec_nt<T, VEC>(thp + r0, tv);
-        load_vec<T, VEC>(cp + r0, cv);
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          rt[c * VEC + v] = tv[v];
-          rc[c * VEC + v] = cv[v];
+        for (int v = 0; v < VEC; ++v) rt[c * VEC + v] = tv[v];
+        if constexpr (!GRID) {
+          T cv[VEC];
+          load_vec<T, VEC>(long_cost_col(a, j, off_m) + r0, cv);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) rc[c * VEC + v] = cv[v];
         }
       }
     };
@@ -143,9 +187,13 @@ long_scan_kernel(LongArgs<T> a) {
     for (int64_t j = j0; j < j1; ++j) {
       double w[VPT];
       double mx = -__builtin_huge_val();
+      double z[2] = {uniform_d(rz[0]), uniform_d(rz[1])};
 #pragma unroll
       for (int k = 0; k < VPT; ++k) {
-        const double x = ((double)rt[k] + 2.0 * b[k]) - (double)rc[k] * inv_rho;
+        double c;
+        if constexpr (GRID) c = grid_cost_at(a, gi0[k], gi1[k], z);
+        else c = (double)rc[k];
+        const double x = ((double)rt[k] + 2.0 * b[k]) - c * inv_rho;
         w[k] = row[k] < R ? x : -__builtin_huge_val();
         mx = fmax(mx, w[k]);
       }
@@ -221,6 +269,8 @@ long_threshold_kernel(LongArgs<T> a) {
   const double* __restrict__ pv = gptr(a.p);
   const T* __restrict__ thp = gptr(a.theta) + j * a.ld;
   const T* __restrict__ cp = long_cost_col(a, j, off_m);
+  const double* zj = a.gdim ? gptr(a.gz) + (j - off_m) * a.gdim : nullptr;
+  auto costv = [&](int r) { return a.gdim ? grid_cost(a, r, zj) : (double)cp[r]; };
   auto visit = [&](auto&& f) {
     for (int s0 = 0; s0 < nsub; s0 += 64) {
       const int s = s0 + lane;
@@ -236,7 +286,7 @@ long_threshold_kernel(LongArgs<T> a) {
 #pragma unroll
           for (int k = 0; k < VPT; ++k) {
             const int r = rbase + ((k / VEC) * LNT + tt) * VEC + (k % VEC);
-            if (r < R) f(((double)thp[r] + 2.0 * long_b(t, pv, pmm, r, Sm)) - (double)cp[r] * a.inv_rho);
+            if (r < R) f(((double)thp[r] + 2.0 * long_b(t, pv, pmm, r, Sm)) - costv(r) * a.inv_rho);
           }
         }
       }
@@ -354,20 +404,21 @@ long_write_kernel(LongArgs<T> a) {
       if (some && n > cap) {
         // more candidates than slots: vector by vector, w from theta and c
         const T* __restrict__ cp = long_cost_col(a, j, off_m);
+        const double* zj = a.gdim ? gptr(a.gz) + (j - off_m) * a.gdim : nullptr;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
           const int r0 = row(c * VEC);
           const int rl = r0 < R ? r0 : rbase;  // rows past R read the tile's first (masked)
-          T tv[VEC], cv[VEC], out[VEC];
+          T tv[VEC], out[VEC];
           load_vec<T, VEC>(thp + rl, tv);
-          load_vec<T, VEC>(cp + rl, cv);
 #pragma unroll
           for (int v = 0; v < VEC; ++v) {
             const int k = c * VEC + v;
             out[v] = nb[k];
             if (r0 + v < R) {
               const double bk = long_b(t, pv, pmm, r0 + v, Sm);
-              const double w = ((double)tv[v] + 2.0 * bk) - (double)cv[v] * inv_rho;
+              const double cc = a.gdim ? grid_cost(a, r0 + v, zj) : (double)cp[r0 + v];
+              const double w = ((double)tv[v] + 2.0 * bk) - cc * inv_rho;
               if (w > lam) {
                 out[v] = (T)(fmax(w - lam, 0.0) - bk);
                 fix[k * LNT + tid] += (double)out[v] - (double)nb[k];

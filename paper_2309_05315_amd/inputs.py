@@ -41,6 +41,7 @@ __all__ = [
     "tiny_problem",
     "line_problem",
     "free_support_grid",
+    "free_support_axis",
     "nested_ellipses",
     "free_support",
 ]
@@ -341,12 +342,19 @@ def line_problem(seed: int, R: int, M: int, dtype: str = "f64", rho: float = 1.0
         iters=iters, dtype=dtype, meta={"seed": seed})
 
 
+def free_support_axis(K: int, M: int):
+    """(n, origin, spacing) of one axis of Xi: the averages (I + M/2)/(M K),
+    I = 0, ..., M(K-1), of M pixel centres (i + 1/2)/K."""
+    return M * (K - 1) + 1, (M / 2) / (M * K), 1.0 / (M * K)
+
+
 def free_support_grid(K: int, M: int, d: int = 2) -> np.ndarray:
     """The set Xi of Theorem c: every average (1/M) sum_m zeta_m of M pixel
-    centres ((i + 1/2)/K per axis) of a K^d grid.  Per axis these are
-    (I + M/2)/(M K), I = 0, ..., M(K-1): a uniform grid of ((K-1)M+1)^d points
-    (row-major, last axis fastest)."""
-    v = (np.arange(M * (K - 1) + 1) + M / 2) / (M * K)
+    centres ((i + 1/2)/K per axis) of a K^d grid, a uniform grid of
+    ((K-1)M+1)^d points (row-major, last axis fastest).  A coordinate is
+    evaluated as origin + I * spacing (one product, one sum, each rounded)."""
+    n, o, h = free_support_axis(K, M)
+    v = o + np.arange(n, dtype=np.float64) * h
     mesh = np.meshgrid(*([v] * d), indexing="ij")
     return np.stack([g.ravel() for g in mesh], axis=1)
 
@@ -385,10 +393,11 @@ def free_support(seed: int = 0, K: int = 60, M: int = 10, dtype: str = "f32", rh
     zeta = np.stack([X.ravel(), Y.ravel()], axis=1)
     q = np.concatenate([nested_ellipses(rng, K) for _ in range(M)])
     S = K * K
+    n, o, h = free_support_axis(K, M)
     return Problem(
         name=f"free_support_K{K}_M{M}", R=xi.shape[0], S=[S] * M, cost=None, q=_round(q, dtype),
         col_index=None, rho=rho, iters=iters, dtype=dtype,
-        meta={"K": K, "M": M, "seed": seed}, xi=xi, zeta=zeta)
+        meta={"K": K, "M": M, "seed": seed, "grid": ([n, n], [o, o], [h, h])}, xi=xi, zeta=zeta)
 
 
 def bundle_sequence(bundles, iters: int, seed: int = 0, alpha=None) -> np.ndarray:

@@ -19,11 +19,11 @@ import numpy as np
 import torch
 
 __all__ = ["lib", "MAMError", "Solver", "Batch", "solver_for", "cost_sq_euclid",
-           "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "FLAG_DIAG", "FLAG_COLD", "FLAG_RELAXED",
+           "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "COST_GRID", "FLAG_DIAG", "FLAG_COLD", "FLAG_RELAXED",
            "STOP_TESTS", "EXPORTED"]
 
 F32, F64 = 0, 1
-COST_PER_COLUMN, COST_SHARED, COST_INDEXED = 0, 1, 2
+COST_PER_COLUMN, COST_SHARED, COST_INDEXED, COST_GRID = 0, 1, 2, 3
 FLAG_DIAG, FLAG_COLD, FLAG_RELAXED = 1, 2, 4
 # stopping tests of Sec. 5 (MAM_STOP_*)
 STOP_TESTS = {"dtheta": 0, "dp": 1, "dist": 2}
@@ -43,7 +43,7 @@ EXPORTED = ["mam_abi_version", "mam_last_error", "mam_create", "mam_set_schedule
             "mam_batch_barycenter", "mam_batch_timing_enable", "mam_batch_timing_read",
             "mam_batch_destroy", "mam_adjoint_workspace_bytes", "mam_record", "mam_backward",
             "mam_bundle_workspace_bytes", "mam_set_bundles", "mam_iterate_bundles",
-            "mam_iterate_until"]
+            "mam_iterate_until", "mam_set_grid"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmam.so")
 
@@ -143,6 +143,7 @@ def lib() -> ctypes.CDLL:
         "mam_bundle_workspace_bytes": (ctypes.c_size_t, [_vp, _vp, ctypes.c_int32]),
         "mam_set_bundles": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
         "mam_iterate_bundles": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp]),
+        "mam_set_grid": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
         "mam_iterate_until": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                                ctypes.c_int64, ctypes.POINTER(StopResult), _vp]),
     }
@@ -221,12 +222,17 @@ class Solver:
     # -- buffers -----------------------------------------------------------
     def bind(self, theta: torch.Tensor, cost: torch.Tensor, q: torch.Tensor,
              index: Optional[torch.Tensor] = None) -> None:
+        grid = self.cost_mode == COST_GRID
         for name, t in (("theta", theta), ("cost", cost), ("q", q)):
-            if t.dtype != self.dtype or t.device.type != "cuda" or not t.is_contiguous():
-                raise ValueError(f"{name} must be a contiguous {self.dtype} CUDA tensor")
+            want = torch.float64 if (grid and name == "cost") else self.dtype
+            if t.dtype != want or t.device.type != "cuda" or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {want} CUDA tensor")
         if theta.shape != (self.T, self.ld):
             raise ValueError(f"theta must have shape {(self.T, self.ld)}")
-        if cost.shape != (self.cost_ncols, self.cost_ld):
+        if grid:
+            if cost.dim() != 2 or cost.shape[0] != self.cost_ncols or cost.shape[1] not in (1, 2):
+                raise ValueError(f"grid cost: the measures' points, shape ({self.cost_ncols}, dim)")
+        elif cost.shape != (self.cost_ncols, self.cost_ld):
             raise ValueError(f"cost must have shape {(self.cost_ncols, self.cost_ld)}")
         if q.shape != (self.T,):
             raise ValueError(f"q must have shape {(self.T,)}")
@@ -239,6 +245,14 @@ class Solver:
         sc = Schedule()
         _check(lib().mam_get_schedule(self._h, ctypes.byref(sc)), "mam_get_schedule")
         return {k: getattr(sc, k) for k, _ in Schedule._fields_}
+
+    def set_grid(self, n: Sequence[int], origin: Sequence[float], spacing: Sequence[float]) -> None:
+        """Barycenter support of a COST_GRID problem: a regular grid with n[k]
+        points per axis at origin[k] + i * spacing[k] (last axis fastest)."""
+        d = len(n)
+        _check(lib().mam_set_grid(self._h, d, (ctypes.c_int64 * d)(*[int(x) for x in n]),
+                                  (ctypes.c_double * d)(*[float(x) for x in origin]),
+                                  (ctypes.c_double * d)(*[float(x) for x in spacing])), "mam_set_grid")
 
     # -- iteration ---------------------------------------------------------
     def init(self, theta0: Optional[torch.Tensor] = None) -> None:
@@ -347,13 +361,17 @@ class Solver:
 
 
 def solver_for(problem, device="cuda", diag: bool = False, cold: bool = False, relaxed: bool = False,
-               **sched) -> Solver:
+               grid: bool = False, **sched) -> Solver:
     """Allocate device buffers for an ``inputs.Problem`` and bind them
     (relaxed: measure constraints sum_r pi_rs <= q_s, with the problem's
-    cost taken as the shifted c - eta)."""
+    cost taken as the shifted c - eta; grid: a problem whose support is a
+    regular grid (meta["grid"]) forms its cost in the kernels from the
+    points instead of storing it)."""
     dt = torch.float32 if problem.dtype == "f32" else torch.float64
     ncols = problem.cost_ncols
-    if problem.col_index is None:
+    if grid:
+        mode = COST_GRID
+    elif problem.col_index is None:
         mode = COST_SHARED
     elif np.array_equal(problem.col_index, np.arange(problem.T)):
         mode = COST_PER_COLUMN
@@ -361,7 +379,11 @@ def solver_for(problem, device="cuda", diag: bool = False, cold: bool = False, r
         mode = COST_INDEXED
     s = Solver(problem.R, problem.S, rho=problem.rho, gamma=problem.gamma, dtype=dt,
                cost_mode=mode, cost_ncols=ncols, diag=diag, cold=cold, relaxed=relaxed, device=device, **sched)
-    if problem.cost is None:
+    if grid:
+        n, origin, spacing = problem.meta["grid"]
+        s.set_grid(n, origin, spacing)
+        cost = torch.from_numpy(np.ascontiguousarray(problem.zeta, dtype=np.float64)).to(device)
+    elif problem.cost is None:
         # a cost given by its points is built on the device (rounded once to dt)
         cost = cost_sq_euclid(torch.from_numpy(problem.xi).to(device), torch.from_numpy(problem.zeta).to(device),
                               dtype=dt, ld=s.cost_ld)

@@ -218,3 +218,23 @@ def test_long_column_path_selection():
     ds = (mam.Desc * 1)(d)
     b = ctypes.c_void_p()
     assert L.mam_batch_create(ctypes.byref(b), ds, 1) == -6
+
+
+def test_grid_cost_validation():
+    L = mam.lib()
+    rc, h = create(R=12, S=[5, 5], cost_mode=mam.COST_GRID, cost_ncols=5)
+    assert rc == 0
+    sc = mam.Schedule()
+    assert L.mam_get_schedule(h, ctypes.byref(sc)) == 0 and sc.rows_per_tile > 0   # long-column path
+    N2, D2 = ctypes.c_int64 * 2, ctypes.c_double * 2
+    assert L.mam_set_grid(h, 2, N2(3, 5), D2(0, 0), D2(1, 1)) == -1     # 15 points, R = 12
+    assert L.mam_set_grid(h, 3, N2(3, 4), D2(0, 0), D2(1, 1)) == -1     # dim 3
+    assert L.mam_set_grid(h, 2, N2(3, 4), D2(0, float("nan")), D2(1, 1)) == -1
+    assert L.mam_set_grid(h, 2, N2(3, 4), D2(0, 0), D2(0.5, 0.25)) == 0
+    L.mam_destroy(h)
+    rc, h = create(R=12, S=[5], cost_mode=mam.COST_SHARED, cost_ncols=5)
+    assert L.mam_set_grid(h, 1, (ctypes.c_int64 * 1)(12), (ctypes.c_double * 1)(0), (ctypes.c_double * 1)(1)) == -1
+    L.mam_destroy(h)
+    d, arr = desc(R=12, S=[5], cost_mode=mam.COST_GRID, cost_ncols=5)
+    b = ctypes.c_void_p()
+    assert L.mam_batch_create(ctypes.byref(b), (mam.Desc * 1)(d), 1) == -6

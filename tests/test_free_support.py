@@ -79,3 +79,15 @@ def test_nested_ellipses_and_point_cost():
     blk = p.cost_block(2)
     assert blk.shape == (p.R, 144)
     np.testing.assert_array_equal(blk[:, 57], p.cost_column(57))
+
+
+def test_grid_parameters_reproduce_xi_bitwise():
+    # the kernels of the grid cost mode evaluate origin + i * spacing with the
+    # same two rounded operations
+    p = inputs.free_support(seed=0, K=12, M=3, dtype="f64")
+    (n0, n1), (o0, o1), (h0, h1) = p.meta["grid"]
+    assert n0 * n1 == p.R
+    r = np.arange(p.R)
+    i0, i1 = r // n1, r % n1
+    np.testing.assert_array_equal(p.xi[:, 0], o0 + i0.astype(np.float64) * h0)
+    np.testing.assert_array_equal(p.xi[:, 1], o1 + i1.astype(np.float64) * h1)

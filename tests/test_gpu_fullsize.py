@@ -127,18 +127,21 @@ def test_batch_of_256_full_size_sampled_problems():
         assert e <= 1e-5
 
 
-def test_free_support_full_size_sampled_columns():
+@pytest.mark.parametrize("grid", [False, True])
+def test_free_support_full_size_sampled_columns(grid):
     """Free-support barycenter of 10 nested-ellipse 60x60 images: the R =
     349,281 support points of Theorem c, T = 36,000 columns, 50 GB of FP32
     plans, default long-column schedule.  theta^6 columns from the GPU's
     theta^5 through the oracle's step with the oracle's own cost (built from
     the points in FP64 and rounded once to float, as the device builds it;
     the two may differ by one float ulp, and the projection moves at most
-    twice as far as w, which the tolerance allows).  The marginal of
-    measure 0 is checked against a plain FP64 sum of its 3,600 columns."""
+    twice as far as w, which the tolerance allows; with grid = True the
+    kernels form the cost from the grid in the oracle's operation order, so
+    the two costs are the same).  The marginal of measure 0 is checked
+    against a plain FP64 sum of its 3,600 columns."""
     p = inputs.free_support(dtype="f32")
-    say(f"{p.name}: R={p.R} M={p.M} T={p.T}")
-    s = mam.solver_for(p)
+    say(f"{p.name}: R={p.R} M={p.M} T={p.T} grid cost {grid}")
+    s = mam.solver_for(p, grid=grid)
     sc = s.schedule()
     say(f"schedule {sc}")
     assert sc["rows_per_tile"] > 0
@@ -165,10 +168,13 @@ def test_free_support_full_size_sampled_columns():
     new, _, t = O.mam_step_columns(th5.T, meas, pm5, cost_cols, p.q[cols].astype(np.float64), p.S, p.rho,
                                    p.gamma)
     got = s.theta[cols_t, :p.R].double().cpu().numpy().T
-    dc = np.abs(s.cost[torch.as_tensor(cols - off[meas], device=s.cost.device), :p.R].double().cpu().numpy().T
-                - cost_cols).max(axis=0)
-    say(f"device cost vs oracle cost on the sampled columns: max |diff| {dc.max():.2e}")
-    assert np.all(dc <= 2.0 ** -23 * np.abs(cost_cols).max(axis=0))
+    if grid:
+        dc = np.zeros(len(cols))
+    else:
+        dc = np.abs(s.cost[torch.as_tensor(cols - off[meas], device=s.cost.device), :p.R].double().cpu().numpy().T
+                    - cost_cols).max(axis=0)
+        say(f"device cost vs oracle cost on the sampled columns: max |diff| {dc.max():.2e}")
+        assert np.all(dc <= 2.0 ** -23 * np.abs(cost_cols).max(axis=0))
     err = np.abs(got - new)
     bound = 2.0 ** -23 * np.abs(new) + 2.0 * dc[None, :] / p.rho
     say(f"{len(cols)} sampled columns: max |diff| / bound = {np.max(err / np.maximum(bound, 1e-300)):.3f}")

@@ -157,3 +157,27 @@ def test_measure_sets_schedule_matches_oracle(dtype):
     s, _ = check(p, 12, rows_per_tile=1024)
     nwg = s.schedule()["workgroups"]
     assert nwg % (8 * p.M) == 0, nwg
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("rows", [0, 1024])
+def test_grid_cost_matches_oracle(dtype, rows):
+    # free-support problem of 3 nested-ellipse 12x12 images: R = 34^2 grid
+    # points; the kernels form the cost from the grid and the pixel centres,
+    # the oracle reads it from the points in FP64 (rounded to the dtype)
+    p = inputs.free_support(seed=3, K=12, M=3, dtype=dtype)
+    sched = {"grid": True}
+    if rows:
+        sched["rows_per_tile"] = rows
+    check(p, 20, **sched)
+
+
+def test_grid_cost_equals_stored_cost():
+    # the same problem with the cost stored (built on the device from the
+    # points) and formed in the kernels: identical results
+    p = inputs.free_support(seed=4, K=10, M=4, dtype="f32")
+    a = run(p, 15, grid=True, rows_per_tile=1024)
+    b = run(p, 15, rows_per_tile=1024)
+    for x, y in zip(a.plans(), b.plans()):
+        np.testing.assert_allclose(x, y, rtol=0, atol=2e-7 * np.abs(y).max())
+    np.testing.assert_allclose(a.barycenter().cpu().numpy(), b.barycenter().cpu().numpy(), rtol=1e-6)

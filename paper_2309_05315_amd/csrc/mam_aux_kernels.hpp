@@ -325,6 +325,19 @@ check_index_kernel(const int32_t* __restrict__ idx, int64_t n, int64_t ncols, do
   if (bad) flag[0] = 1.0;
 }
 
+// ||xi_r - zeta_s||^2 as the sum of rounded squares in axis order (no fused
+// multiply-add), so it equals the plain evaluation of the definition.
+__device__ __forceinline__ double sq_dist(const double* __restrict__ xi, int r,
+                                          const double* __restrict__ zeta, int64_t s, int dim) {
+#pragma clang fp contract(off)
+  double d = 0.0;
+  for (int k = 0; k < dim; ++k) {
+    const double e = xi[(int64_t)r * dim + k] - zeta[s * dim + k];
+    d += e * e;
+  }
+  return d;
+}
+
 // Squared Euclidean cost; the max is reduced with an integer max on the bit
 // pattern (non-negative doubles order like their bits), which is exact.
 __global__ void __launch_bounds__(256)
@@ -335,11 +348,7 @@ sqdist_kernel(const double* __restrict__ xi, int R, const double* __restrict__ z
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
     const int64_t s = i / R;
     const int r = (int)(i - s * R);
-    double d = 0.0;
-    for (int k = 0; k < dim; ++k) {
-      const double e = xi[(int64_t)r * dim + k] - zeta[s * dim + k];
-      d += e * e;
-    }
+    const double d = sq_dist(xi, r, zeta, s, dim);
     mx = fmax(mx, d);
   }
   if (want_max) {
@@ -360,11 +369,7 @@ cost_write_kernel(const double* __restrict__ xi, int R, const double* __restrict
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
     const int64_t s = i / R;
     const int r = (int)(i - s * R);
-    double d = 0.0;
-    for (int k = 0; k < dim; ++k) {
-      const double e = xi[(int64_t)r * dim + k] - zeta[s * dim + k];
-      d += e * e;
-    }
+    const double d = sq_dist(xi, r, zeta, s, dim);
     out[s * out_ld + r] = (T)(normalize ? d / scale : d);
   }
 }

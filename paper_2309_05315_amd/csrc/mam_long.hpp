@@ -32,6 +32,8 @@
 // sum has a fixed order: results are bitwise reproducible.
 #pragma once
 
+#include <utility>
+
 #include "mam_kernels.hpp"
 
 namespace mam {
@@ -73,34 +75,48 @@ struct LongArgs {
   const int32_t* stop;           // early-exit flag, or null
   int64_t T_cols;
   // grid cost (cost_mode MAM_COST_GRID): row r is point (i0, i1) of an
-  // n0 x n1 grid (last axis fastest; gdim 1: just i0 = r) with coordinates
-  // go[k] + i_k * gh[k], and cost column s is the point gz[s*gdim ..]:
-  // c_rs = sum_k (x_rk - z_sk)^2, rounded to the storage type
+  // n0 x n1 grid (last axis fastest; gdim 1: i0 = r, gn1 = 1 and a second
+  // axis of origin and spacing 0) with coordinates go[k] + i_k * gh[k], and
+  // cost column s is the point gz[s*gdim ..]: c_rs = sum_k (x_rk - z_sk)^2,
+  // rounded to the storage type
   int32_t gdim, gn1;
   double go[2], gh[2];
   const double* gz;
 };
 
-// The grid cost of row index pair (i0, i1) and point z, evaluated in the
-// order of its definition (each product and sum rounded, no contraction),
-// then rounded to the storage type as a stored cost would be.
+// Coordinate k of grid index i: origin + i * spacing, each operation rounded
+// (no fused multiply-add).
 template <typename T>
-__device__ __forceinline__ double grid_cost_at(const LongArgs<T>& a, int i0, int i1, const double* z) {
-  const double x0 = __dadd_rn(a.go[0], __dmul_rn((double)i0, a.gh[0]));
-  const double d0 = __dsub_rn(x0, z[0]);
-  double c = __dmul_rn(d0, d0);
-  if (a.gdim == 2) {
-    const double x1 = __dadd_rn(a.go[1], __dmul_rn((double)i1, a.gh[1]));
-    const double d1 = __dsub_rn(x1, z[1]);
-    c = __dadd_rn(c, __dmul_rn(d1, d1));
-  }
+__device__ __forceinline__ double grid_coord(const LongArgs<T>& a, int k, int i) {
+#pragma clang fp contract(off)
+  return a.go[k] + (double)i * a.gh[k];
+}
+
+// The grid cost of the point (x0, x1) and the column's point (z0, z1),
+// evaluated in the order of its definition (each product and sum rounded, no
+// fused multiply-add), then rounded to the storage type as a stored cost
+// would be.  On a one-dimensional grid x1 = z1 = 0, so the second term is +0
+// and c = d0^2 exactly.
+template <typename T>
+__device__ __forceinline__ double grid_cost_xy(double x0, double x1, double z0, double z1) {
+#pragma clang fp contract(off)
+  const double d0 = x0 - z0, d1 = x1 - z1;
+  const double c = d0 * d0 + d1 * d1;
   return (double)(T)c;
 }
 
+// The column's point (z0, z1) of cost column j (z1 = 0 on a 1-D grid).
 template <typename T>
-__device__ __forceinline__ double grid_cost(const LongArgs<T>& a, int r, const double* z) {
-  const int i0 = a.gdim == 2 ? r / a.gn1 : r;
-  return grid_cost_at(a, i0, r - i0 * a.gn1, z);
+__device__ __forceinline__ void grid_point(const LongArgs<T>& a, int64_t j, int64_t off_m, double* z0, double* z1) {
+  const double* z = gptr(a.gz) + (j - off_m) * a.gdim;
+  *z0 = z[0];
+  *z1 = a.gdim == 2 ? z[1] : 0.0;
+}
+
+template <typename T>
+__device__ __forceinline__ double grid_cost(const LongArgs<T>& a, int r, double z0, double z1) {
+  const int i0 = r / a.gn1;
+  return grid_cost_xy<T>(grid_coord(a, 0, i0), grid_coord(a, 1, r - i0 * a.gn1), z0, z1);
 }
 
 template <typename T>
@@ -110,6 +126,17 @@ __device__ __forceinline__ const T* long_cost_col(const LongArgs<T>& a, int64_t 
   else if (a.cost_mode == MAM_COST_SHARED) cc = j - off_m;
   else cc = j;
   return a.cost + cc * a.cost_ld;
+}
+
+// f(integral_constant<int, 0>{}), ..., f(integral_constant<int, N - 1>{}):
+// a loop over buffers whose index stays a compile-time constant.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 // b^(m)_r = t (p_r - p^(m)_r) / S^m: every kernel forms it with this one
@@ -125,6 +152,9 @@ template <typename T, int VPT, int VEC, bool GRID>
 __global__ void __launch_bounds__(LNT)
 long_scan_kernel(LongArgs<T> a) {
   constexpr int NCH = VPT / VEC, RB = LNT * VPT;
+  // columns in flight per wave: two where the registers allow it at two
+  // waves per SIMD (FP32 tiles of 16 values in vectors), else one
+  constexpr int PF = (sizeof(T) == 4 && VPT == 16 && VEC > 1) ? 2 : 1;
   static_assert(VPT % VEC == 0 && VPT <= 16, "tile shape");
   if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -145,89 +175,100 @@ long_scan_kernel(LongArgs<T> a) {
     const double* __restrict__ pv = gptr(a.p);
     const int rbase = rb * RB;
     int row[VPT];
-    double b[VPT];
-    int gi0[GRID ? VPT : 1], gi1[GRID ? VPT : 1];  // grid indices of the rows
+    // 2 b_r, or -inf for rows past R: their w is then -inf (theta and c are
+    // finite), below every threshold, without a select per entry
+    double b2[VPT];
+    double gx0[GRID ? VPT : 1], gx1[GRID ? VPT : 1];  // grid coordinates of the rows
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       row[k] = rbase + ((k / VEC) * LNT + tid) * VEC + (k % VEC);
-      b[k] = row[k] < R ? long_b(t, pv, pmm, row[k], Sm) : 0.0;
+      b2[k] = row[k] < R ? 2.0 * long_b(t, pv, pmm, row[k], Sm) : -__builtin_huge_val();
       if constexpr (GRID) {
-        gi0[k] = a.gdim == 2 ? row[k] / a.gn1 : row[k];
-        gi1[k] = row[k] - gi0[k] * a.gn1;
+        const int i0 = row[k] / a.gn1;
+        gx0[k] = grid_coord(a, 0, i0);
+        gx1[k] = grid_coord(a, 1, row[k] - i0 * a.gn1);
       }
     }
-    // raw theta and c (or the column's point) of the next column in flight
-    // while this one is scanned
-    T rt[VPT], rc[GRID ? 1 : VPT], rq;
-    double rz[2];
-    auto issue = [&](int64_t j) {
+    // raw theta and c (or the column's point) of the next PF columns in
+    // flight while one is scanned: PF buffers, used in turn
+    T rt[PF][VPT], rc[PF][GRID ? 1 : VPT], rq[PF];
+    double rz[PF][2];
+    auto issue = [&](auto S, int64_t j) {
+      constexpr int s = decltype(S)::value;
       const T* __restrict__ thp = theta + j * a.ld;
-      rq = qv[j];
-      if constexpr (GRID) {
-        const double* z = gptr(a.gz) + (j - off_m) * a.gdim;
-        rz[0] = z[0];
-        rz[1] = a.gdim == 2 ? z[1] : 0.0;
-      }
+      rq[s] = qv[j];
+      if constexpr (GRID) grid_point(a, j, off_m, &rz[s][0], &rz[s][1]);
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
         const int r0 = row[c * VEC] < R ? row[c * VEC] : rbase;  // rows past R read the tile's first (masked)
         T tv[VEC];
         load_vec_nt<T, VEC>(thp + r0, tv);
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) rt[c * VEC + v] = tv[v];
+        for (int v = 0; v < VEC; ++v) rt[s][c * VEC + v] = tv[v];
         if constexpr (!GRID) {
           T cv[VEC];
           load_vec<T, VEC>(long_cost_col(a, j, off_m) + r0, cv);
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) rc[c * VEC + v] = cv[v];
+          for (int v = 0; v < VEC; ++v) rc[s][c * VEC + v] = cv[v];
         }
       }
     };
-    if (j0 < j1) issue(j0);
-    for (int64_t j = j0; j < j1; ++j) {
+    // scan column j from buffer S; with NEXT, load column min(j + PF, j1 - 1)
+    // into that buffer (past the item's end it loads its last column again:
+    // unconditional loads keep the buffers in place across iterations)
+    auto column = [&](auto S, auto NEXT, int64_t j) {
+      constexpr int s = decltype(S)::value;
       double w[VPT];
       double mx = -__builtin_huge_val();
-      double z[2] = {uniform_d(rz[0]), uniform_d(rz[1])};
+      const double z0 = uniform_d(rz[s][0]), z1 = uniform_d(rz[s][1]);
 #pragma unroll
       for (int k = 0; k < VPT; ++k) {
         double c;
-        if constexpr (GRID) c = grid_cost_at(a, gi0[k], gi1[k], z);
-        else c = (double)rc[k];
-        const double x = ((double)rt[k] + 2.0 * b[k]) - c * inv_rho;
-        w[k] = row[k] < R ? x : -__builtin_huge_val();
+        if constexpr (GRID) c = grid_cost_xy<T>(gx0[k], gx1[k], z0, z1);
+        else c = (double)rc[s][k];
+        w[k] = ((double)rt[s][k] + b2[k]) - c * inv_rho;
         mx = fmax(mx, w[k]);
       }
-      const double tau = uniform_d((double)rq);
-      if (j + 1 < j1) issue(j + 1);
+      const double tau = uniform_d((double)rq[s]);
+      if constexpr (decltype(NEXT)::value) issue(S, j + PF < j1 ? j + PF : j1 - 1);
       mx = wave_max(mx);
       const double thr = mx - tau;
-      int bits = 0;
-      if (tau > 0.0) {
-#pragma unroll
-        for (int k = 0; k < VPT; ++k) bits |= (int)(w[k] > thr) << k;
-      }
       // slots in slot-major order inside the wave: position = candidates of
-      // earlier slots + earlier lanes of this slot
+      // earlier slots + earlier lanes of this slot (rows past R have w = -inf
+      // and are never candidates)
       const int64_t h = j * nsub + rb * 4 + wv;
       int n = 0;
+      if (tau > 0.0) {
 #pragma unroll
-      for (int k = 0; k < VPT; ++k) {
-        const unsigned long long bal = __ballot((bits >> k) & 1);
-        if ((bits >> k) & 1) {
-          const int pos = n + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-          if (pos < cap) {
-            crow[h * cap + pos] = row[k];
-            cw[h * cap + pos] = w[k];
+        for (int k = 0; k < VPT; ++k) {
+          const bool sel = w[k] > thr;
+          const unsigned long long bal = __ballot(sel);
+          if (sel) {
+            const int pos = n + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            if (pos < cap) {
+              crow[h * cap + pos] = row[k];
+              cw[h * cap + pos] = w[k];
+            }
           }
+          n += __popcll(bal);
         }
-        n += __popcll(bal);
       }
       if (lane == 0) {
         gptr(a.hmax)[h] = mx;
         gptr(a.hcnt)[h] = n;
       }
-    }
+    };
+    using YES = std::true_type;
+    using NO = std::false_type;
+    if (j0 >= j1) continue;
+    // buffer i holds column j + i (clamped to the item's last column)
+    static_for<PF>([&](auto I) { issue(I, j0 + I < j1 ? j0 + I : j1 - 1); });
+    int64_t j = j0;
+    for (; j + PF - 1 < j1; j += PF) static_for<PF>([&](auto I) { column(I, YES{}, j + I); });
+    static_for<PF - 1>([&](auto I) {
+      if (j + I < j1) column(I, NO{}, j + I);
+    });
   }
 }
 
@@ -269,8 +310,9 @@ long_threshold_kernel(LongArgs<T> a) {
   const double* __restrict__ pv = gptr(a.p);
   const T* __restrict__ thp = gptr(a.theta) + j * a.ld;
   const T* __restrict__ cp = long_cost_col(a, j, off_m);
-  const double* zj = a.gdim ? gptr(a.gz) + (j - off_m) * a.gdim : nullptr;
-  auto costv = [&](int r) { return a.gdim ? grid_cost(a, r, zj) : (double)cp[r]; };
+  double z0 = 0.0, z1 = 0.0;
+  if (a.gdim) grid_point(a, j, off_m, &z0, &z1);
+  auto costv = [&](int r) { return a.gdim ? grid_cost(a, r, z0, z1) : (double)cp[r]; };
   auto visit = [&](auto&& f) {
     for (int s0 = 0; s0 < nsub; s0 += 64) {
       const int s = s0 + lane;
@@ -404,7 +446,8 @@ long_write_kernel(LongArgs<T> a) {
       if (some && n > cap) {
         // more candidates than slots: vector by vector, w from theta and c
         const T* __restrict__ cp = long_cost_col(a, j, off_m);
-        const double* zj = a.gdim ? gptr(a.gz) + (j - off_m) * a.gdim : nullptr;
+        double z0 = 0.0, z1 = 0.0;
+        if (a.gdim) grid_point(a, j, off_m, &z0, &z1);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
           const int r0 = row(c * VEC);
@@ -417,7 +460,7 @@ long_write_kernel(LongArgs<T> a) {
             out[v] = nb[k];
             if (r0 + v < R) {
               const double bk = long_b(t, pv, pmm, r0 + v, Sm);
-              const double cc = a.gdim ? grid_cost(a, r0 + v, zj) : (double)cp[r0 + v];
+              const double cc = a.gdim ? grid_cost(a, r0 + v, z0, z1) : (double)cp[r0 + v];
               const double w = ((double)tv[v] + 2.0 * bk) - cc * inv_rho;
               if (w > lam) {
                 out[v] = (T)(fmax(w - lam, 0.0) - bk);

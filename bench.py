@@ -20,6 +20,7 @@ the launch stream), the FP64 run and the oracle's CPU rate on a bounded
 sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 500] [--warmup 10] [--no-cpu] [--copy-probe]
+                    [--no-extras | --extras free_support,adjoint,...]
 """
 from __future__ import annotations
 
@@ -100,9 +101,12 @@ def cpu_baseline(p, n_measures):
                       f"({entries:.3e} plan entries, {dt:.1f} s, single thread)"}
 
 
-def extra_workloads(torch, mam, inputs, log):
-    """The other workloads of the hot path, timed briefly (informational)."""
-    import numpy as np
+EXTRAS = ("balanced_plain", "unbalanced", "batch", "randomized", "stopping", "free_support", "adjoint")
+
+
+def extra_workloads(torch, mam, inputs, log, only=None):
+    """The other workloads of the hot path, timed briefly (informational);
+    ``only``: the names (of EXTRAS) to run, all by default."""
     out = {}
     sync = torch.cuda.synchronize
 
@@ -113,176 +117,188 @@ def extra_workloads(torch, mam, inputs, log):
         sync()
         return time.perf_counter() - t0
 
-    # balanced, FP64, 16x16 grid, 4 measures: launch-bound; eager vs graph replay
+    def want(name):
+        return only is None or name in only
+
     p1 = inputs.balanced_plain()
-    s = mam.solver_for(p1)
-    s.init()
-    s.iterate(10)
-    eager = timed(lambda: s.iterate(p1.iters)) / p1.iters
-    s.graph(50)
-    s.init()
-    s.iterate(50)
-    graph = timed(lambda: s.iterate(p1.iters)) / p1.iters
-    s.close()
-    out["balanced_plain_K16_M4_f64"] = {"iterations": p1.iters, "ms_per_iter_eager": eager * 1e3,
-                                        "ms_per_iter_graph": graph * 1e3}
-    log(f"balanced plain: {eager * 1e3:.4f} ms/iter eager, {graph * 1e3:.4f} ms/iter graph")
-
-    # unbalanced, FP32, 32x32 grid, 50 measures, gamma = 0.01
-    p3 = inputs.unbalanced_dense()
-    s = mam.solver_for(p3)
-    s.init()
-    s.iterate(10)
-    dt = timed(lambda: s.iterate(p3.iters)) / p3.iters
-    s.timing(True)
-    s.iterate(100)
-    col, n = s.timing_read()
-    s.close()
-    ab = algorithmic_bytes(p3)
-    out["unbalanced_K32_M50_f32"] = {"iterations": p3.iters, "ms_per_iter": dt * 1e3,
-                                     "column_kernel_ms": col / n,
-                                     "column_kernel_GBs": ab / (col / n * 1e-3) / 1e9}
-    log(f"unbalanced: {dt * 1e3:.4f} ms/iter, column kernel {col / n:.4f} ms")
-
-    # 256 independent problems (R = k^2, k in 8..32, M in 2..8), FP32, autotuned
-    # schedules per shape group, graph replay
-    from paper_2309_05315_amd import autotune
-    probs = inputs.batched_problems()
-    t0 = time.perf_counter()
-    scheds = autotune.tune_batch(probs)
-    tune_s = time.perf_counter() - t0
-    b = mam.Batch(probs, schedules=scheds)
-    b.graph(25)
-    b.init()
-    b.iterate(25)
-    iters4 = probs[0].iters
-    dt = timed(lambda: b.iterate(iters4)) / iters4
-    b.graph(0)
-    b.timing(True)
-    b.iterate(50)
-    col, n = b.timing_read()
-    b.close()
-    ab = sum(algorithmic_bytes(p) for p in probs)
-    out["batch_256_f32"] = {"problems": len(probs), "iterations": iters4, "ms_per_iter_graph": dt * 1e3,
-                            "autotune_s": tune_s, "schedules": {str(g): v for g, v in scheds.items()},
-                            "column_kernels_ms": col / n, "column_kernels_GBs": ab / (col / n * 1e-3) / 1e9,
-                            "plan_entries": int(sum(p.R * p.T for p in probs))}
-    log(f"batch of {len(probs)}: {dt * 1e3:.4f} ms/iter (graph), column kernels {col / n:.4f} ms")
-
-    # randomized variant on the benchmark workload: 4 bundles of 8 measures,
-    # drawn with probability proportional to alpha_m = 1/M (the same seeded draws
-    # for every run)
     p2 = inputs.balanced_sparse(dtype="f32")
-    bundles = [list(range(i, p2.M, 4)) for i in range(4)]
-    bundle_of = [m % 4 for m in range(p2.M)]
-    seq = inputs.bundle_sequence(bundles, 200, seed=0)
-    s = mam.solver_for(p2)
-    s.init()
-    s.set_bundles(bundle_of)
-    s.iterate_bundles(seq[:20])
-    dt = timed(lambda: s.iterate_bundles(seq[20:]))
-    n_it = len(seq) - 20
-    ent = sum(p2.R * sum(p2.S[m] for m in bundles[b]) for b in seq[20:])
-    s.close()
-    out["randomized_4_bundles_K64_M32_f32"] = {
-        "iterations": n_it, "ms_per_iter": dt / n_it * 1e3, "plan_entry_updates_per_s": ent / dt,
-        "entries_per_iter": ent / n_it}
-    log(f"randomized, 4 bundles: {dt / n_it * 1e3:.4f} ms/iter, {ent / dt:.3e} entries/s")
 
-    # stopping tests on the device (Sec. 5): the cost of a check every 10
-    # iterations against plain iterations (graph replay in both), on the
-    # benchmark workload and on the launch-bound 16x16 problem, and the time a
-    # run of at most 20000 iterations takes when its first check stops it
-    res = {}
-    for name, prob in (("K64_M32_f32", p2), ("K16_M4_f64", p1)):
-        s = mam.solver_for(prob)
-        s.graph(10)
+    if want("balanced_plain"):
+        # balanced, FP64, 16x16 grid, 4 measures: launch-bound; eager vs graph replay
+        s = mam.solver_for(p1)
         s.init()
-        s.iterate(20)
-        r_ = {"plain_ms_per_iter": timed(lambda: s.iterate(200)) / 200 * 1e3}
-        for test in ("dp", "dist", "dtheta"):
-            s.init()
-            s.iterate_until(20, test, -1.0, 10)
-            r_[f"{test}_every_10_ms_per_iter"] = timed(lambda: s.iterate_until(200, test, -1.0, 10)) / 200 * 1e3
+        s.iterate(10)
+        eager = timed(lambda: s.iterate(p1.iters)) / p1.iters
+        s.graph(50)
         s.init()
-        got = {}
-        r_["stop_at_first_check_ms"] = timed(lambda: got.update(s.iterate_until(20000, "dp", float("inf"), 10))) * 1e3
-        r_["stop_at_first_check_iterations"] = got["iterations"]
+        s.iterate(50)
+        graph = timed(lambda: s.iterate(p1.iters)) / p1.iters
         s.close()
-        res[name] = r_
-        log(f"stopping tests {name}: plain {r_['plain_ms_per_iter']:.4f} ms/iter, with checks every 10: "
-            f"dp {r_['dp_every_10_ms_per_iter']:.4f}, dist {r_['dist_every_10_ms_per_iter']:.4f}, "
-            f"dtheta {r_['dtheta_every_10_ms_per_iter']:.4f}; stop at the first check of 20000: "
-            f"{r_['stop_at_first_check_ms']:.2f} ms")
-    out["stopping_tests"] = res
+        out["balanced_plain_K16_M4_f64"] = {"iterations": p1.iters, "ms_per_iter_eager": eager * 1e3,
+                                            "ms_per_iter_graph": graph * 1e3}
+        log(f"balanced plain: {eager * 1e3:.4f} ms/iter eager, {graph * 1e3:.4f} ms/iter graph")
 
-    # free-support barycenter (Theorem c): 10 nested-ellipse 60x60 images,
-    # R = 349,281 support points, T = 36,000 columns, FP32 plans (50 GB):
-    # the long-column path (row tiles, candidate slots, per-column thresholds)
-    pf = inputs.free_support(dtype="f32")
-    res = {"R": pf.R, "M": pf.M, "T": pf.T, "plans_GB": pf.T * pf.R * 4 / 1e9}
-    for mode, grid in (("stored_cost", False), ("grid_cost", True)):
-        s = mam.solver_for(pf, grid=grid)
-        sc = s.schedule()
+    if want("unbalanced"):
+        # unbalanced, FP32, 32x32 grid, 50 measures, gamma = 0.01
+        p3 = inputs.unbalanced_dense()
+        s = mam.solver_for(p3)
         s.init()
-        s.iterate(3)
-        n_it = 20
-        dt = timed(lambda: s.iterate(n_it)) / n_it
+        s.iterate(10)
+        dt = timed(lambda: s.iterate(p3.iters)) / p3.iters
         s.timing(True)
-        s.iterate(5)
+        s.iterate(100)
         col, n = s.timing_read()
-        ws = s.workspace.numel()
         s.close()
-        del s
-        torch.cuda.empty_cache()
-        # algorithmic bytes: theta read and written, the distinct cost read
-        # once (none when the kernels form it from the grid), q
-        abf = 4 * (2 * pf.R * pf.T + (0 if grid else pf.R * pf.distinct_cost_columns()) + pf.T)
-        res[mode] = {"iterations": n_it, "ms_per_iter": dt * 1e3, "plan_entry_updates_per_s": pf.R * pf.T / dt,
-                     "column_kernels_ms": col / n, "algorithmic_bytes_per_iter": abf,
-                     "column_kernels_GBs": abf / (col / n * 1e-3) / 1e9, "workspace_GB": ws / 1e9,
-                     "rows_per_tile": sc["rows_per_tile"], "candidate_slots": sc["candidate_slots"],
-                     "workgroups": sc["workgroups"]}
-        log(f"free support R={pf.R} T={pf.T} ({mode}): {dt * 1e3:.2f} ms/iter, {pf.R * pf.T / dt:.3e} entries/s, "
-            f"column kernels {col / n:.2f} ms ({abf / (col / n * 1e-3) / 1e9:.0f} GB/s algorithmic)")
-    out["free_support_K60_M10_f32"] = res
+        ab = algorithmic_bytes(p3)
+        out["unbalanced_K32_M50_f32"] = {"iterations": p3.iters, "ms_per_iter": dt * 1e3,
+                                         "column_kernel_ms": col / n,
+                                         "column_kernel_GBs": ab / (col / n * 1e-3) / 1e9}
+        log(f"unbalanced: {dt * 1e3:.4f} ms/iter, column kernel {col / n:.4f} ms")
 
-    # reverse mode: 64x64 grid, 8 measures, 100 iterations, FP32, loss ||p_bar - target||^2
-    p5, tgt = inputs.adjoint_problem()
-    tg = torch.as_tensor(tgt, device="cuda:0")
-    res = {"iterations": p5.iters}
-    for ck in (10, 0):
-        s = mam.solver_for(p5)
+    if want("batch"):
+        # 256 independent problems (R = k^2, k in 8..32, M in 2..8), FP32, autotuned
+        # schedules per shape group, graph replay
+        from paper_2309_05315_amd import autotune
+        probs = inputs.batched_problems()
+        t0 = time.perf_counter()
+        scheds = autotune.tune_batch(probs)
+        tune_s = time.perf_counter() - t0
+        b = mam.Batch(probs, schedules=scheds)
+        b.graph(25)
+        b.init()
+        b.iterate(25)
+        iters4 = probs[0].iters
+        dt = timed(lambda: b.iterate(iters4)) / iters4
+        b.graph(0)
+        b.timing(True)
+        b.iterate(50)
+        col, n = b.timing_read()
+        b.close()
+        ab = sum(algorithmic_bytes(p) for p in probs)
+        out["batch_256_f32"] = {"problems": len(probs), "iterations": iters4, "ms_per_iter_graph": dt * 1e3,
+                                "autotune_s": tune_s, "schedules": {str(g): v for g, v in scheds.items()},
+                                "column_kernels_ms": col / n, "column_kernels_GBs": ab / (col / n * 1e-3) / 1e9,
+                                "plan_entries": int(sum(p.R * p.T for p in probs))}
+        log(f"batch of {len(probs)}: {dt * 1e3:.4f} ms/iter (graph), column kernels {col / n:.4f} ms")
+
+    if want("randomized"):
+        # randomized variant on the benchmark workload: 4 bundles of 8 measures,
+        # drawn with probability proportional to alpha_m = 1/M (the same seeded draws
+        # for every run)
+        bundles = [list(range(i, p2.M, 4)) for i in range(4)]
+        bundle_of = [m % 4 for m in range(p2.M)]
+        seq = inputs.bundle_sequence(bundles, 200, seed=0)
+        s = mam.solver_for(p2)
         s.init()
-        rec = timed(lambda: s.record(p5.iters, ck))
-        g = 2.0 * (s.barycenter() - tg)
-        s.backward(g)
-        s.timing(True)
-        bwd = timed(lambda: s.backward(g))
-        ak, n = s.timing_read()
-        sc = s.schedule()
-        ws = s.adj_workspace.numel()
+        s.set_bundles(bundle_of)
+        s.iterate_bundles(seq[:20])
+        dt = timed(lambda: s.iterate_bundles(seq[20:]))
+        n_it = len(seq) - 20
+        ent = sum(p2.R * sum(p2.S[m] for m in bundles[b]) for b in seq[20:])
         s.close()
-        res[f"ckpt_every_{ck}"] = {"record_ms": rec * 1e3, "backward_ms": bwd * 1e3,
-                                   "adjoint_kernel_us": ak / n * 1e3, "adjoint_workspace_GB": ws / 1e9}
-        log(f"adjoint ckpt_every={ck}: record {rec * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms, "
-            f"adjoint kernel {ak / n * 1e3:.1f} us")
-    # algorithmic bytes of one reverse column step: the active-set masks of
-    # two iterations, q's adjoint (read and write), and for every active
-    # entry the sparse adjoint (read, write) and the cost adjoint (read, write)
-    s = mam.solver_for(p5, diag=True)
-    s.init()
-    s.iterate(p5.iters)
-    act = s.diagnostics()["active_per_column"]
-    s.close()
-    mld = sc["threads_per_column"] * (1 if sc["values_per_thread"] <= 8 else 2)
-    abytes = 2 * p5.T * mld + 16 * p5.T + 32 * act * p5.T
-    us = res["ckpt_every_0"]["adjoint_kernel_us"]
-    res["adjoint_kernel_roofline"] = {"bound": "hbm", "algorithmic_bytes_per_launch": abytes,
-                                      "active_entries_per_column": act,
-                                      "achieved": abytes / (us * 1e-6) / 1e9, "peak": PEAK_HBM_GBS,
-                                      "unit": "GB/s", "frac": abytes / (us * 1e-6) / 1e9 / PEAK_HBM_GBS}
-    out["adjoint_K64_M8_f32"] = res
+        out["randomized_4_bundles_K64_M32_f32"] = {
+            "iterations": n_it, "ms_per_iter": dt / n_it * 1e3, "plan_entry_updates_per_s": ent / dt,
+            "entries_per_iter": ent / n_it}
+        log(f"randomized, 4 bundles: {dt / n_it * 1e3:.4f} ms/iter, {ent / dt:.3e} entries/s")
+
+    if want("stopping"):
+        # stopping tests on the device (Sec. 5): the cost of a check every 10
+        # iterations against plain iterations (graph replay in both), on the
+        # benchmark workload and on the launch-bound 16x16 problem, and the time a
+        # run of at most 20000 iterations takes when its first check stops it
+        res = {}
+        for name, prob in (("K64_M32_f32", p2), ("K16_M4_f64", p1)):
+            s = mam.solver_for(prob)
+            s.graph(10)
+            s.init()
+            s.iterate(20)
+            r_ = {"plain_ms_per_iter": timed(lambda: s.iterate(200)) / 200 * 1e3}
+            for test in ("dp", "dist", "dtheta"):
+                s.init()
+                s.iterate_until(20, test, -1.0, 10)
+                r_[f"{test}_every_10_ms_per_iter"] = timed(lambda: s.iterate_until(200, test, -1.0, 10)) / 200 * 1e3
+            s.init()
+            got = {}
+            r_["stop_at_first_check_ms"] = timed(lambda: got.update(s.iterate_until(20000, "dp", float("inf"), 10))) * 1e3
+            r_["stop_at_first_check_iterations"] = got["iterations"]
+            s.close()
+            res[name] = r_
+            log(f"stopping tests {name}: plain {r_['plain_ms_per_iter']:.4f} ms/iter, with checks every 10: "
+                f"dp {r_['dp_every_10_ms_per_iter']:.4f}, dist {r_['dist_every_10_ms_per_iter']:.4f}, "
+                f"dtheta {r_['dtheta_every_10_ms_per_iter']:.4f}; stop at the first check of 20000: "
+                f"{r_['stop_at_first_check_ms']:.2f} ms")
+        out["stopping_tests"] = res
+
+    if want("free_support"):
+        # free-support barycenter (Theorem c): 10 nested-ellipse 60x60 images,
+        # R = 349,281 support points, T = 36,000 columns, FP32 plans (50 GB):
+        # the long-column path (row tiles, candidate slots, per-column thresholds)
+        pf = inputs.free_support(dtype="f32")
+        res = {"R": pf.R, "M": pf.M, "T": pf.T, "plans_GB": pf.T * pf.R * 4 / 1e9}
+        for mode, grid in (("stored_cost", False), ("grid_cost", True)):
+            s = mam.solver_for(pf, grid=grid)
+            sc = s.schedule()
+            s.init()
+            s.iterate(3)
+            n_it = 20
+            dt = timed(lambda: s.iterate(n_it)) / n_it
+            s.timing(True)
+            s.iterate(5)
+            col, n = s.timing_read()
+            ws = s.workspace.numel()
+            s.close()
+            del s
+            torch.cuda.empty_cache()
+            # algorithmic bytes: theta read and written, the distinct cost read
+            # once (none when the kernels form it from the grid), q
+            abf = 4 * (2 * pf.R * pf.T + (0 if grid else pf.R * pf.distinct_cost_columns()) + pf.T)
+            res[mode] = {"iterations": n_it, "ms_per_iter": dt * 1e3, "plan_entry_updates_per_s": pf.R * pf.T / dt,
+                         "column_kernels_ms": col / n, "algorithmic_bytes_per_iter": abf,
+                         "column_kernels_GBs": abf / (col / n * 1e-3) / 1e9, "workspace_GB": ws / 1e9,
+                         "rows_per_tile": sc["rows_per_tile"], "candidate_slots": sc["candidate_slots"],
+                         "workgroups": sc["workgroups"]}
+            log(f"free support R={pf.R} T={pf.T} ({mode}): {dt * 1e3:.2f} ms/iter, {pf.R * pf.T / dt:.3e} entries/s, "
+                f"column kernels {col / n:.2f} ms ({abf / (col / n * 1e-3) / 1e9:.0f} GB/s algorithmic)")
+        out["free_support_K60_M10_f32"] = res
+
+    if want("adjoint"):
+        # reverse mode: 64x64 grid, 8 measures, 100 iterations, FP32, loss ||p_bar - target||^2
+        p5, tgt = inputs.adjoint_problem()
+        tg = torch.as_tensor(tgt, device="cuda:0")
+        res = {"iterations": p5.iters}
+        for ck in (10, 0):
+            s = mam.solver_for(p5)
+            s.init()
+            rec = timed(lambda: s.record(p5.iters, ck))
+            g = 2.0 * (s.barycenter() - tg)
+            s.backward(g)
+            s.timing(True)
+            bwd = timed(lambda: s.backward(g))
+            ak, n = s.timing_read()
+            sc = s.schedule()
+            ws = s.adj_workspace.numel()
+            s.close()
+            res[f"ckpt_every_{ck}"] = {"record_ms": rec * 1e3, "backward_ms": bwd * 1e3,
+                                       "adjoint_kernel_us": ak / n * 1e3, "adjoint_workspace_GB": ws / 1e9}
+            log(f"adjoint ckpt_every={ck}: record {rec * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms, "
+                f"adjoint kernel {ak / n * 1e3:.1f} us")
+        # algorithmic bytes of one reverse column step: the active-set masks of
+        # two iterations, q's adjoint (read and write), and for every active
+        # entry the sparse adjoint (read, write) and the cost adjoint (read, write)
+        s = mam.solver_for(p5, diag=True)
+        s.init()
+        s.iterate(p5.iters)
+        act = s.diagnostics()["active_per_column"]
+        s.close()
+        mld = sc["threads_per_column"] * (1 if sc["values_per_thread"] <= 8 else 2)
+        abytes = 2 * p5.T * mld + 16 * p5.T + 32 * act * p5.T
+        us = res["ckpt_every_0"]["adjoint_kernel_us"]
+        res["adjoint_kernel_roofline"] = {"bound": "hbm", "algorithmic_bytes_per_launch": abytes,
+                                          "active_entries_per_column": act,
+                                          "achieved": abytes / (us * 1e-6) / 1e9, "peak": PEAK_HBM_GBS,
+                                          "unit": "GB/s", "frac": abytes / (us * 1e-6) / 1e9 / PEAK_HBM_GBS}
+        out["adjoint_K64_M8_f32"] = res
+
     return out
 
 
@@ -295,9 +311,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--cpu-measures", type=int, default=12)
     ap.add_argument("--no-extras", action="store_true", help="skip the other workloads")
+    ap.add_argument("--extras", default="", help="comma-separated subset of the other workloads: " + ",".join(EXTRAS))
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
+    only = [x for x in args.extras.split(",") if x] or None
+    if only and not set(only) <= set(EXTRAS):
+        ap.error(f"--extras: choose from {','.join(EXTRAS)}")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -373,7 +393,7 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: 3 x {4 * n} bytes copied")
 
-    extras = None if args.no_extras else extra_workloads(torch, mam, inputs, log)
+    extras = None if args.no_extras else extra_workloads(torch, mam, inputs, log, only)
 
     cpu = None if args.no_cpu else cpu_baseline(p32, args.cpu_measures)
 

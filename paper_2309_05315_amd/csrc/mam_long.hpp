@@ -128,6 +128,16 @@ __device__ __forceinline__ const T* long_cost_col(const LongArgs<T>& a, int64_t 
   return a.cost + cc * a.cost_ld;
 }
 
+// The value of v in lane l (l wave-uniform).
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 // f(integral_constant<int, 0>{}), ..., f(integral_constant<int, N - 1>{}):
 // a loop over buffers whose index stays a compile-time constant.
 template <typename F, int... I>
@@ -493,19 +503,26 @@ long_write_kernel(LongArgs<T> a) {
         }
       }
       if (some) {
-        // the kept entries above lambda; the owner of each row patches it
+        // the kept entries above lambda (n <= cap <= 64): lane e reads entry
+        // e and forms its patch, all at once; then, in entry order, the
+        // owner of each row stores it and adds it to the row sum
         const int64_t h = j * nsub + sub;
-        for (int e = 0; e < n; ++e) {
-          const double x = uniform_d(cw[h * cap + e]);
-          if (!(x > lam)) continue;
-          const int r = uniform_i(crow[h * cap + e]);
-          const int rr = r - rbase;
+        const int e = tid & 63;
+        const double xe = e < n ? cw[h * cap + e] : -__builtin_huge_val();
+        const int re = e < n ? crow[h * cap + e] : rbase;
+        const bool keep = xe > lam;
+        const double bk = keep ? long_b(t, pv, pmm, re, Sm) : 0.0;
+        const T val = (T)(fmax(xe - lam, 0.0) - bk);
+        const double dfix = (double)val - (double)(T)(-bk);
+        unsigned long long sel = __ballot(keep);
+        while (sel != 0ull) {
+          const int l = __builtin_ctzll(sel);
+          sel &= sel - 1ull;
+          const int rr = __builtin_amdgcn_readlane(re, l) - rbase;
           if ((rr / VEC) % LNT == tid) {
-            const double bk = long_b(t, pv, pmm, r, Sm);
-            const T val = (T)(fmax(x - lam, 0.0) - bk);
-            thp[r] = val;
+            thp[rbase + rr] = read_lane(val, l);
             const int k = (rr / (VEC * LNT)) * VEC + rr % VEC;
-            fix[k * LNT + tid] += (double)val - (double)(T)(-bk);
+            fix[k * LNT + tid] += read_lane(dfix, l);
           }
         }
       }

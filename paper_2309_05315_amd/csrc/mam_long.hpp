@@ -138,6 +138,13 @@ __device__ __forceinline__ float read_lane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// w = theta + 2b - c/rho (FP64) from 2b: one expression with one fused
+// multiply-add, so the scan, threshold and write kernels form the same value
+// for an entry.
+__device__ __forceinline__ double long_w(double th, double b2, double c, double inv_rho) {
+  return __builtin_fma(-c, inv_rho, th + b2);
+}
+
 // f(integral_constant<int, 0>{}), ..., f(integral_constant<int, N - 1>{}):
 // a loop over buffers whose index stays a compile-time constant.
 template <typename F, int... I>
@@ -236,7 +243,7 @@ long_scan_kernel(LongArgs<T> a) {
         double c;
         if constexpr (GRID) c = grid_cost_xy<T>(gx0[k], gx1[k], z0, z1);
         else c = (double)rc[s][k];
-        w[k] = ((double)rt[s][k] + b2[k]) - c * inv_rho;
+        w[k] = long_w((double)rt[s][k], b2[k], c, inv_rho);
         mx = fmax(mx, w[k]);
       }
       const double tau = uniform_d((double)rq[s]);
@@ -338,7 +345,7 @@ long_threshold_kernel(LongArgs<T> a) {
 #pragma unroll
           for (int k = 0; k < VPT; ++k) {
             const int r = rbase + ((k / VEC) * LNT + tt) * VEC + (k % VEC);
-            if (r < R) f(((double)thp[r] + 2.0 * long_b(t, pv, pmm, r, Sm)) - costv(r) * a.inv_rho);
+            if (r < R) f(long_w((double)thp[r], 2.0 * long_b(t, pv, pmm, r, Sm), costv(r), a.inv_rho));
           }
         }
       }
@@ -405,8 +412,9 @@ long_write_kernel(LongArgs<T> a) {
   if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;
   extern __shared__ double lds_dyn[];
   double* fix = lds_dyn;  // [VPT][256]
-  __shared__ double s_lam[LNT], s_max[4][LNT];
-  __shared__ int s_cnt[4][LNT];
+  constexpr int WB = 128;  // columns whose thresholds and headers are staged at once
+  __shared__ double s_lam[WB], s_max[4][WB];
+  __shared__ int s_cnt[4][WB];
   const int tid = threadIdx.x;
   const int wv = uniform_i(tid >> 6);
   const int R = a.R, cap = a.cap, nsub = a.nrb * 4;
@@ -434,10 +442,10 @@ long_write_kernel(LongArgs<T> a) {
       nb[k] = (T)(-(row(k) < R ? long_b(t, pv, pmm, row(k), Sm) : 0.0));
       fix[k * LNT + tid] = 0.0;  // each thread touches only its own slots
     }
-    for (int64_t jb = j0; jb < j1; jb += LNT) {
+    for (int64_t jb = j0; jb < j1; jb += WB) {
       // thresholds and this tile's four sub-tile headers of 256 columns
       __syncthreads();  // the previous block's readers are done
-      if (jb + tid < j1) {
+      if (tid < WB && jb + tid < j1) {
         const int64_t jj = jb + tid;
         s_lam[tid] = lamv[jj];
 #pragma unroll
@@ -447,7 +455,7 @@ long_write_kernel(LongArgs<T> a) {
         }
       }
       __syncthreads();
-      const int64_t je = jb + LNT < j1 ? jb + LNT : j1;
+      const int64_t je = jb + WB < j1 ? jb + WB : j1;
     for (int64_t j = jb; j < je; ++j) {
       const double lam = uniform_d(s_lam[j - jb]), lmax = uniform_d(s_max[wv][j - jb]);
       const int n = uniform_i(s_cnt[wv][j - jb]);
@@ -455,26 +463,28 @@ long_write_kernel(LongArgs<T> a) {
       const bool some = lmax > lam;  // some entry of this sub-tile is active
       if (some && n > cap) {
         // more candidates than slots: vector by vector, w from theta and c
+        // (one vector at a time, so this rare path holds few registers)
         const T* __restrict__ cp = long_cost_col(a, j, off_m);
         double z0 = 0.0, z1 = 0.0;
         if (a.gdim) grid_point(a, j, off_m, &z0, &z1);
-#pragma unroll
+#pragma unroll 1
         for (int c = 0; c < NCH; ++c) {
-          const int r0 = row(c * VEC);
+          const int r0 = rbase + (c * LNT + tid) * VEC;
           const int rl = r0 < R ? r0 : rbase;  // rows past R read the tile's first (masked)
           T tv[VEC], out[VEC];
           load_vec<T, VEC>(thp + rl, tv);
 #pragma unroll
           for (int v = 0; v < VEC; ++v) {
-            const int k = c * VEC + v;
-            out[v] = nb[k];
+            out[v] = T(0);  // rows past R are not stored
             if (r0 + v < R) {
               const double bk = long_b(t, pv, pmm, r0 + v, Sm);
+              const T nbk = (T)(-bk);  // the entry's value when inactive (nb of its slot)
               const double cc = a.gdim ? grid_cost(a, r0 + v, z0, z1) : (double)cp[r0 + v];
-              const double w = ((double)tv[v] + 2.0 * bk) - cc * inv_rho;
+              const double w = long_w((double)tv[v], 2.0 * bk, cc, inv_rho);
+              out[v] = nbk;
               if (w > lam) {
                 out[v] = (T)(fmax(w - lam, 0.0) - bk);
-                fix[k * LNT + tid] += (double)out[v] - (double)nb[k];
+                fix[(c * VEC + v) * LNT + tid] += (double)out[v] - (double)nbk;
               }
             }
           }

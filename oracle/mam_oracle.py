@@ -30,6 +30,14 @@ Functions and the passage each follows:
   the objective/feasibility figures used in Sec. 6.3.
 * ``mam_until``  Alg. 1 with one of the stopping tests of Sec. 5 (Stopping
   criteria) evaluated every few iterations in place of "while not converged".
+* ``support_update``  the support step of the fixed-support approach (Sec. 2,
+  the alternation between the LP on a fixed support and the support problem
+  with the plans fixed) in the closed form of the free-support proposition
+  (Prop. 4): each point is the alpha-weighted mean of the measures' points,
+  weighted by the mass the plans carry from it.
+* ``free_support_alternation``  the alternating method of that section
+  (Alg. 2): the cost alpha_m/2 ||xi_r - zeta_s||^2 on the current support,
+  Alg. 1 on it, then the support step on the plans of its last iteration.
 
 Readings where the paper is silent or loose (each is listed in the design doc):
 
@@ -39,7 +47,12 @@ Readings where the paper is silent or loose (each is listed in the design doc):
 * a zero weight q_s = 0 gives the zero column (Remark on Delta_R(tau));
 * when tau is below the rounding resolution of w, the threshold index j* is
   clamped to 1, so the column becomes 0 (the sort formula's own result in
-  floating point, stated explicitly so it never divides by zero).
+  floating point, stated explicitly so it never divides by zero);
+* the plans of the support step are the projections pi_hat^(m) of the last
+  iteration's Step 2 (non-negative, column sums q_s); a point whose row
+  carries no mass keeps its place (the formula's denominator is 0 there);
+* in the alternation, Alg. 1 starts from theta^0 = q_s/R once and each later
+  round continues from the plans of the previous one.
 """
 from __future__ import annotations
 
@@ -64,6 +77,8 @@ __all__ = [
     "mam_until",
     "STOP_TESTS",
     "sq_euclid_cost",
+    "support_update",
+    "free_support_alternation",
 ]
 
 
@@ -377,3 +392,55 @@ def sq_euclid_cost(xi: np.ndarray, zeta: np.ndarray, normalize_max: bool = False
     if normalize_max:
         c = c / c.max()
     return c
+
+
+def support_update(pi: List[np.ndarray], zeta: List[np.ndarray], alpha: Sequence[float],
+                   xi_old: np.ndarray) -> Dict:
+    """The support problem with the plans fixed, solved in closed form
+    (Prop. 4; Sec. 2, the fixed-support approach):
+
+        xi_r = sum_m alpha_m sum_s pi^(m)_rs zeta^(m)_s / sum_m alpha_m sum_s pi^(m)_rs,
+
+    the minimiser of Psi(xi) = sum_m alpha_m sum_{r,s} 1/2 ||xi_r - zeta^(m)_s||^2 pi^(m)_rs.
+    pi[m]: R x S^m plan; zeta[m]: S^m x d points; alpha: M weights; xi_old:
+    R x d.  A row with no mass (denominator 0) keeps xi_old[r].
+    Returns {"xi": R x d, "mass": the denominators (R)}.
+    """
+    xi_old = np.asarray(xi_old, dtype=np.float64)
+    num = np.zeros_like(xi_old)
+    den = np.zeros(xi_old.shape[0])
+    for m in range(len(pi)):
+        P = np.asarray(pi[m], dtype=np.float64)
+        Z = np.asarray(zeta[m], dtype=np.float64)
+        num += alpha[m] * (P @ Z)
+        den += alpha[m] * P.sum(axis=1)
+    xi = xi_old.copy()
+    has = den > 0
+    xi[has] = num[has] / den[has][:, None]
+    return {"xi": xi, "mass": den}
+
+
+def free_support_alternation(xi0: np.ndarray, zeta: List[np.ndarray], q: List[np.ndarray],
+                             alpha: Sequence[float], rho: float, gamma: float = math.inf,
+                             outer: int = 1, inner: int = 1) -> Dict:
+    """The alternating method for the free-support barycenter (Alg. 2; Sec. 2):
+    for k = 0, ..., outer - 1
+        c^(m)_rs = alpha_m * 1/2 ||xi^k_r - zeta^(m)_s||^2   (the cost of (HugeLP) with
+                                                         the weights alpha_m)
+        ``inner`` iterations of Alg. 1 on that support (from theta^0 = q_s/R
+        at k = 0, then from the previous round's plans)
+        xi^{k+1} = support_update(pi_hat of the last iteration).
+    Returns {"xi": the supports xi^1..xi^outer, "p_bar": the barycenter
+    weights of each round, "theta": the final plans}.
+    """
+    xi = np.asarray(xi0, dtype=np.float64)
+    theta = None
+    xis, pbs = [], []
+    for _ in range(outer):
+        cost = [alpha[m] * 0.5 * sq_euclid_cost(xi, zeta[m]) for m in range(len(zeta))]
+        out = mam(cost, q, rho, gamma, inner, theta0=theta)
+        theta = out["theta"]
+        xi = support_update(out["pi_hat"], zeta, alpha, xi)["xi"]
+        xis.append(xi)
+        pbs.append(out["p_bar"])
+    return {"xi": xis, "p_bar": pbs, "theta": theta}

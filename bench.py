@@ -107,6 +107,7 @@ EXTRAS = ("balanced_plain", "unbalanced", "batch", "randomized", "stopping", "fr
 def extra_workloads(torch, mam, inputs, log, only=None):
     """The other workloads of the hot path, timed briefly (informational);
     ``only``: the names (of EXTRAS) to run, all by default."""
+    import numpy as np
     out = {}
     sync = torch.cuda.synchronize
 
@@ -245,6 +246,20 @@ def extra_workloads(torch, mam, inputs, log, only=None):
             s.timing(True)
             s.iterate(5)
             col, n = s.timing_read()
+            s.timing(False)
+            sup = {}
+            if grid:
+                # the support step (Prop. 4): one more iteration, then the
+                # alpha-weighted means of the pixel centres under its plans
+                zt = torch.from_numpy(np.tile(pf.zeta, (pf.M, 1))).cuda()
+                xt = torch.from_numpy(pf.xi.copy()).cuda()
+                al = [1.0 / pf.M] * pf.M
+                s.support_update(al, zt, xt)
+                t_sup = min(timed(lambda: s.support_update(al, zt, xt)) for _ in range(3))
+                sup = {"support_step_ms": t_sup * 1e3, "support_passes_ms": (t_sup - dt) * 1e3,
+                       "support_workspace_GB": s.support_workspace.numel() / 1e9}
+                log(f"free support: support step {t_sup * 1e3:.2f} ms with its iteration, "
+                    f"{(t_sup - dt) * 1e3:.2f} ms for the two passes")
             ws = s.workspace.numel()
             s.close()
             del s
@@ -256,7 +271,7 @@ def extra_workloads(torch, mam, inputs, log, only=None):
                          "column_kernels_ms": col / n, "algorithmic_bytes_per_iter": abf,
                          "column_kernels_GBs": abf / (col / n * 1e-3) / 1e9, "workspace_GB": ws / 1e9,
                          "rows_per_tile": sc["rows_per_tile"], "candidate_slots": sc["candidate_slots"],
-                         "workgroups": sc["workgroups"]}
+                         "workgroups": sc["workgroups"], **sup}
             log(f"free support R={pf.R} T={pf.T} ({mode}): {dt * 1e3:.2f} ms/iter, {pf.R * pf.T / dt:.3e} entries/s, "
                 f"column kernels {col / n:.2f} ms ({abf / (col / n * 1e-3) / 1e9:.0f} GB/s algorithmic)")
         out["free_support_K60_M10_f32"] = res

@@ -283,6 +283,39 @@ mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream);
 mam_status mam_timing_enable(mam_problem* p, int32_t enable);
 mam_status mam_timing_read(mam_problem* p, double* total_ms, int64_t* launches);
 
+/* ---- support step ----------------------------------------------------------
+ * The support problem of the fixed-support approach (Sec. 2: with the plans
+ * fixed, the support points minimise sum_m alpha_m sum_rs ||xi_r - zeta_s||^2 pi_rs)
+ * in the closed form of the free-support proposition (Prop. 4):
+ *   mass_r = sum_m alpha_m sum_s pi^(m)_rs,
+ *   xi_r   = sum_m alpha_m sum_s pi^(m)_rs zeta^(m)_s / mass_r.
+ * mam_support_update first runs one more iteration of Alg. 1 (exactly as
+ * mam_iterate(p, 1, stream) would) and takes as pi^(m) that iteration's
+ * projected plans pi_hat^(m) (Step 2: non-negative, column sums q_s),
+ * rebuilt from the stored theta' as theta' + b^(m); an entry stored as
+ * exactly -b^(m)_r (an inactive one) counts as 0.  A row with mass_r <= 0
+ * keeps its point.  Alternating this call with a cost rebuilt on the new
+ * points (e.g. mam_cost_sq_euclid, scaled by alpha_m/2) is Alg. 2.
+ *
+ *   alpha: host, M doubles, finite and >= 0 (the barycenter weights alpha_m
+ *          of (WB); they are not read from the cost).
+ *   zeta:  device, T x dim doubles: the point of plan column j (measures in
+ *          order, the columns of measure m at its column offset) at j*dim.
+ *   xi:    device, R x dim doubles, row-major; read for rows without mass,
+ *          written for the others.
+ *   mass:  device, R doubles, or NULL.
+ *   dim:   1, 2 or 3.
+ *   ws:    device workspace of mam_support_workspace_bytes(p, dim) bytes
+ *          (256-byte aligned, caller-owned; 0 is returned for invalid input).
+ * Two passes in fixed orders (bitwise reproducible).  Asynchronous on
+ * 'stream'.  Single problems, short and long columns, FP32 and FP64 plans.
+ * Errors: MAM_EINVAL (NULL pointer, dim, alpha, misaligned workspace),
+ * MAM_ENOMEM (workspace NULL or too small), MAM_ESTATE (before mam_init),
+ * MAM_EUNSUPPORTED (batch handles have no such call). */
+size_t mam_support_workspace_bytes(const mam_problem* p, int32_t dim);
+mam_status mam_support_update(mam_problem* p, const double* alpha, const double* zeta, int32_t dim,
+                              double* xi, double* mass, void* ws, size_t bytes, void* stream);
+
 /* ---- reverse mode ----------------------------------------------------------
  * Gradients through the iteration of Alg. 1 (the paper does not treat
  * differentiation; this is the exact derivative of the computed map away

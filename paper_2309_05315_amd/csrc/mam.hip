@@ -23,6 +23,7 @@
 #include "mam.h"
 #include "mam_aux_kernels.hpp"
 #include "mam_dispatch.hpp"
+#include "mam_support.hpp"
 
 namespace {
 
@@ -2056,6 +2057,108 @@ mam_status plan_iterate_bundles(Plan* pl, int64_t iters, const int32_t* seq, hip
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Support step (Prop. 4): chunks of at most C columns of one measure, enough
+// of them for about 8192 workgroups of the partial pass; the workspace holds
+// the chunk tables and the partials.
+// ---------------------------------------------------------------------------
+struct SupportLayout {
+  int64_t C = 0;
+  int nchunks = 0;
+  size_t o_m = 0, o_j0 = 0, o_j1 = 0, o_al = 0, o_part = 0, total = 0;
+};
+
+SupportLayout support_layout(const Prob& p, int dim) {
+  SupportLayout L;
+  const int64_t row_blocks = (p.R + mam::SUP_NT - 1) / mam::SUP_NT;
+  const int64_t want = std::max<int64_t>(p.M, (8192 + row_blocks - 1) / row_blocks);
+  L.C = std::max<int64_t>(64, (p.T + want - 1) / want);
+  int64_t n = 0;
+  for (int64_t m = 0; m < p.M; ++m) n += (p.S[m] + L.C - 1) / L.C;
+  L.nchunks = (int)n;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.o_m = take(n * 4);
+  L.o_j0 = take(n * 8);
+  L.o_j1 = take(n * 8);
+  L.o_al = take(n * 8);
+  L.o_part = take((size_t)n * (dim + 1) * p.R * 8);
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+mam_status launch_support(Plan* pl, const SupportLayout& L, char* ws, int dim, const double* zeta, double* xi,
+                          double* mass, hipStream_t st) {
+  const Prob& p = pl->P[0];
+  mam::SupArgs<T> a;
+  a.theta = static_cast<const T*>(p.theta);
+  a.ld = p.ld;
+  a.R = p.R;
+  a.dim = dim;
+  a.nchunks = L.nchunks;
+  a.ch_m = reinterpret_cast<const int32_t*>(ws + L.o_m);
+  a.ch_j0 = reinterpret_cast<const int64_t*>(ws + L.o_j0);
+  a.ch_j1 = reinterpret_cast<const int64_t*>(ws + L.o_j1);
+  a.alpha = reinterpret_cast<const double*>(ws + L.o_al);
+  a.zeta = zeta;
+  a.p_prev = at<double>(pl, p.o_p_prev);
+  a.pm_prev = at<double>(pl, p.o_pm_prev);
+  a.Sd = at<double>(pl, p.o_Sd);
+  a.t = at<double>(pl, p.o_t);
+  a.partial = reinterpret_cast<double*>(ws + L.o_part);
+  a.xi = xi;
+  a.mass = mass;
+  const unsigned rb = (unsigned)((p.R + mam::SUP_NT - 1) / mam::SUP_NT);
+  hipLaunchKernelGGL(mam::support_partial_kernel<T>, dim3(rb, (unsigned)L.nchunks), dim3(mam::SUP_NT), 0, st, a);
+  LAUNCH_CHECK("support_partial_kernel");
+  hipLaunchKernelGGL(mam::support_final_kernel<T>, dim3((unsigned)((p.R + 255) / 256)), dim3(256), 0, st, a);
+  LAUNCH_CHECK("support_final_kernel");
+  return MAM_OK;
+}
+
+mam_status plan_support_update(Plan* pl, const double* alpha, const double* zeta, int dim, double* xi,
+                               double* mass, void* ws, size_t bytes, hipStream_t st) {
+  if (pl->batch) return fail(MAM_EUNSUPPORTED, "the support step is for single problems");
+  if (!pl->inited) return fail(MAM_ESTATE, "mam_init has not run");
+  if (!alpha || !zeta || !xi) return fail(MAM_EINVAL, "NULL argument");
+  if (dim < 1 || dim > mam::SUP_MAXD) return fail(MAM_EINVAL, "dim must be in [1, %d] (got %d)", mam::SUP_MAXD, dim);
+  const Prob& p = pl->P[0];
+  for (int64_t m = 0; m < p.M; ++m)
+    if (!(alpha[m] >= 0.0) || !std::isfinite(alpha[m]))
+      return fail(MAM_EINVAL, "alpha[%lld] must be finite and >= 0", (long long)m);
+  const SupportLayout L = support_layout(p, dim);
+  if (!ws) return fail(MAM_ENOMEM, "support workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(MAM_EINVAL, "support workspace must be 256-byte aligned");
+  if (bytes < L.total) return fail(MAM_ENOMEM, "support workspace has %zu bytes, needs %zu", bytes, L.total);
+  // one more iteration, keeping the marginals it starts from: its plans
+  // pi_hat = theta' + b are the ones the support step uses
+  TRY(one_iteration(pl, st, 0, nullptr, 0, 1));
+  pl->iters_done += 1;
+  std::vector<int32_t> cm;
+  std::vector<int64_t> cj0, cj1;
+  std::vector<double> cal;
+  for (int64_t m = 0; m < p.M; ++m) {
+    for (int64_t s0 = 0; s0 < p.S[m]; s0 += L.C) {
+      cm.push_back((int32_t)m);
+      cj0.push_back(p.col_off[m] + s0);
+      cj1.push_back(p.col_off[m] + std::min<int64_t>(s0 + L.C, p.S[m]));
+      cal.push_back(alpha[m]);
+    }
+  }
+  char* w = static_cast<char*>(ws);
+  HIP_TRY(hipMemcpyAsync(w + L.o_m, cm.data(), cm.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w + L.o_j0, cj0.data(), cj0.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w + L.o_j1, cj1.data(), cj1.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w + L.o_al, cal.data(), cal.size() * 8, hipMemcpyHostToDevice, st));
+  return pl->dtype == MAM_F32 ? launch_support<float>(pl, L, w, dim, zeta, xi, mass, st)
+                              : launch_support<double>(pl, L, w, dim, zeta, xi, mass, st);
+}
+
 struct mam_problem {
   Plan plan;
 };
@@ -2278,6 +2381,17 @@ mam_status mam_backward(mam_problem* p, const double* grad_p, void* grad_q, void
 }
 
 // ---- randomized variant ----------------------------------------------------
+size_t mam_support_workspace_bytes(const mam_problem* p, int32_t dim) {
+  if (!p || p->plan.P.empty() || dim < 1 || dim > mam::SUP_MAXD) return 0;
+  return support_layout(p->plan.P[0], dim).total;
+}
+
+mam_status mam_support_update(mam_problem* p, const double* alpha, const double* zeta, int32_t dim, double* xi,
+                              double* mass, void* ws, size_t bytes, void* stream) {
+  if (!p) return fail(MAM_EINVAL, "NULL handle");
+  return plan_support_update(&p->plan, alpha, zeta, dim, xi, mass, ws, bytes, static_cast<hipStream_t>(stream));
+}
+
 size_t mam_bundle_workspace_bytes(const mam_problem* p, const int32_t* bundle_of, int32_t nb) {
   if (!p || p->plan.lg.on || bundle_check(&p->plan, bundle_of, nb) != MAM_OK) return 0;
   return bundle_layout(&p->plan, bundle_of, nb, nullptr);

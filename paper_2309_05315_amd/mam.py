@@ -43,7 +43,7 @@ EXPORTED = ["mam_abi_version", "mam_last_error", "mam_create", "mam_set_schedule
             "mam_batch_barycenter", "mam_batch_timing_enable", "mam_batch_timing_read",
             "mam_batch_destroy", "mam_adjoint_workspace_bytes", "mam_record", "mam_backward",
             "mam_bundle_workspace_bytes", "mam_set_bundles", "mam_iterate_bundles",
-            "mam_iterate_until", "mam_set_grid"]
+            "mam_iterate_until", "mam_set_grid", "mam_support_workspace_bytes", "mam_support_update"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmam.so")
 
@@ -144,6 +144,9 @@ def lib() -> ctypes.CDLL:
         "mam_set_bundles": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
         "mam_iterate_bundles": (ctypes.c_int32, [_vp, ctypes.c_int64, _vp, _vp]),
         "mam_set_grid": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
+        "mam_support_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int32]),
+        "mam_support_update": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp,
+                                                ctypes.c_size_t, _vp]),
         "mam_iterate_until": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                                ctypes.c_int64, ctypes.POINTER(StopResult), _vp]),
     }
@@ -320,6 +323,34 @@ class Solver:
         s = np.ascontiguousarray(np.asarray(seq, dtype=np.int32))
         _check(lib().mam_iterate_bundles(self._h, int(s.size), s.ctypes.data_as(_vp), _stream(self.device)),
                "mam_iterate_bundles")
+
+    # -- support step (Prop. 4) ---------------------------------------------
+    def support_update(self, alpha: Sequence[float], zeta: torch.Tensor, xi: torch.Tensor):
+        """Run one more iteration, then move the support points to the
+        alpha-weighted means of the measures' points under that iteration's
+        plans (rows without mass keep theirs).  zeta: (T, dim) float64 on
+        the device, the point of each plan column; xi: (R, dim) float64 on
+        the device, updated in place.  Returns (xi, mass)."""
+        if zeta.dtype != torch.float64 or xi.dtype != torch.float64:
+            raise ValueError("points must be float64")
+        if zeta.dim() != 2 or xi.dim() != 2 or zeta.shape != (self.T, xi.shape[1]) or xi.shape[0] != self.R:
+            raise ValueError(f"zeta must be ({self.T}, dim) and xi ({self.R}, dim)")
+        if not (zeta.is_contiguous() and xi.is_contiguous()):
+            raise ValueError("zeta and xi must be contiguous")
+        dim = int(xi.shape[1])
+        al = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
+        if al.shape != (self.M,):
+            raise ValueError(f"alpha must hold {self.M} weights")
+        n = int(lib().mam_support_workspace_bytes(self._h, dim))
+        if n == 0:
+            raise MAMError(-1, "mam_support_workspace_bytes", f"invalid dimension {dim}")
+        if getattr(self, "support_workspace", None) is None or self.support_workspace.numel() < n:
+            self.support_workspace = torch.empty(n, dtype=torch.uint8, device=self.device)
+        mass = torch.empty(self.R, dtype=torch.float64, device=self.device)
+        _check(lib().mam_support_update(self._h, al.ctypes.data_as(_vp), _ptr(zeta), dim, _ptr(xi), _ptr(mass),
+                                        _ptr(self.support_workspace), self.support_workspace.numel(),
+                                        _stream(self.device)), "mam_support_update")
+        return xi, mass
 
     # -- reverse mode --------------------------------------------------------
     def record(self, iters: int, ckpt_every: int = 0) -> None:

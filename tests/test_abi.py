@@ -238,3 +238,20 @@ def test_grid_cost_validation():
     d, arr = desc(R=12, S=[5], cost_mode=mam.COST_GRID, cost_ncols=5)
     b = ctypes.c_void_p()
     assert L.mam_batch_create(ctypes.byref(b), (mam.Desc * 1)(d), 1) == -6
+
+
+def test_support_step_validation():
+    L = mam.lib()
+    fake = ctypes.c_void_p(0x400000)
+    alpha = (ctypes.c_double * 2)(0.5, 0.5)
+    assert L.mam_support_workspace_bytes(None, 2) == 0
+    assert L.mam_support_update(None, alpha, fake, 2, fake, None, fake, 1 << 20, None) == -1
+    rc, h = create(R=300, S=[40, 17])
+    assert rc == 0
+    assert L.mam_support_workspace_bytes(h, 0) == 0 and L.mam_support_workspace_bytes(h, 4) == 0
+    n1, n2, n3 = (L.mam_support_workspace_bytes(h, d) for d in (1, 2, 3))
+    # chunk tables plus (dim + 1) partial sums per row and chunk
+    # 2 chunks here: each dimension adds 2 * R doubles (up to the 256-byte alignment)
+    assert 0 < n1 < n2 < n3 and n2 - n1 > 2 * 300 * 8 - 256 and n3 - n2 > 2 * 300 * 8 - 256
+    assert L.mam_support_update(h, alpha, fake, 2, fake, None, fake, n2, None) == -7   # no init yet
+    L.mam_destroy(h)

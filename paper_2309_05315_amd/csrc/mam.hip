@@ -2113,8 +2113,13 @@ mam_status launch_support(Plan* pl, const SupportLayout& L, char* ws, int dim, c
   a.partial = reinterpret_cast<double*>(ws + L.o_part);
   a.xi = xi;
   a.mass = mass;
-  const unsigned rb = (unsigned)((p.R + mam::SUP_NT - 1) / mam::SUP_NT);
-  hipLaunchKernelGGL(mam::support_partial_kernel<T>, dim3(rb, (unsigned)L.nchunks), dim3(mam::SUP_NT), 0, st, a);
+  // a 16-byte vector of rows per thread when ld and theta allow it
+  constexpr int V = 16 / sizeof(T);
+  const bool vec = p.ld % V == 0 && reinterpret_cast<uintptr_t>(p.theta) % 16 == 0;
+  const int64_t rows_per_block = (int64_t)mam::SUP_NT * (vec ? V : 1);
+  const dim3 grid((unsigned)((p.R + rows_per_block - 1) / rows_per_block), (unsigned)L.nchunks);
+  if (vec) hipLaunchKernelGGL((mam::support_partial_kernel<T, V>), grid, dim3(mam::SUP_NT), 0, st, a);
+  else hipLaunchKernelGGL((mam::support_partial_kernel<T, 1>), grid, dim3(mam::SUP_NT), 0, st, a);
   LAUNCH_CHECK("support_partial_kernel");
   hipLaunchKernelGGL(mam::support_final_kernel<T>, dim3((unsigned)((p.R + 255) / 256)), dim3(256), 0, st, a);
   LAUNCH_CHECK("support_final_kernel");

@@ -11,15 +11,17 @@
 // inactive one and counts as 0.
 //
 // Two passes, both in fixed orders (bitwise reproducible):
-//   support_partial_kernel  one thread per row, one workgroup per (row block,
-//       chunk of columns of one measure): the chunk's sums of pi_hat and of
-//       pi_hat * zeta_s, streaming theta once (one coalesced load per column);
+//   support_partial_kernel  V rows per thread (one 16-byte vector), one
+//       workgroup per (row block, chunk of columns of one measure): the
+//       chunk's sums of pi_hat and of pi_hat * zeta_s, streaming theta once;
 //   support_final_kernel    per row, the chunks' partials weighted by alpha_m in
 //       chunk order, then the quotient.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "mam_kernels.hpp"
 
 namespace mam {
 
@@ -46,47 +48,72 @@ struct SupArgs {
   double* mass;              // R, or null
 };
 
-template <typename T>
+// V: rows per thread, 1 or one 16-byte vector (4 FP32 or 2 FP64 values; then
+// ld is a multiple of V and theta 16-byte aligned, so a vector never leaves
+// its column's ld entries; rows past R are loaded but not used).
+template <typename T, int V>
 __global__ void __launch_bounds__(SUP_NT) support_partial_kernel(SupArgs<T> a) {
-  const int64_t r = (int64_t)blockIdx.x * SUP_NT + threadIdx.x;
+  constexpr int U = 8;  // columns whose loads are in flight per step
+  const int64_t r0 = ((int64_t)blockIdx.x * SUP_NT + threadIdx.x) * V;
   const int c = blockIdx.y;
-  if (r >= a.R) return;
+  if (r0 >= a.R) return;
   const int m = a.ch_m[c];
   const int64_t j0 = a.ch_j0[c], j1 = a.ch_j1[c];
   const int dim = a.dim;
-  const double b = a.t[0] * (a.p_prev[r] - a.pm_prev[(size_t)m * a.R + r]) / a.Sd[m];
-  const T nb = (T)(-b);
-  double den = 0.0, num[SUP_MAXD] = {0.0, 0.0, 0.0};
-  const T* __restrict__ th = a.theta + r;
+  const double t = a.t[0], Sm = a.Sd[m];
+  const double* __restrict__ pmm = a.pm_prev + (size_t)m * a.R;
+  double b[V];
+  T nb[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const int64_t r = r0 + e < a.R ? r0 + e : r0;
+    b[e] = t * (a.p_prev[r] - pmm[r]) / Sm;
+    nb[e] = (T)(-b[e]);
+  }
+  double den[V], num[V][SUP_MAXD];
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    den[e] = 0.0;
+#pragma unroll
+    for (int k = 0; k < SUP_MAXD; ++k) num[e][k] = 0.0;
+  }
+  const T* __restrict__ th = a.theta + r0;
   const double* __restrict__ z = a.zeta;
-  int64_t j = j0;
-  // eight columns' loads in flight per step
-  for (; j + 8 <= j1; j += 8) {
-    T v[8];
+  auto add = [&](const T (&v)[V], int64_t j) {
+    double zk[SUP_MAXD];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = th[(j + u) * a.ld];
+    for (int k = 0; k < SUP_MAXD; ++k) zk[k] = k < dim ? z[j * dim + k] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const double pi = v[u] == nb ? 0.0 : (double)v[u] + b;
-      den += pi;
+    for (int e = 0; e < V; ++e) {
+      const double pi = v[e] == nb[e] ? 0.0 : (double)v[e] + b[e];
+      den[e] += pi;
 #pragma unroll
       for (int k = 0; k < SUP_MAXD; ++k)
-        if (k < dim) num[k] += pi * z[(j + u) * dim + k];
+        if (k < dim) num[e][k] += pi * zk[k];
     }
+  };
+  int64_t j = j0;
+  for (; j + U <= j1; j += U) {
+    T v[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) load_vec_nt<T, V>(th + (j + u) * a.ld, v[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) add(v[u], j + u);
   }
   for (; j < j1; ++j) {
-    const T v = th[j * a.ld];
-    const double pi = v == nb ? 0.0 : (double)v + b;
-    den += pi;
+    T v[V];
+    load_vec_nt<T, V>(th + j * a.ld, v);
+    add(v, j);
+  }
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    if (r0 + e >= a.R) continue;
+    double* out = a.partial + (size_t)c * (dim + 1) * a.R + r0 + e;
+    out[0] = den[e];
 #pragma unroll
     for (int k = 0; k < SUP_MAXD; ++k)
-      if (k < dim) num[k] += pi * z[j * dim + k];
+      if (k < dim) out[(size_t)(k + 1) * a.R] = num[e][k];
   }
-  double* out = a.partial + (size_t)c * (dim + 1) * a.R;
-  out[r] = den;
-#pragma unroll
-  for (int k = 0; k < SUP_MAXD; ++k)
-    if (k < dim) out[(size_t)(k + 1) * a.R + r] = num[k];
 }
 
 template <typename T>

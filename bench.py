@@ -236,8 +236,12 @@ def extra_workloads(torch, mam, inputs, log, only=None):
         # the long-column path (row tiles, candidate slots, per-column thresholds)
         pf = inputs.free_support(dtype="f32")
         res = {"R": pf.R, "M": pf.M, "T": pf.T, "plans_GB": pf.T * pf.R * 4 / 1e9}
-        for mode, grid in (("stored_cost", False), ("grid_cost", True)):
-            s = mam.solver_for(pf, grid=grid)
+        for mode, grid, sparse in (("stored_cost", False, False), ("grid_cost", True, False),
+                                   ("stored_cost_sparse_store", False, True), ("grid_cost_sparse_store", True, True)):
+            # sparse store: between the iterations of a call the plans are
+            # -b plus the entries above lambda; the timed call ends with the
+            # write-back of all 50 GB
+            s = mam.solver_for(pf, grid=grid, sparse_store=sparse)
             sc = s.schedule()
             s.init()
             s.iterate(3)
@@ -248,7 +252,7 @@ def extra_workloads(torch, mam, inputs, log, only=None):
             col, n = s.timing_read()
             s.timing(False)
             sup = {}
-            if grid:
+            if grid and not sparse:
                 # the support step (Prop. 4): one more iteration, then the
                 # alpha-weighted means of the pixel centres under its plans
                 zt = torch.from_numpy(np.tile(pf.zeta, (pf.M, 1))).cuda()
@@ -264,16 +268,20 @@ def extra_workloads(torch, mam, inputs, log, only=None):
             s.close()
             del s
             torch.cuda.empty_cache()
-            # algorithmic bytes: theta read and written, the distinct cost read
-            # once (none when the kernels form it from the grid), q
+            # algorithmic bytes of a dense iteration: theta read and written, the
+            # distinct cost read once (none when the kernels form it from the
+            # grid), q; the sparse store does not move theta, so no rate is
+            # given for it (its column kernels time excludes the write-back,
+            # its ms_per_iter includes it)
             abf = 4 * (2 * pf.R * pf.T + (0 if grid else pf.R * pf.distinct_cost_columns()) + pf.T)
+            gbs = None if sparse else abf / (col / n * 1e-3) / 1e9
             res[mode] = {"iterations": n_it, "ms_per_iter": dt * 1e3, "plan_entry_updates_per_s": pf.R * pf.T / dt,
                          "column_kernels_ms": col / n, "algorithmic_bytes_per_iter": abf,
-                         "column_kernels_GBs": abf / (col / n * 1e-3) / 1e9, "workspace_GB": ws / 1e9,
+                         "column_kernels_GBs": gbs, "workspace_GB": ws / 1e9,
                          "rows_per_tile": sc["rows_per_tile"], "candidate_slots": sc["candidate_slots"],
                          "workgroups": sc["workgroups"], **sup}
             log(f"free support R={pf.R} T={pf.T} ({mode}): {dt * 1e3:.2f} ms/iter, {pf.R * pf.T / dt:.3e} entries/s, "
-                f"column kernels {col / n:.2f} ms ({abf / (col / n * 1e-3) / 1e9:.0f} GB/s algorithmic)")
+                f"column kernels {col / n:.2f} ms" + (f" ({gbs:.0f} GB/s algorithmic)" if gbs else ""))
         out["free_support_K60_M10_f32"] = res
 
     if want("adjoint"):

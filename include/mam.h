@@ -93,6 +93,23 @@ typedef int32_t mam_status;
                                   balanced mass check is skipped; no reverse
                                   mode; mam_diag.meas_resid reports the excess
                                   max(sum_r pi_hat_rs - q_s, 0). */
+#define MAM_FLAG_SPARSE_STORE 8u /* long columns only (ignored otherwise): between
+                                  the iterations of one call the plans are not
+                                  kept dense.  Every inactive entry of theta'
+                                  equals -b^(m)_r (Step 2 subtracts b from a
+                                  projection that is 0 there), so each
+                                  (column, wave sub-tile) keeps only its
+                                  entries above lambda (at most the candidate
+                                  slots; a sub-tile with more is written dense)
+                                  and each (measure, row) its value -b^(m)_r.
+                                  The write pass then stores a few entries per
+                                  column instead of the whole column, and the
+                                  bound theta is written back once, when
+                                  mam_iterate, mam_iterate_until or
+                                  mam_support_update returns.  Results are
+                                  identical bit for bit; the workspace grows by
+                                  the patch slots (about 8 bytes x candidate
+                                  slots per column and 1024 rows in FP32). */
 
 typedef struct mam_problem mam_problem;
 

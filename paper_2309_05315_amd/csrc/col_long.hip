@@ -11,10 +11,10 @@ LongFns<T> pick_long_vec(int vec) {
   constexpr int VN = VecOf<T>::N;
   if (vec == VN)
     return {&long_scan_kernel<T, VPT, VN, GRID>, &long_threshold_kernel<T, VPT, VN>, &long_write_kernel<T, VPT, VN>,
-            &long_rowsum_kernel<T>};
+            &long_rowsum_kernel<T>, &long_materialize_kernel<T, VPT, VN>};
   if (vec == 1)
     return {&long_scan_kernel<T, VPT, 1, GRID>, &long_threshold_kernel<T, VPT, 1>, &long_write_kernel<T, VPT, 1>,
-            &long_rowsum_kernel<T>};
+            &long_rowsum_kernel<T>, &long_materialize_kernel<T, VPT, 1>};
   return {};
 }
 

@@ -177,6 +177,10 @@ struct LongPlan {
   size_t items_cap = 0;
   size_t o_it_rb = 0, o_it_m = 0, o_it_j0 = 0, o_it_j1 = 0, o_it_poff = 0, o_wg_it = 0;
   size_t o_hmax = 0, o_hcnt = 0, o_crow = 0, o_cw = 0;
+  // sparse store (MAM_FLAG_SPARSE_STORE): patch counts, rows and values per
+  // (column, sub-tile), the two halves of the common values, the parity
+  bool sparse = false;
+  size_t o_pcnt = 0, o_prow = 0, o_pval = 0, o_nbv = 0, o_spar = 0;
 };
 
 struct Plan {
@@ -675,6 +679,15 @@ void build_layout(Plan* pl) {
     lg.o_hcnt = take(nh * 4);
     lg.o_crow = take(nh * (size_t)lg.cap * 4);
     lg.o_cw = take(nh * (size_t)lg.cap * 8);
+    lg.sparse = (pl->P[0].flags & MAM_FLAG_SPARSE_STORE) != 0;
+    if (lg.sparse) {
+      const size_t eb = elem_bytes(pl->dtype);
+      lg.o_pcnt = take(nh * 4);
+      lg.o_prow = take(nh * (size_t)lg.cap * 4);
+      lg.o_pval = take(nh * (size_t)lg.cap * eb);
+      lg.o_nbv = take(2 * (size_t)pl->P[0].M * (size_t)pl->P[0].R * eb);
+      lg.o_spar = take(4);
+    }
   }
   for (Prob& p : pl->P) {
     const size_t R = (size_t)p.R, M = (size_t)p.M;
@@ -1054,6 +1067,14 @@ mam::LongArgs<T> long_args(Plan* pl) {
     a.gh[k] = p.gh[k];
   }
   a.gz = a.gdim ? static_cast<const double*>(p.cost) : nullptr;
+  a.sparse = lg.sparse ? 1 : 0;
+  if (lg.sparse) {
+    a.spar = at<int32_t>(pl, lg.o_spar);
+    a.pcnt = at<int32_t>(pl, lg.o_pcnt);
+    a.prow = at<int32_t>(pl, lg.o_prow);
+    a.pval = at<T>(pl, lg.o_pval);
+    a.nbv = at<T>(pl, lg.o_nbv);
+  }
   return a;
 }
 
@@ -1073,7 +1094,39 @@ mam_status launch_long_columns(Plan* pl, hipStream_t st) {
   LAUNCH_CHECK("long_threshold_kernel");
   hipLaunchKernelGGL(fn.write, dim3(lg.nwg), dim3(mam::LNT), (size_t)lg.vpt * mam::LNT * 8, st, a);
   LAUNCH_CHECK("long_write_kernel");
+  if (lg.sparse) {
+    hipLaunchKernelGGL(mam::long_sparse_flip_kernel, dim3(1), dim3(64), 0, st, a.spar, a.stop);
+    LAUNCH_CHECK("long_sparse_flip_kernel");
+  }
   return MAM_OK;
+}
+
+// Sparse store: every sub-tile dense (after theta^0 is in place), or the
+// stored plans written back into theta (when a call returns).
+template <typename T>
+mam_status long_sparse_reset(Plan* pl, hipStream_t st) {
+  const LongPlan& lg = pl->lg;
+  const int64_t nh = pl->P[0].T * (int64_t)lg.nrb * 4;
+  const int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (nh + 255) / 256));
+  hipLaunchKernelGGL(mam::long_sparse_reset_kernel, dim3(blocks), dim3(256), 0, st, at<int32_t>(pl, lg.o_pcnt), nh,
+                     at<int32_t>(pl, lg.o_spar));
+  LAUNCH_CHECK("long_sparse_reset_kernel");
+  return MAM_OK;
+}
+
+template <typename T>
+mam_status long_writeback(Plan* pl, hipStream_t st) {
+  const LongPlan& lg = pl->lg;
+  mam::LongFns<T> fn = mam::pick_long<T>(lg.vpt, lg.vec, pl->P[0].cost_mode == MAM_COST_GRID);
+  if (!fn.materialize) return fail(MAM_EUNSUPPORTED, "no long-column kernels for vpt=%d vec=%d", lg.vpt, lg.vec);
+  hipLaunchKernelGGL(fn.materialize, dim3(lg.nwg), dim3(mam::LNT), 0, st, long_args<T>(pl));
+  LAUNCH_CHECK("long_materialize_kernel");
+  return MAM_OK;
+}
+
+mam_status sparse_writeback(Plan* pl, hipStream_t st) {
+  if (!pl->lg.on || !pl->lg.sparse || !pl->inited) return MAM_OK;
+  return pl->dtype == MAM_F32 ? long_writeback<float>(pl, st) : long_writeback<double>(pl, st);
 }
 
 template <typename T>
@@ -1258,6 +1311,8 @@ mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
     }
   }
   TRY(pl->dtype == MAM_F32 ? launch_init<float>(pl, theta0, st) : launch_init<double>(pl, theta0, st));
+  if (pl->lg.on && pl->lg.sparse)
+    TRY(pl->dtype == MAM_F32 ? long_sparse_reset<float>(pl, st) : long_sparse_reset<double>(pl, st));
   pl->inited = true;
   pl->default_start = true;
   for (size_t i = 0; i < pl->P.size(); ++i)
@@ -1337,7 +1392,7 @@ mam_status plan_iterate(Plan* pl, int64_t iters, hipStream_t st) {
     if (diag) pl->diag_valid = true;
   }
   pl->iters_done += iters;
-  return MAM_OK;
+  return sparse_writeback(pl, st);
 }
 
 mam_status plan_graph(Plan* pl, int64_t iters) {
@@ -1475,7 +1530,8 @@ mam_status plan_iterate_until(Plan* pl, int64_t max_iters, int test, double tol,
   pl->gate = at<int32_t>(pl, pl->lay.stop);  // StopState.stop is its first member
   const mam_status s = until_run(pl, max_iters, test, tol, every, st, out);
   pl->gate = nullptr;
-  return s;
+  TRY(s);
+  return sparse_writeback(pl, st);
 }
 
 mam_status plan_timing_read(Plan* pl, double* total_ms, int64_t* launches) {
@@ -2144,6 +2200,7 @@ mam_status plan_support_update(Plan* pl, const double* alpha, const double* zeta
   // pi_hat = theta' + b are the ones the support step uses
   TRY(one_iteration(pl, st, 0, nullptr, 0, 1));
   pl->iters_done += 1;
+  TRY(sparse_writeback(pl, st));
   std::vector<int32_t> cm;
   std::vector<int64_t> cj0, cj1;
   std::vector<double> cal;

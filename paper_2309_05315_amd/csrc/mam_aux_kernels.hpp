@@ -516,4 +516,18 @@ grad_cost_kernel(const double* __restrict__ cacc, const int64_t* __restrict__ cp
   }
 }
 
+// Long columns, sparse store (MAM_FLAG_SPARSE_STORE): set-up and parity.
+// Every sub-tile dense (the plans are all in theta) and parity 0.
+__global__ void __launch_bounds__(256) long_sparse_reset_kernel(int32_t* pcnt, int64_t n, int32_t* spar) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) pcnt[i] = -1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) spar[0] = 0;
+}
+
+// After an iteration's write kernel: the stored plans now use the other half
+// of nbv.  Gated like the iteration's other kernels.
+__global__ void long_sparse_flip_kernel(int32_t* spar, const int32_t* stop) {
+  if (stop != nullptr && *stop != 0) return;
+  if (threadIdx.x == 0) spar[0] ^= 1;
+}
+
 }  // namespace mam

@@ -40,6 +40,7 @@ struct LongFns {
   void (*thresh)(LongArgs<T>) = nullptr;
   void (*write)(LongArgs<T>) = nullptr;
   void (*rowsum)(LongArgs<T>, int) = nullptr;
+  void (*materialize)(LongArgs<T>) = nullptr;  // sparse store write-back
 };
 template <typename T>
 LongFns<T> pick_long(int vpt, int vec, bool grid);

@@ -82,6 +82,16 @@ struct LongArgs {
   int32_t gdim, gn1;
   double go[2], gh[2];
   const double* gz;
+  // sparse store (MAM_FLAG_SPARSE_STORE): between iterations the plans are
+  // held per (column, sub-tile) h either as the dense rows in theta
+  // (pcnt[h] < 0) or as pcnt[h] >= 0 patches (row, value) over the value
+  // nbv[par][m][r] that every other entry of measure m's row r holds
+  int32_t sparse, pad1;
+  int32_t* spar;                 // par: which half of nbv holds the stored plans
+  int32_t* pcnt;
+  int32_t* prow;                 // h*cap + e: row of patch e
+  T* pval;                       //            its value
+  T* nbv;                        // 2 x M x R
 };
 
 // Coordinate k of grid index i: origin + i * spacing, each operation rounded
@@ -162,6 +172,49 @@ __device__ __forceinline__ double long_b(double t, const double* p, const double
   return t * (p[r] - pmm[r]) / Sm;
 }
 
+// Thread tt of the tile at rbase owns rows rbase + ((k/VEC)*LNT + tt)*VEC + k%VEC,
+// k < VPT; row offset rr = r - rbase is slot k of thread (rr/VEC) % LNT.
+__device__ __forceinline__ int slot_owner(int rr, int vec) { return (rr / vec) % LNT; }
+__device__ __forceinline__ int slot_of(int rr, int vec) { return (rr / (vec * LNT)) * vec + rr % vec; }
+
+// Sparse store: apply the pc <= cap patches (lane e holds row pr and value
+// pv of patch e) to the values th of thread tt's rows, in patch order.
+template <typename T, int VPT, int VEC>
+__device__ __forceinline__ void apply_patches(int pc, int pr, T pv, int rbase, int tt, T (&th)[VPT]) {
+  for (int e = 0; e < pc; ++e) {
+    const int rr = __builtin_amdgcn_readlane(pr, e) - rbase;
+    const T v = read_lane(pv, e);
+    if (slot_owner(rr, VEC) == tt) {
+      const int k = slot_of(rr, VEC);
+#pragma unroll
+      for (int kk = 0; kk < VPT; ++kk)
+        if (kk == k) th[kk] = v;
+    }
+  }
+}
+
+// The stored plan values of thread tt's rows of the tile at rbase in column j
+// (sub-tile h, measure m), 0 at rows past R: the dense rows, or the
+// measure's common values with the sub-tile's patches.
+template <typename T, int VPT, int VEC>
+__device__ void stored_rows(const LongArgs<T>& a, int64_t j, int64_t h, int rbase, int tt, int m, int par,
+                            T (&th)[VPT]) {
+  const int R = a.R;
+  const int pc = a.sparse ? uniform_i(gptr(a.pcnt)[h]) : -1;
+  const T* __restrict__ src = pc < 0 ? gptr(a.theta) + j * a.ld : gptr(a.nbv) + ((size_t)par * a.M + m) * R;
+#pragma unroll
+  for (int k = 0; k < VPT; ++k) {
+    const int r = rbase + ((k / VEC) * LNT + tt) * VEC + (k % VEC);
+    th[k] = r < R ? src[r] : T(0);
+  }
+  if (pc > 0) {
+    const int lane = threadIdx.x & 63;
+    const int pr = lane < pc ? gptr(a.prow)[h * a.cap + lane] : 0;
+    const T pv = lane < pc ? gptr(a.pval)[h * a.cap + lane] : T(0);
+    apply_patches<T, VPT, VEC>(pc, pr, pv, rbase, tt, th);
+  }
+}
+
 // ---- scan: w, sub-tile maxima, candidates -------------------------------
 // GRID: the cost is formed from the row's grid point and the column's point
 // instead of being read (only theta is streamed).
@@ -182,6 +235,8 @@ long_scan_kernel(LongArgs<T> a) {
   const T* const qv = gptr(a.q);
   int32_t* const crow = gptr(a.crow);
   double* const cw = gptr(a.cw);
+  const bool sparse = a.sparse != 0;
+  const int par = sparse ? uniform_i(*gptr(a.spar)) : 0;
   const int ib = uniform_i(a.wg_it[blockIdx.x]), ie = uniform_i(a.wg_it[blockIdx.x + 1]);
   for (int it = ib; it < ie; ++it) {
     const int rb = uniform_i(a.it_rb[it]), m = uniform_i(a.it_m[it]);
@@ -196,10 +251,13 @@ long_scan_kernel(LongArgs<T> a) {
     // finite), below every threshold, without a select per entry
     double b2[VPT];
     double gx0[GRID ? VPT : 1], gx1[GRID ? VPT : 1];  // grid coordinates of the rows
+    T nbk[VPT];  // sparse store: the stored value of the unpatched entries
+    const T* __restrict__ nbm = sparse ? gptr(a.nbv) + ((size_t)par * a.M + m) * R : nullptr;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       row[k] = rbase + ((k / VEC) * LNT + tid) * VEC + (k % VEC);
       b2[k] = row[k] < R ? 2.0 * long_b(t, pv, pmm, row[k], Sm) : -__builtin_huge_val();
+      nbk[k] = (sparse && row[k] < R) ? nbm[row[k]] : T(0);
       if constexpr (GRID) {
         const int i0 = row[k] / a.gn1;
         gx0[k] = grid_coord(a, 0, i0);
@@ -207,21 +265,38 @@ long_scan_kernel(LongArgs<T> a) {
       }
     }
     // raw theta and c (or the column's point) of the next PF columns in
-    // flight while one is scanned: PF buffers, used in turn
+    // flight while one is scanned: PF buffers, used in turn; with the sparse
+    // store, the column's patch count and lane e's patch instead of theta
+    // when the sub-tile is not dense
     T rt[PF][VPT], rc[PF][GRID ? 1 : VPT], rq[PF];
     double rz[PF][2];
+    int pcs[PF], prs[PF];
+    T pvs[PF];
+    // columns run in blocks: the whole item, or 64 columns with the sparse
+    // store (lane l then holds the patch count of column jlo + l)
+    int64_t jlo = j0, jhi = j1;
+    int pcl = -1;
     auto issue = [&](auto S, int64_t j) {
       constexpr int s = decltype(S)::value;
       const T* __restrict__ thp = theta + j * a.ld;
       rq[s] = qv[j];
       if constexpr (GRID) grid_point(a, j, off_m, &rz[s][0], &rz[s][1]);
+      const int pc = sparse ? __builtin_amdgcn_readlane(pcl, (int)(j - jlo)) : -1;
+      pcs[s] = pc;
+      if (pc >= 0) {
+        const int64_t h = j * nsub + rb * 4 + wv;
+        prs[s] = lane < pc ? gptr(a.prow)[h * cap + lane] : 0;
+        pvs[s] = lane < pc ? gptr(a.pval)[h * cap + lane] : T(0);
+      }
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
         const int r0 = row[c * VEC] < R ? row[c * VEC] : rbase;  // rows past R read the tile's first (masked)
-        T tv[VEC];
-        load_vec_nt<T, VEC>(thp + r0, tv);
+        if (pc < 0) {
+          T tv[VEC];
+          load_vec_nt<T, VEC>(thp + r0, tv);
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) rt[s][c * VEC + v] = tv[v];
+          for (int v = 0; v < VEC; ++v) rt[s][c * VEC + v] = tv[v];
+        }
         if constexpr (!GRID) {
           T cv[VEC];
           load_vec<T, VEC>(long_cost_col(a, j, off_m) + r0, cv);
@@ -235,6 +310,12 @@ long_scan_kernel(LongArgs<T> a) {
     // unconditional loads keep the buffers in place across iterations)
     auto column = [&](auto S, auto NEXT, int64_t j) {
       constexpr int s = decltype(S)::value;
+      if (pcs[s] >= 0) {
+        // sparse store: the common values, then the sub-tile's patches
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) rt[s][k] = nbk[k];
+        apply_patches<T, VPT, VEC>(pcs[s], prs[s], pvs[s], rbase, tid, rt[s]);
+      }
       double w[VPT];
       double mx = -__builtin_huge_val();
       const double z0 = uniform_d(rz[s][0]), z1 = uniform_d(rz[s][1]);
@@ -247,7 +328,7 @@ long_scan_kernel(LongArgs<T> a) {
         mx = fmax(mx, w[k]);
       }
       const double tau = uniform_d((double)rq[s]);
-      if constexpr (decltype(NEXT)::value) issue(S, j + PF < j1 ? j + PF : j1 - 1);
+      if constexpr (decltype(NEXT)::value) issue(S, j + PF < jhi ? j + PF : jhi - 1);
       mx = wave_max(mx);
       const double thr = mx - tau;
       // slots in slot-major order inside the wave: position = candidates of
@@ -278,14 +359,18 @@ long_scan_kernel(LongArgs<T> a) {
     };
     using YES = std::true_type;
     using NO = std::false_type;
-    if (j0 >= j1) continue;
-    // buffer i holds column j + i (clamped to the item's last column)
-    static_for<PF>([&](auto I) { issue(I, j0 + I < j1 ? j0 + I : j1 - 1); });
-    int64_t j = j0;
-    for (; j + PF - 1 < j1; j += PF) static_for<PF>([&](auto I) { column(I, YES{}, j + I); });
-    static_for<PF - 1>([&](auto I) {
-      if (j + I < j1) column(I, NO{}, j + I);
-    });
+    const int64_t jstep = sparse ? 64 : j1 - j0;
+    for (jlo = j0; jlo < j1; jlo += jstep) {
+      jhi = jlo + jstep < j1 ? jlo + jstep : j1;
+      if (sparse) pcl = jlo + lane < jhi ? gptr(a.pcnt)[(jlo + lane) * nsub + rb * 4 + wv] : -1;
+      // buffer i holds column j + i (clamped to the block's last column)
+      static_for<PF>([&](auto I) { issue(I, jlo + I < jhi ? jlo + I : jhi - 1); });
+      int64_t j = jlo;
+      for (; j + PF - 1 < jhi; j += PF) static_for<PF>([&](auto I) { column(I, YES{}, j + I); });
+      static_for<PF - 1>([&](auto I) {
+        if (j + I < jhi) column(I, NO{}, j + I);
+      });
+    }
   }
 }
 
@@ -325,7 +410,7 @@ long_threshold_kernel(LongArgs<T> a) {
   const int64_t off_m = gptr(a.col_off)[m];
   const double* __restrict__ pmm = gptr(a.pm) + (size_t)m * R;
   const double* __restrict__ pv = gptr(a.p);
-  const T* __restrict__ thp = gptr(a.theta) + j * a.ld;
+  const int par = a.sparse ? uniform_i(*gptr(a.spar)) : 0;
   const T* __restrict__ cp = long_cost_col(a, j, off_m);
   double z0 = 0.0, z1 = 0.0;
   if (a.gdim) grid_point(a, j, off_m, &z0, &z1);
@@ -342,10 +427,12 @@ long_threshold_kernel(LongArgs<T> a) {
           if (lane < n) f(cwj[(int64_t)si * cap + lane]);
         } else {
           const int rbase = (si >> 2) * RB, tt = (si & 3) * 64 + lane;
+          T th[VPT];
+          stored_rows<T, VPT, VEC>(a, j, j * nsub + si, rbase, tt, m, par, th);
 #pragma unroll
           for (int k = 0; k < VPT; ++k) {
             const int r = rbase + ((k / VEC) * LNT + tt) * VEC + (k % VEC);
-            if (r < R) f(long_w((double)thp[r], 2.0 * long_b(t, pv, pmm, r, Sm), costv(r), a.inv_rho));
+            if (r < R) f(long_w((double)th[k], 2.0 * long_b(t, pv, pmm, r, Sm), costv(r), a.inv_rho));
           }
         }
       }
@@ -425,6 +512,8 @@ long_write_kernel(LongArgs<T> a) {
   const int32_t* const crow = gptr(a.crow);
   const double* const cw = gptr(a.cw);
   const double* const lamv = gptr(a.lam);
+  const bool sparse = a.sparse != 0;
+  const int par = sparse ? uniform_i(*gptr(a.spar)) : 0;
   const int ib = uniform_i(a.wg_it[blockIdx.x]), ie = uniform_i(a.wg_it[blockIdx.x + 1]);
   for (int it = ib; it < ie; ++it) {
     const int rb = uniform_i(a.it_rb[it]), m = uniform_i(a.it_m[it]);
@@ -442,6 +531,16 @@ long_write_kernel(LongArgs<T> a) {
       nb[k] = (T)(-(row(k) < R ? long_b(t, pv, pmm, row(k), Sm) : 0.0));
       fix[k * LNT + tid] = 0.0;  // each thread touches only its own slots
     }
+    // sparse store: the tile's new common values of measure m, written once
+    // (by the item that starts at the measure's first column) into the half
+    // of nbv the stored plans do not use yet
+    if (sparse && j0 == off_m) {
+      T* __restrict__ nbn = gptr(a.nbv) + ((size_t)(par ^ 1) * a.M + m) * R;
+#pragma unroll
+      for (int k = 0; k < VPT; ++k)
+        if (row(k) < R) nbn[row(k)] = nb[k];
+    }
+    const T* __restrict__ nbo = sparse ? gptr(a.nbv) + ((size_t)par * a.M + m) * R : nullptr;
     for (int64_t jb = j0; jb < j1; jb += WB) {
       // thresholds and this tile's four sub-tile headers of 256 columns
       __syncthreads();  // the previous block's readers are done
@@ -461,18 +560,39 @@ long_write_kernel(LongArgs<T> a) {
       const int n = uniform_i(s_cnt[wv][j - jb]);
       T* __restrict__ thp = theta + j * a.ld;
       const bool some = lmax > lam;  // some entry of this sub-tile is active
+      const int64_t h = j * nsub + sub;
       if (some && n > cap) {
         // more candidates than slots: vector by vector, w from theta and c
-        // (one vector at a time, so this rare path holds few registers)
+        // (one vector at a time, so this rare path holds few registers); the
+        // stored plans of a sparse sub-tile are the common values and its
+        // patches, and the sub-tile is dense in theta afterwards
         const T* __restrict__ cp = long_cost_col(a, j, off_m);
         double z0 = 0.0, z1 = 0.0;
         if (a.gdim) grid_point(a, j, off_m, &z0, &z1);
+        const int pc = sparse ? uniform_i(gptr(a.pcnt)[h]) : -1;
+        const int lane = tid & 63;
+        const int pr = lane < pc ? gptr(a.prow)[h * cap + lane] : 0;
+        const T pvv = lane < pc ? gptr(a.pval)[h * cap + lane] : T(0);
 #pragma unroll 1
         for (int c = 0; c < NCH; ++c) {
           const int r0 = rbase + (c * LNT + tid) * VEC;
           const int rl = r0 < R ? r0 : rbase;  // rows past R read the tile's first (masked)
           T tv[VEC], out[VEC];
-          load_vec<T, VEC>(thp + rl, tv);
+          if (pc < 0) {
+            load_vec<T, VEC>(thp + rl, tv);
+          } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) tv[v] = r0 + v < R ? nbo[r0 + v] : T(0);
+            for (int e = 0; e < pc; ++e) {
+              const int rr = __builtin_amdgcn_readlane(pr, e) - rbase;
+              const T val = read_lane(pvv, e);
+              if (slot_owner(rr, VEC) == tid && slot_of(rr, VEC) / VEC == c) {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v)
+                  if (v == rr % VEC) tv[v] = val;
+              }
+            }
+          }
 #pragma unroll
           for (int v = 0; v < VEC; ++v) {
             out[v] = T(0);  // rows past R are not stored
@@ -496,27 +616,32 @@ long_write_kernel(LongArgs<T> a) {
               if (r0 + v < R) thp[r0 + v] = out[v];
           }
         }
+        if (sparse && lane == 0) gptr(a.pcnt)[h] = -1;
         continue;
       }
+      if (!sparse) {
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const int r0 = row(c * VEC);
-        T out[VEC];
+        for (int c = 0; c < NCH; ++c) {
+          const int r0 = row(c * VEC);
+          T out[VEC];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) out[v] = nb[c * VEC + v];
-        if (r0 + VEC <= R) {
-          store_vec_nt<T, VEC>(thp + r0, out);
-        } else {
+          for (int v = 0; v < VEC; ++v) out[v] = nb[c * VEC + v];
+          if (r0 + VEC <= R) {
+            store_vec_nt<T, VEC>(thp + r0, out);
+          } else {
 #pragma unroll
-          for (int v = 0; v < VEC; ++v)
-            if (r0 + v < R) thp[r0 + v] = out[v];
+            for (int v = 0; v < VEC; ++v)
+              if (r0 + v < R) thp[r0 + v] = out[v];
+          }
         }
+      } else if (!some && (tid & 63) == 0) {
+        gptr(a.pcnt)[h] = 0;  // sparse store: no patch, every entry is -b
       }
       if (some) {
         // the kept entries above lambda (n <= cap <= 64): lane e reads entry
         // e and forms its patch, all at once; then, in entry order, the
-        // owner of each row stores it and adds it to the row sum
-        const int64_t h = j * nsub + sub;
+        // owner of each row stores it (or, with the sparse store, the
+        // patches are kept in slots) and adds it to the row sum
         const int e = tid & 63;
         const double xe = e < n ? cw[h * cap + e] : -__builtin_huge_val();
         const int re = e < n ? crow[h * cap + e] : rbase;
@@ -525,14 +650,22 @@ long_write_kernel(LongArgs<T> a) {
         const T val = (T)(fmax(xe - lam, 0.0) - bk);
         const double dfix = (double)val - (double)(T)(-bk);
         unsigned long long sel = __ballot(keep);
+        if (sparse) {
+          const int pos = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(sel >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((unsigned)sel, 0u));
+          if (keep) {
+            gptr(a.prow)[h * cap + pos] = re;
+            gptr(a.pval)[h * cap + pos] = val;
+          }
+          if (e == 0) gptr(a.pcnt)[h] = __popcll(sel);
+        }
         while (sel != 0ull) {
           const int l = __builtin_ctzll(sel);
           sel &= sel - 1ull;
           const int rr = __builtin_amdgcn_readlane(re, l) - rbase;
-          if ((rr / VEC) % LNT == tid) {
-            thp[rbase + rr] = read_lane(val, l);
-            const int k = (rr / (VEC * LNT)) * VEC + rr % VEC;
-            fix[k * LNT + tid] += read_lane(dfix, l);
+          if (slot_owner(rr, VEC) == tid) {
+            if (!sparse) thp[rbase + rr] = read_lane(val, l);
+            fix[slot_of(rr, VEC) * LNT + tid] += read_lane(dfix, l);
           }
         }
       }
@@ -559,6 +692,64 @@ long_rowsum_kernel(LongArgs<T> a, int rows_per_tile) {
       double s = 0.0;
       for (int64_t j = a.it_j0[it]; j < a.it_j1[it]; ++j) s += (double)a.theta[j * a.ld + r];
       a.partial[a.it_poff[it] + (r - rbase)] = s;
+    }
+  }
+}
+
+// ---- sparse store: write-back --------------------------------------------
+// Write the stored plans back into theta: every sparse sub-tile is stored as
+// its common values (whole vectors) and then its patches (each by the thread
+// owning the row, after its own store), and marked dense.
+template <typename T, int VPT, int VEC>
+__global__ void __launch_bounds__(LNT)
+long_materialize_kernel(LongArgs<T> a) {
+  constexpr int NCH = VPT / VEC, RB = LNT * VPT;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = uniform_i(tid >> 6);
+  const int R = a.R, cap = a.cap, nsub = a.nrb * 4;
+  const int par = uniform_i(*gptr(a.spar));
+  T* const theta = gptr(a.theta);
+  const int ib = uniform_i(a.wg_it[blockIdx.x]), ie = uniform_i(a.wg_it[blockIdx.x + 1]);
+  for (int it = ib; it < ie; ++it) {
+    const int rb = uniform_i(a.it_rb[it]), m = uniform_i(a.it_m[it]);
+    const int64_t j0 = uniform_l(a.it_j0[it]), j1 = uniform_l(a.it_j1[it]);
+    const int rbase = rb * RB;
+    const T* __restrict__ nbm = gptr(a.nbv) + ((size_t)par * a.M + m) * R;
+    T nb[VPT];
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int r = rbase + ((k / VEC) * LNT + tid) * VEC + (k % VEC);
+      nb[k] = r < R ? nbm[r] : T(0);
+    }
+    for (int64_t j = j0; j < j1; ++j) {
+      const int64_t h = j * nsub + rb * 4 + wv;
+      const int pc = uniform_i(gptr(a.pcnt)[h]);
+      if (pc < 0) continue;
+      T* __restrict__ thp = theta + j * a.ld;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int r0 = rbase + (c * LNT + tid) * VEC;
+        T out[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) out[v] = nb[c * VEC + v];
+        if (r0 + VEC <= R) {
+          store_vec_nt<T, VEC>(thp + r0, out);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v)
+            if (r0 + v < R) thp[r0 + v] = out[v];
+        }
+      }
+      if (pc > 0) {
+        const int pr = lane < pc ? gptr(a.prow)[h * cap + lane] : 0;
+        const T pvv = lane < pc ? gptr(a.pval)[h * cap + lane] : T(0);
+        for (int e = 0; e < pc; ++e) {
+          const int r = __builtin_amdgcn_readlane(pr, e);
+          const T val = read_lane(pvv, e);
+          if (slot_owner(r - rbase, VEC) == tid) thp[r] = val;
+        }
+      }
+      if (lane == 0) gptr(a.pcnt)[h] = -1;
     }
   }
 }

@@ -19,12 +19,12 @@ import numpy as np
 import torch
 
 __all__ = ["lib", "MAMError", "Solver", "Batch", "solver_for", "cost_sq_euclid",
-           "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "COST_GRID", "FLAG_DIAG", "FLAG_COLD", "FLAG_RELAXED",
+           "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "COST_GRID", "FLAG_DIAG", "FLAG_COLD", "FLAG_RELAXED", "FLAG_SPARSE_STORE",
            "STOP_TESTS", "EXPORTED"]
 
 F32, F64 = 0, 1
 COST_PER_COLUMN, COST_SHARED, COST_INDEXED, COST_GRID = 0, 1, 2, 3
-FLAG_DIAG, FLAG_COLD, FLAG_RELAXED = 1, 2, 4
+FLAG_DIAG, FLAG_COLD, FLAG_RELAXED, FLAG_SPARSE_STORE = 1, 2, 4, 8
 # stopping tests of Sec. 5 (MAM_STOP_*)
 STOP_TESTS = {"dtheta": 0, "dp": 1, "dist": 2}
 
@@ -187,7 +187,7 @@ class Solver:
                  dtype: torch.dtype = torch.float32, cost_mode: int = COST_SHARED,
                  cost_ncols: Optional[int] = None, ld: Optional[int] = None,
                  cost_ld: Optional[int] = None, diag: bool = False, cold: bool = False,
-                 relaxed: bool = False,
+                 relaxed: bool = False, sparse_store: bool = False,
                  threads_per_column: int = 0, columns_in_flight: int = 0,
                  workgroups: int = 0, xcd_remap: int = 0, order: int = 0, streaming: int = 0,
                  rows_per_tile: int = 0, candidate_slots: int = 0, device="cuda"):
@@ -207,7 +207,8 @@ class Solver:
         d = Desc(dtype=F32 if dtype == torch.float32 else F64, cost_mode=cost_mode,
                  R=self.R, M=self.M, S=self._S_arr, ld=self.ld, cost_ld=self.cost_ld,
                  cost_ncols=self.cost_ncols, rho=float(rho), gamma=float(gamma),
-                 flags=(FLAG_DIAG if diag else 0) | (FLAG_COLD if cold else 0) | (FLAG_RELAXED if relaxed else 0))
+                 flags=(FLAG_DIAG if diag else 0) | (FLAG_COLD if cold else 0) | (FLAG_RELAXED if relaxed else 0)
+                 | (FLAG_SPARSE_STORE if sparse_store else 0))
         h = _vp()
         _check(L.mam_create(ctypes.byref(h), ctypes.byref(d)), "mam_create")
         self._h = h
@@ -392,8 +393,10 @@ class Solver:
 
 
 def solver_for(problem, device="cuda", diag: bool = False, cold: bool = False, relaxed: bool = False,
-               grid: bool = False, **sched) -> Solver:
+               sparse_store: bool = False, grid: bool = False, **sched) -> Solver:
     """Allocate device buffers for an ``inputs.Problem`` and bind them
+    (sparse_store: on long columns, keep the plans as -b plus the active
+    entries between the iterations of a call, MAM_FLAG_SPARSE_STORE)
     (relaxed: measure constraints sum_r pi_rs <= q_s, with the problem's
     cost taken as the shifted c - eta; grid: a problem whose support is a
     regular grid (meta["grid"]) forms its cost in the kernels from the
@@ -409,7 +412,8 @@ def solver_for(problem, device="cuda", diag: bool = False, cold: bool = False, r
     else:
         mode = COST_INDEXED
     s = Solver(problem.R, problem.S, rho=problem.rho, gamma=problem.gamma, dtype=dt,
-               cost_mode=mode, cost_ncols=ncols, diag=diag, cold=cold, relaxed=relaxed, device=device, **sched)
+               cost_mode=mode, cost_ncols=ncols, diag=diag, cold=cold, relaxed=relaxed,
+               sparse_store=sparse_store, device=device, **sched)
     if grid:
         n, origin, spacing = problem.meta["grid"]
         s.set_grid(n, origin, spacing)

@@ -127,8 +127,8 @@ def test_batch_of_256_full_size_sampled_problems():
         assert e <= 1e-5
 
 
-@pytest.mark.parametrize("grid", [False, True])
-def test_free_support_full_size_sampled_columns(grid):
+@pytest.mark.parametrize("grid,sparse", [(False, False), (True, False), (True, True)])
+def test_free_support_full_size_sampled_columns(grid, sparse):
     """Free-support barycenter of 10 nested-ellipse 60x60 images: the R =
     349,281 support points of Theorem c, T = 36,000 columns, 50 GB of FP32
     plans, default long-column schedule.  theta^6 columns from the GPU's
@@ -138,10 +138,12 @@ def test_free_support_full_size_sampled_columns(grid):
     twice as far as w, which the tolerance allows; with grid = True the
     kernels form the cost from the grid in the oracle's operation order, so
     the two costs are the same).  The marginal of measure 0 is checked
-    against a plain FP64 sum of its 3,600 columns."""
+    against a plain FP64 sum of its 3,600 columns.  With the sparse store the
+    plans live as -b plus patches between the iterations of each call and are
+    written back when it returns."""
     p = inputs.free_support(dtype="f32")
-    say(f"{p.name}: R={p.R} M={p.M} T={p.T} grid cost {grid}")
-    s = mam.solver_for(p, grid=grid)
+    say(f"{p.name}: R={p.R} M={p.M} T={p.T} grid cost {grid} sparse store {sparse}")
+    s = mam.solver_for(p, grid=grid, sparse_store=sparse)
     sc = s.schedule()
     say(f"schedule {sc}")
     assert sc["rows_per_tile"] > 0

@@ -184,3 +184,75 @@ def test_grid_cost_equals_stored_cost(dtype, rows):
     for x, y in zip(a.plans(), b.plans()):
         np.testing.assert_array_equal(x, y)
     np.testing.assert_array_equal(a.barycenter().cpu().numpy(), b.barycenter().cpu().numpy())
+
+
+SPARSE_CASES = [
+    ("f64 three tiles", lambda: inputs.tiny_problem(11, R=3000, S=[40, 25, 33], dtype="f64", rho=1.0),
+     dict(rows_per_tile=1024)),
+    ("f32 one row past two tiles", lambda: inputs.tiny_problem(12, R=2049, S=[17, 30], dtype="f32"),
+     dict(rows_per_tile=1024)),
+    ("overflowing sub-tiles", lambda: inputs.tiny_problem(13, R=2600, S=[24, 18], rho=200.0),
+     dict(rows_per_tile=1024, candidate_slots=1)),
+    ("unbalanced", lambda: inputs.tiny_problem(12, R=2200, S=[30, 22, 15], masses=[0.6, 1.0, 1.5], gamma=0.02),
+     dict(rows_per_tile=1024)),
+    ("grid cost f32", lambda: inputs.free_support(seed=4, K=10, M=4, dtype="f32"),
+     dict(rows_per_tile=1024, grid=True)),
+    ("grid cost f64, 16 values per thread", lambda: inputs.free_support(seed=5, K=12, M=3, dtype="f64"),
+     dict(rows_per_tile=4096, grid=True)),
+    ("automatic above 8192 rows", lambda: inputs.tiny_problem(16, R=8193, S=[9, 14], dtype="f32"), {}),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SPARSE_CASES)))
+def test_sparse_store_equals_dense(case):
+    """The sparse store (plans held as -b plus the entries above lambda between
+    the iterations of a call) gives the dense path's plans, marginals and
+    barycenter bit for bit after every call: plain runs, graph replay, a run
+    with a stopping test, a re-initialisation and the support step."""
+    name, gen, sched = SPARSE_CASES[case]
+    p = gen()
+    say(f"case sparse store: {name} R={p.R} S={p.S} {p.dtype} sched={sched}")
+    sd = mam.solver_for(p, **sched)
+    ss = mam.solver_for(p, sparse_store=True, **sched)
+    assert ss.schedule()["rows_per_tile"] > 0
+
+    def same(tag):
+        for x, y in zip(sd.plans(), ss.plans()):
+            np.testing.assert_array_equal(x, y, err_msg=tag)
+        np.testing.assert_array_equal(sd.marginals().cpu().numpy(), ss.marginals().cpu().numpy(), err_msg=tag)
+        np.testing.assert_array_equal(sd.barycenter().cpu().numpy(), ss.barycenter().cpu().numpy(), err_msg=tag)
+
+    for s in (sd, ss):
+        s.init()
+        s.iterate(7)
+    same("after 7 iterations")
+    for s in (sd, ss):
+        s.iterate(1)
+        s.iterate(0)
+    same("after 1 + 0 more")
+    for s in (sd, ss):
+        s.graph(3)
+        s.iterate(7)
+        s.graph(0)
+    same("after 7 with graph replay")
+    rd = sd.iterate_until(12, "dp", -1.0, 5)
+    rs = ss.iterate_until(12, "dp", -1.0, 5)
+    assert rd == rs
+    same("after a run with a stopping test")
+    for s in (sd, ss):
+        s.init()
+        s.iterate(3)
+    same("after a re-initialisation")
+    rng = np.random.default_rng(0)
+    zeta = torch.from_numpy(rng.normal(size=(p.T, 2))).cuda()
+    xi0 = rng.normal(size=(p.R, 2))
+    out = [s.support_update([1.0 / p.M] * p.M, zeta, torch.from_numpy(xi0.copy()).cuda()) for s in (sd, ss)]
+    np.testing.assert_array_equal(out[0][0].cpu().numpy(), out[1][0].cpu().numpy())
+    np.testing.assert_array_equal(out[0][1].cpu().numpy(), out[1][1].cpu().numpy())
+    same("after the support step")
+    # and against the oracle: a fresh start, 3 iterations and the support
+    # step's own iteration
+    cost, q = blocks(p)
+    ora = O.mam(cost, q, p.rho, p.gamma, 4)
+    pb = ss.barycenter().cpu().numpy()
+    assert rel(pb, ora["p_bar"]) <= TOL[p.dtype]

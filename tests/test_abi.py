@@ -35,7 +35,7 @@ def desc(**kw):
     d = mam.Desc(dtype=kw.pop("dtype", mam.F64), cost_mode=kw.pop("cost_mode", mam.COST_PER_COLUMN),
                  R=kw.pop("R", 16), M=len(S), S=arr, ld=kw.pop("ld", 0), cost_ld=kw.pop("cost_ld", 0),
                  cost_ncols=kw.pop("cost_ncols", sum(S)), rho=kw.pop("rho", 1.0),
-                 gamma=kw.pop("gamma", math.inf), flags=0)
+                 gamma=kw.pop("gamma", math.inf), flags=kw.pop("flags", 0))
     assert not kw
     return d, arr
 
@@ -255,3 +255,23 @@ def test_support_step_validation():
     assert 0 < n1 < n2 < n3 and n2 - n1 > 2 * 300 * 8 - 256 and n3 - n2 > 2 * 300 * 8 - 256
     assert L.mam_support_update(h, alpha, fake, 2, fake, None, fake, n2, None) == -7   # no init yet
     L.mam_destroy(h)
+
+
+def test_sparse_store_workspace():
+    """The sparse store adds, on long columns only, the patch slots (a count,
+    and per slot a row and a value) per (column, sub-tile) and two halves of
+    the common values per (measure, row)."""
+    L = mam.lib()
+    sizes = {}
+    for R in (300, 10000):
+        for fl in (0, mam.FLAG_SPARSE_STORE):
+            rc, h = create(R=R, S=[30, 20], flags=fl)
+            assert rc == 0
+            sizes[R, fl] = L.mam_workspace_bytes(h)
+            L.mam_destroy(h)
+    assert sizes[300, 0] == sizes[300, mam.FLAG_SPARSE_STORE]
+    # R = 10000 in FP64: 2048-row tiles, 5 tiles of 4 sub-tiles, 64 slots
+    nh = 50 * 5 * 4
+    extra = nh * 4 + nh * 64 * (4 + 8) + 2 * 2 * 10000 * 8 + 4
+    grown = sizes[10000, mam.FLAG_SPARSE_STORE] - sizes[10000, 0]
+    assert extra <= grown <= extra + 5 * 256

@@ -83,9 +83,10 @@ struct LongArgs {
   double go[2], gh[2];
   const double* gz;
   // sparse store (MAM_FLAG_SPARSE_STORE): between iterations the plans are
-  // held per (column, sub-tile) h either as the dense rows in theta
-  // (pcnt[h] < 0) or as pcnt[h] >= 0 patches (row, value) over the value
-  // nbv[par][m][r] that every other entry of measure m's row r holds
+  // held per (column j, sub-tile s) either as the dense rows in theta
+  // (pcnt[s*T + j] < 0) or as pcnt[s*T + j] >= 0 patches (row, value), in
+  // slots h*cap + e with h = j*nsub + s, over the value nbv[par][m][r] that
+  // every other entry of measure m's row r holds
   int32_t sparse, pad1;
   int32_t* spar;                 // par: which half of nbv holds the stored plans
   int32_t* pcnt;
@@ -194,13 +195,14 @@ __device__ __forceinline__ void apply_patches(int pc, int pr, T pv, int rbase, i
 }
 
 // The stored plan values of thread tt's rows of the tile at rbase in column j
-// (sub-tile h, measure m), 0 at rows past R: the dense rows, or the
+// (sub-tile si, measure m), 0 at rows past R: the dense rows, or the
 // measure's common values with the sub-tile's patches.
 template <typename T, int VPT, int VEC>
-__device__ void stored_rows(const LongArgs<T>& a, int64_t j, int64_t h, int rbase, int tt, int m, int par,
+__device__ void stored_rows(const LongArgs<T>& a, int64_t j, int si, int rbase, int tt, int m, int par,
                             T (&th)[VPT]) {
   const int R = a.R;
-  const int pc = a.sparse ? uniform_i(gptr(a.pcnt)[h]) : -1;
+  const int64_t h = j * (a.nrb * 4) + si;
+  const int pc = a.sparse ? uniform_i(gptr(a.pcnt)[(int64_t)si * a.T_cols + j]) : -1;
   const T* __restrict__ src = pc < 0 ? gptr(a.theta) + j * a.ld : gptr(a.nbv) + ((size_t)par * a.M + m) * R;
 #pragma unroll
   for (int k = 0; k < VPT; ++k) {
@@ -362,7 +364,7 @@ long_scan_kernel(LongArgs<T> a) {
     const int64_t jstep = sparse ? 64 : j1 - j0;
     for (jlo = j0; jlo < j1; jlo += jstep) {
       jhi = jlo + jstep < j1 ? jlo + jstep : j1;
-      if (sparse) pcl = jlo + lane < jhi ? gptr(a.pcnt)[(jlo + lane) * nsub + rb * 4 + wv] : -1;
+      if (sparse) pcl = jlo + lane < jhi ? gptr(a.pcnt)[(int64_t)(rb * 4 + wv) * a.T_cols + jlo + lane] : -1;
       // buffer i holds column j + i (clamped to the block's last column)
       static_for<PF>([&](auto I) { issue(I, jlo + I < jhi ? jlo + I : jhi - 1); });
       int64_t j = jlo;
@@ -428,7 +430,7 @@ long_threshold_kernel(LongArgs<T> a) {
         } else {
           const int rbase = (si >> 2) * RB, tt = (si & 3) * 64 + lane;
           T th[VPT];
-          stored_rows<T, VPT, VEC>(a, j, j * nsub + si, rbase, tt, m, par, th);
+          stored_rows<T, VPT, VEC>(a, j, si, rbase, tt, m, par, th);
 #pragma unroll
           for (int k = 0; k < VPT; ++k) {
             const int r = rbase + ((k / VEC) * LNT + tt) * VEC + (k % VEC);
@@ -555,12 +557,13 @@ long_write_kernel(LongArgs<T> a) {
       }
       __syncthreads();
       const int64_t je = jb + WB < j1 ? jb + WB : j1;
-    for (int64_t j = jb; j < je; ++j) {
+    auto column = [&](int64_t j) {
       const double lam = uniform_d(s_lam[j - jb]), lmax = uniform_d(s_max[wv][j - jb]);
       const int n = uniform_i(s_cnt[wv][j - jb]);
       T* __restrict__ thp = theta + j * a.ld;
       const bool some = lmax > lam;  // some entry of this sub-tile is active
       const int64_t h = j * nsub + sub;
+      int32_t* const pcj = sparse ? gptr(a.pcnt) + (int64_t)sub * a.T_cols + j : nullptr;
       if (some && n > cap) {
         // more candidates than slots: vector by vector, w from theta and c
         // (one vector at a time, so this rare path holds few registers); the
@@ -569,7 +572,7 @@ long_write_kernel(LongArgs<T> a) {
         const T* __restrict__ cp = long_cost_col(a, j, off_m);
         double z0 = 0.0, z1 = 0.0;
         if (a.gdim) grid_point(a, j, off_m, &z0, &z1);
-        const int pc = sparse ? uniform_i(gptr(a.pcnt)[h]) : -1;
+        const int pc = sparse ? uniform_i(*pcj) : -1;
         const int lane = tid & 63;
         const int pr = lane < pc ? gptr(a.prow)[h * cap + lane] : 0;
         const T pvv = lane < pc ? gptr(a.pval)[h * cap + lane] : T(0);
@@ -616,8 +619,8 @@ long_write_kernel(LongArgs<T> a) {
               if (r0 + v < R) thp[r0 + v] = out[v];
           }
         }
-        if (sparse && lane == 0) gptr(a.pcnt)[h] = -1;
-        continue;
+        if (sparse && lane == 0) *pcj = -1;
+        return;
       }
       if (!sparse) {
 #pragma unroll
@@ -634,8 +637,6 @@ long_write_kernel(LongArgs<T> a) {
               if (r0 + v < R) thp[r0 + v] = out[v];
           }
         }
-      } else if (!some && (tid & 63) == 0) {
-        gptr(a.pcnt)[h] = 0;  // sparse store: no patch, every entry is -b
       }
       if (some) {
         // the kept entries above lambda (n <= cap <= 64): lane e reads entry
@@ -657,7 +658,7 @@ long_write_kernel(LongArgs<T> a) {
             gptr(a.prow)[h * cap + pos] = re;
             gptr(a.pval)[h * cap + pos] = val;
           }
-          if (e == 0) gptr(a.pcnt)[h] = __popcll(sel);
+          if (e == 0) *pcj = __popcll(sel);
         }
         while (sel != 0ull) {
           const int l = __builtin_ctzll(sel);
@@ -669,7 +670,26 @@ long_write_kernel(LongArgs<T> a) {
           }
         }
       }
-    }
+    };
+      if (sparse) {
+        // sparse store: only columns whose sub-tile has an active entry need
+        // work; the others get a patch count of 0, 64 columns at a time
+        const int lane = tid & 63;
+        for (int64_t c0 = jb; c0 < je; c0 += 64) {
+          const int64_t jl = c0 + lane;
+          const bool in = jl < je;
+          const bool act = in && s_max[wv][in ? jl - jb : 0] > s_lam[in ? jl - jb : 0];
+          if (in && !act) gptr(a.pcnt)[(int64_t)sub * a.T_cols + jl] = 0;
+          unsigned long long am = __ballot(act);
+          while (am != 0ull) {
+            const int64_t j = c0 + __builtin_ctzll(am);
+            am &= am - 1ull;
+            column(j);
+          }
+        }
+      } else {
+        for (int64_t j = jb; j < je; ++j) column(j);
+      }
     }
     // the item's row sums: (#columns) * (-b) plus the patches
     const double ncols = (double)(j1 - j0);
@@ -723,7 +743,8 @@ long_materialize_kernel(LongArgs<T> a) {
     }
     for (int64_t j = j0; j < j1; ++j) {
       const int64_t h = j * nsub + rb * 4 + wv;
-      const int pc = uniform_i(gptr(a.pcnt)[h]);
+      int32_t* const pcj = gptr(a.pcnt) + (int64_t)(rb * 4 + wv) * a.T_cols + j;
+      const int pc = uniform_i(*pcj);
       if (pc < 0) continue;
       T* __restrict__ thp = theta + j * a.ld;
 #pragma unroll
@@ -749,7 +770,7 @@ long_materialize_kernel(LongArgs<T> a) {
           if (slot_owner(r - rbase, VEC) == tid) thp[r] = val;
         }
       }
-      if (lane == 0) gptr(a.pcnt)[h] = -1;
+      if (lane == 0) *pcj = -1;
     }
   }
 }

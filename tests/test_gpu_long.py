@@ -7,6 +7,7 @@ in seconds; R > 8192 takes it automatically.  A tiny candidate capacity
 forces the fallback that recomputes a column from theta and c.  Tolerances
 as for the short path: 1e-10 (FP64 plans) and 1e-5 (FP32 plans) relative.
 """
+import dataclasses
 import math
 import sys
 
@@ -200,7 +201,15 @@ SPARSE_CASES = [
     ("grid cost f64, 16 values per thread", lambda: inputs.free_support(seed=5, K=12, M=3, dtype="f64"),
      dict(rows_per_tile=4096, grid=True)),
     ("automatic above 8192 rows", lambda: inputs.tiny_problem(16, R=8193, S=[9, 14], dtype="f32"), {}),
+    ("relaxed measure constraints", lambda: shifted(
+        inputs.tiny_problem(32, R=2300, S=[30, 22], masses=[0.8, 1.2], gamma=0.1), 0.0002),
+     dict(rows_per_tile=1024, relaxed=True)),
 ]
+
+
+def shifted(p, eta):
+    """The relaxed extension's distances d = c - eta (FP64 problem)."""
+    return dataclasses.replace(p, cost=p.cost - eta)
 
 
 @pytest.mark.parametrize("case", range(len(SPARSE_CASES)))
@@ -253,6 +262,6 @@ def test_sparse_store_equals_dense(case):
     # and against the oracle: a fresh start, 3 iterations and the support
     # step's own iteration
     cost, q = blocks(p)
-    ora = O.mam(cost, q, p.rho, p.gamma, 4)
+    ora = O.mam(cost, q, p.rho, p.gamma, 4, relaxed=sched.get("relaxed", False))
     pb = ss.barycenter().cpu().numpy()
     assert rel(pb, ora["p_bar"]) <= TOL[p.dtype]

@@ -39,7 +39,7 @@ Functions and the passage each follows:
   (Alg. 2): the cost alpha_m/2 ||xi_r - zeta_s||^2 on the current support,
   Alg. 1 on it, then the support step on the plans of its last iteration.
 
-Readings where the paper is silent or loose (each is listed in the design doc):
+Readings where the paper is silent or loose:
 
 * theta^0_rs = q_s / R (Alg. 1 leaves theta^0 arbitrary);
 * the returned barycenter is sum_m a_m p^(m) of the final theta^K (Alg. 1

@@ -25,6 +25,7 @@ sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -86,6 +87,22 @@ def run_gpu(p, steps, warmup, torch, mam):
     return dt, pbar, col_ms / max(n, 1), n, sched
 
 
+def final_state(p, iters, torch, mam):
+    """The state the timed run reached, recomputed untimed with diagnostics
+    on its last iteration: objective W_hat = sum c pi_hat, dist_L (the
+    marginals' distance to agreement), the measure-constraint residual, the
+    threshold passes and active entries per column."""
+    s = mam.solver_for(p, device="cuda:0", diag=True)
+    s.init()
+    s.iterate(iters)
+    d = s.diagnostics()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return {k: d[k] for k in ("iterations", "W_hat", "dist_L", "meas_resid", "dtheta_inf",
+                              "rounds_per_column", "active_per_column")}
+
+
 def cpu_baseline(p, n_measures):
     import numpy as np
     from oracle import mam_oracle as O
@@ -101,7 +118,8 @@ def cpu_baseline(p, n_measures):
                       f"({entries:.3e} plan entries, {dt:.1f} s, single thread)"}
 
 
-EXTRAS = ("balanced_plain", "unbalanced", "batch", "randomized", "stopping", "free_support", "adjoint")
+EXTRAS = ("balanced_plain", "unbalanced", "batch", "randomized", "stopping", "free_support", "adjoint",
+          "large_rho")
 
 
 def extra_workloads(torch, mam, inputs, log, only=None):
@@ -322,6 +340,29 @@ def extra_workloads(torch, mam, inputs, log, only=None):
                                           "unit": "GB/s", "frac": abytes / (us * 1e-6) / 1e9 / PEAK_HBM_GBS}
         out["adjoint_K64_M8_f32"] = res
 
+    if want("large_rho"):
+        # the benchmark workload at rho = R * mean(S^m): the cost term c/rho is
+        # tiny next to theta, so active sets are large and the threshold search
+        # does more passes (the regime where the candidate filter matters least)
+        pr = inputs.balanced_sparse(dtype="f32")
+        pr = dataclasses.replace(pr, rho=float(pr.R * np.mean(pr.S)))
+        s = mam.solver_for(pr)
+        s.init()
+        s.iterate(10)
+        n_it = 100
+        dt = timed(lambda: s.iterate(n_it)) / n_it
+        s.timing(True)
+        s.iterate(50)
+        col, n = s.timing_read()
+        s.close()
+        d = final_state(pr, 160, torch, mam)
+        out["large_rho_K64_M32_f32"] = {"rho": pr.rho, "iterations": n_it, "ms_per_iter": dt * 1e3,
+                                        "plan_entry_updates_per_s": pr.R * pr.T / dt, "column_kernel_ms": col / n,
+                                        "column_kernel_GBs": algorithmic_bytes(pr) / (col / n * 1e-3) / 1e9,
+                                        "state_after_160": d}
+        log(f"rho = R * mean(S) = {pr.rho:.3g}: {dt * 1e3:.4f} ms/iter, column kernel {col / n:.4f} ms, "
+            f"{d['rounds_per_column']:.2f} passes and {d['active_per_column']:.1f} active entries per column")
+
     return out
 
 
@@ -364,12 +405,15 @@ def main():
     achieved = ab / (col_ms32 * 1e-3) / 1e9
     log(f"fp32: {dt32 / args.steps * 1e3:.4f} ms/iter, column kernel {col_ms32:.4f} ms, "
         f"{achieved:.0f} GB/s algorithmic, schedule {sched}")
+    state32 = final_state(p32, args.warmup + args.steps, torch, mam)
+    log(f"fp32 state after {state32['iterations']} iterations: {state32}")
 
     fp64 = None
     if not args.no_fp64:
         p64 = inputs.balanced_sparse(dtype="f64")
         dt64, pb64, col_ms64, _, sched64 = run_gpu(p64, args.steps, args.warmup, torch, mam)
         ab64 = algorithmic_bytes(p64)
+        state64 = final_state(p64, args.warmup + args.steps, torch, mam)
         fp64 = {
             "value": entries * args.steps / dt64,
             "ms_per_step": dt64 / args.steps * 1e3,
@@ -378,6 +422,8 @@ def main():
             "fp32_speedup": dt64 / dt32,
             "barycenter_rel_l1_fp32_vs_fp64": float(np.abs(pb32 - pb64).sum() / np.abs(pb64).sum()),
             "barycenter_rel_max_fp32_vs_fp64": float(np.abs(pb32 - pb64).max() / np.abs(pb64).max()),
+            "state": state64,
+            "objective_rel_fp32_vs_fp64": abs(state32["W_hat"] - state64["W_hat"]) / abs(state64["W_hat"]),
         }
         log(f"fp64: {fp64['ms_per_step']:.4f} ms/iter; fp32/fp64 barycenter rel L1 "
             f"{fp64['barycenter_rel_l1_fp32_vs_fp64']:.3e}")
@@ -436,7 +482,8 @@ def main():
         "config": {"workload": "balanced sparse WB, 64x64 grid (R=4096), M=32 thresholded blob "
                                "measures, indexed squared-Euclidean grid cost, rho=1, FP32 plans",
                    "R": p32.R, "M": p32.M, "T": p32.T, "S_min": min(p32.S), "S_max": max(p32.S),
-                   "iterations": args.steps, "schedule": sched},
+                   "S_drawn": sorted(int(x) for x in p32.S), "iterations": args.steps, "schedule": sched},
+        "state": state32,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "column_kernel", "algorithmic_bytes_per_launch": ab,

@@ -118,6 +118,48 @@ def cpu_baseline(p, n_measures):
                       f"({entries:.3e} plan entries, {dt:.1f} s, single thread)"}
 
 
+def _oracle_measures_worker(args):
+    """One process of the paper's parallel scheme: Step 2 and the marginal of
+    Step 3 for its measures, from theta^0 = q_s/R (the problem is rebuilt
+    here, so nothing large crosses the process boundary).  Returns the
+    seconds of its numpy work and its plan entries."""
+    ms, dtype = args
+    import numpy as np
+    from oracle import mam_oracle as O
+    from paper_2309_05315_amd import inputs
+    p = inputs.balanced_sparse(dtype=dtype)
+    a = O.averaging_weights(p.S)
+    pm = np.stack([np.full(p.R, float(p.q_block(m).sum()) / p.R) for m in range(p.M)])
+    pbar = (a[:, None] * pm).sum(axis=0)
+    t, _ = O.damping(pbar, pm, p.S, p.rho, p.gamma)
+    blocks = {m: p.cost_block(m) for m in ms}
+    t0 = time.perf_counter()
+    for m in ms:
+        q = p.q_block(m)
+        theta = np.repeat((q / p.R)[None, :], p.R, axis=0)
+        corr = t * (pbar - pm[m]) / p.S[m]
+        w = theta + 2.0 * corr[:, None] - blocks[m] / p.rho
+        ph = O.proj_simplex_sort(w, q)[0]
+        (ph - corr[:, None]).sum(axis=1)
+    return time.perf_counter() - t0, p.R * sum(p.S[m] for m in ms)
+
+
+def cpu_baseline_parallel(p, workers):
+    """The paper's own parallel scheme (one process per group of measures,
+    Step 2 in parallel, the averaging as the gathering step): one iteration
+    over all measures on 'workers' host processes; the wall time is the
+    slowest process's."""
+    import multiprocessing as mp
+    parts = [list(range(w, p.M, workers)) for w in range(workers)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_measures_worker, [(ms, p.dtype) for ms in parts])
+    wall = max(dt for dt, _ in res)
+    entries = sum(e for _, e in res)
+    return {"value": entries / wall, "unit": "plan-entry updates/s", "cores": workers, "kind": "oracle",
+            "sample": f"1 iteration of the FP64 numpy oracle over all {p.M} measures, {workers} processes "
+                      f"(measures dealt round robin; wall time = the slowest process, {wall:.2f} s)"}
+
+
 EXTRAS = ("balanced_plain", "unbalanced", "batch", "randomized", "stopping", "free_support", "adjoint",
           "large_rho")
 
@@ -388,8 +430,19 @@ def main():
         sys.exit(2)
 
     import numpy as np
+    from paper_2309_05315_amd import inputs
+
+    # the paper's parallel CPU scheme runs first, in fresh processes started
+    # before this process touches the GPU
+    cpu_par = None
+    if not args.no_cpu:
+        p_cpu = inputs.balanced_sparse(dtype="f32")
+        workers = max(1, min(16, len(os.sched_getaffinity(0)), p_cpu.M))
+        cpu_par = cpu_baseline_parallel(p_cpu, workers)
+        log(f"oracle, paper's parallel scheme on {workers} processes: {cpu_par['value']:.3e} entries/s")
+
     import torch
-    from paper_2309_05315_amd import inputs, mam
+    from paper_2309_05315_amd import mam
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -491,6 +544,7 @@ def main():
                      "avg_launch_ms": col_ms32, "launches_timed": ncol},
         "fp64": fp64,
         "cpu_baseline": cpu,
+        "cpu_baseline_parallel": cpu_par,
         "extras": extras,
     }
     print(json.dumps(out), flush=True)

@@ -10,11 +10,13 @@ template <typename T, int VPT, bool GRID>
 LongFns<T> pick_long_vec(int vec) {
   constexpr int VN = VecOf<T>::N;
   if (vec == VN)
-    return {&long_scan_kernel<T, VPT, VN, GRID>, &long_threshold_kernel<T, VPT, VN>, &long_write_kernel<T, VPT, VN>,
-            &long_rowsum_kernel<T>, &long_materialize_kernel<T, VPT, VN>};
+    return {&long_scan_kernel<T, VPT, VN, GRID, false>, &long_threshold_kernel<T, VPT, VN>,
+            &long_write_kernel<T, VPT, VN>, &long_rowsum_kernel<T>, &long_materialize_kernel<T, VPT, VN>,
+            &long_scan_kernel<T, VPT, VN, GRID, true>};
   if (vec == 1)
-    return {&long_scan_kernel<T, VPT, 1, GRID>, &long_threshold_kernel<T, VPT, 1>, &long_write_kernel<T, VPT, 1>,
-            &long_rowsum_kernel<T>, &long_materialize_kernel<T, VPT, 1>};
+    return {&long_scan_kernel<T, VPT, 1, GRID, false>, &long_threshold_kernel<T, VPT, 1>,
+            &long_write_kernel<T, VPT, 1>, &long_rowsum_kernel<T>, &long_materialize_kernel<T, VPT, 1>,
+            &long_scan_kernel<T, VPT, 1, GRID, true>};
   return {};
 }
 

@@ -1088,7 +1088,8 @@ mam_status launch_long_columns(Plan* pl, hipStream_t st) {
   mam::LongArgs<T> a = long_args<T>(pl);
   hipLaunchKernelGGL(mam::damping_kernel, dim3(1), dim3(256), 0, st, a.d2part, p.nb, p.rho, p.gamma, a.t, a.stop);
   LAUNCH_CHECK("damping_kernel");
-  hipLaunchKernelGGL(fn.scan, dim3(lg.nwg), dim3(mam::LNT), 0, st, a);
+  if (lg.sparse) hipLaunchKernelGGL(fn.scan_sparse, dim3(lg.nwg), dim3(mam::LNT), (size_t)lg.vpt * mam::LNT * 8, st, a);
+  else hipLaunchKernelGGL(fn.scan, dim3(lg.nwg), dim3(mam::LNT), 0, st, a);
   LAUNCH_CHECK("long_scan_kernel");
   hipLaunchKernelGGL(fn.thresh, dim3((unsigned)((p.T + 3) / 4)), dim3(256), 0, st, a);
   LAUNCH_CHECK("long_threshold_kernel");

@@ -41,6 +41,7 @@ struct LongFns {
   void (*write)(LongArgs<T>) = nullptr;
   void (*rowsum)(LongArgs<T>, int) = nullptr;
   void (*materialize)(LongArgs<T>) = nullptr;  // sparse store write-back
+  void (*scan_sparse)(LongArgs<T>) = nullptr;  // sparse-store scan
 };
 template <typename T>
 LongFns<T> pick_long(int vpt, int vec, bool grid);

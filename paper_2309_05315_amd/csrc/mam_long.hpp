@@ -219,14 +219,20 @@ __device__ void stored_rows(const LongArgs<T>& a, int64_t j, int si, int rbase, 
 
 // ---- scan: w, sub-tile maxima, candidates -------------------------------
 // GRID: the cost is formed from the row's grid point and the column's point
-// instead of being read (only theta is streamed).
-template <typename T, int VPT, int VEC, bool GRID>
+// instead of being read (only theta is streamed).  SP: the sparse-store
+// instance; an unpatched entry of a sparse sub-tile has theta = the common
+// value, so theta + 2b is a per-row constant of the item ('base', in
+// registers) and w costs one fused multiply-add; 2b itself sits in LDS for
+// dense sub-tiles and patched rows (dynamic LDS: VPT*256 doubles, each
+// thread reading only its own slots).
+template <typename T, int VPT, int VEC, bool GRID, bool SP>
 __global__ void __launch_bounds__(LNT)
 long_scan_kernel(LongArgs<T> a) {
   constexpr int NCH = VPT / VEC, RB = LNT * VPT;
   // columns in flight per wave: two where the registers allow it at two
-  // waves per SIMD (FP32 tiles of 16 values in vectors), else one
-  constexpr int PF = (sizeof(T) == 4 && VPT == 16 && VEC > 1) ? 2 : 1;
+  // waves per SIMD (FP32 tiles of 16 values in vectors), else one (and one
+  // in the sparse-store instance, whose columns mostly load no theta)
+  constexpr int PF = (!SP && sizeof(T) == 4 && VPT == 16 && VEC > 1) ? 2 : 1;
   static_assert(VPT % VEC == 0 && VPT <= 16, "tile shape");
   if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -237,8 +243,10 @@ long_scan_kernel(LongArgs<T> a) {
   const T* const qv = gptr(a.q);
   int32_t* const crow = gptr(a.crow);
   double* const cw = gptr(a.cw);
-  const bool sparse = a.sparse != 0;
+  constexpr bool sparse = SP;
   const int par = sparse ? uniform_i(*gptr(a.spar)) : 0;
+  extern __shared__ double lds_dyn[];
+  double* const lds_b2 = lds_dyn;  // SP: [VPT][LNT]
   const int ib = uniform_i(a.wg_it[blockIdx.x]), ie = uniform_i(a.wg_it[blockIdx.x + 1]);
   for (int it = ib; it < ie; ++it) {
     const int rb = uniform_i(a.it_rb[it]), m = uniform_i(a.it_m[it]);
@@ -251,15 +259,20 @@ long_scan_kernel(LongArgs<T> a) {
     int row[VPT];
     // 2 b_r, or -inf for rows past R: their w is then -inf (theta and c are
     // finite), below every threshold, without a select per entry
-    double b2[VPT];
+    double b2[SP ? 1 : VPT];
+    double base[SP ? VPT : 1];  // SP: common value + 2b of the row
     double gx0[GRID ? VPT : 1], gx1[GRID ? VPT : 1];  // grid coordinates of the rows
-    T nbk[VPT];  // sparse store: the stored value of the unpatched entries
     const T* __restrict__ nbm = sparse ? gptr(a.nbv) + ((size_t)par * a.M + m) * R : nullptr;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       row[k] = rbase + ((k / VEC) * LNT + tid) * VEC + (k % VEC);
-      b2[k] = row[k] < R ? 2.0 * long_b(t, pv, pmm, row[k], Sm) : -__builtin_huge_val();
-      nbk[k] = (sparse && row[k] < R) ? nbm[row[k]] : T(0);
+      const double b2k = row[k] < R ? 2.0 * long_b(t, pv, pmm, row[k], Sm) : -__builtin_huge_val();
+      if constexpr (SP) {
+        lds_b2[k * LNT + tid] = b2k;
+        base[k] = (double)(row[k] < R ? nbm[row[k]] : T(0)) + b2k;
+      } else {
+        b2[k] = b2k;
+      }
       if constexpr (GRID) {
         const int i0 = row[k] / a.gn1;
         gx0[k] = grid_coord(a, 0, i0);
@@ -312,22 +325,53 @@ long_scan_kernel(LongArgs<T> a) {
     // unconditional loads keep the buffers in place across iterations)
     auto column = [&](auto S, auto NEXT, int64_t j) {
       constexpr int s = decltype(S)::value;
-      if (pcs[s] >= 0) {
-        // sparse store: the common values, then the sub-tile's patches
-#pragma unroll
-        for (int k = 0; k < VPT; ++k) rt[s][k] = nbk[k];
-        apply_patches<T, VPT, VEC>(pcs[s], prs[s], pvs[s], rbase, tid, rt[s]);
-      }
       double w[VPT];
       double mx = -__builtin_huge_val();
       const double z0 = uniform_d(rz[s][0]), z1 = uniform_d(rz[s][1]);
+      auto cost_k = [&](int k) -> double {
+        if constexpr (GRID) return grid_cost_xy<T>(gx0[k], gx1[k], z0, z1);
+        else return (double)rc[s][k];
+      };
+      if constexpr (SP) {
+        // theta + 2b of every entry: base for a sparse sub-tile, the dense
+        // rows plus 2b from LDS otherwise; w is one fused multiply-add each
+        const bool sp = pcs[s] >= 0;
+        double bs[VPT];
+        if (sp) {
 #pragma unroll
-      for (int k = 0; k < VPT; ++k) {
-        double c;
-        if constexpr (GRID) c = grid_cost_xy<T>(gx0[k], gx1[k], z0, z1);
-        else c = (double)rc[s][k];
-        w[k] = long_w((double)rt[s][k], b2[k], c, inv_rho);
-        mx = fmax(mx, w[k]);
+          for (int k = 0; k < VPT; ++k) bs[k] = base[k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < VPT; ++k) bs[k] = (double)rt[s][k] + lds_b2[k * LNT + tid];
+        }
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+          w[k] = __builtin_fma(-cost_k(k), inv_rho, bs[k]);
+          mx = fmax(mx, w[k]);
+        }
+        if (sp) {
+          // the patched rows (each patch raises its entry, so the maximum
+          // only grows)
+          for (int e = 0; e < pcs[s]; ++e) {
+            const int rr = __builtin_amdgcn_readlane(prs[s], e) - rbase;
+            const T v = read_lane(pvs[s], e);
+            if (slot_owner(rr, VEC) == tid) {
+              const int kp = slot_of(rr, VEC), r = rbase + rr;
+              const double c = GRID ? grid_cost(a, r, z0, z1) : (double)long_cost_col(a, j, off_m)[r];
+              const double wn = long_w((double)v, lds_b2[kp * LNT + tid], c, inv_rho);
+#pragma unroll
+              for (int kk = 0; kk < VPT; ++kk)
+                if (kk == kp) w[kk] = wn;
+              mx = fmax(mx, wn);
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+          w[k] = long_w((double)rt[s][k], b2[k], cost_k(k), inv_rho);
+          mx = fmax(mx, w[k]);
+        }
       }
       const double tau = uniform_d((double)rq[s]);
       if constexpr (decltype(NEXT)::value) issue(S, j + PF < jhi ? j + PF : jhi - 1);

@@ -109,7 +109,10 @@ typedef int32_t mam_status;
                                   mam_support_update returns.  Results are
                                   identical bit for bit; the workspace grows by
                                   the patch slots (about 8 bytes x candidate
-                                  slots per column and 1024 rows in FP32). */
+                                  slots per column and 1024 rows in FP32).
+                                  The write-back costs about one dense write
+                                  pass, so the flag pays off for calls of
+                                  more than one iteration. */
 
 typedef struct mam_problem mam_problem;
 

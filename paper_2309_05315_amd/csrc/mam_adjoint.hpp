@@ -25,6 +25,8 @@
 // start theta^0 = q/R adds sum_r X_rs / R to qbar_s.
 #pragma once
 
+#include <type_traits>
+
 #include "mam_kernels.hpp"
 
 namespace mam {
@@ -56,10 +58,10 @@ struct AdjArgs {
 // which some thread has more takes a slow path that walks the bits (same
 // summation order, so results do not depend on the path).  The work of a
 // column is a dependent chain (mask -> gathers -> group sum -> writes), so
-// columns are pipelined: masks are loaded two columns ahead and the V, U,
-// cost-adjoint and q-adjoint entries gathered one column ahead, so no
-// read-modify-write waits on memory inside a column step.  V is read from global memory (it is a few
-// tens of KB per measure and stays in L2).
+// columns are pipelined: masks are loaded four columns ahead and the V, U,
+// cost-adjoint and q-adjoint entries gathered two columns ahead, so no
+// read-modify-write waits on memory inside a column step.  V is read from
+// global memory (it is a few tens of KB per measure and stays in L2).
 //
 // Dynamic LDS: NG*VPT*NT doubles of row-sum accumulators (each row owned by
 // one thread of a group: no atomics).
@@ -84,13 +86,12 @@ adjoint_kernel(AdjArgs a) {
   const int R = a.R, vs = a.vec_shift;
   auto row = [&](int k) { return (((k >> vs) * NT + tid) << vs) | (k & ((1 << vs) - 1)); };
 
-  // one column in flight: its masks, up to two active slots and their X values
-  struct Col {
+  // one column in flight: its masks, its first two active slots and the
+  // loaded V, U and cost-adjoint entries there, and its q adjoint
+  struct Gat {
     unsigned bk, bk1;
     int k0, k1;      // active slots (-1: none)
-    double x0, x1;   // X = V + U at those slots (U only where also active at k+1)
-    double c0, c1;   // the cost adjoint there, read ahead for its update
-    double qa;       // q's adjoint of the column (thread 0), read ahead likewise
+    double v0, u0, c0, v1, u1, c1, qa;
   };
   __shared__ double red_s[2][NW > 1 ? NW : 1];
   __shared__ double red_n[2][NW > 1 ? NW : 1];
@@ -108,78 +109,85 @@ adjoint_kernel(AdjArgs a) {
     __syncthreads();
 
     auto colj = [&](int64_t t) { return j0 + g + (int64_t)NG * t; };
-    auto load_masks = [&](int64_t j, unsigned& bk, unsigned& bk1) {
-      bk = 0u;
-      bk1 = 0u;
-      if (j < j1) {
-        bk = reinterpret_cast<const W*>(a.mk + j * a.mld)[tid];
-        if (a.mk1) bk1 = reinterpret_cast<const W*>(a.mk1 + j * a.mld)[tid];
-      }
+    // every load below is issued by every lane of every step (addresses
+    // clamped into the segment, unused values ignored): with a fixed number of
+    // loads per step a wait covers only the loads it needs, never the ones
+    // issued after them
+    auto jclamp = [&](int64_t j) { return j < j1 ? j : j1 - 1; };
+    const uint8_t* const mk1p = a.mk1 ? a.mk1 : a.mk;
+    const bool has1 = a.mk1 != nullptr;
+    unsigned mring[3][2];  // raw mask words of three columns
+    Gat gr[3];             // gathered entries of three columns
+    auto load_masks = [&](auto S, int64_t t) {
+      constexpr int s = decltype(S)::value;
+      const int64_t j = jclamp(colj(t));
+      mring[s][0] = reinterpret_cast<const W*>(a.mk + j * a.mld)[tid];
+      mring[s][1] = reinterpret_cast<const W*>(mk1p + j * a.mld)[tid];
     };
-    // gathers of a column whose masks are known (fast path: <= 2 active slots)
-    auto gather = [&](int64_t j, Col& c) {
-      c.k0 = c.k1 = -1;
-      c.x0 = c.x1 = 0.0;
-      c.c0 = c.c1 = 0.0;
-      c.qa = (tid == 0 && j < j1) ? a.qacc[j] : 0.0;
-      unsigned b = c.bk;
-      if (b) {
-        const double* __restrict__ Uc = a.U + j * (int64_t)R;
-        const double* __restrict__ Cc = a.cacc + j * (int64_t)R;
-        c.k0 = __builtin_ctz(b);
-        const int r0 = row(c.k0);
-        c.x0 = Vm[r0];
-        c.c0 = Cc[r0];
-        if ((c.bk1 >> c.k0) & 1u) c.x0 += Uc[r0];
-        b &= b - 1;
-        if (b) {
-          c.k1 = __builtin_ctz(b);
-          const int r1 = row(c.k1);
-          c.x1 = Vm[r1];
-          c.c1 = Cc[r1];
-          if ((c.bk1 >> c.k1) & 1u) c.x1 += Uc[r1];
-        }
-      }
+    // the column's masks (waiting for them) and the loads of its first two
+    // active slots, X = V (+ U where also active at k+1) formed when used
+    auto gather = [&](auto S, int64_t t) {
+      constexpr int s = decltype(S)::value;
+      Gat& c = gr[s];
+      const bool in = colj(t) < j1;
+      const int64_t j = jclamp(colj(t));
+      c.bk = in ? mring[s][0] : 0u;
+      c.bk1 = (in && has1) ? mring[s][1] : 0u;
+      const unsigned b1 = c.bk & (c.bk - 1u);
+      c.k0 = c.bk ? __builtin_ctz(c.bk) : -1;
+      c.k1 = b1 ? __builtin_ctz(b1) : -1;
+      const int r0 = c.k0 >= 0 ? row(c.k0) : 0, r1 = c.k1 >= 0 ? row(c.k1) : 0;
+      const double* __restrict__ Uc = a.U + j * (int64_t)R;
+      const double* __restrict__ Cc = a.cacc + j * (int64_t)R;
+      c.v0 = Vm[r0];
+      c.u0 = Uc[r0];
+      c.c0 = Cc[r0];
+      c.v1 = Vm[r1];
+      c.u1 = Uc[r1];
+      c.c1 = Cc[r1];
+      c.qa = a.qacc[j];
     };
 
-    // column t is gathered, column t+1 gathered ahead, masks of t+2 in flight
-    Col cur, nxt;
-    unsigned mb, mb1;
-    load_masks(colj(0), cur.bk, cur.bk1);
-    load_masks(colj(1), nxt.bk, nxt.bk1);
-    gather(colj(0), cur);
-    for (int64_t t = 0; colj(t) < j1; ++t) {
-      load_masks(colj(t + 2), mb, mb1);
-      gather(colj(t + 1), nxt);
-
+    auto process = [&](auto S, int64_t t) {
+      constexpr int s = decltype(S)::value;
+      const Gat& c = gr[s];
       const int64_t j = colj(t);
       double* __restrict__ Uc = a.U + j * (int64_t)R;
-      const unsigned bk = cur.bk, bk1 = cur.bk1;
+      const unsigned bk = c.bk, bk1 = c.bk1;
       const bool wave_any = __ballot(bk != 0u) != 0ull;
       const bool wave_slow = __ballot(__popc(bk) > 2) != 0ull;
-      double s = 0.0;
+      double x0 = 0.0, x1 = 0.0;
+      if (c.k0 >= 0) {
+        x0 = c.v0;
+        if ((bk1 >> c.k0) & 1u) x0 += c.u0;
+      }
+      if (c.k1 >= 0) {
+        x1 = c.v1;
+        if ((bk1 >> c.k1) & 1u) x1 += c.u1;
+      }
+      double sum = 0.0;
       if (wave_slow) {
         for (unsigned b = bk; b; b &= b - 1) {
           const int r = row(__builtin_ctz(b));
           double v = Vm[r];
           if ((bk1 >> __builtin_ctz(b)) & 1u) v += Uc[r];
-          s += v;
+          sum += v;
         }
       } else {
-        s = cur.x0 + cur.x1;  // slot order, as the slow path
+        sum = x0 + x1;  // slot order, as the slow path
       }
       double n = (double)__popc(bk);
       // group sums of X over A and of |A| (fixed order)
       if (wave_any) {
-        s = wave_reduce<OpSum>(s);
+        sum = wave_reduce<OpSum>(sum);
         n = wave_reduce<OpSum>(n);
       } else {
-        s = 0.0;
+        sum = 0.0;
         n = 0.0;
       }
       if constexpr (NW > 1) {
         if (lane == 0) {
-          red_s[par][wv] = s;
+          red_s[par][wv] = sum;
           red_n[par][wv] = n;
         }
         __syncthreads();
@@ -189,13 +197,13 @@ adjoint_kernel(AdjArgs a) {
           ss += red_s[par][i];
           nn += red_n[par][i];
         }
-        s = uniform_d(ss);
+        sum = uniform_d(ss);
         n = uniform_d(nn);
         par ^= 1;
       }
       if (n != 0.0) {  // n = 0: tau = 0 or an empty projection, nothing active
-        const double mean = s / n;
-        if (tid == 0) a.qacc[j] = cur.qa + mean;
+        const double mean = sum / n;
+        if (tid == 0) a.qacc[j] = c.qa + mean;
         if (wave_any) {
           double* __restrict__ Cc = a.cacc + j * (int64_t)R;
           if (wave_slow) {
@@ -211,26 +219,51 @@ adjoint_kernel(AdjArgs a) {
               fix[k * NT + tid] += wb;
             }
           } else {
-            if (cur.k0 >= 0) {
-              const int r = row(cur.k0);
-              const double wb = cur.x0 - mean;
+            if (c.k0 >= 0) {
+              const int r = row(c.k0);
+              const double wb = x0 - mean;
               Uc[r] = wb;
-              Cc[r] = cur.c0 + wb;
-              fix[cur.k0 * NT + tid] += wb;
+              Cc[r] = c.c0 + wb;
+              fix[c.k0 * NT + tid] += wb;
             }
-            if (cur.k1 >= 0) {
-              const int r = row(cur.k1);
-              const double wb = cur.x1 - mean;
+            if (c.k1 >= 0) {
+              const int r = row(c.k1);
+              const double wb = x1 - mean;
               Uc[r] = wb;
-              Cc[r] = cur.c1 + wb;
-              fix[cur.k1 * NT + tid] += wb;
+              Cc[r] = c.c1 + wb;
+              fix[c.k1 * NT + tid] += wb;
             }
           }
         }
       }
-      cur = nxt;
-      nxt.bk = mb;
-      nxt.bk1 = mb1;
+    };
+
+    // step t: masks of column t+4 requested, column t+2 gathered (its masks
+    // arrived two steps ago), column t processed (gathered two steps ago);
+    // slot of column i = i mod 3, unrolled so every slot index is static
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    auto step = [&](auto P, auto G, auto M, int64_t t) {
+      load_masks(M, t + 4);
+      gather(G, t + 2);
+      process(P, t);
+    };
+    if (colj(0) < j1) {
+      load_masks(I0{}, 0);
+      load_masks(I1{}, 1);
+      load_masks(I2{}, 2);
+      gather(I0{}, 0);
+      load_masks(I0{}, 3);
+      gather(I1{}, 1);
+      for (int64_t t = 0;; t += 3) {
+        step(I0{}, I2{}, I1{}, t);
+        if (colj(t + 1) >= j1) break;
+        step(I1{}, I0{}, I2{}, t + 1);
+        if (colj(t + 2) >= j1) break;
+        step(I2{}, I1{}, I0{}, t + 2);
+        if (colj(t + 3) >= j1) break;
+      }
     }
 
     // the segment's row sums of wbar, groups in order

@@ -68,6 +68,10 @@ struct AdjArgs {
 template <int NT, int VPT>
 __global__ void __launch_bounds__(GroupShape<NT>::WG)
 adjoint_kernel(AdjArgs a) {
+  // column slots in flight (gathers RING-1 columns ahead, masks RING+1):
+  // four or five slots are no faster and five lower the resident workgroups
+  constexpr int RING = 3;
+  static_assert(RING >= 3, "masks are requested two steps before their gather");
   using W = typename MaskWord<VPT>::type;
   constexpr int WG = GroupShape<NT>::WG;
   constexpr int NG = GroupShape<NT>::NG;
@@ -116,8 +120,8 @@ adjoint_kernel(AdjArgs a) {
     auto jclamp = [&](int64_t j) { return j < j1 ? j : j1 - 1; };
     const uint8_t* const mk1p = a.mk1 ? a.mk1 : a.mk;
     const bool has1 = a.mk1 != nullptr;
-    unsigned mring[3][2];  // raw mask words of three columns
-    Gat gr[3];             // gathered entries of three columns
+    unsigned mring[RING][2];  // raw mask words, slot = column mod RING
+    Gat gr[RING];             // gathered entries, slot = column mod RING
     auto load_masks = [&](auto S, int64_t t) {
       constexpr int s = decltype(S)::value;
       const int64_t j = jclamp(colj(t));
@@ -238,31 +242,30 @@ adjoint_kernel(AdjArgs a) {
       }
     };
 
-    // step t: masks of column t+4 requested, column t+2 gathered (its masks
-    // arrived two steps ago), column t processed (gathered two steps ago);
-    // slot of column i = i mod 3, unrolled so every slot index is static
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    auto step = [&](auto P, auto G, auto M, int64_t t) {
-      load_masks(M, t + 4);
-      gather(G, t + 2);
-      process(P, t);
+    // step t: masks of column t+RING+1 requested, column t+RING-1 gathered
+    // (its masks arrived two steps ago), column t processed (gathered RING-1
+    // steps ago); unrolled RING times so every slot index is static
+    auto step = [&](auto U, int64_t t) {
+      constexpr int u = decltype(U)::value;
+      load_masks(std::integral_constant<int, (u + 1) % RING>{}, t + RING + 1);
+      gather(std::integral_constant<int, (u + RING - 1) % RING>{}, t + RING - 1);
+      process(U, t);
     };
     if (colj(0) < j1) {
-      load_masks(I0{}, 0);
-      load_masks(I1{}, 1);
-      load_masks(I2{}, 2);
-      gather(I0{}, 0);
-      load_masks(I0{}, 3);
-      gather(I1{}, 1);
-      for (int64_t t = 0;; t += 3) {
-        step(I0{}, I2{}, I1{}, t);
-        if (colj(t + 1) >= j1) break;
-        step(I1{}, I0{}, I2{}, t + 1);
-        if (colj(t + 2) >= j1) break;
-        step(I2{}, I1{}, I0{}, t + 2);
-        if (colj(t + 3) >= j1) break;
+      static_for<RING>([&](auto I) { load_masks(I, decltype(I)::value); });
+      gather(std::integral_constant<int, 0>{}, 0);
+      load_masks(std::integral_constant<int, 0>{}, RING);
+      static_for<RING - 2>([&](auto I) {
+        gather(std::integral_constant<int, decltype(I)::value + 1>{}, decltype(I)::value + 1);
+      });
+      for (int64_t t = 0;; t += RING) {
+        bool done = false;
+        static_for<RING>([&](auto I) {
+          if (done) return;
+          step(I, t + decltype(I)::value);
+          if (colj(t + decltype(I)::value + 1) >= j1) done = true;
+        });
+        if (done) break;
       }
     }
 

@@ -37,9 +37,22 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "mam.h"
 
 namespace mam {
+
+// f(integral_constant<int, 0>{}), ..., f(integral_constant<int, N - 1>{}):
+// a loop over buffers whose index stays a compile-time constant.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 template <typename T> struct VecOf;
 template <> struct VecOf<float>  { static constexpr int N = 4; using type = float4; };

@@ -156,17 +156,6 @@ __device__ __forceinline__ double long_w(double th, double b2, double c, double 
   return __builtin_fma(-c, inv_rho, th + b2);
 }
 
-// f(integral_constant<int, 0>{}), ..., f(integral_constant<int, N - 1>{}):
-// a loop over buffers whose index stays a compile-time constant.
-template <typename F, int... I>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
 // b^(m)_r = t (p_r - p^(m)_r) / S^m: every kernel forms it with this one
 // expression, so all of them see the same value.
 __device__ __forceinline__ double long_b(double t, const double* p, const double* pmm, int r, double Sm) {

@@ -103,19 +103,32 @@ def final_state(p, iters, torch, mam):
                               "rounds_per_column", "active_per_column")}
 
 
-def cpu_baseline(p, n_measures):
-    import numpy as np
+def host_cpu() -> str:
+    """The host's CPU model and logical core count, for the baseline records."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical cores"
+
+
+def cpu_baseline(p, n_measures, iters=2):
     from oracle import mam_oracle as O
     k = min(n_measures, p.M)
     cost = [p.cost_block(m) for m in range(k)]
     q = [p.q_block(m) for m in range(k)]
     t0 = time.perf_counter()
-    O.mam(cost, q, p.rho, p.gamma, 1)
+    O.mam(cost, q, p.rho, p.gamma, iters)
     dt = time.perf_counter() - t0
-    entries = p.R * sum(p.S[:k])
+    entries = p.R * sum(p.S[:k]) * iters
     return {"value": entries / dt, "unit": "plan-entry updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 iteration of the FP64 numpy oracle over the first {k} of {p.M} measures "
-                      f"({entries:.3e} plan entries, {dt:.1f} s, single thread)"}
+            "sample": f"{iters} iteration(s) of the FP64 numpy oracle over the first {k} of {p.M} measures "
+                      f"({entries:.3e} plan-entry updates, {dt:.1f} s, single thread on {host_cpu()})"}
 
 
 def _oracle_measures_worker(args):
@@ -157,7 +170,8 @@ def cpu_baseline_parallel(p, workers):
     entries = sum(e for _, e in res)
     return {"value": entries / wall, "unit": "plan-entry updates/s", "cores": workers, "kind": "oracle",
             "sample": f"1 iteration of the FP64 numpy oracle over all {p.M} measures, {workers} processes "
-                      f"(measures dealt round robin; wall time = the slowest process, {wall:.2f} s)"}
+                      f"(measures dealt round robin; wall time = the slowest process, {wall:.2f} s) "
+                      f"on {host_cpu()}"}
 
 
 EXTRAS = ("balanced_plain", "unbalanced", "batch", "randomized", "stopping", "free_support", "adjoint",
@@ -415,7 +429,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
-    ap.add_argument("--cpu-measures", type=int, default=12)
+    ap.add_argument("--cpu-measures", type=int, default=32)
     ap.add_argument("--no-extras", action="store_true", help="skip the other workloads")
     ap.add_argument("--extras", default="", help="comma-separated subset of the other workloads: " + ",".join(EXTRAS))
     ap.add_argument("--copy-probe", action="store_true",

@@ -51,4 +51,5 @@ def test_cpu_baseline_record():
     assert set(rec) == {"value", "unit", "cores", "kind", "sample"}
     assert rec["kind"] == "oracle" and rec["cores"] == 1 and rec["value"] > 0
     assert rec["unit"] == "plan-entry updates/s"
-    assert "first 2 of 3 measures" in rec["sample"] and f"{40 * 21:.3e}" in rec["sample"]
+    assert "first 2 of 3 measures" in rec["sample"] and f"{40 * 21 * 2:.3e}" in rec["sample"]
+    assert "logical cores" in rec["sample"]

@@ -122,9 +122,11 @@ def cpu_baseline(p, n_measures, iters=2):
     k = min(n_measures, p.M)
     cost = [p.cost_block(m) for m in range(k)]
     q = [p.q_block(m) for m in range(k)]
-    t0 = time.perf_counter()
-    O.mam(cost, q, p.rho, p.gamma, iters)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):  # one core, BLAS included
+        t0 = time.perf_counter()
+        O.mam(cost, q, p.rho, p.gamma, iters)
+        dt = time.perf_counter() - t0
     entries = p.R * sum(p.S[:k]) * iters
     return {"value": entries / dt, "unit": "plan-entry updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} iteration(s) of the FP64 numpy oracle over the first {k} of {p.M} measures "

@@ -134,6 +134,25 @@ def test_bitwise_determinism():
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_large_finite_gamma_is_bitwise_balanced(dtype):
+    """A finite gamma at or above rho * max_k d_k leaves t = 1 in every
+    iteration (Alg. 1, the damping of the unbalanced case), so the iterates
+    equal the balanced ones bit for bit; the bound is taken from the oracle's
+    d history with a wide margin for the GPU's own rounding."""
+    import dataclasses
+    p = inputs.balanced_sparse(K=16, M=5, iters=40, dtype=dtype)
+    cost, q = blocks(p)
+    hist = O.mam(cost, q, p.rho, math.inf, 40, record=True)["hist"]["d"]
+    bound = 10.0 * p.rho * max(hist)
+    say(f"case gamma=inf vs gamma={bound:.3e} dtype={dtype} R={p.R} M={p.M}")
+    a = run_gpu(p, 40)
+    b = run_gpu(dataclasses.replace(p, gamma=bound), 40)
+    assert np.array_equal(a["p_bar"], b["p_bar"])
+    for x, y in zip(a["theta"], b["theta"]):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("gamma", [math.inf, 0.05])
 def test_diagnostics_match_oracle(gamma):
     masses = None if math.isinf(gamma) else [0.7, 1.0, 1.3]

@@ -153,6 +153,32 @@ def test_large_finite_gamma_is_bitwise_balanced(dtype):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_unbalanced_mass_relation_per_iteration(dtype):
+    """Every column of theta' is pi_hat - t b^(m) with pi_hat summing to q_s
+    (Alg. 1, Prop. 3), so each measure's mass moves by
+    sum_r p^(m),k+1 = sum q^(m) - t^k (sum_r p^k - sum_r p^(m),k), with t^k the
+    damping of that iteration; checked on the device's own iterates."""
+    p = inputs.tiny_problem(21, R=700, S=[40, 65, 33], masses=[0.7, 1.0, 1.3], gamma=0.05, dtype=dtype)
+    s = mam.solver_for(p, diag=True)
+    s.init()
+    qsum = np.array([p.q_block(m).sum() for m in range(p.M)])
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    ts = []
+    for k in range(8):
+        pm = s.marginals().cpu().numpy()
+        pb = s.barycenter().cpu().numpy()
+        s.iterate(1)
+        t = s.diagnostics()["t"]
+        ts.append(t)
+        pm1 = s.marginals().cpu().numpy()
+        want = qsum - t * (pb.sum() - pm.sum(axis=1))
+        err = np.abs(pm1.sum(axis=1) - want).max() / qsum.max()
+        assert err <= tol, (k, err)
+    say(f"  t over 8 iterations: {[round(x, 4) for x in ts]}")
+    assert min(ts) < 1.0  # the damped branch was taken
+
+
 @pytest.mark.parametrize("gamma", [math.inf, 0.05])
 def test_diagnostics_match_oracle(gamma):
     masses = None if math.isinf(gamma) else [0.7, 1.0, 1.3]

@@ -225,12 +225,19 @@ def extra_workloads(torch, mam, inputs, log, only=None):
         s.timing(True)
         s.iterate(100)
         col, n = s.timing_read()
+        s.timing(False)
+        # the same iterations replayed from a captured graph (50 per launch)
+        s.graph(50)
+        s.init()
+        s.iterate(50)
+        dtg = timed(lambda: s.iterate(p3.iters)) / p3.iters
         s.close()
         ab = algorithmic_bytes(p3)
         out["unbalanced_K32_M50_f32"] = {"iterations": p3.iters, "ms_per_iter": dt * 1e3,
+                                         "ms_per_iter_graph": dtg * 1e3,
                                          "column_kernel_ms": col / n,
                                          "column_kernel_GBs": ab / (col / n * 1e-3) / 1e9}
-        log(f"unbalanced: {dt * 1e3:.4f} ms/iter, column kernel {col / n:.4f} ms")
+        log(f"unbalanced: {dt * 1e3:.4f} ms/iter, {dtg * 1e3:.4f} ms/iter graph, column kernel {col / n:.4f} ms")
 
     if want("batch"):
         # 256 independent problems (R = k^2, k in 8..32, M in 2..8), FP32, autotuned

@@ -56,7 +56,7 @@ def mam_pbar_t(cost: List[torch.Tensor], q: List[torch.Tensor], rho: float, iter
         t = torch.ones((), dtype=torch.float64)
         if not math.isinf(gamma):
             d = torch.sqrt(sum(((p - pm[m]) ** 2).sum() / S[m] for m in range(len(S))))
-            if float(rho * d) > gamma:
+            if float((rho * d).detach()) > gamma:
                 t = gamma / (rho * d)
         new = []
         for m in range(len(S)):

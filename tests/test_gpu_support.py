@@ -77,6 +77,40 @@ def test_support_step_matches_oracle(dtype, dim, rows):
     assert np.abs(pb - run["p_bar"]).sum() / np.abs(run["p_bar"]).sum() <= TOL[dtype][0]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_support_step_with_sparse_store_equals_dense(dtype):
+    """With the sparse store the plans live as -b plus their patches between
+    iterations; the support step writes them back before reading them, so
+    points, masses and the plans themselves equal the dense run bit for bit,
+    over two calls in a row."""
+    p = inputs.tiny_problem(35, R=2600, S=[37, 52, 29], dtype=dtype, rho=2.0)
+    rng = np.random.default_rng(7)
+    zeta = torch.from_numpy(rng.normal(size=(p.T, 2))).cuda()
+    xi0 = rng.normal(size=(p.R, 2))
+    alpha = [0.2, 0.5, 0.3]
+    out = []
+    for sparse in (False, True):
+        say(f"case support R={p.R} dtype={dtype} rows_per_tile=1024 sparse_store={sparse}")
+        s = mam.solver_for(p, rows_per_tile=1024, sparse_store=sparse)
+        s.init()
+        s.iterate(3)
+        xi = torch.from_numpy(xi0.copy()).cuda()
+        res = []
+        for _ in range(2):
+            xi, mass = s.support_update(alpha, zeta, xi)
+            s.iterate(2)
+            res.append((xi.cpu().numpy().copy(), mass.cpu().numpy().copy()))
+        out.append((res, [x.copy() for x in s.plans()], s.barycenter().cpu().numpy()))
+        s.close()
+    (ra, pa, ba), (rb, pb, bb) = out
+    for (xa, ma), (xb, mb) in zip(ra, rb):
+        np.testing.assert_array_equal(xa, xb)
+        np.testing.assert_array_equal(ma, mb)
+    for x, y in zip(pa, pb):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(ba, bb)
+
+
 def test_support_step_is_reproducible_and_keeps_massless_rows():
     # zero weights leave whole rows without mass after the first iteration
     p = inputs.tiny_problem(40, R=200, S=[30, 25], zero_frac=0.5, rho=0.05)

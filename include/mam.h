@@ -58,7 +58,11 @@ typedef int32_t mam_status;
 #define MAM_EHIP          -3  /* a HIP runtime call failed */
 #define MAM_ENOTBALANCED  -4  /* balanced mode (gamma = inf) with unequal masses */
 #define MAM_ENONFINITE    -5  /* a NaN/Inf or negative weight in the inputs or state */
-#define MAM_EUNSUPPORTED  -6  /* size outside what the kernels handle (R > 8192) */
+#define MAM_EUNSUPPORTED  -6  /* a size or feature outside what the path taken
+                                  provides: R > 2^28 or M > 65535 (mam_create),
+                                  R > 8192 inside a batch, a schedule no kernel
+                                  instance covers, diagnostics, reverse mode or
+                                  bundles on long columns (R > 8192) */
 #define MAM_ESTATE        -7  /* call out of order (e.g. iterate before init) */
 
 #define MAM_F32 0
@@ -196,7 +200,10 @@ const char* mam_last_error(void);
 /* Validate d and create a handle.  No HIP call is made.  Errors: MAM_EINVAL
  * (R, M, S^m < 1; ld < R; rho <= 0 or not finite; gamma < 0 or NaN; unknown
  * dtype or cost_mode; shared cost with some S^m > cost_ncols),
- * MAM_EUNSUPPORTED (R > 8192).  On error *out is set to NULL. */
+ * MAM_EUNSUPPORTED (R > 2^28, the long-column path's int32 row indices, or
+ * M > 65535).  Columns of up to 8192 rows are held by one workgroup; longer
+ * ones take the long-column path (several workgroups per column).  On
+ * error *out is set to NULL. */
 mam_status mam_create(mam_problem** out, const mam_desc* d);
 
 /* Override the launch schedule; must precede mam_set_workspace. */
@@ -327,8 +334,11 @@ mam_status mam_timing_read(mam_problem* p, double* total_ms, int64_t* launches);
  *   dim:   1, 2 or 3.
  *   ws:    device workspace of mam_support_workspace_bytes(p, dim) bytes
  *          (256-byte aligned, caller-owned; 0 is returned for invalid input).
- * Two passes in fixed orders (bitwise reproducible).  Asynchronous on
- * 'stream'.  Single problems, short and long columns, FP32 and FP64 plans.
+ * Two passes in fixed orders (bitwise reproducible).  Stream-ordered on
+ * 'stream'; the call synchronizes it once, after queueing the upload of
+ * its column tables (host memory the call owns and frees on return), and
+ * the support passes it launches then run asynchronously.  Single
+ * problems, short and long columns, FP32 and FP64 plans.
  * Errors: MAM_EINVAL (NULL pointer, dim, alpha, misaligned workspace),
  * MAM_ENOMEM (workspace NULL or too small), MAM_ESTATE (before mam_init),
  * MAM_EUNSUPPORTED (batch handles have no such call). */

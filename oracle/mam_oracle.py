@@ -19,8 +19,8 @@ Functions and the passage each follows:
   section on relaxing the marginals of q^(m) as well, and its proposition):
   projection onto {u >= 0, sum u <= tau} by clamping at 0 and, if the clamped
   vector carries more than tau, the simplex projection.
-* ``marginals``, ``averaging_weights``, ``proj_L``  Prop. 2 (eqs. (pr), (row_sol)).
-* ``dist_L``  the reduction of dist_L to R-vectors stated after Alg. 1.
+* ``marginals``, ``averaging_weights``, ``average``, ``proj_L``  Prop. 2 (eqs. (pr), (row_sol)).
+* ``dist_L``, ``dist_L_marginals``  the reduction of dist_L to R-vectors stated after Alg. 1.
 * ``unbalanced_prox``  eq. (Unbalanced-prox).
 * ``damping``  the t^k rule of Alg. 1 (Step 1).
 * ``mam``  Alg. 1 with the deterministic choice M^k = {1, ..., M}.
@@ -65,9 +65,11 @@ __all__ = [
     "proj_simplex_sort",
     "proj_subsimplex",
     "averaging_weights",
+    "average",
     "marginals",
     "proj_L",
     "dist_L",
+    "dist_L_marginals",
     "unbalanced_prox",
     "damping",
     "mam_step",
@@ -165,13 +167,23 @@ def proj_L(theta: List[np.ndarray]):
     return pi, p, pm
 
 
+def average(pm: np.ndarray, S: Sequence[int]) -> np.ndarray:
+    """p = sum_m a_m p^(m), eq. (pr) (Alg. 1, Step 1)."""
+    a = averaging_weights(S)
+    return (a[:, None] * pm).sum(axis=0)
+
+
+def dist_L_marginals(pm: np.ndarray, S: Sequence[int]) -> float:
+    """dist_L of plans whose row sums are ``pm`` (M x R): by Prop. 2 the
+    distance depends on the plans only through their marginals,
+    sqrt(sum_m ||p - p^(m)||^2 / S^m) with p = sum_m a_m p^(m) (text after Alg. 1)."""
+    p = average(pm, S)
+    return math.sqrt(sum(float(((p - pm[m]) ** 2).sum()) / S[m] for m in range(len(S))))
+
+
 def dist_L(theta: List[np.ndarray]) -> float:
     """dist_L(theta) = sqrt(sum_m ||p - p^(m)||^2 / S^m) (text after Alg. 1)."""
-    S = [th.shape[1] for th in theta]
-    a = averaging_weights(S)
-    pm = marginals(theta)
-    p = (a[:, None] * pm).sum(axis=0)
-    return math.sqrt(sum(float(((p - pm[m]) ** 2).sum()) / S[m] for m in range(len(S))))
+    return dist_L_marginals(marginals(theta), [th.shape[1] for th in theta])
 
 
 def unbalanced_prox(theta: List[np.ndarray], rho: float, gamma: float) -> List[np.ndarray]:
@@ -219,8 +231,7 @@ def mam_step(theta: List[np.ndarray], pm: np.ndarray, cost: List[np.ndarray],
     """
     S = [th.shape[1] for th in theta]
     M = len(S)
-    a = averaging_weights(S)
-    p = (a[:, None] * pm).sum(axis=0)                    # Step 1
+    p = average(pm, S)                                    # Step 1
     t, d = damping(p, pm, S, rho, gamma)
     active = set(range(M)) if chosen is None else set(int(m) for m in chosen)
     new_theta, pi_hat = [], []
@@ -303,8 +314,7 @@ def mam(cost: List[np.ndarray], q: List[np.ndarray], rho: float,
             hist["p"].append(info["p"])
         info["pm_old"] = pm
         pm = pm_new
-    a = averaging_weights(S)
-    p_bar = (a[:, None] * pm).sum(axis=0)
+    p_bar = average(pm, S)
     out = {"p_bar": p_bar, "theta": theta, "pm": pm, "pi_hat": info["pi_hat"],
            "t": info["t"], "p_prev": info["p"], "pm_prev": info.get("pm_old")}
     if record:

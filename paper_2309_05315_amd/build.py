@@ -4,8 +4,9 @@
 
 Every translation unit under csrc/ is compiled for gfx950 in parallel and
 linked into one shared library.  Packed FP32 instructions are disabled
-(-packed-fp32-ops target feature) and no fast-math flag is used, so the
-compensated row sums keep their meaning.
+(-packed-fp32-ops target feature) and no fast-math flag is used: the
+kernels' FP64 row sums, thresholds and the cost helper's operation order
+rely on IEEE rounding.
 """
 from __future__ import annotations
 

@@ -2218,6 +2218,9 @@ mam_status plan_support_update(Plan* pl, const double* alpha, const double* zeta
   HIP_TRY(hipMemcpyAsync(w + L.o_j0, cj0.data(), cj0.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(w + L.o_j1, cj1.data(), cj1.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(w + L.o_al, cal.data(), cal.size() * 8, hipMemcpyHostToDevice, st));
+  // the tables come from pageable vectors freed when this call returns: the
+  // copies must have read them first
+  HIP_TRY(hipStreamSynchronize(st));
   return pl->dtype == MAM_F32 ? launch_support<float>(pl, L, w, dim, zeta, xi, mass, st)
                               : launch_support<double>(pl, L, w, dim, zeta, xi, mass, st);
 }

@@ -366,7 +366,8 @@ struct Rounds {
 // kernel therefore keeps no per-entry state beyond the raw theta and c of
 // the columns in flight: w is recomputed where needed, each column writes
 // -b^(m) patched at its active rows, and the segment's row sums are
-// (#columns) * (-b^(m)) plus the patches' differences, accumulated in LDS.
+// (#columns) * (-b^(m)) plus the patches' values pi_hat, accumulated in LDS
+// in double before the update is rounded to the storage type.
 //
 // Threshold of a column (tau = q_s > 0): Newton steps
 //   lam' = (sum_{w > lam} w - tau) / #{w > lam}
@@ -695,7 +696,7 @@ column_kernel(ColArgs<T> a) {
               if ((mask[kc] >> k) & 1) {
                 const double ph = fmax(w[kc][k] - lout[kc], 0.0);
                 out[v] = (T)(ph - lds_b[k * NT + tid]);
-                fix[k * NT + tid] += (double)out[v] - (double)nb[k];
+                fix[k * NT + tid] += ph;  // theta' - (-b) before rounding
                 if constexpr (DIAG) {
                   colsum += ph;
                   dW += (double)cp[r0 + v] * ph;
@@ -750,7 +751,15 @@ column_kernel(ColArgs<T> a) {
       }
     }
 
-    // partial row sums of the segment: (#columns) * (-b) + patches, groups in order
+    // partial row sums of the segment: (#columns) * (-b) + patches, groups in
+    // order, all in double from the unrounded updates.  With float plans the
+    // stored -b of every inactive entry carries the same rounding error in
+    // all columns of a measure; summing the stored values would add S^m
+    // times that error to the row each iteration, a drift that grows
+    // linearly with the iteration count.  An inactive entry's stored value
+    // enters nothing else (it is inactive again or, if it becomes active,
+    // off by a relative 2^-24 of b), so the marginals follow the double
+    // iteration and the rounding stays per entry.
     __syncthreads();
     const double ncols = (double)(j1 - j0);
     for (int i = gtid; i < VPT * NT; i += WG) {
@@ -760,7 +769,7 @@ column_kernel(ColArgs<T> a) {
         double f = lds_fix[i];
 #pragma unroll
         for (int gg = 1; gg < NG; ++gg) f += lds_fix[(size_t)gg * VPT * NT + i];
-        a.partial[uniform_l(a.seg_poff[si]) + r] = ncols * (double)(T)(-lds_b[i]) + f;
+        a.partial[uniform_l(a.seg_poff[si]) + r] = f - ncols * lds_b[i];
       }
     }
   }

@@ -639,8 +639,9 @@ long_write_kernel(LongArgs<T> a) {
               const double w = long_w((double)tv[v], 2.0 * bk, cc, inv_rho);
               out[v] = nbk;
               if (w > lam) {
-                out[v] = (T)(fmax(w - lam, 0.0) - bk);
-                fix[(c * VEC + v) * LNT + tid] += (double)out[v] - (double)nbk;
+                const double ph = fmax(w - lam, 0.0);
+                out[v] = (T)(ph - bk);
+                fix[(c * VEC + v) * LNT + tid] += ph;  // theta' - (-b) before rounding
               }
             }
           }
@@ -681,8 +682,8 @@ long_write_kernel(LongArgs<T> a) {
         const int re = e < n ? crow[h * cap + e] : rbase;
         const bool keep = xe > lam;
         const double bk = keep ? long_b(t, pv, pmm, re, Sm) : 0.0;
-        const T val = (T)(fmax(xe - lam, 0.0) - bk);
-        const double dfix = (double)val - (double)(T)(-bk);
+        const double dfix = fmax(xe - lam, 0.0);  // theta' - (-b) before rounding
+        const T val = (T)(dfix - bk);
         unsigned long long sel = __ballot(keep);
         if (sparse) {
           const int pos = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(sel >> 32),
@@ -724,12 +725,15 @@ long_write_kernel(LongArgs<T> a) {
         for (int64_t j = jb; j < je; ++j) column(j);
       }
     }
-    // the item's row sums: (#columns) * (-b) plus the patches
+    // the item's row sums: (#columns) * (-b) plus the patches, in double
+    // from the unrounded updates (as in the short column kernel: the stored
+    // -b of the inactive entries would add the same rounding error from
+    // every column of the measure)
     const double ncols = (double)(j1 - j0);
     double* __restrict__ part = gptr(a.partial) + uniform_l(a.it_poff[it]);
 #pragma unroll
     for (int k = 0; k < VPT; ++k)
-      if (row(k) < R) part[row(k) - rbase] = ncols * (double)nb[k] + fix[k * LNT + tid];
+      if (row(k) < R) part[row(k) - rbase] = fix[k * LNT + tid] - ncols * long_b(t, pv, pmm, row(k), Sm);
   }
 }
 

@@ -1,8 +1,10 @@
 """HIP path vs the FP64 oracle, element by element (MI355X only).
 
 Tolerances (relative): 1e-10 for FP64 plans, 1e-5 for FP32 plans, on the
-barycenter (L1 and max norms) and, for FP64, on the plans themselves.  The
-oracle consumes exactly the (rounded) inputs the GPU consumes.
+barycenter (L1 and max norms), on every plan entry (max norm of the
+difference over the max norm of the oracle's plans, per measure) and on the
+marginals p^(m).  The oracle consumes exactly the (rounded) inputs the GPU
+consumes.
 """
 import math
 import sys
@@ -56,9 +58,11 @@ def check(p, iters, gate_theta=True, **sched):
     eth = max(rel(a, b, np.inf) for a, b in zip(g["theta"], ora["theta"]))
     say(f"  p_bar rel L1 {e1:.3e}  max {einf:.3e}  theta rel max {eth:.3e}")
     assert e1 <= tol and einf <= tol
-    if gate_theta and p.dtype == "f64":
+    if gate_theta:
         assert eth <= tol
-    np.testing.assert_allclose(g["pm"], ora["pm"], rtol=0, atol=tol * np.abs(ora["pm"]).max() * 10)
+    epm = np.abs(g["pm"] - ora["pm"]).max() / np.abs(ora["pm"]).max()
+    say(f"  marginals rel max {epm:.3e}")
+    assert epm <= tol
     return g, ora
 
 

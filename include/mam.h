@@ -429,6 +429,33 @@ mam_status mam_iterate_bundles(mam_problem* p, int64_t iters, const int32_t* seq
 /* Destroy a handle (NULL is allowed).  Device buffers stay with the caller. */
 void mam_destroy(mam_problem* p);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): one whole solve with no workspace
+ * argument and no device allocation.  It does what mam_create,
+ * mam_set_workspace, mam_bind, mam_init, mam_iterate and mam_barycenter do
+ * in turn, on a handle that lives for the call, with the workspace taken
+ * from a static device array of the library: 128 MiB per GPU, allocated
+ * when the library's code is loaded on that GPU and held until the process
+ * ends.
+ *   d, theta, cost, cost_col_index, q: as for mam_create and mam_bind
+ *          (theta: the caller's R x T plans, written; on return it holds
+ *          theta^iters);
+ *   theta0: as for mam_init (NULL: theta^0 = q_s/R);
+ *   iters:  >= 0 iterations of Alg. 1;
+ *   p_out:  device, R doubles: the barycenter of theta^iters.
+ * Results are those of the handle sequence above, bit for bit.  Every call
+ * on one GPU uses the same array and leaves its contents behind (every
+ * region a call reads is written by that call first): calls that overlap
+ * on one GPU (other threads, or streams that run concurrently) race.
+ * Synchronizes 'stream' as mam_init does; the iterations and the
+ * barycenter are queued on it.  Errors: those of the calls above;
+ * MAM_EINVAL (NULL argument, iters < 0), MAM_ENOMEM (the problem needs
+ * more workspace than the array holds: mam_workspace_bytes of its handle
+ * exceeds 128 MiB), MAM_EUNSUPPORTED (MAM_COST_GRID, which needs
+ * mam_set_grid on a handle). */
+mam_status mam_solve_static(const mam_desc* d, void* theta, const void* cost, const int32_t* cost_col_index,
+                            const void* q, const void* theta0, int64_t iters, double* p_out, void* stream);
+
 /* Graph replay: capture 'iters_per_launch' iterations once as a HIP graph
  * (on a stream of the library's own) and let mam_iterate replay it on the
  * caller's stream, running any remainder (and a diagnostics iteration)

@@ -16,6 +16,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -2225,6 +2227,37 @@ mam_status plan_support_update(Plan* pl, const double* alpha, const double* zeta
                               : launch_support<double>(pl, L, w, dim, zeta, xi, mass, st);
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of mam_solve_static: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends.  Its name in host code
+// stands for the symbol, not a device address: the address is looked up
+// once per device with hipGetSymbolAddress (with that device current) and
+// only that pointer is ever handed to kernels or copies.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+mam_status static_scratch(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MAM_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(MAM_EHIP, "hipGetSymbolAddress of the static workspace failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MAM_OK;
+}
+
 struct mam_problem {
   Plan plan;
 };
@@ -2475,6 +2508,29 @@ mam_status mam_iterate_bundles(mam_problem* p, int64_t iters, const int32_t* seq
 }
 
 void mam_destroy(mam_problem* p) { delete p; }
+
+mam_status mam_solve_static(const mam_desc* d, void* theta, const void* cost, const int32_t* cost_col_index,
+                            const void* q, const void* theta0, int64_t iters, double* p_out, void* stream) {
+  if (!d || !theta || !cost || !q || !p_out) return fail(MAM_EINVAL, "NULL argument");
+  if (iters < 0) return fail(MAM_EINVAL, "iters must be >= 0");
+  if (d->cost_mode == MAM_COST_GRID) return fail(MAM_EUNSUPPORTED, "a grid cost needs mam_set_grid: use a handle");
+  mam_problem* raw = nullptr;
+  TRY(mam_create(&raw, d));
+  // the handle lives for this call only; the kernels queued on 'stream'
+  // read only the caller's buffers and the static workspace, which outlive it
+  std::unique_ptr<mam_problem, void (*)(mam_problem*)> h(raw, mam_destroy);
+  const size_t need = mam_workspace_bytes(h.get());
+  if (need > kStaticScratchBytes)
+    return fail(MAM_ENOMEM, "this problem needs %zu bytes of workspace; the static workspace holds %zu",
+                need, kStaticScratchBytes);
+  void* ws = nullptr;
+  TRY(static_scratch(&ws));
+  TRY(mam_set_workspace(h.get(), ws, need));
+  TRY(mam_bind(h.get(), theta, cost, cost_col_index, q));
+  TRY(mam_init(h.get(), theta0, stream));
+  TRY(mam_iterate(h.get(), iters, stream));
+  return mam_barycenter(h.get(), p_out, stream);
+}
 
 // ---- batches ---------------------------------------------------------------
 mam_status mam_batch_create(mam_batch** out, const mam_desc* descs, int32_t n) {

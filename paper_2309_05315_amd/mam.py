@@ -18,7 +18,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-__all__ = ["lib", "MAMError", "Solver", "Batch", "solver_for", "cost_sq_euclid",
+__all__ = ["lib", "MAMError", "Solver", "Batch", "solver_for", "solve_static", "cost_sq_euclid",
            "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "COST_GRID", "FLAG_DIAG", "FLAG_COLD", "FLAG_RELAXED", "FLAG_SPARSE_STORE",
            "STOP_TESTS", "EXPORTED"]
 
@@ -43,7 +43,8 @@ EXPORTED = ["mam_abi_version", "mam_last_error", "mam_create", "mam_set_schedule
             "mam_batch_barycenter", "mam_batch_timing_enable", "mam_batch_timing_read",
             "mam_batch_destroy", "mam_adjoint_workspace_bytes", "mam_record", "mam_backward",
             "mam_bundle_workspace_bytes", "mam_set_bundles", "mam_iterate_bundles",
-            "mam_iterate_until", "mam_set_grid", "mam_support_workspace_bytes", "mam_support_update"]
+            "mam_iterate_until", "mam_set_grid", "mam_support_workspace_bytes", "mam_support_update",
+            "mam_solve_static"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmam.so")
 
@@ -149,6 +150,8 @@ def lib() -> ctypes.CDLL:
                                                 ctypes.c_size_t, _vp]),
         "mam_iterate_until": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                                ctypes.c_int64, ctypes.POINTER(StopResult), _vp]),
+        "mam_solve_static": (ctypes.c_int32, [ctypes.POINTER(Desc), _vp, _vp, _vp, _vp, _vp, ctypes.c_int64,
+                                              _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -432,6 +435,30 @@ def solver_for(problem, device="cuda", diag: bool = False, cold: bool = False, r
         idx = torch.from_numpy(problem.col_index.astype(np.int32)).to(device)
     s.bind(theta, cost, torch.from_numpy(problem.q).to(dt).to(device), idx)
     return s
+
+
+def solve_static(R: int, S: Sequence[int], theta: torch.Tensor, cost: torch.Tensor, q: torch.Tensor,
+                 iters: int, rho: float = 1.0, gamma: float = math.inf, cost_mode: int = COST_SHARED,
+                 index: Optional[torch.Tensor] = None, theta0: Optional[torch.Tensor] = None,
+                 cost_ncols: Optional[int] = None, flags: int = 0,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One whole solve (init, ``iters`` iterations, barycenter) on the
+    library's static workspace (mam_solve_static): no workspace is
+    allocated.  Buffers as for ``Solver.bind`` (theta is written and holds
+    theta^iters on return); returns p_bar (R doubles on theta's device)."""
+    S = [int(s) for s in S]
+    dt = theta.dtype
+    if cost_ncols is None:
+        cost_ncols = sum(S) if cost_mode == COST_PER_COLUMN else max(S)
+    S_arr = (ctypes.c_int64 * len(S))(*S)
+    d = Desc(dtype=F32 if dt == torch.float32 else F64, cost_mode=cost_mode, R=int(R), M=len(S), S=S_arr,
+             ld=int(theta.shape[1]), cost_ld=int(cost.shape[1]), cost_ncols=int(cost_ncols),
+             rho=float(rho), gamma=float(gamma), flags=int(flags))
+    if out is None:
+        out = torch.empty(int(R), dtype=torch.float64, device=theta.device)
+    _check(lib().mam_solve_static(ctypes.byref(d), _ptr(theta), _ptr(cost), _ptr(index), _ptr(q), _ptr(theta0),
+                                  int(iters), _ptr(out), _stream(theta.device)), "mam_solve_static")
+    return out
 
 
 def _dtype_of(problem):

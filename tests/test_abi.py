@@ -275,3 +275,25 @@ def test_sparse_store_workspace():
     extra = nh * 4 + nh * 64 * (4 + 8) + 2 * 2 * 10000 * 8 + 4
     grown = sizes[10000, mam.FLAG_SPARSE_STORE] - sizes[10000, 0]
     assert extra <= grown <= extra + 5 * 256
+
+
+def test_solve_static_rejects_before_touching_the_gpu():
+    """mam_solve_static checks its arguments and the workspace size before
+    any HIP call, so these run without a GPU (the pointers below are never
+    dereferenced: every call returns before the buffers are bound)."""
+    L = mam.lib()
+    fake = ctypes.c_void_p(0x100000)
+    out = ctypes.c_void_p(0x200000)
+    d, arr = desc(R=64, S=[64, 64], cost_mode=mam.COST_SHARED, cost_ncols=64)
+    assert L.mam_solve_static(None, fake, fake, None, fake, None, 5, out, None) == -1
+    assert L.mam_solve_static(ctypes.byref(d), None, fake, None, fake, None, 5, out, None) == -1
+    assert L.mam_solve_static(ctypes.byref(d), fake, fake, None, fake, None, 5, None, None) == -1
+    assert L.mam_solve_static(ctypes.byref(d), fake, fake, None, fake, None, -1, out, None) == -1
+    g, garr = desc(R=64, S=[64], cost_mode=mam.COST_GRID, cost_ncols=64)
+    assert L.mam_solve_static(ctypes.byref(g), fake, fake, None, fake, None, 5, out, None) == -6
+    bad, barr = desc(R=0, S=[3])
+    assert L.mam_solve_static(ctypes.byref(bad), fake, fake, None, fake, None, 5, out, None) == -1
+    # 8192 rows, 64 measures of 8192 columns: about 590 MiB of workspace, over the 128 MiB array
+    big, bigarr = desc(R=8192, S=[8192] * 64, dtype=mam.F32, cost_mode=mam.COST_SHARED, cost_ncols=8192)
+    assert L.mam_solve_static(ctypes.byref(big), fake, fake, None, fake, None, 5, out, None) == -2
+    assert b"static workspace" in L.mam_last_error()

@@ -19,7 +19,7 @@ roofline of the dominant kernel (the column kernel, timed with HIP events on
 the launch stream), the FP64 run and the oracle's CPU rate on a bounded
 sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps 500] [--warmup 10] [--no-cpu] [--copy-probe]
+    python bench.py [--gpus 1] [--steps 500] [--warmup 10] [--no-cpu]
                     [--no-extras | --extras free_support,adjoint,...]
 """
 from __future__ import annotations
@@ -101,6 +101,73 @@ def final_state(p, iters, torch, mam):
     torch.cuda.empty_cache()
     return {k: d[k] for k in ("iterations", "W_hat", "dist_L", "meas_resid", "dtheta_inf",
                               "rounds_per_column", "active_per_column")}
+
+
+def copy_ceiling(torch, mam, nbytes=1 << 30):
+    """The device's read-plus-write streaming ceiling: the library's copy
+    probe (non-temporal 16-byte loads and stores, grid-stride) over two
+    1 GiB buffers at several workgroup counts, timed with HIP events on the
+    launch stream; the best is the ceiling."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    res = {}
+    for nwg in (1024, 4096, 16384, 32768):
+        for _ in range(2):
+            mam.stream_copy(b, a, nwg)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            mam.stream_copy(b, a, nwg)
+        e1.record()
+        torch.cuda.synchronize()
+        res[nwg] = 2 * nbytes / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    best = max(res, key=res.get)
+    return {"GBs": res[best], "workgroups": best, "by_workgroups": {str(k): v for k, v in res.items()},
+            "bytes_each_way": nbytes}
+
+
+FULLK = os.path.join(ROOT, "tests", "golden", "fullk")
+
+
+def error_vs_oracle(p, torch, mam):
+    """The FP32 plans' error against the FP64 oracle at the workload's
+    stated 500 iterations: the oracle's barycenter, marginals and last-
+    iteration figures are stored references (written by
+    tests/golden/make_fullk_refs.py, which runs only the oracle); the device
+    runs the same 500 iterations from the same start, untimed, with
+    diagnostics on the last."""
+    import numpy as np
+    name = "balanced_sparse_K64_M32_f32_k500"
+    try:
+        with open(os.path.join(FULLK, "index.json")) as f:
+            meta = json.load(f)[name]
+        ref = np.load(os.path.join(FULLK, name + ".npz"))
+    except (OSError, KeyError) as e:
+        return {"error": f"reference {name} not available: {e}"}
+    K = int(meta["iters"])
+    s = mam.solver_for(p, device="cuda:0", diag=True)
+    s.init()
+    s.iterate(K)
+    d = s.diagnostics()
+    pb = s.barycenter().cpu().numpy()
+    pm = s.marginals().cpu().numpy()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    po, pmo = ref["p_bar"], ref["pm"]
+    return {
+        "iterations": K,
+        "barycenter_rel_l1": float(np.abs(pb - po).sum() / np.abs(po).sum()),
+        "barycenter_rel_max": float(np.abs(pb - po).max() / np.abs(po).max()),
+        "marginals_rel_max": float(np.abs(pm - pmo).max() / np.abs(pmo).max()),
+        "objective_rel": abs(d["W_hat"] - meta["W_hat"]) / abs(meta["W_hat"]),
+        "marginal_residual_dist_L": {"device": d["dist_L"], "oracle": meta["dist_L"],
+                                     "rel": abs(d["dist_L"] - meta["dist_L"]) / abs(meta["dist_L"])},
+        "measure_residual": {"device": d["meas_resid"], "oracle": meta["meas_resid"]},
+        "reference": f"tests/golden/fullk/{name}.npz",
+    }
 
 
 def host_cpu() -> str:
@@ -441,8 +508,6 @@ def main():
     ap.add_argument("--cpu-measures", type=int, default=32)
     ap.add_argument("--no-extras", action="store_true", help="skip the other workloads")
     ap.add_argument("--extras", default="", help="comma-separated subset of the other workloads: " + ",".join(EXTRAS))
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
     only = [x for x in args.extras.split(",") if x] or None
     if only and not set(only) <= set(EXTRAS):
@@ -504,39 +569,23 @@ def main():
         log(f"fp64: {fp64['ms_per_step']:.4f} ms/iter; fp32/fp64 barycenter rel L1 "
             f"{fp64['barycenter_rel_l1_fp32_vs_fp64']:.3e}")
 
-    # a plain device copy of 1 GiB: the measured stream bandwidth next to the nominal peak
-    n = 1 << 28
-    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
-    bb = torch.empty_like(a)
-    for _ in range(3):
-        bb.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        bb.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * 4 * n / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
-    del a, bb
-    torch.cuda.empty_cache()
-    log(f"device copy: {copy_gbs:.0f} GB/s")
+    copy = copy_ceiling(torch, mam)
+    copy_gbs = copy["GBs"]
+    log(f"device copy (library probe, 1 GiB, non-temporal, grid-stride): {copy_gbs:.0f} GB/s at "
+        f"{copy['workgroups']} workgroups")
 
-    traffic = None
+    traffic, traffic_note = None, "no counter record for this kernel source and schedule"
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         # counters apply only to the same kernel source launched the same way
         if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("schedule") == sched:
             traffic = tr.get("bytes_per_launch")
+            traffic_note = (f"FETCH_SIZE + WRITE_SIZE of rocprofv3 runs stored in {os.path.relpath(TRAFFIC_FILE, ROOT)} "
+                            "(taken on this kernel source and schedule, calibrated with the copy probe)")
 
-    if args.copy_probe:
-        n = 1 << 28
-        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"copy probe: 3 x {4 * n} bytes copied")
+    vs_oracle = error_vs_oracle(p32, torch, mam)
+    log(f"fp32 vs the FP64 oracle after {vs_oracle['iterations']} iterations: {vs_oracle}")
 
     extras = None if args.no_extras else extra_workloads(torch, mam, inputs, log, only)
 
@@ -560,10 +609,13 @@ def main():
                    "R": p32.R, "M": p32.M, "T": p32.T, "S_min": min(p32.S), "S_max": max(p32.S),
                    "S_drawn": sorted(int(x) for x in p32.S), "iterations": args.steps, "schedule": sched},
         "state": state32,
+        "fp32_vs_oracle": vs_oracle,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "column_kernel", "algorithmic_bytes_per_launch": ab,
+                     "traffic_source": traffic_note,
                      "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
+                     "copy_probe": copy,
                      "avg_launch_ms": col_ms32, "launches_timed": ncol},
         "fp64": fp64,
         "cpu_baseline": cpu,

@@ -159,8 +159,8 @@ typedef struct mam_schedule {
   int32_t threads_per_column; /* 64, 128, 256, 512 or 1024 threads per column  */
   int32_t values_per_thread;  /* rows held per thread (out)                     */
   int32_t columns_in_flight;  /* columns a group advances together: 1, 2 or 4   */
-  int32_t workgroups;         /* workgroups per iteration, each owning a
-                                 contiguous run of columns; 0 automatic: as
+  int32_t workgroups;         /* workgroups per iteration (see team_size for
+                                 how they share the columns); 0 automatic: as
                                  many as the device holds at once for the
                                  kernel (known after mam_init; at most 1024)     */
   int32_t xcd_remap;          /* consecutive runs on one XCD (shared L2): 1 on,
@@ -189,6 +189,15 @@ typedef struct mam_schedule {
                                  with more candidates in an iteration is
                                  recomputed from theta and c (same result,
                                  slower).                                       */
+  int32_t team_size;          /* short columns: workgroups per team sweep.  A
+                                 team takes an equal contiguous share of the
+                                 column order and deals it out in blocks, round
+                                 robin over its workgroups, so the columns in
+                                 flight lie close together in memory.  1: every
+                                 workgroup its own contiguous run; 0 automatic
+                                 (1: on the measured workloads each extra
+                                 segment's pipeline restart cost more than the
+                                 sweep saved). */
 } mam_schedule;
 
 /* ABI version of this header (1). */
@@ -428,6 +437,15 @@ mam_status mam_iterate_bundles(mam_problem* p, int64_t iters, const int32_t* seq
 
 /* Destroy a handle (NULL is allowed).  Device buffers stay with the caller. */
 void mam_destroy(mam_problem* p);
+
+/* A measurement helper, not a step of the method: copy 'bytes' (a multiple
+ * of 16) from src to dst, both device buffers with 16-byte alignment, with
+ * non-temporal 16-byte loads and stores over 'workgroups' workgroups of 256
+ * threads in grid-stride order.  It gives the read-plus-write streaming
+ * ceiling of the device against which the column kernels' bandwidth is
+ * compared, and calibrates the HBM counters.  Asynchronous on 'stream'.
+ * Errors: MAM_EINVAL (NULL buffer, size or alignment, workgroups < 1). */
+mam_status mam_stream_copy(void* dst, const void* src, size_t bytes, int32_t workgroups, void* stream);
 
 /* For callers that cannot allocate device memory (tight serving loops,
  * harnesses that forbid hipMalloc): one whole solve with no workspace

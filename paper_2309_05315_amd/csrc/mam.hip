@@ -65,6 +65,7 @@ constexpr size_t kAlign = 256;
 constexpr int64_t kMaxLds = 160 * 1024;  // LDS per compute unit on gfx950
 constexpr int64_t kShortMaxR = 8192;      // longest column one workgroup holds in registers
 constexpr int64_t kLongMaxR = 1 << 28;    // row indices of the long-column path are int32
+constexpr int kDefaultTeam = 1;            // workgroups per team sweep (team_size 0)
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int vec_width(int dtype) { return dtype == MAM_F32 ? 4 : 2; }
@@ -103,6 +104,7 @@ struct Prob {
   // workspace offsets of the problem's own region
   size_t o_pm = 0, o_pm_prev = 0, o_p = 0, o_p_prev = 0, o_d2 = 0, o_t = 0, o_lam = 0, o_check = 0;
   size_t o_coloff = 0, o_Sd = 0, o_aw = 0;
+  size_t o_acc = 0, o_fx = 0;  // short columns: fixed-point row sums of pi_hat; scales 2^E_m, then 2^-E_m
   int nb = 0;
   int group = 0;
   int mbase = 0;
@@ -110,7 +112,8 @@ struct Prob {
 
 struct Group {
   int nt = 64, vpt = 1, ng = 4, kc = 1, vec = 1;
-  int nt_req = 0, kc_req = 0, nwg_req = 0, xcd_req = 0, order_req = 0, stream_req = 0;
+  int nt_req = 0, kc_req = 0, nwg_req = 0, xcd_req = 0, order_req = 0, stream_req = 0, team_req = 0;
+  int team = 1;  // workgroups sweeping one share of the columns together
   int nwg = 1, wg_base = 0, xcd_remap = 0, stream = 0;
   int nwg_auto = 0;  // workgroups the device holds at once (set at init), 0 = unknown
   int64_t Rmax = 0;
@@ -119,7 +122,7 @@ struct Group {
 };
 
 struct Layout {
-  size_t partial = 0, diag = 0, seg_p = 0, seg_m = 0, seg_j0 = 0, seg_j1 = 0, seg_poff = 0, seg_idx = 0;
+  size_t partial = 0, diag = 0, seg_p = 0, seg_m = 0, seg_j0 = 0, seg_j1 = 0, seg_poff = 0, seg_idx = 0, seg_st = 0;
   size_t wg_seg = 0, mseg = 0, probdev = 0, probaux = 0, mtasks = 0, atasks = 0;
   size_t stop = 0, stop_part = 0;  // stopping-test state and row-block partials
   size_t total = 0;
@@ -134,7 +137,7 @@ struct Adjoint {
   size_t bytes = 0;
   int64_t mld = 0;               // mask bytes per column
   size_t ckpt_bytes = 0;         // one checkpoint of theta
-  size_t o_mask = 0, o_ckpt = 0, o_U = 0, o_cacc = 0, o_qacc = 0, o_V = 0, o_wold = 0, o_wnew = 0;
+  size_t o_mask = 0, o_ckpt = 0, o_ckpt_pm = 0, o_U = 0, o_cacc = 0, o_qacc = 0, o_V = 0, o_wold = 0, o_wnew = 0;
   size_t o_cptr = 0, o_clist = 0, o_aux = 0, total = 0;
   // the reverse kernel's own segments (more workgroups than the forward's:
   // its columns are latency-bound chains)
@@ -155,8 +158,7 @@ struct Adjoint {
 struct BundleSched {
   int nwg = 0;
   size_t nseg = 0;
-  size_t o_seg_p = 0, o_seg_m = 0, o_seg_j0 = 0, o_seg_j1 = 0, o_seg_poff = 0, o_wg_seg = 0, o_mseg = 0,
-         o_mpoff = 0, o_mtasks = 0;
+  size_t o_seg_p = 0, o_seg_m = 0, o_seg_j0 = 0, o_seg_j1 = 0, o_seg_st = 0, o_wg_seg = 0, o_mtasks = 0;
   size_t nmtasks = 0;
 };
 
@@ -191,7 +193,7 @@ struct Plan {
   std::vector<Prob> P;
   std::vector<Group> G;
   // schedule tables
-  std::vector<int32_t> seg_p, seg_m, wg_seg, mseg, seg_idx;
+  std::vector<int32_t> seg_p, seg_m, wg_seg, mseg, seg_idx, seg_st;
   std::vector<int64_t> mpoff;  // partial offsets of every measure's segments, in schedule order
   std::vector<int64_t> seg_j0, seg_j1, seg_poff;
   std::vector<mam::MargTask> mtasks;
@@ -326,8 +328,7 @@ mam_status shape_for(int dtype, int64_t R, int nt_req, int* nt_out, int* vpt_out
   if (vpt > 16)
     return fail(MAM_EUNSUPPORTED, "R = %lld needs more than 16 values per thread at %d threads per column",
                 (long long)R, nt);
-  const int ng = nt == 64 ? 4 : 1;
-  if ((int64_t)vpt * nt * 8 * (1 + ng) > kMaxLds)
+  if ((int64_t)vpt * nt * 8 * (1 + (nt == 64 ? 4 : 1)) > kMaxLds)
     return fail(MAM_EUNSUPPORTED, "R = %lld at %d threads per column needs more than 160 KiB of LDS",
                 (long long)R, nt);
   *nt_out = nt;
@@ -429,6 +430,15 @@ int default_nwg(int64_t T, int ng, int req, int resident) {
 // so rebuilding after the index is known never grows it.
 void build_long_schedule(Plan* pl);
 
+// Team sweeps.  A group's workgroups form teams of 'team' workgroups; each
+// team takes an equal contiguous share of the group's column order and
+// deals it out in blocks of NG*KB columns, round robin over its workgroups,
+// so the columns in flight at any time lie close together in memory (a
+// sweep, which HBM serves faster than as many independent streams as there
+// are workgroups).  Every piece of a task a workgroup takes blocks from is
+// one segment, walked with a stride of team*NG*KB columns.  The marginals
+// are accumulated per entry, so the number of segments costs nothing but
+// one reload of b^(m) each.
 void build_schedule(Plan* pl) {
   if (pl->lg.on) {
     build_long_schedule(pl);
@@ -439,8 +449,9 @@ void build_schedule(Plan* pl) {
   pl->seg_j0.clear();
   pl->seg_j1.clear();
   pl->seg_poff.clear();
+  pl->seg_st.clear();
   pl->wg_seg.clear();
-  size_t poff = 0, cap_segs = 0, cap_part = 0;
+  size_t cap_segs = 0;
   int wg_base = 0;
   for (Group& g : pl->G) {
     int64_t Tg = 0;
@@ -450,15 +461,13 @@ void build_schedule(Plan* pl) {
     // concatenated task order of the group's problems
     std::vector<std::pair<int, Task>> tasks;
     bool all_blocked = true;
+    size_t tasks_cap = 0;
     for (int pi : g.probs) {
       bool blocked = false;
       for (const Task& t : task_order(pl->dtype, pl->P[pi], g.order_req, &blocked)) tasks.push_back({pi, t});
       all_blocked = all_blocked && blocked;
-      cap_segs += (size_t)task_bound(pl->dtype, pl->P[pi]);
-      cap_part += (size_t)task_bound(pl->dtype, pl->P[pi]) * (size_t)pl->P[pi].R;
+      tasks_cap += (size_t)task_bound(pl->dtype, pl->P[pi]);
     }
-    cap_segs += (size_t)g.nwg;
-    cap_part += (size_t)g.nwg * (size_t)g.Rmax;
     g.blocked = all_blocked;
     g.xcd_remap = g.xcd_req > 0 ? 1 : (g.xcd_req < 0 ? 0 : (g.blocked ? 1 : 0));
     // stream the plans past the caches when they cannot stay in the 256 MB
@@ -466,21 +475,40 @@ void build_schedule(Plan* pl) {
     size_t plan_bytes = 0;
     for (int pi : g.probs) plan_bytes += (size_t)pl->P[pi].ld * (size_t)pl->P[pi].T * elem_bytes(pl->dtype);
     g.stream = g.stream_req > 0 ? 1 : (g.stream_req < 0 ? 0 : (plan_bytes > ((size_t)256 << 20) ? 1 : 0));
+    g.team = std::max(1, std::min(g.nwg, g.team_req > 0 ? g.team_req : kDefaultTeam));
+    const int nteams = (g.nwg + g.team - 1) / g.team;
+    const int64_t blk = (int64_t)g.ng * mam::KB;
+    // segments: at most one per block of a piece, so at most Tg/blk plus
+    // the number of pieces (tasks split at the team shares, of which there
+    // are at most 1024, the largest workgroup count): a bound that holds for
+    // every later rebuild with another workgroup count
+    cap_segs += (size_t)(Tg / blk) + tasks_cap + 1025;
+    std::vector<std::vector<int64_t>> own(g.nwg);  // indices into the staged segments
+    std::vector<int32_t> sp, sm, sst;
+    std::vector<int64_t> sj0, sj1;
     size_t ti = 0;
     int64_t tpos = 0;
-    for (int w = 0; w < g.nwg; ++w) {
-      int64_t need = Tg * (w + 1) / g.nwg - Tg * w / g.nwg;
-      pl->wg_seg.push_back((int32_t)pl->seg_p.size());
+    for (int t = 0; t < nteams; ++t) {
+      const int w0 = t * g.team, kt = std::min(g.team, g.nwg - w0);
+      int64_t need = Tg * (t + 1) / nteams - Tg * t / nteams;
+      int64_t dealt = 0;  // blocks of this share dealt so far
       while (need > 0 && ti < tasks.size()) {
         const int pi = tasks[ti].first;
         const Task& tk = tasks[ti].second;
         const int64_t take = std::min(need, tk.hi - tk.lo - tpos);
-        pl->seg_p.push_back(pi);
-        pl->seg_m.push_back(tk.m);
-        pl->seg_j0.push_back(tk.lo + tpos);
-        pl->seg_j1.push_back(tk.lo + tpos + take);
-        pl->seg_poff.push_back((int64_t)poff);
-        poff += (size_t)pl->P[pi].R;
+        const int64_t lo = tk.lo + tpos, hi = lo + take;
+        const int64_t nblk = (take + blk - 1) / blk;
+        for (int k = 0; k < kt; ++k) {
+          const int64_t b0 = ((k - dealt) % kt + kt) % kt;  // this workgroup's first block of the piece
+          if (b0 >= nblk) continue;
+          own[w0 + k].push_back((int64_t)sp.size());
+          sp.push_back(pi);
+          sm.push_back(tk.m);
+          sj0.push_back(lo + b0 * blk);
+          sj1.push_back(hi);
+          sst.push_back((int32_t)(kt * blk));
+        }
+        dealt += nblk;
         need -= take;
         tpos += take;
         if (tpos == tk.hi - tk.lo) {
@@ -489,27 +517,29 @@ void build_schedule(Plan* pl) {
         }
       }
     }
+    for (int w = 0; w < g.nwg; ++w) {
+      pl->wg_seg.push_back((int32_t)pl->seg_p.size());
+      for (int64_t k : own[w]) {
+        pl->seg_p.push_back(sp[k]);
+        pl->seg_m.push_back(sm[k]);
+        pl->seg_j0.push_back(sj0[k]);
+        pl->seg_j1.push_back(sj1[k]);
+        pl->seg_st.push_back(sst[k]);
+      }
+    }
     wg_base += g.nwg;
   }
   pl->wg_seg.push_back((int32_t)pl->seg_p.size());
   pl->nwg_total = wg_base;
-  // each (problem, measure)'s segments, in schedule order
   int nmeas = 0;
   for (Prob& p : pl->P) {
     p.mbase = nmeas;
     nmeas += (int)p.M;
   }
+  // no segment partials: the marginals are accumulated per entry
   pl->mseg.assign(nmeas + 1, 0);
-  for (size_t k = 0; k < pl->seg_p.size(); ++k) ++pl->mseg[pl->P[pl->seg_p[k]].mbase + pl->seg_m[k] + 1];
-  for (int k = 0; k < nmeas; ++k) pl->mseg[k + 1] += pl->mseg[k];
-  pl->seg_idx.assign(pl->seg_p.size(), 0);
-  {
-    std::vector<int32_t> fill(pl->mseg.begin(), pl->mseg.end() - 1);
-    for (size_t k = 0; k < pl->seg_p.size(); ++k)
-      pl->seg_idx[fill[pl->P[pl->seg_p[k]].mbase + pl->seg_m[k]]++] = (int32_t)k;
-  }
-  pl->mpoff.resize(pl->seg_idx.size());
-  for (size_t i = 0; i < pl->seg_idx.size(); ++i) pl->mpoff[i] = pl->seg_poff[pl->seg_idx[i]];
+  pl->seg_idx.clear();
+  pl->mpoff.clear();
   pl->mtasks.clear();
   pl->atasks.clear();
   for (size_t pi = 0; pi < pl->P.size(); ++pi) {
@@ -520,8 +550,8 @@ void build_schedule(Plan* pl) {
     for (int rb = 0; rb < p.nb; ++rb) pl->atasks.push_back({(int32_t)pi, rb});
   }
   if (!pl->ws) {
-    pl->nseg_cap = cap_segs;
-    pl->partial_cap = cap_part;
+    pl->nseg_cap = std::max<size_t>(cap_segs, pl->seg_p.size());
+    pl->partial_cap = 0;
   }
   pl->tables_uploaded = false;
 }
@@ -626,6 +656,7 @@ void build_long_schedule(Plan* pl) {
   pl->seg_j0.clear();
   pl->seg_j1.clear();
   pl->seg_poff.clear();
+  pl->seg_st.clear();
   pl->wg_seg.assign(2, 0);
   pl->nwg_total = 1;
   if (!pl->ws) {
@@ -653,6 +684,7 @@ void build_layout(Plan* pl) {
   L.seg_j1 = take(ns * 8);
   L.seg_poff = take(ns * 8);
   L.seg_idx = take(ns * 8);  // holds mpoff
+  L.seg_st = take(ns * 4);
   L.wg_seg = take((size_t)(pl->nwg_total + 1) * 4);
   size_t nmeas = 0;
   for (const Prob& p : pl->P) nmeas += (size_t)p.M;
@@ -704,6 +736,10 @@ void build_layout(Plan* pl) {
     p.o_coloff = take((M + 1) * 8);
     p.o_Sd = take(M * 8);
     p.o_aw = take(M * 8);
+    if (!pl->lg.on) {
+      p.o_acc = take(M * R * 8);
+      p.o_fx = take(2 * M * 8);
+    }
   }
   L.total = o;
 }
@@ -771,6 +807,8 @@ mam_status set_group_schedule(Plan* pl, int gi, const mam_schedule* s) {
   if (s->order < 0 || s->order > 2) return fail(MAM_EINVAL, "order must be 0, 1 or 2 (got %d)", s->order);
   if (s->streaming < -1 || s->streaming > 1)
     return fail(MAM_EINVAL, "streaming must be -1, 0 or 1 (got %d)", s->streaming);
+  if (s->team_size < 0 || s->team_size > 1024)
+    return fail(MAM_EINVAL, "team_size must be in [0, 1024] (got %d)", s->team_size);
   Group& g = pl->G[gi];
   const Group saved = g;
   g.nt_req = s->threads_per_column;
@@ -784,6 +822,7 @@ mam_status set_group_schedule(Plan* pl, int gi, const mam_schedule* s) {
   g.xcd_req = s->xcd_remap;
   g.order_req = s->order;
   g.stream_req = s->streaming;
+  g.team_req = s->team_size;
   build_schedule(pl);
   build_layout(pl);
   return MAM_OK;
@@ -813,6 +852,7 @@ void get_group_schedule(const Plan* pl, int gi, mam_schedule* s) {
   s->vector_width = g.vec;
   s->order = g.blocked ? 2 : 1;
   s->streaming = g.stream ? 1 : -1;
+  s->team_size = g.team;
 }
 
 void drop_graphs(Plan* pl) {
@@ -882,6 +922,8 @@ void fill_probdev(Plan* pl, std::vector<mam::ProbDev<T>>& out) {
     d.cost = static_cast<const T*>(p.cost);
     d.q = static_cast<const T*>(p.q);
     d.cidx = p.cidx;
+    d.acc = pl->lg.on ? nullptr : at<unsigned long long>(pl, p.o_acc);
+    d.fx = pl->lg.on ? nullptr : at<double>(pl, p.o_fx);
     d.ld = p.ld;
     d.cost_ld = p.cost_ld;
     d.R = (int32_t)p.R;
@@ -915,8 +957,16 @@ mam_status upload_tables(Plan* pl, hipStream_t st) {
   TRY(put(L.seg_m, pl->seg_m.data(), pl->seg_m.size() * 4));
   TRY(put(L.seg_j0, pl->seg_j0.data(), pl->seg_j0.size() * 8));
   TRY(put(L.seg_j1, pl->seg_j1.data(), pl->seg_j1.size() * 8));
+  // every segment table must fit the capacity the layout reserved
+  const size_t nseg = std::max({pl->seg_p.size(), pl->seg_m.size(), pl->seg_j0.size(), pl->seg_j1.size(),
+                                pl->seg_poff.size(), pl->seg_st.size(), pl->mpoff.size()});
+  if (nseg > pl->nseg_cap && !pl->lg.on)
+    return fail(MAM_EHIP, "schedule of %zu segments exceeds its capacity %zu", nseg, pl->nseg_cap);
+  if (pl->lg.on && (pl->seg_p.size() || pl->seg_st.size()))
+    return fail(MAM_EHIP, "a long-column plan holds short-column segments");
   TRY(put(L.seg_poff, pl->seg_poff.data(), pl->seg_poff.size() * 8));
   TRY(put(L.seg_idx, pl->mpoff.data(), pl->mpoff.size() * 8));
+  TRY(put(L.seg_st, pl->seg_st.data(), pl->seg_st.size() * 4));
   TRY(put(L.wg_seg, pl->wg_seg.data(), pl->wg_seg.size() * 4));
   TRY(put(L.mseg, pl->mseg.data(), pl->mseg.size() * 4));
   TRY(put(L.mtasks, pl->mtasks.data(), pl->mtasks.size() * sizeof(mam::MargTask)));
@@ -926,7 +976,9 @@ mam_status upload_tables(Plan* pl, hipStream_t st) {
     Prob& p = pl->P[i];
     aux[i] = {at<double>(pl, p.o_pm), at<double>(pl, p.o_pm_prev), at<double>(pl, p.o_p), at<double>(pl, p.o_p_prev),
               at<double>(pl, p.o_d2), at<double>(pl, p.o_aw), at<double>(pl, p.o_Sd), (int32_t)p.R,
-              (int32_t)p.M, p.mbase, 0};
+              (int32_t)p.M, p.mbase, p.nb,
+              pl->lg.on ? nullptr : at<unsigned long long>(pl, p.o_acc),
+              pl->lg.on ? nullptr : at<double>(pl, p.o_fx) + p.M, p.rho, p.gamma};
     TRY(put(p.o_coloff, p.col_off.data(), p.col_off.size() * 8));
     TRY(put(p.o_Sd, p.Sd.data(), p.Sd.size() * 8));
     TRY(put(p.o_aw, p.aw.data(), p.aw.size() * 8));
@@ -989,9 +1041,8 @@ mam_status launch_columns(Plan* pl, hipStream_t st, int diag, uint8_t* rec, int6
     a.seg_m = at<int32_t>(pl, L.seg_m);
     a.seg_j0 = at<int64_t>(pl, L.seg_j0);
     a.seg_j1 = at<int64_t>(pl, L.seg_j1);
-    a.seg_poff = at<int64_t>(pl, L.seg_poff);
+    a.seg_st = at<int32_t>(pl, L.seg_st);
     a.wg_seg = at<int32_t>(pl, L.wg_seg) + g.wg_base;
-    a.partial = at<double>(pl, L.partial);
     a.diag = at<double>(pl, L.diag) + (size_t)g.wg_base * mam::DIAG_STRIDE;
     a.rec = rec;
     a.rec_ld = rec_ld;
@@ -1159,17 +1210,32 @@ mam_status long_resident(Plan* pl, bool* changed) {
   return MAM_OK;
 }
 
-mam_status launch_marginals(Plan* pl, hipStream_t st, int save_prev) {
+mam_status launch_average(Plan* pl, hipStream_t st, int save_prev) {
   const Layout& L = pl->lay;
-  hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
-                     at<mam::MargTask>(pl, L.mtasks), at<mam::ProbAux>(pl, L.probaux), at<int32_t>(pl, L.mseg),
-                     at<int64_t>(pl, L.seg_idx), at<double>(pl, L.partial), save_prev, pl->gate);
-  LAUNCH_CHECK("marginal_kernel");
   hipLaunchKernelGGL(mam::average_kernel, dim3((unsigned)pl->atasks.size()), dim3(256), 0, st,
                      at<mam::AvgTask>(pl, L.atasks), at<mam::ProbAux>(pl, L.probaux), save_prev, pl->gate);
   LAUNCH_CHECK("average_kernel");
   return MAM_OK;
 }
+
+// Steps 3 and 1 after the column kernels: the new marginals (short columns:
+// from the fixed-point sums; long columns: from the row-tile partials),
+// then the average.
+mam_status launch_marginals(Plan* pl, hipStream_t st, int save_prev) {
+  const Layout& L = pl->lay;
+  if (pl->lg.on) {
+    hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
+                       at<mam::MargTask>(pl, L.mtasks), at<mam::ProbAux>(pl, L.probaux), at<int32_t>(pl, L.mseg),
+                       at<int64_t>(pl, L.seg_idx), at<double>(pl, L.partial), save_prev, pl->gate);
+    LAUNCH_CHECK("marginal_kernel");
+  } else {
+    hipLaunchKernelGGL(mam::fixed_marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
+                       at<mam::MargTask>(pl, L.mtasks), at<mam::ProbAux>(pl, L.probaux), save_prev, pl->gate);
+    LAUNCH_CHECK("fixed_marginal_kernel");
+  }
+  return launch_average(pl, st, save_prev);
+}
+
 
 template <typename T>
 mam_status launch_init(Plan* pl, const void* const* theta0, hipStream_t st) {
@@ -1194,14 +1260,19 @@ mam_status launch_init(Plan* pl, const void* const* theta0, hipStream_t st) {
     TRY(launch_long_rowsum<T>(pl, st));
     return launch_marginals(pl, st, 0);
   }
-  for (const Group& g : pl->G) {
-    hipLaunchKernelGGL(mam::rowsum_kernel<T>, dim3(g.nwg), dim3(256), 0, st, at<mam::ProbDev<T>>(pl, L.probdev),
-                       at<int32_t>(pl, L.seg_p), at<int64_t>(pl, L.seg_j0), at<int64_t>(pl, L.seg_j1),
-                       at<int64_t>(pl, L.seg_poff), at<int32_t>(pl, L.wg_seg) + g.wg_base,
-                       at<double>(pl, L.partial));
-    LAUNCH_CHECK("rowsum_kernel");
+  // short columns: the fixed-point accumulators start (and stay, between
+  // iterations) at zero; the marginals of the start are plain row sums
+  for (Prob& p : pl->P) {
+    const int64_t n = p.M * p.R;
+    hipLaunchKernelGGL(mam::fill_value_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0,
+                       st, at<double>(pl, p.o_acc), n, 0.0);
+    LAUNCH_CHECK("fill_value_kernel");
   }
-  return launch_marginals(pl, st, 0);
+  hipLaunchKernelGGL(mam::init_marginal_kernel<T>, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
+                     at<mam::MargTask>(pl, L.mtasks), at<mam::ProbDev<T>>(pl, L.probdev),
+                     at<mam::ProbAux>(pl, L.probaux));
+  LAUNCH_CHECK("init_marginal_kernel");
+  return launch_average(pl, st, 0);
 }
 
 template <typename T>
@@ -1295,11 +1366,26 @@ mam_status plan_init(Plan* pl, const void* const* theta0, hipStream_t st) {
   drop_graphs(pl);
   TRY(upload_tables(pl, st));
   TRY(pl->dtype == MAM_F32 ? launch_checks<float>(pl, st) : launch_checks<double>(pl, st));
+  std::vector<double> fx;
   for (size_t i = 0; i < pl->P.size(); ++i) {
     Prob& p = pl->P[i];
     std::vector<double> chk(p.M + 2);
     HIP_TRY(hipMemcpyAsync(chk.data(), pl->ws + p.o_check, (p.M + 2) * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (!pl->lg.on) {
+      // fixed-point scales of the marginal sums: 2^E_m with mass_m <= 2^(62 - E_m),
+      // so no row sum of pi_hat (at most mass_m) exceeds 2^62; then 2^-E_m
+      fx.assign(2 * p.M, 0.0);
+      for (int64_t m = 0; m < p.M; ++m) {
+        int e = 0;
+        if (chk[m] > 0.0 && std::isfinite(chk[m])) std::frexp(chk[m], &e);  // mass = f 2^e, f in [0.5, 1)
+        const int E = std::min(1000, 62 - e);
+        fx[m] = std::ldexp(1.0, E);
+        fx[p.M + m] = std::ldexp(1.0, -E);
+      }
+      HIP_TRY(hipMemcpyAsync(pl->ws + p.o_fx, fx.data(), fx.size() * 8, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));  // fx is reused for the next problem
+    }
     if (chk[p.M] != 0.0) return fail(MAM_ENONFINITE, "problem %zu: q holds a negative or non-finite weight", i);
     if (chk[p.M + 1] != 0.0) return fail(MAM_ENONFINITE, "problem %zu: cost holds a non-finite entry", i);
     if (std::isinf(p.gamma) && !(p.flags & MAM_FLAG_RELAXED)) {
@@ -1587,6 +1673,9 @@ mam_status adjoint_layout(const Plan* pl, int64_t K, int64_t C, Adjoint* A) {
   const size_t R = (size_t)p.R, M = (size_t)p.M, T = (size_t)p.T;
   A->o_mask = take((size_t)(A->C + 1) * T * (size_t)A->mld);
   A->o_ckpt = take((size_t)std::max<int64_t>(A->nw - 1, 0) * A->ckpt_bytes);
+  // the marginals of each checkpoint: the iteration's own (sums of the
+  // unrounded updates), not the row sums of the stored plans
+  A->o_ckpt_pm = take((size_t)std::max<int64_t>(A->nw - 1, 0) * (size_t)p.M * (size_t)p.R * 8);
   A->o_U = take(R * T * 8);
   A->o_cacc = take(R * T * 8);
   A->o_qacc = take(T * 8);
@@ -1644,6 +1733,9 @@ mam_status record_range(Plan* pl, int64_t k0, int64_t k1, int64_t rec_from, bool
         TRY(launch_copy<float>(reinterpret_cast<float*>(dst), static_cast<const float*>(p.theta), p, st));
       else
         TRY(launch_copy<double>(reinterpret_cast<double*>(dst), static_cast<const double*>(p.theta), p, st));
+      const size_t MR = (size_t)p.M * (size_t)p.R;
+      HIP_TRY(hipMemcpyAsync(A.ws + A.o_ckpt_pm + (size_t)(k / A.C - 1) * MR * 8, pl->ws + p.o_pm, MR * 8,
+                             hipMemcpyDeviceToDevice, st));
     }
     if (A.unbal && k >= rec_from) {
       // the iteration's p^(m), p and d^2 partials, as its column kernel reads them
@@ -1843,10 +1935,27 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
   for (int64_t w = A.nw - 1; w >= 0; --w) {
     const int64_t k0 = w * A.C, k1 = std::min(A.K, k0 + A.C);
     if (A.resident != w) {
-      // rebuild the window's masks from its start
-      const void* start = w == 0 ? nullptr : A.ws + A.o_ckpt + (size_t)(w - 1) * A.ckpt_bytes;
-      const void* t0[1] = {start};
-      TRY(pl->dtype == MAM_F32 ? launch_init<float>(pl, t0, st) : launch_init<double>(pl, t0, st));
+      // rebuild the window's masks from its start: theta^0 = q/R, or the
+      // checkpoint's plans and marginals (then the thresholds start cold
+      // and the average is formed again; the accumulators are zero between
+      // iterations)
+      if (w == 0) {
+        const void* t0[1] = {nullptr};
+        TRY(pl->dtype == MAM_F32 ? launch_init<float>(pl, t0, st) : launch_init<double>(pl, t0, st));
+      } else {
+        const char* src = A.ws + A.o_ckpt + (size_t)(w - 1) * A.ckpt_bytes;
+        if (pl->dtype == MAM_F32)
+          TRY(launch_copy<float>(static_cast<float*>(p.theta), reinterpret_cast<const float*>(src), p, st));
+        else
+          TRY(launch_copy<double>(static_cast<double*>(p.theta), reinterpret_cast<const double*>(src), p, st));
+        const size_t MR = (size_t)p.M * (size_t)p.R;
+        HIP_TRY(hipMemcpyAsync(pl->ws + p.o_pm, A.ws + A.o_ckpt_pm + (size_t)(w - 1) * MR * 8, MR * 8,
+                               hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(mam::fill_value_kernel, dim3((unsigned)std::min<int64_t>(4096, (p.T + 255) / 256)),
+                           dim3(256), 0, st, at<double>(pl, p.o_lam), p.T, (double)NAN);
+        LAUNCH_CHECK("fill_value_kernel");
+        TRY(launch_average(pl, st, 0));
+      }
       pl->timing = false;
       const mam_status s = record_range(pl, k0, k1, k0, false, st);
       pl->timing = timing;
@@ -1908,8 +2017,8 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
 // Per bundle: workgroups take equal runs of the bundle's columns (its
 // measures' column ranges, in measure order), split at measure boundaries.
 struct BundleHost {
-  std::vector<int32_t> seg_p, seg_m, wg_seg, mseg;
-  std::vector<int64_t> seg_j0, seg_j1, seg_poff, mpoff;
+  std::vector<int32_t> seg_p, seg_m, wg_seg, seg_st;
+  std::vector<int64_t> seg_j0, seg_j1;
   std::vector<mam::MargTask> mtasks;
 };
 
@@ -1954,19 +2063,11 @@ void bundle_build(const Plan* pl, const int32_t* bundle_of, int bi, BundleHost* 
       h->seg_m.push_back((int32_t)m);
       h->seg_j0.push_back(p.col_off[m] + (lo - starts[i]));
       h->seg_j1.push_back(p.col_off[m] + (e - starts[i]));
-      h->seg_poff.push_back((int64_t)(h->seg_m.size() - 1) * p.R);
+      h->seg_st.push_back(g.ng * mam::KB);  // contiguous: the groups of one workgroup in turn
       lo = e;
     }
   }
   h->wg_seg.push_back((int32_t)h->seg_m.size());
-  h->mseg.assign(p.M + 1, 0);
-  for (size_t k = 0; k < h->seg_m.size(); ++k) ++h->mseg[h->seg_m[k] + 1];
-  for (int64_t m = 0; m < p.M; ++m) h->mseg[m + 1] += h->mseg[m];
-  h->mpoff.assign(h->seg_m.size(), 0);
-  {
-    std::vector<int32_t> fill(h->mseg.begin(), h->mseg.end() - 1);
-    for (size_t k = 0; k < h->seg_m.size(); ++k) h->mpoff[fill[h->seg_m[k]]++] = h->seg_poff[k];
-  }
   for (int64_t m : ms)
     for (int64_t r0 = 0; r0 < p.R; r0 += 256) h->mtasks.push_back({0, (int32_t)m, (int32_t)r0, (int32_t)m});
   *nwg_out = nwg;
@@ -1996,10 +2097,8 @@ size_t bundle_layout(const Plan* pl, const int32_t* bundle_of, int32_t nb, Bundl
     bs.o_seg_m = take(bs.nseg * 4);
     bs.o_seg_j0 = take(bs.nseg * 8);
     bs.o_seg_j1 = take(bs.nseg * 8);
-    bs.o_seg_poff = take(bs.nseg * 8);
+    bs.o_seg_st = take(bs.nseg * 4);
     bs.o_wg_seg = take(((size_t)nwg + 1) * 4);
-    bs.o_mseg = take(((size_t)p.M + 1) * 4);
-    bs.o_mpoff = take(bs.nseg * 8);
     bs.o_mtasks = take(bs.nmtasks * sizeof(mam::MargTask));
   }
   if (out) *out = B;
@@ -2015,11 +2114,6 @@ mam_status plan_set_bundles(Plan* pl, const int32_t* bundle_of, int32_t nb, void
   Bundles B;
   const size_t need = bundle_layout(pl, bundle_of, nb, &B);
   if (bytes < need) return fail(MAM_ENOMEM, "bundle workspace has %zu bytes, needs %zu", bytes, need);
-  const Prob& p = pl->P[0];
-  for (int i = 0; i < nb; ++i) {
-    // a bundle's partials fit in the plan's partial buffer
-    if (B.b[i].nseg * (size_t)p.R > pl->partial_cap) return fail(MAM_EUNSUPPORTED, "bundle %d has too many segments", i);
-  }
   B.ws = static_cast<char*>(ws);
   for (int i = 0; i < nb; ++i) {
     BundleHost h;
@@ -2034,10 +2128,8 @@ mam_status plan_set_bundles(Plan* pl, const int32_t* bundle_of, int32_t nb, void
     TRY(put(bs.o_seg_m, h.seg_m.data(), h.seg_m.size() * 4));
     TRY(put(bs.o_seg_j0, h.seg_j0.data(), h.seg_j0.size() * 8));
     TRY(put(bs.o_seg_j1, h.seg_j1.data(), h.seg_j1.size() * 8));
-    TRY(put(bs.o_seg_poff, h.seg_poff.data(), h.seg_poff.size() * 8));
+    TRY(put(bs.o_seg_st, h.seg_st.data(), h.seg_st.size() * 4));
     TRY(put(bs.o_wg_seg, h.wg_seg.data(), h.wg_seg.size() * 4));
-    TRY(put(bs.o_mseg, h.mseg.data(), h.mseg.size() * 4));
-    TRY(put(bs.o_mpoff, h.mpoff.data(), h.mpoff.size() * 8));
     TRY(put(bs.o_mtasks, h.mtasks.data(), h.mtasks.size() * sizeof(mam::MargTask)));
     HIP_TRY(hipStreamSynchronize(st));  // host staging is released at the end of this loop body
   }
@@ -2056,9 +2148,8 @@ mam_status launch_bundle_columns(Plan* pl, const BundleSched& bs, hipStream_t st
   a.seg_m = reinterpret_cast<const int32_t*>(bw + bs.o_seg_m);
   a.seg_j0 = reinterpret_cast<const int64_t*>(bw + bs.o_seg_j0);
   a.seg_j1 = reinterpret_cast<const int64_t*>(bw + bs.o_seg_j1);
-  a.seg_poff = reinterpret_cast<const int64_t*>(bw + bs.o_seg_poff);
+  a.seg_st = reinterpret_cast<const int32_t*>(bw + bs.o_seg_st);
   a.wg_seg = reinterpret_cast<const int32_t*>(bw + bs.o_wg_seg);
-  a.partial = at<double>(pl, L.partial);
   a.diag = at<double>(pl, L.diag);
   a.rec = nullptr;
   a.rec_ld = 0;
@@ -2099,12 +2190,10 @@ mam_status plan_iterate_bundles(Plan* pl, int64_t iters, const int32_t* seq, hip
     TRY(pl->dtype == MAM_F32 ? launch_bundle_columns<float>(pl, bs, st) : launch_bundle_columns<double>(pl, bs, st));
     if (pl->timing) HIP_TRY(hipEventRecord(e1, st));
     // new marginals of the bundle's measures only, then the average of all
-    hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)bs.nmtasks), dim3(256), 0, st,
+    hipLaunchKernelGGL(mam::fixed_marginal_kernel, dim3((unsigned)bs.nmtasks), dim3(256), 0, st,
                        reinterpret_cast<const mam::MargTask*>(pl->bund.ws + bs.o_mtasks),
-                       at<mam::ProbAux>(pl, L.probaux), reinterpret_cast<const int32_t*>(pl->bund.ws + bs.o_mseg),
-                       reinterpret_cast<const int64_t*>(pl->bund.ws + bs.o_mpoff), at<double>(pl, L.partial), 0,
-                       nullptr);
-    LAUNCH_CHECK("marginal_kernel");
+                       at<mam::ProbAux>(pl, L.probaux), 0, nullptr);
+    LAUNCH_CHECK("fixed_marginal_kernel");
     hipLaunchKernelGGL(mam::average_kernel, dim3((unsigned)pl->atasks.size()), dim3(256), 0, st,
                        at<mam::AvgTask>(pl, L.atasks), at<mam::ProbAux>(pl, L.probaux), 0, nullptr);
     LAUNCH_CHECK("average_kernel");
@@ -2508,6 +2597,18 @@ mam_status mam_iterate_bundles(mam_problem* p, int64_t iters, const int32_t* seq
 }
 
 void mam_destroy(mam_problem* p) { delete p; }
+
+mam_status mam_stream_copy(void* dst, const void* src, size_t bytes, int32_t workgroups, void* stream) {
+  if (!dst || !src) return fail(MAM_EINVAL, "NULL buffer");
+  if (bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
+    return fail(MAM_EINVAL, "buffers and size must be multiples of 16 bytes");
+  if (workgroups < 1) return fail(MAM_EINVAL, "workgroups must be >= 1");
+  if (bytes == 0) return MAM_OK;
+  hipLaunchKernelGGL(mam::stream_copy_kernel, dim3(workgroups), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const mam::f4nt*>(src), static_cast<mam::f4nt*>(dst), (int64_t)(bytes / 16));
+  LAUNCH_CHECK("stream_copy_kernel");
+  return MAM_OK;
+}
 
 mam_status mam_solve_static(const mam_desc* d, void* theta, const void* cost, const int32_t* cost_col_index,
                             const void* q, const void* theta0, int64_t iters, double* p_out, void* stream) {

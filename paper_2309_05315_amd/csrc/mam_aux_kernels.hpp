@@ -20,7 +20,10 @@ struct ProbAux {
   const double* Sd;  // S^m as double
   int32_t R, M;
   int32_t mbase;     // index of (this problem, measure 0) in the measure list
-  int32_t pad;
+  int32_t nb;        // d^2 partials
+  unsigned long long* acc;  // M x R fixed-point row sums of pi_hat (short columns)
+  const double* fxinv;      // M inverse scales 2^-E_m of those sums
+  double rho, gamma;
 };
 
 struct MargTask {
@@ -68,6 +71,61 @@ marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ 
   double* const pm = gptr(P.pm);
   if (save_prev) gptr(P.pm_prev)[o] = pm[o];
   pm[o] = s;
+}
+
+// Short columns: p^(m)_r = sum_s theta'_rs = sum_s pi_hat_rs - S^m b^(m)_r,
+// with the pi_hat sum from the column kernel's fixed-point accumulator and
+// b^(m)_r = t (p_r - p^(m)_r) / S^m formed from the marginals and the t^k
+// the column kernel used (same inputs, same operations).  The accumulator
+// is cleared for the next iteration.
+__global__ void __launch_bounds__(256)
+fixed_marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ probs, int save_prev,
+                      const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;  // early exit: the run has stopped
+  const MargTask tk = tasks[blockIdx.x];
+  const ProbAux& P = probs[tk.prob];
+  const int R = uniform_i(P.R);
+  const int r = tk.r0 + threadIdx.x;
+  const double t = damping_t(gptr(P.d2part), uniform_i(P.nb), uniform_d(P.rho), uniform_d(P.gamma),
+                             threadIdx.x & 63);
+  if (r >= R) return;
+  const size_t o = (size_t)tk.m * R + r;
+  double* const pm = gptr(P.pm);
+  unsigned long long* const acc = gptr(P.acc);
+  const double Sm = gptr(P.Sd)[tk.m];
+  const double old = pm[o];
+  const double b = t * (gptr(P.p)[r] - old) / Sm;
+  const double s = (double)acc[o] * gptr(P.fxinv)[tk.m] - Sm * b;
+  acc[o] = 0ull;
+  if (save_prev) gptr(P.pm_prev)[o] = old;
+  pm[o] = s;
+}
+
+// Short columns, at the start: p^(m)_r = sum_s theta_rs in double, columns
+// in order, eight loads in flight (theta of the caller's start, or q_s/R).
+template <typename T>
+__global__ void __launch_bounds__(256)
+init_marginal_kernel(const MargTask* __restrict__ tasks, const ProbDev<T>* __restrict__ probs,
+                     const ProbAux* __restrict__ aux) {
+  const MargTask tk = tasks[blockIdx.x];
+  const ProbDev<T>& P = probs[tk.prob];
+  const int R = uniform_i(P.R);
+  const int r = tk.r0 + threadIdx.x;
+  const int rr = r < R ? r : tk.r0;  // rows past R read the task's first row (in bounds) and store nothing
+  const T* const theta = gptr((const T*)uniform_l((int64_t)P.theta));
+  const int64_t ld = uniform_l(P.ld);
+  const int64_t j0 = uniform_l(gptr(P.col_off)[tk.m]), j1 = uniform_l(gptr(P.col_off)[tk.m + 1]);
+  constexpr int U = 8;
+  double s = 0.0;
+  for (int64_t j = j0; j < j1; j += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = j + u < j1 ? (double)theta[(j + u) * ld + rr] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (j + u < j1) s += v[u];
+  }
+  if (r < R) gptr(aux[tk.prob].pm)[(size_t)tk.m * R + r] = s;
 }
 
 // p_r = sum_m a_m p^(m)_r, and the block's partial sum of
@@ -261,23 +319,14 @@ copy_kernel(T* __restrict__ theta, int64_t ld, int R, const T* __restrict__ src,
   }
 }
 
-// Row sums of the plans into the segment partials (initialisation).
-template <typename T>
+// Bandwidth probe: n16 blocks of 16 bytes from src to dst, non-temporal
+// loads and stores, grid-stride (every workgroup steps over the whole range,
+// so the blocks in flight at any time lie together in memory).
 __global__ void __launch_bounds__(256)
-rowsum_kernel(const ProbDev<T>* __restrict__ probs, const int32_t* __restrict__ seg_p,
-              const int64_t* __restrict__ seg_j0, const int64_t* __restrict__ seg_j1,
-              const int64_t* __restrict__ seg_poff, const int32_t* __restrict__ wg_seg,
-              double* __restrict__ partial) {
-  const int wg = blockIdx.x;
-  for (int si = wg_seg[wg]; si < wg_seg[wg + 1]; ++si) {
-    const ProbDev<T>& P = probs[seg_p[si]];
-    const T* const theta = gptr((const T*)P.theta);
-    for (int r = threadIdx.x; r < P.R; r += 256) {
-      double s = 0.0;
-      for (int64_t j = seg_j0[si]; j < seg_j1[si]; ++j) s += (double)theta[j * P.ld + r];
-      partial[seg_poff[si] + r] = s;
-    }
-  }
+stream_copy_kernel(const f4nt* __restrict__ src, f4nt* __restrict__ dst, int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 // Input validation: per-measure mass of q (fixed order) and a flag for any

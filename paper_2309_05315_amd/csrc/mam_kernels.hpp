@@ -5,11 +5,15 @@
 //   column kernel  : per plan column, fuses the broadcast correction and the
 //                    reflection (w = theta + 2b - c/rho, Alg. 1 Step 2 and
 //                    Prop. 2 eq. (row_sol)), the exact projection onto
-//                    Delta_R(q_s) (Prop. 3), the update theta' = pi_hat - b,
-//                    and the row sums of theta' (Step 3) as fixed-order
-//                    per-segment partials.  It streams theta once in and once
-//                    out and reads each cost column once: HBM bound.
-//   marginal kernel: p^(m)_r = sum of the partials of measure m (fixed order).
+//                    Delta_R(q_s) (Prop. 3) and the update theta' = pi_hat - b.
+//                    The row sums of theta' (Step 3) are -S^m b plus the row
+//                    sums of pi_hat, which is nonzero only at the active
+//                    entries: each thread sums its rows' pi_hat over a
+//                    segment's columns in double and adds the sums to the
+//                    marginal's accumulator as 64-bit fixed-point integers.
+//                    It streams theta once in and once out and reads each
+//                    cost column once: HBM bound.
+//   marginal kernel: p^(m)_r = (fixed-point sum) - S^m b^(m)_r.
 //   average kernel : p = sum_m a_m p^(m) (eq. (pr)) and the partial sums of
 //                    d^2 = sum_m ||p - p^(m)||^2 / S^m used by the t^k rule.
 //
@@ -30,8 +34,14 @@
 // column stays in registers (held as w in double) for all passes; each pass
 // is one compare/select/add per value plus a group reduction.
 //
-// All reductions have a fixed order, so results are bitwise reproducible
-// run to run; there are no floating-point atomics.
+// Fixed-point row sums.  Integer addition is associative, so the sums do not
+// depend on the order in which columns finish: results are bitwise
+// reproducible run to run and for every launch schedule, with no
+// floating-point atomics.  Measure m uses the scale 2^E_m with
+// mass_m <= 2^(62 - E_m) (mass_m = sum_s q_s); every pi_hat row sum is at
+// most mass_m, so no sum overflows 2^62, and each entry is rounded to the
+// nearest multiple of 2^-E_m (a relative 2^-63 of the mass).  All other
+// reductions have a fixed order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -210,6 +220,21 @@ __device__ __forceinline__ T* gptr(T* p) {
 __device__ __forceinline__ double wave_sum(double v) { return wave_reduce<OpSum>(v); }
 __device__ __forceinline__ double wave_max(double v) { return wave_reduce<OpMax>(v); }
 
+// t^k of Alg. 1 (Step 1) from the nb <= 64 partial sums of
+// d^2 = sum_m ||p - p^(m)||^2 / S^m: every wave sums them in a fixed order
+// (one partial per lane), so t is wave-uniform without LDS, and every kernel
+// that needs t forms the same value.
+__device__ __forceinline__ double damping_t(const double* d2part, int nb, double rho, double gam, int lane) {
+  double d2 = lane < nb ? d2part[lane] : 0.0;
+  d2 = wave_reduce<OpSum>(d2);
+  return (__builtin_isinf(gam) || rho * sqrt(d2) <= gam) ? 1.0 : gam / (rho * sqrt(d2));
+}
+
+// Fixed-point value of pi_hat >= 0 at scale fx = 2^E (round to nearest).
+__device__ __forceinline__ unsigned long long to_fixed(double ph, double fx) {
+  return __double2ull_rn(ph * fx);
+}
+
 // One problem as the column kernel sees it (a batch holds many).
 template <typename T>
 struct ProbDev {
@@ -217,6 +242,8 @@ struct ProbDev {
   const T* cost;
   const T* q;
   const int32_t* cidx;
+  unsigned long long* acc;  // M x R fixed-point sums of pi_hat (zero between iterations)
+  const double* fx;         // M scales 2^E_m of the fixed-point sums
   int64_t ld, cost_ld;
   int32_t R, cost_mode;
   int32_t nb, warm;       // nb: d^2 partials; warm: use stored thresholds as starts
@@ -238,9 +265,8 @@ struct ColArgs {
   const int32_t* seg_m;   // measure of each segment
   const int64_t* seg_j0;  // first column
   const int64_t* seg_j1;  // one past the last column
-  const int64_t* seg_poff;// offset of the segment's row-sum partial in 'partial'
+  const int32_t* seg_st;  // column stride between the segment's blocks
   const int32_t* wg_seg;  // segments of workgroup w: [wg_seg[w], wg_seg[w+1])
-  double* partial;
   double* diag;           // nwg x DIAG_STRIDE (single-problem plans)
   uint8_t* rec;           // null, or: per column j, the threads' active-set
                           // mask words at rec + j*rec_ld (single-problem plans)
@@ -364,10 +390,10 @@ struct Rounds {
 // update is theta'_r = -b_r whatever theta and c were: every column of a
 // segment is the constant vector -b^(m) except at its active rows.  The
 // kernel therefore keeps no per-entry state beyond the raw theta and c of
-// the columns in flight: w is recomputed where needed, each column writes
-// -b^(m) patched at its active rows, and the segment's row sums are
-// (#columns) * (-b^(m)) plus the patches' values pi_hat, accumulated in LDS
-// in double before the update is rounded to the storage type.
+// the columns in flight: each column writes -b^(m) patched at its active
+// rows, and the marginal's row sums are -S^m b^(m) plus the patches' values
+// pi_hat (taken before the update is rounded to the storage type), which
+// the active entries add to a fixed-point accumulator.
 //
 // Threshold of a column (tau = q_s > 0): Newton steps
 //   lam' = (sum_{w > lam} w - tau) / #{w > lam}
@@ -387,10 +413,18 @@ struct Rounds {
 // waits inside a step.  STREAM instances load and store theta with the
 // non-temporal policy (plans larger than the Infinity Cache).
 //
-// Dynamic LDS: VPT*NT doubles of b^(m) (each thread reads only its own
-// slots), then NG*VPT*NT doubles of row-sum patches, one block per group.
+// Dynamic LDS: VPT*NT doubles of b^(m) (with one group per workgroup each
+// thread reads and writes only its own slots), then NG*VPT*NT doubles of
+// row sums of pi_hat, one block per group (own slots per thread).
+// Waves per SIMD the register allocation must allow: five while a thread
+// holds at most 16 bytes of a column step, four up to 32, else two.
+// Without the bound the compiler spends registers freely and the smaller
+// shapes lose a resident wave.
+template <typename T, int VPT, int KC>
+constexpr int col_waves() { return sizeof(T) * VPT * KC <= 16 ? 5 : (sizeof(T) * VPT * KC <= 32 ? 4 : 2); }
+
 template <typename T, int NT, int VPT, int VEC, int KC, bool DIAG, bool STREAM = false>
-__global__ void __launch_bounds__(GroupShape<NT>::WG)
+__global__ void __launch_bounds__(GroupShape<NT>::WG, (col_waves<T, VPT, KC>()))
 column_kernel(ColArgs<T> a) {
   constexpr int WG = GroupShape<NT>::WG;
   constexpr int NG = GroupShape<NT>::NG;  // independent column groups per workgroup
@@ -420,7 +454,7 @@ column_kernel(ColArgs<T> a) {
   const int tid = gtid % NT;
   const int lane = gtid & 63;
   const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
-  double* fix = lds_fix + (size_t)g * VPT * NT;
+  double* const fix = lds_fix + (size_t)g * VPT * NT;  // this group's row sums of pi_hat, own slots per thread
 
   if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;  // early exit: the run has stopped
 
@@ -444,21 +478,26 @@ column_kernel(ColArgs<T> a) {
     double* const lamv = gptr((double*)uniform_l((int64_t)P.lam));
     const int m = uniform_i(a.seg_m[si]);
     const int64_t j0 = uniform_l(a.seg_j0[si]), j1 = uniform_l(a.seg_j1[si]);
+    const int64_t stride = uniform_i(a.seg_st[si]);  // columns from one block of the group to its next
     const double Sm = uniform_d(gptr(P.Sd)[m]);
+    unsigned long long* const accm = gptr((unsigned long long*)uniform_l((int64_t)P.acc)) + (size_t)m * R;
+    const double fxm = uniform_d(gptr(P.fx)[m]);
     const int64_t off_m = uniform_l(gptr(P.col_off)[m]);
     const double* __restrict__ pmm = gptr(P.pm) + (size_t)m * R;
     const double* __restrict__ pv = gptr(P.p);
 
     // Column steps of this group: blocks of KB columns taken in turn by the
-    // NG groups, each walked KC columns at a time.  The raw loads of the
-    // next step are issued before the current step's threshold rounds and
-    // stores, so their HBM latency overlaps that work.
+    // NG groups (and, with a segment stride beyond NG*KB, by the other
+    // workgroups of a team sweeping the same columns), each walked KC
+    // columns at a time.  The raw loads of the next step are issued before
+    // the current step's threshold rounds and stores, so their HBM latency
+    // overlaps that work.
     static_assert(KB % KC == 0, "KC must divide the column block");
     constexpr int SPB = KB / KC;  // steps per block
     const int64_t gbase = j0 + (int64_t)g * KB;
-    auto step_exists = [&](int64_t i) -> bool { return gbase + (i / SPB) * (int64_t)(NG * KB) < j1; };
+    auto step_exists = [&](int64_t i) -> bool { return gbase + (i / SPB) * stride < j1; };
     auto step_col = [&](int64_t i, int kc, int64_t& j) -> bool {
-      const int64_t base = gbase + (i / SPB) * (int64_t)(NG * KB);
+      const int64_t base = gbase + (i / SPB) * stride;
       const int64_t bend = base + KB < j1 ? base + KB : j1;
       j = base + (i % SPB) * KC + kc;
       return j < bend;
@@ -471,18 +510,22 @@ column_kernel(ColArgs<T> a) {
       return cost + cc * cost_ld;
     };
     // raw theta and cost of the next PF steps, one buffer per step in flight,
-    // with each column's weight q_s and stored threshold (the warm start)
+    // with each column's weight q_s and stored threshold (the warm start).
+    // Loads are unconditional: a column slot past the segment's end loads
+    // the segment's first column and is ignored.  (Conditional loads into
+    // the rotating buffers made the compiler copy whole buffers per step.)
     T rt[PF][KC][VPT], rc[PF][KC][VPT], rq[PF][KC];
     double rl[PF][KC];
+    auto step_col_clamped = [&](int64_t i, int kc) -> int64_t {
+      int64_t j;
+      return step_col(i, kc, j) ? j : j0;
+    };
     // an indexed cost's column numbers are read one issued step ahead, so
     // forming a cost address never waits on memory
     int32_t cnext[KC];
     auto load_index = [&](int64_t i) {
 #pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        int64_t j;
-        cnext[kc] = (cost_mode == MAM_COST_INDEXED && step_col(i, kc, j)) ? cidx[j] : 0;
-      }
+      for (int kc = 0; kc < KC; ++kc) cnext[kc] = cidx[step_col_clamped(i, kc)];
     };
     if (cost_mode == MAM_COST_INDEXED) load_index(0);
     auto issue = [&](int64_t i, T (&bt)[KC][VPT], T (&bc)[KC][VPT], T (&bq)[KC], double (&bl)[KC]) {
@@ -492,68 +535,65 @@ column_kernel(ColArgs<T> a) {
       if (cost_mode == MAM_COST_INDEXED) load_index(i + 1);
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
-        int64_t j;
-        if (step_col(i, kc, j)) {
-          bq[kc] = qv[j];
-          bl[kc] = lamv[j];
-          const T* __restrict__ thp = theta + j * ld;
-          int64_t cc;
-          if (cost_mode == MAM_COST_INDEXED) cc = uniform_i(cthis[kc]);
-          else if (cost_mode == MAM_COST_SHARED) cc = j - off_m;
-          else cc = j;
-          const T* __restrict__ cp = cost + cc * cost_ld;
+        const int64_t j = step_col_clamped(i, kc);
+        bq[kc] = qv[j];
+        bl[kc] = lamv[j];
+        const T* __restrict__ thp = theta + j * ld;
+        int64_t cc;
+        if (cost_mode == MAM_COST_INDEXED) cc = uniform_i(cthis[kc]);
+        else if (cost_mode == MAM_COST_SHARED) cc = j - off_m;
+        else cc = j;
+        const T* __restrict__ cp = cost + cc * cost_ld;
 #pragma unroll
-          for (int c = 0; c < NCH; ++c) {
-            // rows past R read the column's first vector (in bounds) and are masked later
-            const int r0 = (c * NT + tid) * VEC < R ? (c * NT + tid) * VEC : 0;
-            T tv[VEC], cv[VEC];
-            if constexpr (STREAM) load_vec_nt<T, VEC>(thp + r0, tv);
-            else load_vec<T, VEC>(thp + r0, tv);
-            load_vec<T, VEC>(cp + r0, cv);
+        for (int c = 0; c < NCH; ++c) {
+          // rows past R read the column's first vector (in bounds); their
+          // b = -inf makes them inactive whatever they hold
+          const int r0 = (c * NT + tid) * VEC < R ? (c * NT + tid) * VEC : 0;
+          T tv[VEC], cv[VEC];
+          if constexpr (STREAM) load_vec_nt<T, VEC>(thp + r0, tv);
+          else load_vec<T, VEC>(thp + r0, tv);
+          load_vec<T, VEC>(cp + r0, cv);
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-              bt[kc][c * VEC + v] = tv[v];
-              bc[kc][c * VEC + v] = cv[v];
-            }
+          for (int v = 0; v < VEC; ++v) {
+            bt[kc][c * VEC + v] = tv[v];
+            bc[kc][c * VEC + v] = cv[v];
           }
         }
       }
     };
     // the first raw loads overlap the set-up below
 #pragma unroll
-    for (int b = 0; b < PF; ++b)
-      if (step_exists(b)) issue(b, rt[b], rc[b], rq[b], rl[b]);
+    for (int b = 0; b < PF; ++b) issue(b, rt[b], rc[b], rq[b], rl[b]);
 
-    // t^k of this problem from its d^2 partials: every wave sums them in a
-    // fixed order (one partial per lane), so t is wave-uniform without LDS
-    const int nbp = uniform_i(P.nb);
-    double d2 = lane < nbp ? gptr(P.d2part)[lane] : 0.0;
-    d2 = wave_sum(d2);
-    const double rho = uniform_d(P.rho), gam = uniform_d(P.gamma);
-    const double t = (__builtin_isinf(gam) || rho * sqrt(d2) <= gam) ? 1.0 : gam / (rho * sqrt(d2));
+    // t^k of this problem from its d^2 partials
+    const double t = damping_t(gptr(P.d2part), uniform_i(P.nb), uniform_d(P.rho), uniform_d(P.gamma), lane);
     if (gtid == 0 && j0 == 0) gptr(P.t_out)[0] = t;
 
-    // b^(m) = t (p - p^(m)) / S^m for this thread's rows, kept in LDS
-    __syncthreads();  // previous segment's readers are done
+    // b^(m) = t (p - p^(m)) / S^m at this thread's rows, in LDS (a thread
+    // holds the same rows in every column of the segment; with several
+    // groups per workgroup, group 0 writes the rows every group reads, so
+    // the previous segment's readers must be done first).  A row past R gets
+    // b = -inf, which makes its w = -inf (never active, never the maximum)
+    // without a select per entry.
+    if constexpr (NG > 1) __syncthreads();
     if (g == 0) {
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const int r = (c * NT + tid) * VEC + v;
-          lds_b[(c * VEC + v) * NT + tid] = (r < R) ? t * (pv[r] - pmm[r]) / Sm : 0.0;
-        }
+      for (int k = 0; k < VPT; ++k) {
+        const int r = ((k / VEC) * NT + tid) * VEC + (k % VEC);
+        lds_b[k * NT + tid] = (r < R) ? t * (pv[r] - pmm[r]) / Sm : -__builtin_huge_val();
       }
     }
+    if constexpr (NG > 1) __syncthreads();  // group 0 wrote every group's b
 #pragma unroll
     for (int k = 0; k < VPT; ++k) fix[k * NT + tid] = 0.0;
-    __syncthreads();
     T nb[VPT];  // -b^(m) rounded to the storage type: every inactive entry's new value
 #pragma unroll
     for (int k = 0; k < VPT; ++k) nb[k] = (T)(-lds_b[k * NT + tid]);
 
     auto body = [&](int64_t step, T (&bt)[KC][VPT], T (&bc)[KC][VPT], T (&bq)[KC], double (&bl)[KC]) {
       // ---- reflect the step's columns: w = theta + 2b - c/rho (double) ----
+      // (a column slot past the segment's end is computed too, on defined
+      // values, and then ignored: no select per entry)
       double w[KC][VPT];
       T told[DIAG ? KC : 1][DIAG ? VPT : 1];
       bool valid[KC];
@@ -563,9 +603,7 @@ column_kernel(ColArgs<T> a) {
         valid[kc] = step_col(step, kc, jj[kc]);
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
-          const int r = ((k / VEC) * NT + tid) * VEC + (k % VEC);
-          const double x = ((double)bt[kc][k] + 2.0 * lds_b[k * NT + tid]) - (double)bc[kc][k] * inv_rho;
-          w[kc][k] = (valid[kc] && r < R) ? x : -__builtin_huge_val();
+          w[kc][k] = ((double)bt[kc][k] + 2.0 * lds_b[k * NT + tid]) - (double)bc[kc][k] * inv_rho;
           if constexpr (DIAG) told[kc][k] = bt[kc][k];
         }
       }
@@ -576,7 +614,7 @@ column_kernel(ColArgs<T> a) {
         qcol[kc] = (double)bq[kc];
         lcol[kc] = bl[kc];
       }
-      if (step_exists(step + PF)) issue(step + PF, bt, bc, bq, bl);
+      issue(step + PF, bt, bc, bq, bl);
 
       // ---- thresholds ----
       double tau[KC], lam[KC];
@@ -669,10 +707,15 @@ column_kernel(ColArgs<T> a) {
       }
 
       // ---- theta' = -b, patched at the active rows with max(w - lam, 0) - b ----
-      // With relaxed columns the projection onto {u >= 0, sum u <= q_s} is
-      // max(w - max(lam, 0), 0): the clamped column if it carries at most q_s
-      // (then the simplex threshold is <= 0), else the simplex projection.
-      // The stored warm start stays the simplex threshold.
+      // Only a wave holding an active entry looks at the mask bits; it also
+      // adds the patches' pi_hat, before rounding, to the thread's row sums
+      // (an inactive entry's stored -b enters nothing else: it is inactive
+      // again or, if it becomes active, off by a relative 2^-24 of b, so the
+      // marginals follow the double iteration).  With relaxed columns the
+      // projection onto {u >= 0, sum u <= q_s} is max(w - max(lam, 0), 0):
+      // the clamped column if it carries at most q_s (then the simplex
+      // threshold is <= 0), else the simplex projection.  The stored warm
+      // start stays the simplex threshold.
       double lout[KC];
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) lout[kc] = relaxed ? fmax(lam[kc], 0.0) : lam[kc];
@@ -684,35 +727,42 @@ column_kernel(ColArgs<T> a) {
         double colsum = 0.0;
         const T* __restrict__ cp = cost;
         if constexpr (DIAG) cp = cost_col(j);
+        T out[VPT];
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) out[k] = nb[k];
+        if (__ballot(mask[kc] != 0) != 0ull) {
+#pragma unroll
+          for (int k = 0; k < VPT; ++k) {
+            if ((mask[kc] >> k) & 1) {
+              const double ph = fmax(w[kc][k] - lout[kc], 0.0);
+              out[k] = (T)(ph - lds_b[k * NT + tid]);
+              fix[k * NT + tid] += ph;
+              if constexpr (DIAG) {
+                colsum += ph;
+                dW += (double)cp[((k / VEC) * NT + tid) * VEC + (k % VEC)] * ph;
+              }
+            }
+          }
+        }
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
           const int r0 = (c * NT + tid) * VEC;
           if (r0 < R) {
-            T out[VEC];
+            if constexpr (DIAG) {
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-              const int k = c * VEC + v;
-              out[v] = nb[k];
-              if ((mask[kc] >> k) & 1) {
-                const double ph = fmax(w[kc][k] - lout[kc], 0.0);
-                out[v] = (T)(ph - lds_b[k * NT + tid]);
-                fix[k * NT + tid] += ph;  // theta' - (-b) before rounding
-                if constexpr (DIAG) {
-                  colsum += ph;
-                  dW += (double)cp[r0 + v] * ph;
-                }
-              }
-              if constexpr (DIAG) {
-                if (r0 + v < R) dTh = fmax(dTh, fabs((double)out[v] - (double)told[kc][k]));
-              }
+              for (int v = 0; v < VEC; ++v)
+                if (r0 + v < R) dTh = fmax(dTh, fabs((double)out[c * VEC + v] - (double)told[kc][c * VEC + v]));
             }
+            T ov[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) ov[v] = out[c * VEC + v];
             if (r0 + VEC <= R) {
-              if constexpr (STREAM) store_vec_nt<T, VEC>(thp + r0, out);
-              else store_vec<T, VEC>(thp + r0, out);
+              if constexpr (STREAM) store_vec_nt<T, VEC>(thp + r0, ov);
+              else store_vec<T, VEC>(thp + r0, ov);
             } else {
 #pragma unroll
               for (int v = 0; v < VEC; ++v)
-                if (r0 + v < R) thp[r0 + v] = out[v];
+                if (r0 + v < R) thp[r0 + v] = ov[v];
             }
           }
         }
@@ -750,27 +800,13 @@ column_kernel(ColArgs<T> a) {
         body(step + 1, rt[1], rc[1], rq[1], rl[1]);
       }
     }
-
-    // partial row sums of the segment: (#columns) * (-b) + patches, groups in
-    // order, all in double from the unrounded updates.  With float plans the
-    // stored -b of every inactive entry carries the same rounding error in
-    // all columns of a measure; summing the stored values would add S^m
-    // times that error to the row each iteration, a drift that grows
-    // linearly with the iteration count.  An inactive entry's stored value
-    // enters nothing else (it is inactive again or, if it becomes active,
-    // off by a relative 2^-24 of b), so the marginals follow the double
-    // iteration and the rounding stays per entry.
-    __syncthreads();
-    const double ncols = (double)(j1 - j0);
-    for (int i = gtid; i < VPT * NT; i += WG) {
-      const int k = i / NT, tt = i % NT;
-      const int r = ((k / VEC) * NT + tt) * VEC + (k % VEC);
-      if (r < R) {
-        double f = lds_fix[i];
+    // the segment's row sums of pi_hat (double, in column order) into the
+    // fixed-point accumulators: one integer addition per row with mass,
+    // whose total does not depend on the order of the segments
 #pragma unroll
-        for (int gg = 1; gg < NG; ++gg) f += lds_fix[(size_t)gg * VPT * NT + i];
-        a.partial[uniform_l(a.seg_poff[si]) + r] = f - ncols * lds_b[i];
-      }
+    for (int k = 0; k < VPT; ++k) {
+      const double f = fix[k * NT + tid];
+      if (f != 0.0) atomicAdd(accm + ((k / VEC) * NT + tid) * VEC + (k % VEC), to_fixed(f, fxm));
     }
   }
 

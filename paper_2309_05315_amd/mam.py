@@ -18,7 +18,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-__all__ = ["lib", "MAMError", "Solver", "Batch", "solver_for", "solve_static", "cost_sq_euclid",
+__all__ = ["lib", "MAMError", "Solver", "Batch", "solver_for", "solve_static", "stream_copy", "cost_sq_euclid",
            "F32", "F64", "COST_PER_COLUMN", "COST_SHARED", "COST_INDEXED", "COST_GRID", "FLAG_DIAG", "FLAG_COLD", "FLAG_RELAXED", "FLAG_SPARSE_STORE",
            "STOP_TESTS", "EXPORTED"]
 
@@ -44,7 +44,7 @@ EXPORTED = ["mam_abi_version", "mam_last_error", "mam_create", "mam_set_schedule
             "mam_batch_destroy", "mam_adjoint_workspace_bytes", "mam_record", "mam_backward",
             "mam_bundle_workspace_bytes", "mam_set_bundles", "mam_iterate_bundles",
             "mam_iterate_until", "mam_set_grid", "mam_support_workspace_bytes", "mam_support_update",
-            "mam_solve_static"]
+            "mam_solve_static", "mam_stream_copy"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmam.so")
 
@@ -71,7 +71,8 @@ class Schedule(ctypes.Structure):
                 ("columns_in_flight", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("vector_width", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("streaming", ctypes.c_int32),
-                ("rows_per_tile", ctypes.c_int32), ("candidate_slots", ctypes.c_int32)]
+                ("rows_per_tile", ctypes.c_int32), ("candidate_slots", ctypes.c_int32),
+                ("team_size", ctypes.c_int32)]
 
 
 class StopResult(ctypes.Structure):
@@ -150,6 +151,7 @@ def lib() -> ctypes.CDLL:
                                                 ctypes.c_size_t, _vp]),
         "mam_iterate_until": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                                ctypes.c_int64, ctypes.POINTER(StopResult), _vp]),
+        "mam_stream_copy": (ctypes.c_int32, [_vp, _vp, ctypes.c_size_t, ctypes.c_int32, _vp]),
         "mam_solve_static": (ctypes.c_int32, [ctypes.POINTER(Desc), _vp, _vp, _vp, _vp, _vp, ctypes.c_int64,
                                               _vp, _vp]),
     }
@@ -193,7 +195,7 @@ class Solver:
                  relaxed: bool = False, sparse_store: bool = False,
                  threads_per_column: int = 0, columns_in_flight: int = 0,
                  workgroups: int = 0, xcd_remap: int = 0, order: int = 0, streaming: int = 0,
-                 rows_per_tile: int = 0, candidate_slots: int = 0, device="cuda"):
+                 rows_per_tile: int = 0, candidate_slots: int = 0, team_size: int = 0, device="cuda"):
         L = lib()
         self.device = torch.device(device)
         self.R, self.S = int(R), [int(s) for s in S]
@@ -216,10 +218,10 @@ class Solver:
         _check(L.mam_create(ctypes.byref(h), ctypes.byref(d)), "mam_create")
         self._h = h
         if (threads_per_column or columns_in_flight or workgroups or xcd_remap or order or streaming
-                or rows_per_tile or candidate_slots):
+                or rows_per_tile or candidate_slots or team_size):
             sc = Schedule(threads_per_column=threads_per_column, columns_in_flight=columns_in_flight,
                           workgroups=workgroups, xcd_remap=xcd_remap, order=order, streaming=streaming,
-                          rows_per_tile=rows_per_tile, candidate_slots=candidate_slots)
+                          rows_per_tile=rows_per_tile, candidate_slots=candidate_slots, team_size=team_size)
             _check(L.mam_set_schedule(h, ctypes.byref(sc)), "mam_set_schedule")
         nbytes = int(L.mam_workspace_bytes(h))
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
@@ -459,6 +461,15 @@ def solve_static(R: int, S: Sequence[int], theta: torch.Tensor, cost: torch.Tens
     _check(lib().mam_solve_static(ctypes.byref(d), _ptr(theta), _ptr(cost), _ptr(index), _ptr(q), _ptr(theta0),
                                   int(iters), _ptr(out), _stream(theta.device)), "mam_solve_static")
     return out
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, workgroups: int) -> None:
+    """Device copy with the library's bandwidth probe (mam_stream_copy)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    _check(lib().mam_stream_copy(_ptr(dst), _ptr(src), nbytes, int(workgroups), _stream(src.device)),
+           "mam_stream_copy")
 
 
 def _dtype_of(problem):

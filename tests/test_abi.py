@@ -293,7 +293,11 @@ def test_solve_static_rejects_before_touching_the_gpu():
     assert L.mam_solve_static(ctypes.byref(g), fake, fake, None, fake, None, 5, out, None) == -6
     bad, barr = desc(R=0, S=[3])
     assert L.mam_solve_static(ctypes.byref(bad), fake, fake, None, fake, None, 5, out, None) == -1
-    # 8192 rows, 64 measures of 8192 columns: about 590 MiB of workspace, over the 128 MiB array
-    big, bigarr = desc(R=8192, S=[8192] * 64, dtype=mam.F32, cost_mode=mam.COST_SHARED, cost_ncols=8192)
+    # 8192 rows, 1024 measures: the marginals alone (three M x R double arrays) exceed the 128 MiB array
+    big, bigarr = desc(R=8192, S=[2] * 1024, dtype=mam.F32, cost_mode=mam.COST_SHARED, cost_ncols=2)
+    hb = ctypes.c_void_p()
+    assert L.mam_create(ctypes.byref(hb), ctypes.byref(big)) == 0
+    assert L.mam_workspace_bytes(hb) > (128 << 20)
+    L.mam_destroy(hb)
     assert L.mam_solve_static(ctypes.byref(big), fake, fake, None, fake, None, 5, out, None) == -2
     assert b"static workspace" in L.mam_last_error()

@@ -978,7 +978,7 @@ mam_status upload_tables(Plan* pl, hipStream_t st) {
               at<double>(pl, p.o_d2), at<double>(pl, p.o_aw), at<double>(pl, p.o_Sd), (int32_t)p.R,
               (int32_t)p.M, p.mbase, p.nb,
               pl->lg.on ? nullptr : at<unsigned long long>(pl, p.o_acc),
-              pl->lg.on ? nullptr : at<double>(pl, p.o_fx) + p.M, p.rho, p.gamma};
+              pl->lg.on ? nullptr : at<double>(pl, p.o_fx) + p.M, p.rho, p.gamma, at<double>(pl, p.o_t)};
     TRY(put(p.o_coloff, p.col_off.data(), p.col_off.size() * 8));
     TRY(put(p.o_Sd, p.Sd.data(), p.Sd.size() * 8));
     TRY(put(p.o_aw, p.aw.data(), p.aw.size() * 8));
@@ -1218,9 +1218,13 @@ mam_status launch_average(Plan* pl, hipStream_t st, int save_prev) {
   return MAM_OK;
 }
 
-// Steps 3 and 1 after the column kernels: the new marginals (short columns:
-// from the fixed-point sums; long columns: from the row-tile partials),
-// then the average.
+// Steps 3 and 1 after the column kernels.  Short columns: with at most
+// kFusedCloseM measures per problem, one row-parallel kernel (the new
+// marginals from the fixed-point sums, then the average: one launch fewer);
+// with more, the marginals of every (measure, row block) in parallel, then
+// the average.  Long columns: the marginals from the row-tile partials, then
+// the average.
+constexpr int64_t kFusedCloseM = 8;
 mam_status launch_marginals(Plan* pl, hipStream_t st, int save_prev) {
   const Layout& L = pl->lay;
   if (pl->lg.on) {
@@ -1228,11 +1232,19 @@ mam_status launch_marginals(Plan* pl, hipStream_t st, int save_prev) {
                        at<mam::MargTask>(pl, L.mtasks), at<mam::ProbAux>(pl, L.probaux), at<int32_t>(pl, L.mseg),
                        at<int64_t>(pl, L.seg_idx), at<double>(pl, L.partial), save_prev, pl->gate);
     LAUNCH_CHECK("marginal_kernel");
-  } else {
-    hipLaunchKernelGGL(mam::fixed_marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
-                       at<mam::MargTask>(pl, L.mtasks), at<mam::ProbAux>(pl, L.probaux), save_prev, pl->gate);
-    LAUNCH_CHECK("fixed_marginal_kernel");
+    return launch_average(pl, st, save_prev);
   }
+  int64_t mmax = 0;
+  for (const Prob& p : pl->P) mmax = std::max(mmax, p.M);
+  if (mmax <= kFusedCloseM) {
+    hipLaunchKernelGGL(mam::close_kernel, dim3((unsigned)pl->atasks.size()), dim3(256), 0, st,
+                       at<mam::AvgTask>(pl, L.atasks), at<mam::ProbAux>(pl, L.probaux), save_prev, pl->gate);
+    LAUNCH_CHECK("close_kernel");
+    return MAM_OK;
+  }
+  hipLaunchKernelGGL(mam::fixed_marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
+                     at<mam::MargTask>(pl, L.mtasks), at<mam::ProbAux>(pl, L.probaux), save_prev, pl->gate);
+  LAUNCH_CHECK("fixed_marginal_kernel");
   return launch_average(pl, st, save_prev);
 }
 

@@ -9,32 +9,6 @@
 
 namespace mam {
 
-// One problem as the marginal and average kernels see it.
-struct ProbAux {
-  double* pm;        // M x R
-  double* pm_prev;   // M x R, marginals before the last iteration (diagnostics)
-  double* p;         // R
-  double* p_prev;    // R
-  double* d2part;    // ceil(R/256) partial sums of d^2
-  const double* aw;  // averaging weights a_m
-  const double* Sd;  // S^m as double
-  int32_t R, M;
-  int32_t mbase;     // index of (this problem, measure 0) in the measure list
-  int32_t nb;        // d^2 partials
-  unsigned long long* acc;  // M x R fixed-point row sums of pi_hat (short columns)
-  const double* fxinv;      // M inverse scales 2^-E_m of those sums
-  double rho, gamma;
-};
-
-struct MargTask {
-  int32_t prob, m, r0;
-  int32_t list;  // partial-offset list: the measure's, or (long columns) its row tile's
-};
-
-struct AvgTask {
-  int32_t prob, rb;
-};
-
 // p^(m)_r = sum over the segments of measure m, in schedule order.  The
 // partials' offsets come as one list per measure, or per (measure, row tile)
 // for long columns (mpoff[mseg[k] .. mseg[k+1]), k = the task's list);
@@ -73,32 +47,13 @@ marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ 
   pm[o] = s;
 }
 
-// Short columns: p^(m)_r = sum_s theta'_rs = sum_s pi_hat_rs - S^m b^(m)_r,
-// with the pi_hat sum from the column kernel's fixed-point accumulator and
-// b^(m)_r = t (p_r - p^(m)_r) / S^m formed from the marginals and the t^k
-// the column kernel used (same inputs, same operations).  The accumulator
-// is cleared for the next iteration.
+// Short columns: the new marginals (close_marginal) of every task's rows.
 __global__ void __launch_bounds__(256)
 fixed_marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ probs, int save_prev,
                       const int32_t* __restrict__ stop) {
   if (stop != nullptr && *stop != 0) return;  // early exit: the run has stopped
   const MargTask tk = tasks[blockIdx.x];
-  const ProbAux& P = probs[tk.prob];
-  const int R = uniform_i(P.R);
-  const int r = tk.r0 + threadIdx.x;
-  const double t = damping_t(gptr(P.d2part), uniform_i(P.nb), uniform_d(P.rho), uniform_d(P.gamma),
-                             threadIdx.x & 63);
-  if (r >= R) return;
-  const size_t o = (size_t)tk.m * R + r;
-  double* const pm = gptr(P.pm);
-  unsigned long long* const acc = gptr(P.acc);
-  const double Sm = gptr(P.Sd)[tk.m];
-  const double old = pm[o];
-  const double b = t * (gptr(P.p)[r] - old) / Sm;
-  const double s = (double)acc[o] * gptr(P.fxinv)[tk.m] - Sm * b;
-  acc[o] = 0ull;
-  if (save_prev) gptr(P.pm_prev)[o] = old;
-  pm[o] = s;
+  close_marginal(tk, probs[tk.prob], save_prev, threadIdx.x);
 }
 
 // Short columns, at the start: p^(m)_r = sum_s theta_rs in double, columns
@@ -128,53 +83,24 @@ init_marginal_kernel(const MargTask* __restrict__ tasks, const ProbDev<T>* __res
   if (r < R) gptr(aux[tk.prob].pm)[(size_t)tk.m * R + r] = s;
 }
 
-// p_r = sum_m a_m p^(m)_r, and the block's partial sum of
-// sum_r sum_m (p_r - p^(m)_r)^2 / S^m.
+// Short columns: Steps 3 and 1 of every task's block of 256 rows (close_rows).
+__global__ void __launch_bounds__(256)
+close_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ probs, int save_prev,
+             const int32_t* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;  // early exit: the run has stopped
+  __shared__ double sh[4];
+  const AvgTask tk = tasks[blockIdx.x];
+  close_rows(tk, probs[tk.prob], save_prev, threadIdx.x, sh);
+}
+
+// Step 1 for every task's block of 256 rows (close_average).
 __global__ void __launch_bounds__(256)
 average_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ probs, int save_prev,
                const int32_t* __restrict__ stop) {
   if (stop != nullptr && *stop != 0) return;  // early exit: the run has stopped
   __shared__ double sh[4];
   const AvgTask tk = tasks[blockIdx.x];
-  const ProbAux& P = probs[tk.prob];
-  const int R = P.R, M = P.M;
-  const int r = tk.rb * 256 + threadIdx.x;
-  const double* const pm = gptr(P.pm);
-  const double* const aw = gptr(P.aw);
-  const double* const Sd = gptr(P.Sd);
-  double* const p = gptr(P.p);
-  double d2 = 0.0;
-  if (r < R) {
-    // eight measures' loads in flight at a time; the sums keep the order m = 0, 1, ...
-    constexpr int U = 8;
-    double pr = 0.0;
-    for (int m0 = 0; m0 < M; m0 += U) {
-      double v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = m0 + u < M ? pm[(size_t)(m0 + u) * R + r] : 0.0;
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (m0 + u < M) pr += aw[m0 + u] * v[u];
-    }
-    for (int m0 = 0; m0 < M; m0 += U) {
-      double v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = m0 + u < M ? pm[(size_t)(m0 + u) * R + r] : 0.0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (m0 + u < M) {
-          const double e = pr - v[u];
-          d2 += e * e / Sd[m0 + u];
-        }
-      }
-    }
-    if (save_prev) gptr(P.p_prev)[r] = p[r];
-    p[r] = pr;
-  }
-  d2 = wave_sum(d2);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d2;
-  __syncthreads();
-  if (threadIdx.x == 0) gptr(P.d2part)[tk.rb] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  close_average(tk, probs[tk.prob], save_prev, threadIdx.x, sh);
 }
 
 // ---------------------------------------------------------------------------

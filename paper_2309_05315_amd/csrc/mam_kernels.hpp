@@ -235,6 +235,172 @@ __device__ __forceinline__ unsigned long long to_fixed(double ph, double fx) {
   return __double2ull_rn(ph * fx);
 }
 
+// One problem as the marginal and average kernels see it.
+struct ProbAux {
+  double* pm;        // M x R
+  double* pm_prev;   // M x R, marginals before the last iteration (diagnostics)
+  double* p;         // R
+  double* p_prev;    // R
+  double* d2part;    // ceil(R/256) partial sums of d^2
+  const double* aw;  // averaging weights a_m
+  const double* Sd;  // S^m as double
+  int32_t R, M;
+  int32_t mbase;     // index of (this problem, measure 0) in the measure list
+  int32_t nb;        // d^2 partials
+  unsigned long long* acc;  // M x R fixed-point row sums of pi_hat (short columns)
+  const double* fxinv;      // M inverse scales 2^-E_m of those sums
+  double rho, gamma;
+  const double* t;          // t^k of the iteration, as its column kernel formed it
+};
+
+struct MargTask {
+  int32_t prob, m, r0;
+  int32_t list;  // partial-offset list: the measure's, or (long columns) its row tile's
+};
+
+struct AvgTask {
+  int32_t prob, rb;
+};
+
+// Short columns, Step 3: p^(m)_r = sum_s theta'_rs = sum_s pi_hat_rs - S^m b^(m)_r,
+// with the pi_hat sum from the column kernel's fixed-point accumulator and
+// b^(m)_r = t (p_r - p^(m)_r) / S^m formed from the marginals and the t^k
+// the column kernel used (same inputs, same operations).  The accumulator
+// is cleared for the next iteration.  Row tk.r0 + tidx; a whole wave calls
+// it (t is a wave reduction).
+__device__ __forceinline__ void close_marginal(const MargTask& tk, const ProbAux& P, int save_prev, int tidx) {
+  const int R = uniform_i(P.R);
+  const int r = tk.r0 + tidx;
+  const double t = damping_t(gptr(P.d2part), uniform_i(P.nb), uniform_d(P.rho), uniform_d(P.gamma), tidx & 63);
+  if (r >= R) return;
+  const size_t o = (size_t)tk.m * R + r;
+  double* const pm = gptr(P.pm);
+  unsigned long long* const acc = gptr(P.acc);
+  const double Sm = gptr(P.Sd)[tk.m];
+  const double old = pm[o];
+  const double b = t * (gptr(P.p)[r] - old) / Sm;
+  const double s = (double)acc[o] * gptr(P.fxinv)[tk.m] - Sm * b;
+  acc[o] = 0ull;
+  if (save_prev) gptr(P.pm_prev)[o] = old;
+  pm[o] = s;
+}
+
+// p_r = sum_m a_m p^(m)_r, and the block's partial sum of
+// sum_r sum_m (p_r - p^(m)_r)^2 / S^m.
+// Called by all 256 threads of a workgroup (tidx = thread index; sh: four
+// doubles of LDS).
+__device__ __forceinline__ void close_average(const AvgTask& tk, const ProbAux& P, int save_prev, int tidx,
+                                              double* sh) {
+  const int R = P.R, M = P.M;
+  const int r = tk.rb * 256 + tidx;
+  const double* const pm = gptr(P.pm);
+  const double* const aw = gptr(P.aw);
+  const double* const Sd = gptr(P.Sd);
+  double* const p = gptr(P.p);
+  double d2 = 0.0;
+  if (r < R) {
+    // eight measures' loads in flight at a time; the sums keep the order m = 0, 1, ...
+    constexpr int U = 8;
+    double pr = 0.0;
+    for (int m0 = 0; m0 < M; m0 += U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = m0 + u < M ? pm[(size_t)(m0 + u) * R + r] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (m0 + u < M) pr += aw[m0 + u] * v[u];
+    }
+    for (int m0 = 0; m0 < M; m0 += U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = m0 + u < M ? pm[(size_t)(m0 + u) * R + r] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (m0 + u < M) {
+          const double e = pr - v[u];
+          d2 += e * e / Sd[m0 + u];
+        }
+      }
+    }
+    if (save_prev) gptr(P.p_prev)[r] = p[r];
+    p[r] = pr;
+  }
+  d2 = wave_sum(d2);
+  if ((tidx & 63) == 0) sh[tidx >> 6] = d2;
+  __syncthreads();
+  if (tidx == 0) gptr(P.d2part)[tk.rb] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// Short columns, Steps 3 and 1 of one block of 256 rows, fused: both are
+// row-parallel.  Row r's new marginals are
+//   p^(m)_r = sum_s pi_hat_rs - S^m b^(m)_r,  b^(m)_r = t (p_r - p^(m)_r) / S^m
+// (the pi_hat sum from the column kernel's fixed-point accumulator, which is
+// cleared; t as the column kernel formed it; p and p^(m) of the iterate,
+// each read by this thread alone before it overwrites them), then
+// p_r = sum_m a_m p^(m)_r and the block's partial sum of
+// sum_r sum_m (p_r - p^(m)_r)^2 / S^m.  Called by all 256 threads of a
+// workgroup (tidx = thread index; sh: four doubles of LDS).
+__device__ __forceinline__ void close_rows(const AvgTask& tk, const ProbAux& P, int save_prev, int tidx,
+                                           double* sh) {
+  const int R = uniform_i(P.R), M = uniform_i(P.M);
+  const int r = tk.rb * 256 + tidx;
+  const double t = uniform_d(*gptr(P.t));
+  double* const pm = gptr(P.pm);
+  unsigned long long* const acc = gptr(P.acc);
+  const double* const aw = gptr(P.aw);
+  const double* const Sd = gptr(P.Sd);
+  const double* const fxinv = gptr(P.fxinv);
+  double* const p = gptr(P.p);
+  double d2 = 0.0;
+  if (r < R) {
+    const double pold = p[r];
+    double pr = 0.0;
+    constexpr int U = 8;  // eight measures' loads in flight; sums in the order m = 0, 1, ...
+    for (int m0 = 0; m0 < M; m0 += U) {
+      double old[U];
+      unsigned long long ac[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t o = (size_t)(m0 + u) * R + r;
+        old[u] = m0 + u < M ? pm[o] : 0.0;
+        ac[u] = m0 + u < M ? acc[o] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (m0 + u < M) {
+          const int m = m0 + u;
+          const size_t o = (size_t)m * R + r;
+          const double Sm = Sd[m];
+          const double b = t * (pold - old[u]) / Sm;
+          const double v = (double)ac[u] * fxinv[m] - Sm * b;
+          acc[o] = 0ull;
+          if (save_prev) gptr(P.pm_prev)[o] = old[u];
+          pm[o] = v;
+          pr += aw[m] * v;
+        }
+      }
+    }
+    for (int m0 = 0; m0 < M; m0 += U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = m0 + u < M ? pm[(size_t)(m0 + u) * R + r] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (m0 + u < M) {
+          const double e = pr - v[u];
+          d2 += e * e / Sd[m0 + u];
+        }
+      }
+    }
+    if (save_prev) gptr(P.p_prev)[r] = pold;
+    p[r] = pr;
+  }
+  d2 = wave_reduce<OpSum>(d2);
+  if ((tidx & 63) == 0) sh[tidx >> 6] = d2;
+  __syncthreads();
+  if (tidx == 0) gptr(P.d2part)[tk.rb] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
 // One problem as the column kernel sees it (a batch holds many).
 template <typename T>
 struct ProbDev {
@@ -844,6 +1010,7 @@ column_kernel(ColArgs<T> a) {
       o[7] = 0.0;
     }
   }
+
 }
 
 }  // namespace mam

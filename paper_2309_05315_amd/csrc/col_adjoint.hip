@@ -1,32 +1,29 @@
-// Reverse-mode column kernel instances: the shapes of the forward column
-// kernel (64 threads with 1-16 values per thread, 128-1024 threads with
-// 4-16); the vector width is a run-time argument of the row mapping.
+// Reverse-mode column kernel instances: every mask size the forward column
+// kernel records (64-1024 threads per column, 8- or 16-bit mask words, so
+// 1-32 mask bytes per lane), 1, 2 or 4 columns per wave at a time.
 #include "mam_adjoint.hpp"
 #include "mam_dispatch.hpp"
 
 namespace mam {
 
-template <int NT>
-AdjFn pick_adjoint_vpt(int vpt) {
-  if constexpr (NT == 64) {
-    if (vpt == 1) return &adjoint_kernel<NT, 1>;
-    if (vpt == 2) return &adjoint_kernel<NT, 2>;
-  }
-  switch (vpt) {
-    case 4: return &adjoint_kernel<NT, 4>;
-    case 8: return &adjoint_kernel<NT, 8>;
-    case 16: return &adjoint_kernel<NT, 16>;
+template <int KC>
+AdjFn pick_adjoint_lb(int lane_bytes) {
+  switch (lane_bytes) {
+    case 1: return &adjoint_kernel<1, KC>;
+    case 2: return &adjoint_kernel<2, KC>;
+    case 4: return &adjoint_kernel<4, KC>;
+    case 8: return &adjoint_kernel<8, KC>;
+    case 16: return &adjoint_kernel<16, KC>;
+    case 32: return &adjoint_kernel<32, KC>;
     default: return nullptr;
   }
 }
 
-AdjFn pick_adjoint(int nt, int vpt) {
-  switch (nt) {
-    case 64: return pick_adjoint_vpt<64>(vpt);
-    case 128: return pick_adjoint_vpt<128>(vpt);
-    case 256: return pick_adjoint_vpt<256>(vpt);
-    case 512: return pick_adjoint_vpt<512>(vpt);
-    case 1024: return pick_adjoint_vpt<1024>(vpt);
+AdjFn pick_adjoint(int lane_bytes, int kc) {
+  switch (kc) {
+    case 1: return pick_adjoint_lb<1>(lane_bytes);
+    case 2: return pick_adjoint_lb<2>(lane_bytes);
+    case 4: return pick_adjoint_lb<4>(lane_bytes);
     default: return nullptr;
   }
 }

@@ -129,6 +129,9 @@ struct Layout {
 };
 
 // Reverse-mode state of a single-problem plan (mam_record / mam_backward).
+// columns one wave of the reverse column kernel takes at a time
+constexpr int kAdjCols = 2;
+
 struct Adjoint {
   bool valid = false;
   int64_t K = 0, C = 1, nw = 0;  // iterations, window length, windows
@@ -137,15 +140,8 @@ struct Adjoint {
   size_t bytes = 0;
   int64_t mld = 0;               // mask bytes per column
   size_t ckpt_bytes = 0;         // one checkpoint of theta
-  size_t o_mask = 0, o_ckpt = 0, o_ckpt_pm = 0, o_U = 0, o_cacc = 0, o_qacc = 0, o_V = 0, o_wold = 0, o_wnew = 0;
-  size_t o_cptr = 0, o_clist = 0, o_aux = 0, total = 0;
-  // the reverse kernel's own segments (more workgroups than the forward's:
-  // its columns are latency-bound chains)
-  static constexpr int kMaxWg = 2048;
-  int nwg = 0;
-  size_t nseg_cap = 0;
-  size_t o_seg_m = 0, o_seg_j0 = 0, o_seg_j1 = 0, o_seg_poff = 0, o_wg_seg = 0, o_mseg = 0, o_seg_idx = 0,
-         o_partial = 0;
+  size_t o_mask = 0, o_ckpt = 0, o_ckpt_pm = 0, o_U = 0, o_cacc = 0, o_qacc = 0, o_V = 0, o_wold = 0;
+  size_t o_wacc = 0, o_mx = 0, o_cptr = 0, o_clist = 0, total = 0;
   // unbalanced problems: p, p^(m) and the d^2 partials of every recorded
   // iteration (same slot ring as the masks), and the two-pass buffers
   bool unbal = false;
@@ -1693,20 +1689,10 @@ mam_status adjoint_layout(const Plan* pl, int64_t K, int64_t C, Adjoint* A) {
   A->o_qacc = take(T * 8);
   A->o_V = take(M * R * 8);
   A->o_wold = take(M * R * 8);
-  A->o_wnew = take(M * R * 8);
+  A->o_wacc = take(M * R * 8);
+  A->o_mx = take(mam::kAdjSlots * 8);
   A->o_cptr = take((size_t)(p.cost_ncols + 1) * 8);
   A->o_clist = take(T * 4);
-  A->o_aux = take(sizeof(mam::ProbAux));
-  // reverse schedule: at most kMaxWg workgroups, each run split at measure boundaries
-  A->nseg_cap = (size_t)Adjoint::kMaxWg + (size_t)M;
-  A->o_seg_m = take(A->nseg_cap * 4);
-  A->o_seg_j0 = take(A->nseg_cap * 8);
-  A->o_seg_j1 = take(A->nseg_cap * 8);
-  A->o_seg_poff = take(A->nseg_cap * 8);
-  A->o_wg_seg = take(((size_t)Adjoint::kMaxWg + 1) * 4);
-  A->o_mseg = take((M + 1) * 4);
-  A->o_seg_idx = take(A->nseg_cap * 8);  // holds the partial offsets in measure order
-  A->o_partial = take(A->nseg_cap * R * 8);
   A->unbal = !std::isinf(p.gamma);
   if (A->unbal) {
     const size_t slots = (size_t)(A->C + 1);
@@ -1764,77 +1750,6 @@ mam_status record_range(Plan* pl, int64_t k0, int64_t k1, int64_t rec_from, bool
   return MAM_OK;
 }
 
-// Segments of the reverse kernel: nwg workgroups take equal runs of the
-// measure-major column order, split at measure boundaries; each measure's
-// segments in schedule order for the marginal kernel.  Uploaded into the
-// adjoint workspace (synchronous).
-mam_status upload_adjoint_tables(Plan* pl, int nwg, hipStream_t st) {
-  Adjoint& A = pl->adj;
-  const Prob& p = pl->P[0];
-  std::vector<int32_t> seg_m, wg_seg, mseg(p.M + 1, 0), seg_idx;
-  std::vector<int64_t> seg_j0, seg_j1, seg_poff;
-  for (int w = 0; w < nwg; ++w) {
-    wg_seg.push_back((int32_t)seg_m.size());
-    int64_t lo = p.T * w / nwg, hi = p.T * (w + 1) / nwg;
-    while (lo < hi) {
-      const int64_t m = std::upper_bound(p.col_off.begin(), p.col_off.end(), lo) - p.col_off.begin() - 1;
-      const int64_t e = std::min(hi, p.col_off[m + 1]);
-      seg_m.push_back((int32_t)m);
-      seg_j0.push_back(lo);
-      seg_j1.push_back(e);
-      seg_poff.push_back((int64_t)(seg_m.size() - 1) * p.R);
-      lo = e;
-    }
-  }
-  wg_seg.push_back((int32_t)seg_m.size());
-  if (seg_m.size() > A.nseg_cap) return fail(MAM_EHIP, "reverse schedule exceeds its capacity");
-  for (size_t k = 0; k < seg_m.size(); ++k) ++mseg[seg_m[k] + 1];
-  for (int64_t m = 0; m < p.M; ++m) mseg[m + 1] += mseg[m];
-  seg_idx.assign(seg_m.size(), 0);
-  {
-    std::vector<int32_t> fill(mseg.begin(), mseg.end() - 1);
-    for (size_t k = 0; k < seg_m.size(); ++k) seg_idx[fill[seg_m[k]]++] = (int32_t)k;
-  }
-  std::vector<int64_t> mpoff(seg_idx.size());
-  for (size_t i = 0; i < seg_idx.size(); ++i) mpoff[i] = seg_poff[seg_idx[i]];
-  auto put = [&](size_t off, const void* src, size_t n) -> mam_status {
-    if (n) HIP_TRY(hipMemcpyAsync(A.ws + off, src, n, hipMemcpyHostToDevice, st));
-    return MAM_OK;
-  };
-  TRY(put(A.o_seg_m, seg_m.data(), seg_m.size() * 4));
-  TRY(put(A.o_seg_j0, seg_j0.data(), seg_j0.size() * 8));
-  TRY(put(A.o_seg_j1, seg_j1.data(), seg_j1.size() * 8));
-  TRY(put(A.o_seg_poff, seg_poff.data(), seg_poff.size() * 8));
-  TRY(put(A.o_wg_seg, wg_seg.data(), wg_seg.size() * 4));
-  TRY(put(A.o_mseg, mseg.data(), mseg.size() * 4));
-  TRY(put(A.o_seg_idx, mpoff.data(), mpoff.size() * 8));
-  HIP_TRY(hipStreamSynchronize(st));
-  A.nwg = nwg;
-  return MAM_OK;
-}
-
-// Workgroups of the reverse kernel the device holds at once (at most kMaxWg).
-mam_status adjoint_resident(const Plan* pl, int* out) {
-  const Group& g = pl->G[0];
-  mam::AdjFn fn = mam::pick_adjoint(g.nt, g.vpt);
-  if (!fn) return fail(MAM_EUNSUPPORTED, "no reverse column kernel for nt=%d vpt=%d", g.nt, g.vpt);
-  int dev = 0, cus = 0, blocks = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const size_t shmem = (size_t)g.vpt * g.nt * 8 * g.ng;
-  if (shmem > 65536)
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shmem));
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(fn),
-                                                       g.nt == 64 ? 256 : g.nt, shmem));
-  const int64_t cols_per_group = g.ng;
-  int64_t n = (int64_t)std::max(1, blocks) * std::max(1, cus);
-  n = std::min<int64_t>(n, Adjoint::kMaxWg);
-  n = std::min<int64_t>(n, std::max<int64_t>(1, pl->P[0].T / cols_per_group));
-  *out = (int)std::max<int64_t>(1, n);
-  return MAM_OK;
-}
-
 mam_status plan_record(Plan* pl, int64_t K, int64_t C, void* ws, size_t bytes, hipStream_t st) {
   Adjoint A;
   TRY(adjoint_layout(pl, K, C, &A));
@@ -1863,17 +1778,11 @@ mam_status plan_record(Plan* pl, int64_t K, int64_t C, void* ws, size_t bytes, h
     for (int64_t m = 0; m < p.M; ++m)
       for (int64_t j = p.col_off[m]; j < p.col_off[m + 1]; ++j) clist[fill[col_of(j, m)]++] = (int32_t)j;
   }
-  mam::ProbAux aux = {reinterpret_cast<double*>(A.ws + A.o_wnew), nullptr, nullptr, nullptr, nullptr,
-                      at<double>(pl, p.o_aw), at<double>(pl, p.o_Sd), (int32_t)p.R, (int32_t)p.M, p.mbase, 0};
   HIP_TRY(hipMemcpyAsync(A.ws + A.o_cptr, cptr.data(), cptr.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(A.ws + A.o_clist, clist.data(), clist.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(A.ws + A.o_aux, &aux, sizeof(aux), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   pl->adj = A;
   pl->adj.valid = false;
-  int nwg_adj = 1;
-  TRY(adjoint_resident(pl, &nwg_adj));
-  TRY(upload_adjoint_tables(pl, nwg_adj, st));
   TRY(record_range(pl, 0, K, (A.nw - 1) * A.C, true, st));
   pl->iters_done += K;
   pl->adj.resident = A.nw - 1;
@@ -1903,13 +1812,16 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
   if (!gp || !gq || !gc) return fail(MAM_EINVAL, "grad_p, grad_q and grad_cost must be non-NULL");
   const Prob& p = pl->P[0];
   const Group& g = pl->G[0];
-  const Layout& L = pl->lay;
   double* V = reinterpret_cast<double*>(A.ws + A.o_V);
   double* wold = reinterpret_cast<double*>(A.ws + A.o_wold);
-  double* wnew = reinterpret_cast<double*>(A.ws + A.o_wnew);
+  auto* wacc = reinterpret_cast<unsigned long long*>(A.ws + A.o_wacc);
+  auto* mx = reinterpret_cast<unsigned long long*>(A.ws + A.o_mx);
   const int64_t MR = p.M * p.R;
-  hipLaunchKernelGGL(mam::adjoint_start_kernel, dim3((unsigned)std::min<int64_t>(4096, (MR + 255) / 256)), dim3(256),
-                     0, st, gp, at<double>(pl, p.o_aw), V, wold, (int)p.R, (int)p.M);
+  const unsigned mr_blocks = (unsigned)std::min<int64_t>(4096, (MR + 255) / 256);
+  hipLaunchKernelGGL(mam::adjoint_reset_kernel, dim3(mr_blocks), dim3(256), 0, st, wacc, MR, mx);
+  LAUNCH_CHECK("adjoint_reset_kernel");
+  hipLaunchKernelGGL(mam::adjoint_start_kernel, dim3(mr_blocks), dim3(256), 0, st, gp, at<double>(pl, p.o_aw), V, wold,
+                     (int)p.R, (int)p.M, mx);
   LAUNCH_CHECK("adjoint_start_kernel");
   const int64_t RT = p.R * p.T;
   hipLaunchKernelGGL(mam::fill_value_kernel, dim3((unsigned)std::min<int64_t>(8192, (RT + 255) / 256)), dim3(256), 0,
@@ -1919,29 +1831,36 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
                      st, reinterpret_cast<double*>(A.ws + A.o_qacc), p.T, 0.0);
   LAUNCH_CHECK("fill_value_kernel");
 
-  mam::AdjFn fn = mam::pick_adjoint(g.nt, g.vpt);
-  if (!fn) return fail(MAM_EUNSUPPORTED, "no reverse column kernel for nt=%d vpt=%d", g.nt, g.vpt);
-  const size_t shmem = (size_t)g.vpt * g.nt * 8 * g.ng;  // row-sum accumulators only
-  if (shmem > 65536)
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shmem));
+  // one wave per column, kAdjCols columns at a time; lane l reads mld/64
+  // bytes of a column's mask
+  const int lane_bytes = (int)(A.mld / 64);
+  mam::AdjFn fn = mam::pick_adjoint(lane_bytes, kAdjCols);
+  if (!fn || A.mld % 64) return fail(MAM_EUNSUPPORTED, "no reverse column kernel for %lld mask bytes per column",
+                                     (long long)A.mld);
+  double smax = 0.0;
+  for (int64_t m = 0; m < p.M; ++m) smax = std::max(smax, (double)(p.col_off[m + 1] - p.col_off[m]));
   mam::AdjArgs a;
-  a.seg_m = reinterpret_cast<const int32_t*>(A.ws + A.o_seg_m);
-  a.seg_j0 = reinterpret_cast<const int64_t*>(A.ws + A.o_seg_j0);
-  a.seg_j1 = reinterpret_cast<const int64_t*>(A.ws + A.o_seg_j1);
-  a.seg_poff = reinterpret_cast<const int64_t*>(A.ws + A.o_seg_poff);
-  a.wg_seg = reinterpret_cast<const int32_t*>(A.ws + A.o_wg_seg);
-  a.partial = reinterpret_cast<double*>(A.ws + A.o_partial);
   a.mld = A.mld;
+  a.col_off = at<int64_t>(pl, p.o_coloff);
   a.U = reinterpret_cast<double*>(A.ws + A.o_U);
   a.cacc = reinterpret_cast<double*>(A.ws + A.o_cacc);
   a.qacc = reinterpret_cast<double*>(A.ws + A.o_qacc);
   a.V = V;
+  a.wacc = wacc;
+  a.mx = mx;
+  a.smax = smax;
+  a.T = p.T;
   a.R = (int32_t)p.R;
-  a.vec_shift = g.vec == 4 ? 2 : (g.vec == 2 ? 1 : 0);
-  a.nwg = A.nwg;
-  a.xcd_remap = 0;
-  const int wgsize = g.nt == 64 ? 256 : g.nt;
+  a.M = (int32_t)p.M;
+  a.nt = g.nt;
+  a.vs = g.vec == 4 ? 2 : (g.vec == 2 ? 1 : 0);
+  a.wshift = g.vpt <= 8 ? 3 : 4;
+  // one batch of columns per wave (measured faster than resident waves
+  // looping over batches); the kernel loops only past 2^22 workgroups
+  const int64_t nbatch = (p.T + kAdjCols - 1) / kAdjCols;
+  const unsigned adj_blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nbatch + 3) / 4, (int64_t)1 << 22));
+  const unsigned nbr = (unsigned)((p.R + 255) / 256);
+  int64_t step = 0;  // reverse steps taken: the bound slots rotate mod 3
 
   const bool timing = pl->timing;
   for (int64_t w = A.nw - 1; w >= 0; --w) {
@@ -1984,36 +1903,31 @@ mam_status plan_backward(Plan* pl, const double* gp, void* gq, void* gc, hipStre
         if (!e0 || !e1) return fail(MAM_EHIP, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(e0, st));
       }
-      hipLaunchKernelGGL(fn, dim3(A.nwg), dim3(wgsize), shmem, st, a);
+      a.slot = (int32_t)(step % 3);
+      hipLaunchKernelGGL(fn, dim3(adj_blocks), dim3(256), 0, st, a);
       LAUNCH_CHECK("adjoint_kernel");
       if (timing) HIP_TRY(hipEventRecord(e1, st));
-      hipLaunchKernelGGL(mam::marginal_kernel, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
-                         at<mam::MargTask>(pl, L.mtasks), reinterpret_cast<const mam::ProbAux*>(A.ws + A.o_aux),
-                         reinterpret_cast<const int32_t*>(A.ws + A.o_mseg),
-                         reinterpret_cast<const int64_t*>(A.ws + A.o_seg_idx),
-                         reinterpret_cast<const double*>(A.ws + A.o_partial), 0, nullptr);
-      LAUNCH_CHECK("marginal_kernel");
-      const unsigned nbr = (unsigned)((p.R + 255) / 256);
       if (!A.unbal) {
-        hipLaunchKernelGGL(mam::adjoint_average_kernel, dim3(nbr), dim3(256), 0, st, wnew, wold, V,
-                           at<double>(pl, p.o_Sd), at<double>(pl, p.o_aw), (int)p.R, (int)p.M);
+        hipLaunchKernelGGL(mam::adjoint_average_kernel, dim3(nbr), dim3(256), 0, st, wacc, wold, V,
+                           at<double>(pl, p.o_Sd), at<double>(pl, p.o_aw), (int)p.R, (int)p.M, mx, a.slot, smax);
         LAUNCH_CHECK("adjoint_average_kernel");
       } else {
         const size_t sl = (size_t)(k % (A.C + 1));
-        const size_t MR = (size_t)p.M * (size_t)p.R;
-        const double* pmk = reinterpret_cast<const double*>(A.ws + A.o_pm_rec) + sl * MR;
+        const size_t MRs = (size_t)p.M * (size_t)p.R;
+        const double* pmk = reinterpret_cast<const double*>(A.ws + A.o_pm_rec) + sl * MRs;
         const double* pk = reinterpret_cast<const double*>(A.ws + A.o_p_rec) + sl * (size_t)p.R;
         const double* d2k = reinterpret_cast<const double*>(A.ws + A.o_d2_rec) + sl * (size_t)p.nb;
         double* bbar = reinterpret_cast<double*>(A.ws + A.o_bbar);
         double* tpart = reinterpret_cast<double*>(A.ws + A.o_tpart);
-        hipLaunchKernelGGL(mam::adjoint_unbal1_kernel, dim3(nbr), dim3(256), 0, st, wnew, wold, V,
-                           at<double>(pl, p.o_Sd), pmk, pk, bbar, tpart, (int)p.R, (int)p.M);
+        hipLaunchKernelGGL(mam::adjoint_unbal1_kernel, dim3(nbr), dim3(256), 0, st, wacc, wold, V,
+                           at<double>(pl, p.o_Sd), pmk, pk, bbar, tpart, (int)p.R, (int)p.M, mx, a.slot, smax);
         LAUNCH_CHECK("adjoint_unbal1_kernel");
-        hipLaunchKernelGGL(mam::adjoint_unbal2_kernel, dim3(nbr), dim3(256), 0, st, bbar, wnew, wold, V, pmk, pk,
-                           d2k, p.nb, tpart, (int)nbr, at<double>(pl, p.o_Sd), at<double>(pl, p.o_aw), p.rho,
-                           p.gamma, (int)p.R, (int)p.M);
+        hipLaunchKernelGGL(mam::adjoint_unbal2_kernel, dim3(nbr), dim3(256), 0, st, bbar, V, pmk, pk, d2k, p.nb,
+                           tpart, (int)nbr, at<double>(pl, p.o_Sd), at<double>(pl, p.o_aw), p.rho, p.gamma, (int)p.R,
+                           (int)p.M, mx, a.slot);
         LAUNCH_CHECK("adjoint_unbal2_kernel");
       }
+      ++step;
     }
   }
   TRY(pl->dtype == MAM_F32 ? backward_finish<float>(pl, gq, gc, st) : backward_finish<double>(pl, gq, gc, st));

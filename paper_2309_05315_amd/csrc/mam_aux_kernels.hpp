@@ -361,27 +361,44 @@ __global__ void zero_kernel(double* p, int n) {
 
 // ---- reverse mode (see mam_adjoint.hpp for the step) ----
 
+// Row r of measure m's W_new from its fixed-point accumulator (which is
+// cleared for the next step); NaN when the step's bound was not finite.
+__device__ __forceinline__ double adj_take_w(unsigned long long* wacc, size_t o, const AdjScale& sc) {
+  const double w = sc.ok ? adj_from_fixed(wacc[o], sc.E) : __builtin_nan("");
+  wacc[o] = 0ull;
+  return w;
+}
+
 // Transposed averaging of one reverse step, per row r:
 //   bbar_m = 2 W_new - W_old - S^m V_m,  pbar = sum_m bbar_m / S^m,
-//   V_m <- -bbar_m / S^m + a_m pbar,  W_old <- W_new.
+//   V_m <- -bbar_m / S^m + a_m pbar,  W_old <- W_new,
+// and the bound of |V| for the next step.
 __global__ void __launch_bounds__(256)
-adjoint_average_kernel(const double* __restrict__ wnew, double* __restrict__ wold, double* __restrict__ V,
-                       const double* __restrict__ Sd, const double* __restrict__ aw, int R, int M) {
+adjoint_average_kernel(unsigned long long* __restrict__ wacc, double* __restrict__ wold, double* __restrict__ V,
+                       const double* __restrict__ Sd, const double* __restrict__ aw, int R, int M,
+                       unsigned long long* __restrict__ mx, int slot, double smax) {
+  const AdjScale sc = adj_scale(mx, slot, smax);
   const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= R) return;
-  double pbar = 0.0;
-  for (int m = 0; m < M; ++m) {
-    const size_t o = (size_t)m * R + r;
-    const double bb = 2.0 * wnew[o] - wold[o] - Sd[m] * V[o];
-    pbar += bb / Sd[m];
+  double vmx = 0.0;
+  if (r < R) {
+    double pbar = 0.0;
+    for (int m = 0; m < M; ++m) {
+      const size_t o = (size_t)m * R + r;
+      // W_new is written back over W_old below, so read it once here
+      const double wn = adj_take_w(wacc, o, sc);
+      const double bb = 2.0 * wn - wold[o] - Sd[m] * V[o];
+      wold[o] = wn;
+      V[o] = bb;  // bbar_m, held until pbar is known
+      pbar += bb / Sd[m];
+    }
+    for (int m = 0; m < M; ++m) {
+      const size_t o = (size_t)m * R + r;
+      const double v = -V[o] / Sd[m] + aw[m] * pbar;
+      V[o] = v;
+      vmx = fmax(vmx, adj_mag(v));
+    }
   }
-  for (int m = 0; m < M; ++m) {
-    const size_t o = (size_t)m * R + r;
-    const double wn = wnew[o];
-    const double bb = 2.0 * wn - wold[o] - Sd[m] * V[o];
-    V[o] = -bb / Sd[m] + aw[m] * pbar;
-    wold[o] = wn;
-  }
+  adj_raise_block(mx + (slot + 1) % 3, vmx);
 }
 
 // Transposed averaging with the unbalanced damping.  Step 1 of Alg. 1 scales
@@ -391,19 +408,24 @@ adjoint_average_kernel(const double* __restrict__ wnew, double* __restrict__ wol
 // bbar_m = 2 W_new - W_old - S^m V_m, the adjoint of e_m is
 //   ebar_m = t bbar_m / S^m - tbar t e_m / (S^m d^2),  tbar = sum_m <bbar_m, e_m> / S^m
 // (second term only while t < 1), and V_m <- a_m sum_j ebar_j - ebar_m.
-// First pass: bbar and the per-block partials of tbar (fixed order).
+// First pass: bbar (W_old <- W_new) and the per-block partials of tbar
+// (fixed order).
 __global__ void __launch_bounds__(256)
-adjoint_unbal1_kernel(const double* __restrict__ wnew, const double* __restrict__ wold,
+adjoint_unbal1_kernel(unsigned long long* __restrict__ wacc, double* __restrict__ wold,
                       const double* __restrict__ V, const double* __restrict__ Sd,
                       const double* __restrict__ pm_k, const double* __restrict__ p_k,
-                      double* __restrict__ bbar, double* __restrict__ tpart, int R, int M) {
+                      double* __restrict__ bbar, double* __restrict__ tpart, int R, int M,
+                      const unsigned long long* __restrict__ mx, int slot, double smax) {
   __shared__ double sh[4];
+  const AdjScale sc = adj_scale(mx, slot, smax);
   const int r = blockIdx.x * 256 + threadIdx.x;
   double acc = 0.0;
   if (r < R) {
     for (int m = 0; m < M; ++m) {
       const size_t o = (size_t)m * R + r;
-      const double bb = 2.0 * wnew[o] - wold[o] - Sd[m] * V[o];
+      const double wn = adj_take_w(wacc, o, sc);
+      const double bb = 2.0 * wn - wold[o] - Sd[m] * V[o];
+      wold[o] = wn;
       bbar[o] = bb;
       acc += bb * (p_k[r] - pm_k[o]) / Sd[m];
     }
@@ -415,47 +437,62 @@ adjoint_unbal1_kernel(const double* __restrict__ wnew, const double* __restrict_
 }
 
 // Second pass: tbar, d and t of the iteration (from its recorded d^2
-// partials), then ebar, V and W_old <- W_new per row.
+// partials), then ebar and V per row, and the bound of |V| for the next step.
 __global__ void __launch_bounds__(256)
-adjoint_unbal2_kernel(const double* __restrict__ bbar, const double* __restrict__ wnew,
-                      double* __restrict__ wold, double* __restrict__ V,
+adjoint_unbal2_kernel(const double* __restrict__ bbar, double* __restrict__ V,
                       const double* __restrict__ pm_k, const double* __restrict__ p_k,
                       const double* __restrict__ d2_k, int nd2, const double* __restrict__ tpart, int ntp,
                       const double* __restrict__ Sd, const double* __restrict__ aw, double rho, double gamma,
-                      int R, int M) {
+                      int R, int M, unsigned long long* __restrict__ mx, int slot) {
   const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= R) return;
-  double tb = 0.0, d2 = 0.0;
-  for (int i = 0; i < ntp; ++i) tb += tpart[i];
-  for (int i = 0; i < nd2; ++i) d2 += d2_k[i];
-  const double d = sqrt(d2);
-  const bool damped = !__builtin_isinf(gamma) && rho * d > gamma;
-  const double t = damped ? gamma / (rho * d) : 1.0;
-  const double c = damped ? tb * t / d2 : 0.0;
-  double pbar = 0.0;
-  for (int m = 0; m < M; ++m) {
-    const size_t o = (size_t)m * R + r;
-    pbar += (t * bbar[o] - c * (p_k[r] - pm_k[o])) / Sd[m];
+  double vmx = 0.0;
+  if (r < R) {
+    double tb = 0.0, d2 = 0.0;
+    for (int i = 0; i < ntp; ++i) tb += tpart[i];
+    for (int i = 0; i < nd2; ++i) d2 += d2_k[i];
+    const double d = sqrt(d2);
+    const bool damped = !__builtin_isinf(gamma) && rho * d > gamma;
+    const double t = damped ? gamma / (rho * d) : 1.0;
+    const double c = damped ? tb * t / d2 : 0.0;
+    double pbar = 0.0;
+    for (int m = 0; m < M; ++m) {
+      const size_t o = (size_t)m * R + r;
+      pbar += (t * bbar[o] - c * (p_k[r] - pm_k[o])) / Sd[m];
+    }
+    for (int m = 0; m < M; ++m) {
+      const size_t o = (size_t)m * R + r;
+      const double eb = (t * bbar[o] - c * (p_k[r] - pm_k[o])) / Sd[m];
+      const double v = aw[m] * pbar - eb;
+      V[o] = v;
+      vmx = fmax(vmx, adj_mag(v));
+    }
   }
-  for (int m = 0; m < M; ++m) {
-    const size_t o = (size_t)m * R + r;
-    const double eb = (t * bbar[o] - c * (p_k[r] - pm_k[o])) / Sd[m];
-    V[o] = aw[m] * pbar - eb;
-    wold[o] = wnew[o];
-  }
+  adj_raise_block(mx + (slot + 1) % 3, vmx);
 }
 
-// Start of the reverse sweep: V_m = a_m * dL/dp_bar, W_old = 0.
+// Start of the reverse sweep: the bound slots and the W accumulators cleared.
+__global__ void __launch_bounds__(256)
+adjoint_reset_kernel(unsigned long long* __restrict__ wacc, int64_t n, unsigned long long* __restrict__ mx) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) wacc[i] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x < kAdjSlots) mx[threadIdx.x] = 0ull;
+}
+
+// Then V_m = a_m * dL/dp_bar, W_old = 0, and the bound of |V| for the
+// first reverse step (slot 0).
 __global__ void __launch_bounds__(256)
 adjoint_start_kernel(const double* __restrict__ gp, const double* __restrict__ aw, double* __restrict__ V,
-                     double* __restrict__ wold, int R, int M) {
+                     double* __restrict__ wold, int R, int M, unsigned long long* __restrict__ mx) {
   const int64_t n = (int64_t)R * M;
+  double vmx = 0.0;
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const int m = (int)(i / R);
     const int r = (int)(i - (int64_t)m * R);
-    V[i] = aw[m] * gp[r];
+    const double v = aw[m] * gp[r];
+    V[i] = v;
     wold[i] = 0.0;
+    vmx = fmax(vmx, adj_mag(v));
   }
+  adj_raise_block(mx, vmx);
 }
 
 // qbar_s = qacc_s + (sum_r V^0_m,r) / R for the columns of measure m (one

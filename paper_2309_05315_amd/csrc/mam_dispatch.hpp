@@ -48,10 +48,11 @@ LongFns<T> pick_long(int vpt, int vec, bool grid);
 extern template LongFns<float> pick_long<float>(int, int, bool);
 extern template LongFns<double> pick_long<double>(int, int, bool);
 
-// Reverse-mode column kernel for (threads per column, values per thread).
+// Reverse-mode column kernel for (mask bytes per lane, columns per wave at
+// a time); nullptr if none exists.
 struct AdjArgs;
 using AdjFn = void (*)(AdjArgs);
-AdjFn pick_adjoint(int nt, int vpt);
+AdjFn pick_adjoint(int lane_bytes, int kc);
 
 extern template ColFn<float> pick_column_kc<float, 1>(int, int, int, int);
 extern template ColFn<float> pick_column_kc<float, 2>(int, int, int, int);

@@ -68,6 +68,10 @@ CASES = {
     "percol_R4099": lambda dt: inputs.tiny_problem(6, R=4099, S=[6, 7], dtype=dt),
     "indexed_R50": lambda dt: indexed_tiny(7, R=50, S=[20, 13], dtype=dt),
     "grid_K8_M3": lambda dt: inputs.balanced_plain(K=8, M=3, dtype=dt),
+    # the reverse kernel finds a column's measure by one ballot up to 65
+    # measures and by a search beyond
+    "percol_M65": lambda dt: inputs.tiny_problem(13, R=24, S=[3, 1, 2, 4] * 16 + [2], dtype=dt),
+    "percol_M66": lambda dt: inputs.tiny_problem(14, R=24, S=[3, 1, 2, 4] * 16 + [2, 5], dtype=dt),
 }
 
 
@@ -113,6 +117,14 @@ def test_checkpoint_windows_and_repeated_backward_are_bitwise_equal():
         gq2, gc2 = s.backward(torch.as_tensor(u))
         assert np.array_equal(gq2.double().cpu().numpy(), gq)
         assert np.array_equal(gc2[:, :p.R].double().cpu().numpy(), gc)
+
+
+def test_zero_loss_gradient_gives_zero_gradients():
+    """dL/dp_bar = 0: every adjoint is 0 (the fixed-point row sums then run
+    at scale 1 and stay 0)."""
+    p = inputs.tiny_problem(15, R=50, S=[20, 13], dtype="f64")
+    _, gq, gc, _ = gpu_grads(p, 8, grad_p=np.zeros(p.R))
+    assert np.all(gq == 0.0) and np.all(gc == 0.0)
 
 
 def test_zero_iterations():

@@ -432,6 +432,20 @@ def extra_workloads(torch, mam, inputs, log, only=None):
                          "workgroups": sc["workgroups"], **sup}
             log(f"free support R={pf.R} T={pf.T} ({mode}): {dt * 1e3:.2f} ms/iter, {pf.R * pf.T / dt:.3e} entries/s, "
                 f"column kernels {col / n:.2f} ms" + (f" ({gbs:.0f} GB/s algorithmic)" if gbs else ""))
+        # the figures the free-support experiment reports (Sec. 6.3): the plan
+        # objective W_hat and dist_L(pi_hat) of the last iteration, from the
+        # long-column path's own diagnostics (outside every timed region)
+        s = mam.solver_for(pf, grid=True, sparse_store=True, diag=True)
+        s.init()
+        n_d = 50
+        s.iterate(n_d)
+        d = s.diagnostics()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        res["state_after_50"] = {k: (None if isinstance(v, float) and v != v else v) for k, v in d.items()}
+        log(f"free support after {n_d} iterations: W_hat {d['W_hat']:.6e}, dist_L {d['dist_L']:.3e}, "
+            f"measure residual {d['meas_resid']:.1e}")
         out["free_support_K60_M10_f32"] = res
 
     if want("adjoint"):

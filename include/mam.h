@@ -61,8 +61,9 @@ typedef int32_t mam_status;
 #define MAM_EUNSUPPORTED  -6  /* a size or feature outside what the path taken
                                   provides: R > 2^28 or M > 65535 (mam_create),
                                   R > 8192 inside a batch, a schedule no kernel
-                                  instance covers, diagnostics, reverse mode or
-                                  bundles on long columns (R > 8192) */
+                                  instance covers, reverse mode or bundles on
+                                  long columns (R > 8192), the theta stopping
+                                  test with MAM_FLAG_SPARSE_STORE */
 #define MAM_ESTATE        -7  /* call out of order (e.g. iterate before init) */
 
 #define MAM_F32 0
@@ -294,7 +295,8 @@ typedef struct mam_stop_result {
  * SYNCHRONIZES the stream (it returns when the run has ended) and fills
  * *out.  mam_diagnostics afterwards describes the last iteration when it was
  * a MAM_STOP_DTHETA check.  Errors: MAM_EINVAL (arguments), MAM_ESTATE
- * (before mam_init), MAM_EUNSUPPORTED (batch). */
+ * (before mam_init), MAM_EUNSUPPORTED (batch; MAM_STOP_DTHETA on long
+ * columns with MAM_FLAG_SPARSE_STORE). */
 mam_status mam_iterate_until(mam_problem* p, int64_t max_iters, int32_t test, double tol, int64_t check_every,
                              mam_stop_result* out, void* stream);
 
@@ -310,7 +312,13 @@ mam_status mam_marginals(mam_problem* p, double* pm_dev, void* stream);
 
 /* Diagnostics of the last iteration that ran with MAM_FLAG_DIAG.
  * SYNCHRONIZES the stream.  MAM_ESTATE if none ran yet, MAM_ENONFINITE if
- * the barycenter holds a NaN or Inf (the struct is still filled). */
+ * the barycenter holds a NaN or Inf (the struct is still filled).  Short and
+ * long columns; on long columns W_hat, meas_resid and the per-column counts
+ * come from the threshold pass (pi_hat = max(w - lambda, 0) at the entries
+ * the write pass patches, summed per column in a fixed order and over
+ * columns in column order), dtheta_inf from the write pass, and with
+ * MAM_FLAG_SPARSE_STORE dtheta_inf is NaN (no dense copy of the previous
+ * plans exists to compare with). */
 mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream);
 
 /* Kernel timing: while enabled, HIP events bracket every launch of the

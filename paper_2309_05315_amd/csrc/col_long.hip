@@ -10,13 +10,15 @@ template <typename T, int VPT, bool GRID>
 LongFns<T> pick_long_vec(int vec) {
   constexpr int VN = VecOf<T>::N;
   if (vec == VN)
-    return {&long_scan_kernel<T, VPT, VN, GRID, false>, &long_threshold_kernel<T, VPT, VN>,
-            &long_write_kernel<T, VPT, VN>, &long_rowsum_kernel<T>, &long_materialize_kernel<T, VPT, VN>,
-            &long_scan_kernel<T, VPT, VN, GRID, true>};
+    return {&long_scan_kernel<T, VPT, VN, GRID, false>, &long_threshold_kernel<T, VPT, VN, false>,
+            &long_write_kernel<T, VPT, VN, false>, &long_rowsum_kernel<T>, &long_materialize_kernel<T, VPT, VN>,
+            &long_scan_kernel<T, VPT, VN, GRID, true>, &long_threshold_kernel<T, VPT, VN, true>,
+            &long_write_kernel<T, VPT, VN, true>};
   if (vec == 1)
-    return {&long_scan_kernel<T, VPT, 1, GRID, false>, &long_threshold_kernel<T, VPT, 1>,
-            &long_write_kernel<T, VPT, 1>, &long_rowsum_kernel<T>, &long_materialize_kernel<T, VPT, 1>,
-            &long_scan_kernel<T, VPT, 1, GRID, true>};
+    return {&long_scan_kernel<T, VPT, 1, GRID, false>, &long_threshold_kernel<T, VPT, 1, false>,
+            &long_write_kernel<T, VPT, 1, false>, &long_rowsum_kernel<T>, &long_materialize_kernel<T, VPT, 1>,
+            &long_scan_kernel<T, VPT, 1, GRID, true>, &long_threshold_kernel<T, VPT, 1, true>,
+            &long_write_kernel<T, VPT, 1, true>};
   return {};
 }
 

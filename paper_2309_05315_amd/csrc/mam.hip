@@ -181,6 +181,9 @@ struct LongPlan {
   // (column, sub-tile), the two halves of the common values, the parity
   bool sparse = false;
   size_t o_pcnt = 0, o_prow = 0, o_pval = 0, o_nbv = 0, o_spar = 0;
+  // diagnostics: 4 doubles per column (threshold kernel), DIAG_STRIDE per
+  // write workgroup
+  size_t o_ldiag = 0, o_wdiag = 0;
 };
 
 struct Plan {
@@ -704,6 +707,8 @@ void build_layout(Plan* pl) {
     lg.o_it_j1 = take(ni * 8);
     lg.o_it_poff = take(ni * 8);
     lg.o_wg_it = take(((size_t)std::max(lg.nwg, 1024) + 1) * 4);
+    lg.o_ldiag = take(T * 4 * 8);
+    lg.o_wdiag = take((size_t)std::max(lg.nwg, 1024) * mam::DIAG_STRIDE * 8);
     const size_t nh = T * (size_t)lg.nrb * 4;  // (column, sub-tile) headers
     lg.o_hmax = take(nh * 8);
     lg.o_hcnt = take(nh * 4);
@@ -1116,6 +1121,8 @@ mam::LongArgs<T> long_args(Plan* pl) {
     a.gh[k] = p.gh[k];
   }
   a.gz = a.gdim ? static_cast<const double*>(p.cost) : nullptr;
+  a.ldiag = at<double>(pl, lg.o_ldiag);
+  a.wdiag = at<double>(pl, lg.o_wdiag);
   a.sparse = lg.sparse ? 1 : 0;
   if (lg.sparse) {
     a.spar = at<int32_t>(pl, lg.o_spar);
@@ -1129,7 +1136,7 @@ mam::LongArgs<T> long_args(Plan* pl) {
 
 // t^k, then scan, threshold and write (the scan rewrites every header).
 template <typename T>
-mam_status launch_long_columns(Plan* pl, hipStream_t st) {
+mam_status launch_long_columns(Plan* pl, hipStream_t st, int diag) {
   const Prob& p = pl->P[0];
   const LongPlan& lg = pl->lg;
   mam::LongFns<T> fn = mam::pick_long<T>(lg.vpt, lg.vec, pl->P[0].cost_mode == MAM_COST_GRID);
@@ -1140,9 +1147,10 @@ mam_status launch_long_columns(Plan* pl, hipStream_t st) {
   if (lg.sparse) hipLaunchKernelGGL(fn.scan_sparse, dim3(lg.nwg), dim3(mam::LNT), (size_t)lg.vpt * mam::LNT * 8, st, a);
   else hipLaunchKernelGGL(fn.scan, dim3(lg.nwg), dim3(mam::LNT), 0, st, a);
   LAUNCH_CHECK("long_scan_kernel");
-  hipLaunchKernelGGL(fn.thresh, dim3((unsigned)((p.T + 3) / 4)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(diag ? fn.thresh_diag : fn.thresh, dim3((unsigned)((p.T + 3) / 4)), dim3(256), 0, st, a);
   LAUNCH_CHECK("long_threshold_kernel");
-  hipLaunchKernelGGL(fn.write, dim3(lg.nwg), dim3(mam::LNT), (size_t)lg.vpt * mam::LNT * 8, st, a);
+  hipLaunchKernelGGL(diag ? fn.write_diag : fn.write, dim3(lg.nwg), dim3(mam::LNT), (size_t)lg.vpt * mam::LNT * 8, st,
+                     a);
   LAUNCH_CHECK("long_write_kernel");
   if (lg.sparse) {
     hipLaunchKernelGGL(mam::long_sparse_flip_kernel, dim3(1), dim3(64), 0, st, a.spar, a.stop);
@@ -1430,8 +1438,8 @@ mam_status one_iteration(Plan* pl, hipStream_t st, int diag, uint8_t* rec = null
     HIP_TRY(hipEventRecord(e0, st));
   }
   if (pl->lg.on) {
-    if (diag || rec) return fail(MAM_EUNSUPPORTED, "diagnostics and the reverse mode are not available for long columns");
-    TRY(pl->dtype == MAM_F32 ? launch_long_columns<float>(pl, st) : launch_long_columns<double>(pl, st));
+    if (rec) return fail(MAM_EUNSUPPORTED, "the reverse mode is not available for long columns");
+    TRY(pl->dtype == MAM_F32 ? launch_long_columns<float>(pl, st, diag) : launch_long_columns<double>(pl, st, diag));
   } else {
     TRY(pl->dtype == MAM_F32 ? launch_columns<float>(pl, st, diag, rec, rec_ld)
                               : launch_columns<double>(pl, st, diag, rec, rec_ld));
@@ -1470,7 +1478,6 @@ mam_status plan_iterate(Plan* pl, int64_t iters, hipStream_t st) {
   if (iters < 0) return fail(MAM_EINVAL, "iters must be >= 0");
   if (!pl->inited) return fail(MAM_ESTATE, "mam_init has not run");
   const bool want_diag = !pl->batch && (pl->P[0].flags & MAM_FLAG_DIAG);
-  if (want_diag && pl->lg.on) return fail(MAM_EUNSUPPORTED, "diagnostics are not computed for long columns");
   int64_t k = 0;
   if (pl->graph_iters > 0 && !pl->timing) {
     // keep the last iteration outside the graph when it computes diagnostics
@@ -1525,8 +1532,12 @@ mam_status until_period(Plan* pl, hipStream_t st, int test, int64_t every) {
                        ss);
     LAUNCH_CHECK("stop_partial_kernel");
   }
+  // the per-workgroup maxima of |theta' - theta|: the column kernel's, or
+  // the long write kernel's
+  const double* dslots = pl->lg.on ? at<double>(pl, pl->lg.o_wdiag) : at<double>(pl, L.diag);
+  const int nslots = pl->lg.on ? pl->lg.nwg : pl->nwg_total;
   hipLaunchKernelGGL(mam::stop_final_kernel, dim3(1), dim3(256), 0, st, ss, test, at<double>(pl, L.stop_part),
-                     pr.nb, at<double>(pl, L.diag), pl->nwg_total, pl->host_flag);
+                     pr.nb, dslots, nslots, pl->host_flag);
   LAUNCH_CHECK("stop_final_kernel");
   return MAM_OK;
 }
@@ -1624,6 +1635,8 @@ mam_status plan_iterate_until(Plan* pl, int64_t max_iters, int test, double tol,
   if (test != MAM_STOP_DTHETA && test != MAM_STOP_DP && test != MAM_STOP_DIST)
     return fail(MAM_EINVAL, "unknown stopping test %d", test);
   if (std::isnan(tol)) return fail(MAM_EINVAL, "tol is NaN");
+  if (test == MAM_STOP_DTHETA && pl->lg.on && pl->lg.sparse)
+    return fail(MAM_EUNSUPPORTED, "the theta test is not available with the sparse store");
   pl->gate = at<int32_t>(pl, pl->lay.stop);  // StopState.stop is its first member
   const mam_status s = until_run(pl, max_iters, test, tol, every, st, out);
   pl->gate = nullptr;
@@ -2409,27 +2422,51 @@ mam_status mam_diagnostics(mam_problem* p, mam_diag* out, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Prob& pr = pl->P[0];
   const size_t R = pr.R, M = pr.M;
-  std::vector<double> pm(M * R), pmp(M * R), pv(R), pp(R), dg((size_t)pl->nwg_total * mam::DIAG_STRIDE);
+  const bool lg = pl->lg.on;
+  const int nslots = lg ? pl->lg.nwg : pl->nwg_total;
+  std::vector<double> pm(M * R), pmp(M * R), pv(R), pp(R), dg((size_t)nslots * mam::DIAG_STRIDE);
+  std::vector<double> cd(lg ? (size_t)pr.T * 4 : 0);
   double t = 0.0;
   HIP_TRY(hipMemcpyAsync(pm.data(), pl->ws + pr.o_pm, M * R * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(pmp.data(), pl->ws + pr.o_pm_prev, M * R * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(pv.data(), pl->ws + pr.o_p, R * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(pp.data(), pl->ws + pr.o_p_prev, R * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(dg.data(), pl->ws + pl->lay.diag, dg.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(dg.data(), pl->ws + (lg ? pl->lg.o_wdiag : pl->lay.diag), dg.size() * 8,
+                         hipMemcpyDeviceToHost, st));
+  if (lg) HIP_TRY(hipMemcpyAsync(cd.data(), pl->ws + pl->lg.o_ldiag, cd.size() * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(&t, pl->ws + pr.o_t, 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   mam_diag r{};
   r.iterations = pl->iters_done;
   r.t = t;
   double rounds = 0.0, active = 0.0, cols = 0.0;
-  for (int w = 0; w < pl->nwg_total; ++w) {
-    const double* o = &dg[(size_t)w * mam::DIAG_STRIDE];
-    r.W_hat += o[0];
-    r.meas_resid = std::max(r.meas_resid, o[1]);
-    r.dtheta_inf = std::max(r.dtheta_inf, o[2]);
-    rounds += o[3];
-    active += o[4];
-    cols += o[5];
+  if (lg) {
+    // long columns: per-column figures of the threshold kernel (summed in
+    // column order), and the write workgroups' maxima of the change (NaN
+    // with the sparse store, which keeps no dense copy of the old plans)
+    for (int64_t j = 0; j < pr.T; ++j) {
+      const double* o = &cd[(size_t)j * 4];
+      r.W_hat += o[0];
+      r.meas_resid = std::max(r.meas_resid, o[1]);
+      rounds += o[2];
+      active += o[3];
+    }
+    cols = (double)pr.T;
+    if (pl->lg.sparse) {
+      r.dtheta_inf = NAN;
+    } else {
+      for (int w = 0; w < nslots; ++w) r.dtheta_inf = std::max(r.dtheta_inf, dg[(size_t)w * mam::DIAG_STRIDE + 2]);
+    }
+  } else {
+    for (int w = 0; w < nslots; ++w) {
+      const double* o = &dg[(size_t)w * mam::DIAG_STRIDE];
+      r.W_hat += o[0];
+      r.meas_resid = std::max(r.meas_resid, o[1]);
+      r.dtheta_inf = std::max(r.dtheta_inf, o[2]);
+      rounds += o[3];
+      active += o[4];
+      cols += o[5];
+    }
   }
   r.rounds_per_column = cols > 0 ? rounds / cols : 0.0;
   r.active_per_column = cols > 0 ? active / cols : 0.0;

@@ -42,6 +42,8 @@ struct LongFns {
   void (*rowsum)(LongArgs<T>, int) = nullptr;
   void (*materialize)(LongArgs<T>) = nullptr;  // sparse store write-back
   void (*scan_sparse)(LongArgs<T>) = nullptr;  // sparse-store scan
+  void (*thresh_diag)(LongArgs<T>) = nullptr;  // with the iteration's diagnostics
+  void (*write_diag)(LongArgs<T>) = nullptr;
 };
 template <typename T>
 LongFns<T> pick_long(int vpt, int vec, bool grid);

@@ -93,6 +93,13 @@ struct LongArgs {
   int32_t* prow;                 // h*cap + e: row of patch e
   T* pval;                       //            its value
   T* nbv;                        // 2 x M x R
+  // diagnostics of the iteration (the DIAG instances): per column j,
+  // ldiag[4j..4j+3] = <c_s, pi_hat_s>, the column's measure residual, its
+  // threshold rounds and active entries; per write workgroup w,
+  // wdiag[w*DIAG_STRIDE + 2] = max |theta' - theta| over its entries (dense
+  // store only)
+  double* ldiag;
+  double* wdiag;
 };
 
 // Coordinate k of grid index i: origin + i * spacing, each operation rounded
@@ -414,7 +421,7 @@ long_scan_kernel(LongArgs<T> a) {
 // one, lane e takes kept entry e, or (more than E candidates) lane l
 // recomputes the VPT values of thread 64*wave + l of the tile.  The wave
 // sums in a fixed tree: the order is fixed.
-template <typename T, int VPT, int VEC>
+template <typename T, int VPT, int VEC, bool DIAG>
 __global__ void __launch_bounds__(256)
 long_threshold_kernel(LongArgs<T> a) {
   constexpr int RB = LNT * VPT;
@@ -426,7 +433,13 @@ long_threshold_kernel(LongArgs<T> a) {
   const double tau = uniform_d((double)gptr(a.q)[j]);
   double* const lamv = gptr(a.lam);
   if (!(tau > 0.0)) {
-    if (lane == 0) lamv[j] = __builtin_huge_val();  // q_s = 0: the column is 0
+    if (lane == 0) {
+      lamv[j] = __builtin_huge_val();  // q_s = 0: the column is 0
+      if constexpr (DIAG) {
+        double* const dj = gptr(a.ldiag) + j * 4;
+        dj[0] = dj[1] = dj[2] = dj[3] = 0.0;
+      }
+    }
     return;
   }
   const double* __restrict__ hm = gptr(a.hmax) + j * nsub;
@@ -459,7 +472,7 @@ long_threshold_kernel(LongArgs<T> a) {
         rel &= rel - 1;
         const int n = uniform_i(hc[si]);
         if (n <= cap) {
-          if (lane < n) f(cwj[(int64_t)si * cap + lane]);
+          if (lane < n) f(cwj[(int64_t)si * cap + lane], gptr(a.crow)[(j * nsub + si) * (int64_t)cap + lane]);
         } else {
           const int rbase = (si >> 2) * RB, tt = (si & 3) * 64 + lane;
           T th[VPT];
@@ -467,7 +480,7 @@ long_threshold_kernel(LongArgs<T> a) {
 #pragma unroll
           for (int k = 0; k < VPT; ++k) {
             const int r = rbase + ((k / VEC) * LNT + tt) * VEC + (k % VEC);
-            if (r < R) f(long_w((double)th[k], 2.0 * long_b(t, pv, pmm, r, Sm), costv(r), a.inv_rho));
+            if (r < R) f(long_w((double)th[k], 2.0 * long_b(t, pv, pmm, r, Sm), costv(r), a.inv_rho), r);
           }
         }
       }
@@ -475,11 +488,12 @@ long_threshold_kernel(LongArgs<T> a) {
   };
   const double lprev = lamv[j];
   double lam = (a.warm && lprev == lprev && lprev > lo) ? lprev : lo;
-  int nprev = -1;
+  int nprev = -1, nrounds = 0, nact = 0;
   for (int round = 0; round < R + 4; ++round) {
+    ++nrounds;
     double S = 0.0, mnA = __builtin_huge_val(), mxN = -__builtin_huge_val();
     double nd = 0.0;
-    visit([&](double x) {
+    visit([&](double x, int) {
       if (x > lam) {
         S += x;
         nd += 1.0;
@@ -506,6 +520,7 @@ long_threshold_kernel(LongArgs<T> a) {
     const double ln = (S - tau) / (double)n;
     if (ln >= lo && (n == nprev || (mnA >= ln && mxN <= ln))) {
       lam = ln;  // the set above lam is exactly the active set
+      nact = n;
       break;
     }
     nprev = n;
@@ -515,6 +530,30 @@ long_threshold_kernel(LongArgs<T> a) {
   // {u >= 0, sum u <= q_s} (the write pass patches only entries above it)
   if (a.relaxed) lam = fmax(lam, 0.0);
   if (lane == 0) lamv[j] = lam;
+  if constexpr (DIAG) {
+    // the column's pi_hat = max(w - lam, 0) at the same entries and in the
+    // same arithmetic as the write pass: its sum against q_s and against the
+    // cost (fixed order: sub-tiles in order, lanes by the wave sum)
+    double cs = 0.0, wc = 0.0;
+    if (lam < __builtin_huge_val()) {
+      visit([&](double x, int r) {
+        if (x > lam) {
+          const double ph = fmax(x - lam, 0.0);
+          cs += ph;
+          wc += costv(r) * ph;
+        }
+      });
+    }
+    cs = wave_sum(cs);
+    wc = wave_sum(wc);
+    if (lane == 0) {
+      double* const dj = gptr(a.ldiag) + j * 4;
+      dj[0] = wc;
+      dj[1] = a.relaxed ? fmax(cs - tau, 0.0) : fabs(cs - tau);
+      dj[2] = (double)nrounds;
+      dj[3] = (double)(lam < __builtin_huge_val() ? nact : 0);
+    }
+  }
 }
 
 // ---- write: theta' and the tile's row-sum partials ----------------------
@@ -527,11 +566,12 @@ long_threshold_kernel(LongArgs<T> a) {
 // LDS together (one column per thread), so no column waits on memory for
 // them.  Dynamic LDS: VPT*256 doubles of row-sum patches (each row owned by
 // one thread: no atomics).
-template <typename T, int VPT, int VEC>
+template <typename T, int VPT, int VEC, bool DIAG>
 __global__ void __launch_bounds__(LNT)
 long_write_kernel(LongArgs<T> a) {
   constexpr int NCH = VPT / VEC, RB = LNT * VPT;
   if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;
+  double dth = 0.0;  // DIAG, dense store: max |theta' - theta| of this thread's entries
   extern __shared__ double lds_dyn[];
   double* fix = lds_dyn;  // [VPT][256]
   constexpr int WB = 128;  // columns whose thresholds and headers are staged at once
@@ -645,6 +685,11 @@ long_write_kernel(LongArgs<T> a) {
               }
             }
           }
+          if constexpr (DIAG) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+              if (r0 + v < R) dth = fmax(dth, fabs((double)out[v] - (double)tv[v]));
+          }
           if (r0 + VEC <= R) {
             store_vec_nt<T, VEC>(thp + r0, out);
           } else {
@@ -655,6 +700,27 @@ long_write_kernel(LongArgs<T> a) {
         }
         if (sparse && lane == 0) *pcj = -1;
         return;
+      }
+      // DIAG, dense store: the entries' old values, and which of them the
+      // patches below overwrite
+      T old[VPT];
+      unsigned pmask = 0u;
+      if constexpr (DIAG) {
+        if (!sparse) {
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const int r0 = row(c * VEC);
+            T ov[VEC];
+            if (r0 + VEC <= R) {
+              load_vec<T, VEC>(thp + r0, ov);
+            } else {
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) ov[v] = r0 + v < R ? thp[r0 + v] : T(0);
+            }
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) old[c * VEC + v] = ov[v];
+          }
+        }
       }
       if (!sparse) {
 #pragma unroll
@@ -701,7 +767,25 @@ long_write_kernel(LongArgs<T> a) {
           if (slot_owner(rr, VEC) == tid) {
             if (!sparse) thp[rbase + rr] = read_lane(val, l);
             fix[slot_of(rr, VEC) * LNT + tid] += read_lane(dfix, l);
+            if constexpr (DIAG) {
+              if (!sparse) {
+                const int sl = slot_of(rr, VEC);
+                const double nv = (double)read_lane(val, l);
+#pragma unroll
+                for (int k = 0; k < VPT; ++k)
+                  if (k == sl) dth = fmax(dth, fabs(nv - (double)old[k]));
+                pmask |= 1u << sl;
+              }
+            }
           }
+        }
+      }
+      if constexpr (DIAG) {
+        // every other entry of the sub-tile became -b
+        if (!sparse) {
+#pragma unroll
+          for (int k = 0; k < VPT; ++k)
+            if (row(k) < R && !((pmask >> k) & 1u)) dth = fmax(dth, fabs((double)nb[k] - (double)old[k]));
         }
       }
     };
@@ -734,6 +818,15 @@ long_write_kernel(LongArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < VPT; ++k)
       if (row(k) < R) part[row(k) - rbase] = fix[k * LNT + tid] - ncols * long_b(t, pv, pmm, row(k), Sm);
+  }
+  if constexpr (DIAG) {
+    __shared__ double sh_dth[4];
+    const double m = wave_max(dth);
+    if ((tid & 63) == 0) sh_dth[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0)
+      gptr(a.wdiag)[(size_t)blockIdx.x * DIAG_STRIDE + 2] =
+          sparse ? __builtin_nan("") : fmax(fmax(sh_dth[0], sh_dth[1]), fmax(sh_dth[2], sh_dth[3]));
   }
 }
 

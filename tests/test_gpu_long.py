@@ -138,16 +138,84 @@ def test_stopping_test_on_long_columns():
 
 def test_unsupported_on_long_columns():
     p = inputs.tiny_problem(19, R=1100, S=[10, 12])
-    s = mam.solver_for(p, rows_per_tile=1024, diag=True)
-    s.init()
-    with pytest.raises(mam.MAMError):
-        s.iterate(2)  # diagnostics are not computed on this path
     s = mam.solver_for(p, rows_per_tile=1024)
     s.init()
     with pytest.raises(mam.MAMError):
         s.record(3)
     with pytest.raises(mam.MAMError):
         s.set_bundles([0, 1])
+    s = mam.solver_for(p, rows_per_tile=1024, sparse_store=True)
+    s.init()
+    with pytest.raises(mam.MAMError):
+        s.iterate_until(4, "dtheta", 1e-3, 2)  # the sparse store keeps no dense copy to compare
+
+
+DIAG_CASES = [
+    ("three tiles, ragged last one", lambda: inputs.tiny_problem(21, R=3000, S=[40, 25, 33], dtype="f64"),
+     dict(rows_per_tile=1024)),
+    ("unbalanced, damped", lambda: inputs.tiny_problem(22, R=2200, S=[30, 22, 15], masses=[0.6, 1.0, 1.5],
+                                                        gamma=0.02, dtype="f64"), dict(rows_per_tile=1024)),
+    ("overflowing sub-tiles", lambda: inputs.tiny_problem(23, R=2600, S=[24, 18], rho=200.0, dtype="f64",
+                                                          zero_frac=0.2), dict(rows_per_tile=1024, candidate_slots=1)),
+    ("grid cost", lambda: inputs.free_support(seed=6, K=12, M=3, dtype="f64"), dict(rows_per_tile=1024, grid=True)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(DIAG_CASES)))
+@pytest.mark.parametrize("sparse", [False, True])
+def test_long_diagnostics_match_oracle(case, sparse):
+    """The figures of the last iteration on the long-column path: W_hat and the
+    measure residual from the threshold kernel, ||theta^{k+1} - theta^k||_inf
+    from the write kernel (dense store; NaN with the sparse store), dist_L from
+    the marginals, against the oracle's."""
+    name, gen, sched = DIAG_CASES[case]
+    p = gen()
+    say(f"case long diagnostics: {name} R={p.R} S={p.S} sparse={sparse}")
+    cost, q = blocks(p)
+    k = 9
+    prev = O.mam(cost, q, p.rho, p.gamma, k - 1)
+    ora = O.mam(cost, q, p.rho, p.gamma, k)
+    od = O.diagnostics(cost, q, ora["pi_hat"], ora["theta"], prev["theta"])
+    s = mam.solver_for(p, diag=True, sparse_store=sparse, **sched)
+    assert s.schedule()["rows_per_tile"] > 0
+    s.init()
+    s.iterate(k)
+    gd = s.diagnostics()
+    say(f"  W_hat {gd['W_hat']:.12e} / {od['W_hat']:.12e}; dist_L {gd['dist_L']:.6e} / {od['dist_L']:.6e}; "
+        f"resid {gd['meas_resid']:.1e} / {od['meas_resid']:.1e}; dtheta {gd['dtheta_inf']:.6e} / "
+        f"{od['dtheta_inf']:.6e}; rounds {gd['rounds_per_column']:.3f} active {gd['active_per_column']:.3f}")
+    assert gd["iterations"] == k
+    assert abs(gd["W_hat"] - od["W_hat"]) <= 1e-10 * abs(od["W_hat"])
+    assert abs(gd["dist_L"] - od["dist_L"]) <= 1e-8 * max(od["dist_L"], 1e-12)
+    qmax = max(float(np.abs(x).max()) for x in q)
+    assert gd["meas_resid"] <= 1e-12 * qmax and od["meas_resid"] <= 1e-12 * qmax
+    if sparse:
+        assert math.isnan(gd["dtheta_inf"])
+    else:
+        assert abs(gd["dtheta_inf"] - od["dtheta_inf"]) <= 1e-10 * od["dtheta_inf"]
+    assert gd["rounds_per_column"] >= 1.0 and gd["active_per_column"] >= 1.0
+    np.testing.assert_allclose(gd["dp_norm"], np.linalg.norm(ora["p_bar"] - prev["p_bar"]), rtol=1e-8)
+    np.testing.assert_allclose(gd["t"], ora["t"], rtol=1e-12)
+    assert rel(s.barycenter().cpu().numpy(), ora["p_bar"]) <= 1e-10
+
+
+def test_theta_stopping_test_on_long_columns():
+    """||theta^{k+1} - theta^k||_inf checked on the device every 3 iterations
+    from the write kernel's maxima, against the oracle's run."""
+    p = inputs.tiny_problem(24, R=2300, S=[20, 31], rho=2.0, dtype="f64")
+    cost, q = blocks(p)
+    ora = O.mam_until(cost, q, p.rho, 30, "dtheta", -1.0, 3)
+    s = mam.solver_for(p, rows_per_tile=1024)
+    s.init()
+    r = s.iterate_until(30, "dtheta", -1.0, 3)
+    assert r["iterations"] == 30 and r["checks"] == 10
+    assert r["value"] == pytest.approx(ora["values"][-1], rel=1e-10)
+    tol = float(np.median(ora["values"]))
+    want = O.mam_until(cost, q, p.rho, 30, "dtheta", tol, 3)
+    s.init()
+    r = s.iterate_until(30, "dtheta", tol, 3)
+    assert r["converged"] and r["iterations"] == want["iters"]
+    assert rel(s.barycenter().cpu().numpy(), want["p_bar"]) <= 1e-10
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

@@ -299,12 +299,26 @@ def extra_workloads(torch, mam, inputs, log, only=None):
         s.iterate(50)
         dtg = timed(lambda: s.iterate(p3.iters)) / p3.iters
         s.close()
+        # the damping t^k of every iteration of a run from the start (Alg. 1,
+        # eq. (Unbalanced-prox)): how often the unbalanced rule damps
+        s = mam.solver_for(p3, diag=True)
+        s.init()
+        ts = []
+        for _ in range(p3.iters):
+            s.iterate(1)
+            ts.append(s.diagnostics()["t"])
+        s.close()
+        ts = np.asarray(ts)
         ab = algorithmic_bytes(p3)
         out["unbalanced_K32_M50_f32"] = {"iterations": p3.iters, "ms_per_iter": dt * 1e3,
                                          "ms_per_iter_graph": dtg * 1e3,
                                          "column_kernel_ms": col / n,
-                                         "column_kernel_GBs": ab / (col / n * 1e-3) / 1e9}
-        log(f"unbalanced: {dt * 1e3:.4f} ms/iter, {dtg * 1e3:.4f} ms/iter graph, column kernel {col / n:.4f} ms")
+                                         "column_kernel_GBs": ab / (col / n * 1e-3) / 1e9,
+                                         "damped_fraction": float(np.mean(ts < 1.0)),
+                                         "t_min": float(ts.min()), "t_last": float(ts[-1]),
+                                         "first_undamped_iteration": int(np.argmax(ts >= 1.0)) + 1 if np.any(ts >= 1.0) else None}
+        log(f"unbalanced: {dt * 1e3:.4f} ms/iter, {dtg * 1e3:.4f} ms/iter graph, column kernel {col / n:.4f} ms, "
+            f"t < 1 in {np.mean(ts < 1.0):.1%} of {p3.iters} iterations")
 
     if want("batch"):
         # 256 independent problems (R = k^2, k in 8..32, M in 2..8), FP32, autotuned

@@ -230,6 +230,21 @@ __device__ __forceinline__ double damping_t(const double* d2part, int nb, double
   return (__builtin_isinf(gam) || rho * sqrt(d2) <= gam) ? 1.0 : gam / (rho * sqrt(d2));
 }
 
+// The nearest float to x and its neighbours: float_up(x) >= x and
+// float_down(x) <= x (the float conversion rounds to nearest; one step in the
+// last place fixes the side), NaN for NaN.  The bounds of the threshold
+// certificate need only the side, not the exact directed rounding.
+__device__ __forceinline__ float float_up(double x) {
+  const float f = (float)x;
+  const int b = __float_as_int(f);
+  return (double)f < x ? __int_as_float(f >= 0.0f ? b + 1 : b - 1) : f;
+}
+__device__ __forceinline__ float float_down(double x) {
+  const float f = (float)x;
+  const int b = __float_as_int(f);
+  return (double)f > x ? __int_as_float(f > 0.0f ? b - 1 : (f == 0.0f ? (int)0x80000001 : b + 1)) : f;
+}
+
 // Fixed-point value of pi_hat >= 0 at scale fx = 2^E (round to nearest).
 __device__ __forceinline__ unsigned long long to_fixed(double ph, double fx) {
   return __double2ull_rn(ph * fx);
@@ -761,15 +776,18 @@ column_kernel(ColArgs<T> a) {
       // (a column slot past the segment's end is computed too, on defined
       // values, and then ignored: no select per entry)
       double w[KC][VPT];
+      double wl[KC];  // the lane's largest w of each column
       T told[DIAG ? KC : 1][DIAG ? VPT : 1];
       bool valid[KC];
       int64_t jj[KC];
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         valid[kc] = step_col(step, kc, jj[kc]);
+        wl[kc] = -__builtin_huge_val();
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
           w[kc][k] = ((double)bt[kc][k] + 2.0 * lds_b[k * NT + tid]) - (double)bc[kc][k] * inv_rho;
+          wl[kc] = fmax(wl[kc], w[kc][k]);
           if constexpr (DIAG) told[kc][k] = bt[kc][k];
         }
       }
@@ -816,28 +834,32 @@ column_kernel(ColArgs<T> a) {
           cold[kc] = lam[kc] != lam[kc];
           if (act[kc]) {
             const double l = lam[kc];
-            double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
+            double lo = __builtin_huge_val(), hi;
             int bits = 0;
+            bool wave_act = false;
 #pragma unroll
             for (int k = 0; k < VPT; ++k) {
-              // usually no lane of the wave holds an active entry in slot k:
-              // a uniform branch keeps that case to one compare and one max
               const double x = w[kc][k];
               const unsigned long long bal = __ballot(x > l);
-              if (bal == 0ull) {
-                hi = fmax(hi, x);
-              } else {
+              if (bal != 0ull) {
                 const bool in = x > l;
+                wave_act = true;
                 n[kc] += __popcll(bal);
                 bits |= (int)in << k;
                 S[kc] += in ? x : 0.0;
                 lo = fmin(lo, in ? x : __builtin_huge_val());
-                hi = fmax(hi, in ? -__builtin_huge_val() : x);
               }
             }
+            if (!wave_act) {
+              hi = wl[kc];
+            } else {
+              hi = -__builtin_huge_val();
+#pragma unroll
+              for (int k = 0; k < VPT; ++k) hi = fmax(hi, ((bits >> k) & 1) ? -__builtin_huge_val() : w[kc][k]);
+            }
             mask[kc] = bits;
-            mnA[kc] = __double2float_rd(lo);
-            mxN[kc] = __double2float_ru(hi);
+            mnA[kc] = float_down(lo);
+            mxN[kc] = float_up(hi);
             wmx[kc] = hi;  // with lam = NaN nothing is active: hi = w_max
           }
         }

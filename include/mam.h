@@ -157,7 +157,13 @@ typedef struct mam_diag {
  * In mam_set_schedule a 0 field means automatic; values_per_thread and
  * vector_width are outputs of mam_get_schedule only. */
 typedef struct mam_schedule {
-  int32_t threads_per_column; /* 64, 128, 256, 512 or 1024 threads per column  */
+  int32_t threads_per_column; /* 64, 128, 256, 512 or 1024 threads per column;
+                                 16 or 32 for short columns (R <= 16*nt rows):
+                                 sub-wave groups, 64/nt columns per wave side
+                                 by side, one column in flight, no
+                                 diagnostics (MAM_FLAG_DIAG, the theta
+                                 stopping test) or reverse mode with them
+                                 (MAM_EUNSUPPORTED).  0 automatic (64 or more) */
   int32_t values_per_thread;  /* rows held per thread (out)                     */
   int32_t columns_in_flight;  /* columns a group advances together: 1, 2 or 4   */
   int32_t workgroups;         /* workgroups per iteration (see team_size for

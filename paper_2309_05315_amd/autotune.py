@@ -10,6 +10,10 @@ shape: dtype, cost mode, R, M, the S^m list and the number of cost columns.
     sched = autotune.tune(problem)                  # kwargs for mam.solver_for
     scheds = autotune.tune_batch(problems)          # {group: schedule} for mam.Batch
 
+Schedules of 16 or 32 threads per column (sub-wave groups) compute no
+diagnostics; tune without them (threads_per_column >= 64 candidates) for a
+solver that will run with diag=True or the reverse mode.
+
 Cache file: $MAM_AUTOTUNE_CACHE, else ~/.cache/paper_2309_05315_amd/autotune.json.
 """
 from __future__ import annotations
@@ -72,15 +76,19 @@ def _default_threads(p) -> int:
 def candidates(p, wide: bool = True) -> List[dict]:
     """Schedules to try: the default threads per column and its neighbours,
     one or two columns in flight, and (wide) the column order, XCD remap and
-    two workgroup counts.  Invalid ones are rejected by the library and skipped."""
+    two workgroup counts.  Short columns (one wave per column by default)
+    also try sub-wave groups of 16 and 32 lanes.  Invalid ones are rejected by
+    the library and skipped."""
     nt0 = _default_threads(p)
     nts = [nt for nt in (nt0 // 2, nt0, nt0 * 2) if 64 <= nt <= 1024]
+    if nt0 == 64:
+        nts = [16, 32] + nts
     orders = [1, 2] if (wide and mam._cost_mode_of(p) != mam.COST_PER_COLUMN) else [0]
     xcds = [1, -1] if wide else [0]
     wgs = [0, 512] if wide else [0]
     out = []
     for nt in nts:
-        for kc in (1, 2):
+        for kc in ((1,) if nt < 64 else (1, 2)):
             for order in orders:
                 for xcd in xcds:
                     for wg in wgs:
@@ -164,12 +172,12 @@ def tune_batch(problems, iters: int = 6, warm: int = 2, use_cache: bool = True) 
         if key in cache:
             out[g] = dict(cache[key]["schedule"])
             continue
-        nt0 = _default_threads(sub[0])
+        nt0 = max(_default_threads(p) for p in sub)
         best, best_ms = None, float("inf")
-        for nt in (nt0 // 2, nt0, nt0 * 2):
-            if not 64 <= nt <= 1024:
+        for nt in ((16, 32) if nt0 == 64 else ()) + (nt0 // 2, nt0, nt0 * 2):
+            if not 16 <= nt <= 1024 or (32 < nt < 64):
                 continue
-            for kc in (1, 2):
+            for kc in ((1,) if nt < 64 else (1, 2)):
                 for xcd in (1, -1):
                     sc = {"threads_per_column": nt, "columns_in_flight": kc, "xcd_remap": xcd}
                     ms = _time_batch(sub, sc, iters, warm)

@@ -309,10 +309,15 @@ mam_status read_desc(const mam_desc* d, int index, Prob* out) {
   return MAM_OK;
 }
 
+// Column groups per workgroup of 256 threads for nt threads per column:
+// sub-wave groups (16 or 32 lanes) and single waves share a workgroup.
+int groups_per_wg(int nt) { return nt <= 64 ? 256 / nt : 1; }
+
 // Threads per column and values per thread for R rows.  Default: the fewest
 // threads that keep a thread at 16 (float) or 8 (double) values, so a column
 // group fits twice per compute unit (registers and LDS); one wave per
 // column whenever that suffices (no barriers in the threshold rounds).
+// 16 or 32 threads per column (several columns per wave) only on request.
 mam_status shape_for(int dtype, int64_t R, int nt_req, int* nt_out, int* vpt_out) {
   int nt = nt_req;
   if (nt == 0) {
@@ -320,14 +325,14 @@ mam_status shape_for(int dtype, int64_t R, int nt_req, int* nt_out, int* vpt_out
     nt = 64;
     while (nt < 1024 && (int64_t)nt * target < R) nt *= 2;
   }
-  if (nt != 64 && nt != 128 && nt != 256 && nt != 512 && nt != 1024)
-    return fail(MAM_EINVAL, "threads_per_column must be 64, 128, 256, 512 or 1024 (got %d)", nt);
+  if (nt != 16 && nt != 32 && nt != 64 && nt != 128 && nt != 256 && nt != 512 && nt != 1024)
+    return fail(MAM_EINVAL, "threads_per_column must be 16, 32, 64, 128, 256, 512 or 1024 (got %d)", nt);
   int vpt = pow2_ceil((R + nt - 1) / nt);
   if (nt >= 128 && vpt < 4) vpt = 4;  // multi-wave groups hold at least 4 values per thread
   if (vpt > 16)
     return fail(MAM_EUNSUPPORTED, "R = %lld needs more than 16 values per thread at %d threads per column",
                 (long long)R, nt);
-  if ((int64_t)vpt * nt * 8 * (1 + (nt == 64 ? 4 : 1)) > kMaxLds)
+  if ((int64_t)vpt * nt * 8 * (1 + groups_per_wg(nt)) > kMaxLds)
     return fail(MAM_EUNSUPPORTED, "R = %lld at %d threads per column needs more than 160 KiB of LDS",
                 (long long)R, nt);
   *nt_out = nt;
@@ -343,7 +348,9 @@ mam_status group_shape(Plan* pl, Group& g) {
   g.nt = nt;
   g.vpt = vpt;
   g.kc = kc;
-  g.ng = nt == 64 ? 4 : 1;
+  if (nt < 64 && kc != 1)
+    return fail(MAM_EINVAL, "16 or 32 threads per column take one column in flight (got %d)", kc);
+  g.ng = groups_per_wg(nt);
   g.vec = vec_width(pl->dtype);  // until binding checks the alignment
   return MAM_OK;
 }
@@ -1051,9 +1058,11 @@ mam_status launch_columns(Plan* pl, hipStream_t st, int diag, uint8_t* rec, int6
     a.nwg = g.nwg;
     a.xcd_remap = g.xcd_remap;
     const int kc = g.vec == 1 ? 1 : g.kc;
+    if (g.nt < 64 && (diag || rec))
+      return fail(MAM_EUNSUPPORTED, "diagnostics and the reverse mode need 64 or more threads per column");
     mam::ColFn<T> fn = mam::pick_column<T>(g.nt, g.vpt, g.vec, kc, diag, g.stream);
     if (!fn) return fail(MAM_EUNSUPPORTED, "no column kernel for nt=%d vpt=%d vec=%d kc=%d", g.nt, g.vpt, g.vec, kc);
-    const int wgsize = g.nt == 64 ? 256 : g.nt;
+    const int wgsize = g.nt <= 64 ? 256 : g.nt;
     const size_t shmem = (size_t)g.vpt * g.nt * 8 * (1 + g.ng);
     if (shmem > 65536) {
       // above the default dynamic-LDS limit: opt this kernel in
@@ -1339,7 +1348,7 @@ mam_status resident_workgroups(Plan* pl, bool* changed) {
     const int kc = g.vec == 1 ? 1 : g.kc;
     mam::ColFn<T> fn = mam::pick_column<T>(g.nt, g.vpt, g.vec, kc, 0, g.stream);
     if (!fn) continue;
-    const int wgsize = g.nt == 64 ? 256 : g.nt;
+    const int wgsize = g.nt <= 64 ? 256 : g.nt;
     const size_t shmem = (size_t)g.vpt * g.nt * 8 * (1 + g.ng);
     if (shmem > 65536)
       HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2098,7 +2107,7 @@ mam_status launch_bundle_columns(Plan* pl, const BundleSched& bs, hipStream_t st
   const int kc = g.vec == 1 ? 1 : g.kc;
   mam::ColFn<T> fn = mam::pick_column<T>(g.nt, g.vpt, g.vec, kc, 0, g.stream);
   if (!fn) return fail(MAM_EUNSUPPORTED, "no column kernel for nt=%d vpt=%d vec=%d kc=%d", g.nt, g.vpt, g.vec, kc);
-  const int wgsize = g.nt == 64 ? 256 : g.nt;
+  const int wgsize = g.nt <= 64 ? 256 : g.nt;
   const size_t shmem = (size_t)g.vpt * g.nt * 8 * (1 + g.ng);
   if (shmem > 65536)
     HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -20,8 +20,16 @@ ColFn<T> pick_column_kc(int nt, int vpt, int vec, int stream);
 template <typename T>
 ColFn<T> pick_column_diag(int nt, int vpt, int vec);
 
+// Sub-wave instance (16 or 32 lanes per column, one column in flight, no
+// diagnostics) or nullptr.
+template <typename T>
+ColFn<T> pick_subwave(int nt, int vpt, int vec, int stream);
+extern template ColFn<float> pick_subwave<float>(int, int, int, int);
+extern template ColFn<double> pick_subwave<double>(int, int, int, int);
+
 template <typename T>
 inline ColFn<T> pick_column(int nt, int vpt, int vec, int kc, int diag, int stream) {
+  if (nt < 64) return (diag || kc != 1) ? nullptr : pick_subwave<T>(nt, vpt, vec, stream);
   if (diag) return pick_column_diag<T>(nt, vpt, vec);
   switch (kc) {
     case 1: return pick_column_kc<T, 1>(nt, vpt, vec, stream);

@@ -9,7 +9,9 @@ from paper_2309_05315_amd import autotune, inputs
 def test_candidates_and_keys():
     p = inputs.tiny_problem(1, R=300, S=[40, 17], dtype="f32", shared=False)
     c = autotune.candidates(p)
-    assert {x["threads_per_column"] for x in c} == {64, 128}      # float, R = 300: 64 by default, and its neighbours
+    # float, R = 300: 64 by default, its neighbours, and sub-wave groups of 16 and 32 lanes
+    assert {x["threads_per_column"] for x in c} == {16, 32, 64, 128}
+    assert all(x["columns_in_flight"] == 1 for x in c if x["threads_per_column"] < 64)
     assert all(x["order"] == 0 for x in c)          # per-column cost: one order only
     q = inputs.tiny_problem(1, R=64, S=[64, 64], dtype="f32", shared=True)
     assert {x["order"] for x in autotune.candidates(q)} == {1, 2}

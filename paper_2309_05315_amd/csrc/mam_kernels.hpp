@@ -776,18 +776,15 @@ column_kernel(ColArgs<T> a) {
       // (a column slot past the segment's end is computed too, on defined
       // values, and then ignored: no select per entry)
       double w[KC][VPT];
-      double wl[KC];  // the lane's largest w of each column
       T told[DIAG ? KC : 1][DIAG ? VPT : 1];
       bool valid[KC];
       int64_t jj[KC];
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         valid[kc] = step_col(step, kc, jj[kc]);
-        wl[kc] = -__builtin_huge_val();
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
           w[kc][k] = ((double)bt[kc][k] + 2.0 * lds_b[k * NT + tid]) - (double)bc[kc][k] * inv_rho;
-          wl[kc] = fmax(wl[kc], w[kc][k]);
           if constexpr (DIAG) told[kc][k] = bt[kc][k];
         }
       }
@@ -834,28 +831,24 @@ column_kernel(ColArgs<T> a) {
           cold[kc] = lam[kc] != lam[kc];
           if (act[kc]) {
             const double l = lam[kc];
-            double lo = __builtin_huge_val(), hi;
+            double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
             int bits = 0;
-            bool wave_act = false;
 #pragma unroll
             for (int k = 0; k < VPT; ++k) {
+              // usually no lane of the wave holds an active entry in slot k:
+              // a uniform branch keeps that case to one compare and one max
               const double x = w[kc][k];
               const unsigned long long bal = __ballot(x > l);
-              if (bal != 0ull) {
+              if (bal == 0ull) {
+                hi = fmax(hi, x);
+              } else {
                 const bool in = x > l;
-                wave_act = true;
                 n[kc] += __popcll(bal);
                 bits |= (int)in << k;
                 S[kc] += in ? x : 0.0;
                 lo = fmin(lo, in ? x : __builtin_huge_val());
+                hi = fmax(hi, in ? -__builtin_huge_val() : x);
               }
-            }
-            if (!wave_act) {
-              hi = wl[kc];
-            } else {
-              hi = -__builtin_huge_val();
-#pragma unroll
-              for (int k = 0; k < VPT; ++k) hi = fmax(hi, ((bits >> k) & 1) ? -__builtin_huge_val() : w[kc][k]);
             }
             mask[kc] = bits;
             mnA[kc] = float_down(lo);

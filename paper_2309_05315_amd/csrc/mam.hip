@@ -1293,9 +1293,14 @@ mam_status launch_init(Plan* pl, const void* const* theta0, hipStream_t st) {
                        st, at<double>(pl, p.o_acc), n, 0.0);
     LAUNCH_CHECK("fill_value_kernel");
   }
-  hipLaunchKernelGGL(mam::init_marginal_kernel<T>, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st,
-                     at<mam::MargTask>(pl, L.mtasks), at<mam::ProbDev<T>>(pl, L.probdev),
-                     at<mam::ProbAux>(pl, L.probaux));
+  // vector loads when every problem's plans are 16-byte aligned with a
+  // leading dimension that is a multiple of the vector
+  bool aligned = true;
+  for (const Prob& p : pl->P) aligned = aligned && p.aligned;
+  constexpr int VN = sizeof(T) == 4 ? 4 : 2;
+  auto fn = aligned ? &mam::init_marginal_kernel<T, VN> : &mam::init_marginal_kernel<T, 1>;
+  hipLaunchKernelGGL(fn, dim3((unsigned)pl->mtasks.size()), dim3(256), 0, st, at<mam::MargTask>(pl, L.mtasks),
+                     at<mam::ProbDev<T>>(pl, L.probdev), at<mam::ProbAux>(pl, L.probaux));
   LAUNCH_CHECK("init_marginal_kernel");
   return launch_average(pl, st, 0);
 }

@@ -56,31 +56,58 @@ fixed_marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restr
   close_marginal(tk, probs[tk.prob], save_prev, threadIdx.x);
 }
 
-// Short columns, at the start: p^(m)_r = sum_s theta_rs in double, columns
-// in order, eight loads in flight (theta of the caller's start, or q_s/R).
-template <typename T>
+// Short columns, at the start: p^(m)_r = sum_s theta_rs in double (theta of
+// the caller's start, or q_s/R).  A workgroup takes one task (a measure, 256
+// rows); wave w sums the columns j0 + w, j0 + w + 4, ... in order, VEC rows
+// per lane per load and U columns in flight, and the four waves' sums are
+// added in wave order: a fixed order, so the result is reproducible.
+template <typename T, int VEC>
 __global__ void __launch_bounds__(256)
 init_marginal_kernel(const MargTask* __restrict__ tasks, const ProbDev<T>* __restrict__ probs,
                      const ProbAux* __restrict__ aux) {
+  constexpr int PASSES = 256 / (64 * VEC);  // row passes of a wave over the task's 256 rows
+  constexpr int U = 8;
+  __shared__ double part[4][256];
   const MargTask tk = tasks[blockIdx.x];
   const ProbDev<T>& P = probs[tk.prob];
   const int R = uniform_i(P.R);
-  const int r = tk.r0 + threadIdx.x;
-  const int rr = r < R ? r : tk.r0;  // rows past R read the task's first row (in bounds) and store nothing
+  const int wv = uniform_i((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const T* const theta = gptr((const T*)uniform_l((int64_t)P.theta));
   const int64_t ld = uniform_l(P.ld);
   const int64_t j0 = uniform_l(gptr(P.col_off)[tk.m]), j1 = uniform_l(gptr(P.col_off)[tk.m + 1]);
-  constexpr int U = 8;
-  double s = 0.0;
-  for (int64_t j = j0; j < j1; j += U) {
-    double v[U];
+  double s[PASSES][VEC];
+  int rows[PASSES];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = j + u < j1 ? (double)theta[(j + u) * ld + rr] : 0.0;
+  for (int ps = 0; ps < PASSES; ++ps) {
+    const int r0 = tk.r0 + (ps * 64 + lane) * VEC;
+    rows[ps] = r0 < R ? r0 : tk.r0;  // vectors past R read the task's first rows and are not stored
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) s[ps][v] = 0.0;
+  }
+  for (int64_t j = j0 + wv; j < j1; j += 4 * U) {
+    T x[U][PASSES][VEC];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t jj = j + 4 * u < j1 ? j + 4 * u : j0;
+#pragma unroll
+      for (int ps = 0; ps < PASSES; ++ps) load_vec<T, VEC>(theta + jj * ld + rows[ps], x[u][ps]);
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (j + u < j1) s += v[u];
+      if (j + 4 * u < j1) {
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) s[ps][v] += (double)x[u][ps][v];
+      }
   }
-  if (r < R) gptr(aux[tk.prob].pm)[(size_t)tk.m * R + r] = s;
+#pragma unroll
+  for (int ps = 0; ps < PASSES; ++ps)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) part[wv][(ps * 64 + lane) * VEC + v] = s[ps][v];
+  __syncthreads();
+  const int t = threadIdx.x, r = tk.r0 + t;
+  if (r < R) gptr(aux[tk.prob].pm)[(size_t)tk.m * R + r] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
 }
 
 // Short columns: Steps 3 and 1 of every task's block of 256 rows (close_rows).

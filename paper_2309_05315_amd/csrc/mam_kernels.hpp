@@ -8,9 +8,10 @@
 //                    Delta_R(q_s) (Prop. 3) and the update theta' = pi_hat - b.
 //                    The row sums of theta' (Step 3) are -S^m b plus the row
 //                    sums of pi_hat, which is nonzero only at the active
-//                    entries: each thread sums its rows' pi_hat over a
-//                    segment's columns in double and adds the sums to the
-//                    marginal's accumulator as 64-bit fixed-point integers.
+//                    entries: each active entry's pi_hat is rounded to a
+//                    64-bit fixed-point integer, each thread sums its rows'
+//                    integers over a segment's columns and adds the sums to
+//                    the marginal's accumulator.
 //                    It streams theta once in and once out and reads each
 //                    cost column once: HBM bound.
 //   marginal kernel: p^(m)_r = (fixed-point sum) - S^m b^(m)_r.
@@ -34,14 +35,17 @@
 // column stays in registers (held as w in double) for all passes; each pass
 // is one compare/select/add per value plus a group reduction.
 //
-// Fixed-point row sums.  Integer addition is associative, so the sums do not
-// depend on the order in which columns finish: results are bitwise
-// reproducible run to run and for every launch schedule, with no
-// floating-point atomics.  Measure m uses the scale 2^E_m with
-// mass_m <= 2^(62 - E_m) (mass_m = sum_s q_s); every pi_hat row sum is at
-// most mass_m, so no sum overflows 2^62, and each entry is rounded to the
-// nearest multiple of 2^-E_m (a relative 2^-63 of the mass).  All other
-// reductions have a fixed order.
+// Fixed-point row sums.  Every entry is rounded on its own and integer
+// addition is associative, so the sums depend neither on the order in which
+// columns finish nor on how the columns are split into segments: results are
+// bitwise reproducible run to run and equal for every workgroup count,
+// column order, team size, XCD mapping and number of columns in flight, with
+// no floating-point atomics.  (The threshold's own sums follow the lanes'
+// rows, so another thread shape can move them by a rounding.)  Measure m
+// uses the scale 2^E_m with mass_m <= 2^(62 - E_m) (mass_m = sum_s q_s);
+// every pi_hat row sum is at most mass_m, so no sum overflows 2^63, and each
+// entry is rounded to the nearest multiple of 2^-E_m (a relative 2^-63 of
+// the mass).  All other reductions have a fixed order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -626,7 +630,7 @@ column_kernel(ColArgs<T> a) {
   __shared__ double sh_diag[WG / 64][6];
   extern __shared__ double lds_dyn[];
   double* lds_b = lds_dyn;                // [VPT][NT]
-  double* lds_fix = lds_dyn + VPT * NT;   // [NG][VPT][NT]
+  unsigned long long* lds_fix = reinterpret_cast<unsigned long long*>(lds_dyn + VPT * NT);  // [NG][VPT][NT]
 
   const int gtid = threadIdx.x;
   // the group index is wave-uniform (a group is one wave, or the whole
@@ -635,7 +639,8 @@ column_kernel(ColArgs<T> a) {
   const int tid = gtid % NT;
   const int lane = gtid & 63;
   const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
-  double* const fix = lds_fix + (size_t)g * VPT * NT;  // this group's row sums of pi_hat, own slots per thread
+  // this group's fixed-point row sums of pi_hat, own slots per thread
+  unsigned long long* const fix = lds_fix + (size_t)g * VPT * NT;
 
   if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;  // early exit: the run has stopped
 
@@ -766,7 +771,7 @@ column_kernel(ColArgs<T> a) {
     }
     if constexpr (NG > 1) __syncthreads();  // group 0 wrote every group's b
 #pragma unroll
-    for (int k = 0; k < VPT; ++k) fix[k * NT + tid] = 0.0;
+    for (int k = 0; k < VPT; ++k) fix[k * NT + tid] = 0ull;
     T nb[VPT];  // -b^(m) rounded to the storage type: every inactive entry's new value
 #pragma unroll
     for (int k = 0; k < VPT; ++k) nb[k] = (T)(-lds_b[k * NT + tid]);
@@ -917,7 +922,7 @@ column_kernel(ColArgs<T> a) {
             if ((mask[kc] >> k) & 1) {
               const double ph = fmax(w[kc][k] - lout[kc], 0.0);
               out[k] = (T)(ph - lds_b[k * NT + tid]);
-              fix[k * NT + tid] += ph;
+              fix[k * NT + tid] += to_fixed(ph, fxm);
               if constexpr (DIAG) {
                 colsum += ph;
                 dW += (double)cp[((k / VEC) * NT + tid) * VEC + (k % VEC)] * ph;
@@ -981,13 +986,12 @@ column_kernel(ColArgs<T> a) {
         body(step + 1, rt[1], rc[1], rq[1], rl[1]);
       }
     }
-    // the segment's row sums of pi_hat (double, in column order) into the
-    // fixed-point accumulators: one integer addition per row with mass,
-    // whose total does not depend on the order of the segments
+    // the segment's fixed-point row sums of pi_hat into the accumulators:
+    // one integer addition per row with mass
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
-      const double f = fix[k * NT + tid];
-      if (f != 0.0) atomicAdd(accm + ((k / VEC) * NT + tid) * VEC + (k % VEC), to_fixed(f, fxm));
+      const unsigned long long f = fix[k * NT + tid];
+      if (f != 0ull) atomicAdd(accm + ((k / VEC) * NT + tid) * VEC + (k % VEC), f);
     }
   }
 

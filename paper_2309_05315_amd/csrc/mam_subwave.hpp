@@ -9,8 +9,8 @@
 // column w = theta + 2b - c/rho in FP64 (Alg. 1 Step 2, Prop. 2 eq.
 // (row_sol)), the exact projection onto Delta_R(q_s) by warm-started Newton
 // steps with the same exactness certificate (Prop. 3), theta' = pi_hat - b,
-// and the row sums of pi_hat into the marginal's 64-bit fixed-point
-// accumulators at the end of every segment.  Only the reductions differ: they
+// and the row sums of pi_hat, each entry rounded to 64-bit fixed point,
+// into the marginal's accumulators at the end of every segment.  Only the reductions differ: they
 // run over the group's NT lanes with DPP row operations (a butterfly, so every
 // lane of the group ends with the same total), and every per-column value is
 // held per lane, since the groups of a wave are at different columns.
@@ -61,13 +61,14 @@ __global__ void __launch_bounds__(256) subwave_kernel(ColArgs<T> a) {
   constexpr int NCH = VPT / VEC;  // vector chunks per thread
   extern __shared__ double lds_dyn[];
   double* lds_b = lds_dyn;               // [VPT][NT], the segment's b (shared by the groups)
-  double* lds_fix = lds_dyn + VPT * NT;  // [NG][VPT][NT], each group's row sums of pi_hat
+  // [NG][VPT][NT], each group's fixed-point row sums of pi_hat
+  unsigned long long* lds_fix = reinterpret_cast<unsigned long long*>(lds_dyn + VPT * NT);
 
   const int gtid = threadIdx.x;
   const int g = gtid / NT;  // group (not wave-uniform)
   const int tid = gtid % NT;
   const int lane = gtid & 63;
-  double* const fix = lds_fix + (size_t)g * VPT * NT;
+  unsigned long long* const fix = lds_fix + (size_t)g * VPT * NT;
 
   if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;  // the run has stopped
 
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(256) subwave_kernel(ColArgs<T> a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < VPT; ++k) fix[k * NT + tid] = 0.0;
+    for (int k = 0; k < VPT; ++k) fix[k * NT + tid] = 0ull;
     T nb[VPT];
 #pragma unroll
     for (int k = 0; k < VPT; ++k) nb[k] = (T)(-lds_b[k * NT + tid]);
@@ -223,7 +224,7 @@ __global__ void __launch_bounds__(256) subwave_kernel(ColArgs<T> a) {
           if ((mask >> k) & 1) {
             const double ph = fmax(w[k] - lout, 0.0);
             out[k] = (T)(ph - lds_b[k * NT + tid]);
-            fix[k * NT + tid] += ph;
+            fix[k * NT + tid] += to_fixed(ph, fxm);
           }
         }
       }
@@ -267,8 +268,8 @@ __global__ void __launch_bounds__(256) subwave_kernel(ColArgs<T> a) {
     // the segment's row sums of pi_hat into the fixed-point accumulators
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
-      const double f = fix[k * NT + tid];
-      if (f != 0.0) atomicAdd(accm + ((k / VEC) * NT + tid) * VEC + (k % VEC), to_fixed(f, fxm));
+      const unsigned long long f = fix[k * NT + tid];
+      if (f != 0ull) atomicAdd(accm + ((k / VEC) * NT + tid) * VEC + (k % VEC), f);
     }
   }
 }

@@ -139,6 +139,33 @@ def test_bitwise_determinism():
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nt", [16, 256])
+def test_bitwise_equal_across_schedules(dtype, nt):
+    """Every pi_hat entry enters the marginals' row sums as its own
+    fixed-point integer, so for one thread shape the iterate does not depend
+    on how the columns are dealt to workgroups: workgroup count, team sweeps,
+    column order, XCD mapping and columns in flight give the same plans,
+    marginals and barycenter bit for bit."""
+    p = inputs.balanced_sparse(K=16, M=6, iters=30, dtype=dtype)
+    scheds = [dict(), dict(workgroups=7), dict(workgroups=333, team_size=4), dict(order=2, xcd_remap=1),
+              dict(order=1, xcd_remap=-1, workgroups=64, team_size=16)]
+    if nt == 256:
+        scheds.append(dict(columns_in_flight=2))
+    ref = None
+    for sc in scheds:
+        g = run_gpu(p, 30, threads_per_column=nt, **sc)
+        say(f"case nt={nt} {dtype} sched={g['solver'].schedule()}")
+        g["solver"].close()
+        if ref is None:
+            ref = g
+            continue
+        assert np.array_equal(g["p_bar"], ref["p_bar"]), sc
+        assert np.array_equal(g["pm"], ref["pm"]), sc
+        for x, y in zip(g["theta"], ref["theta"]):
+            assert np.array_equal(x, y), sc
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_large_finite_gamma_is_bitwise_balanced(dtype):
     """A finite gamma at or above rho * max_k d_k leaves t = 1 in every
     iteration (Alg. 1, the damping of the unbalanced case), so the iterates

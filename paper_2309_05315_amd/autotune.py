@@ -77,15 +77,17 @@ def candidates(p, wide: bool = True) -> List[dict]:
     """Schedules to try: the default threads per column and its neighbours,
     one or two columns in flight, and (wide) the column order, XCD remap and
     two workgroup counts.  Short columns (one wave per column by default)
-    also try sub-wave groups of 16 and 32 lanes.  Invalid ones are rejected by
-    the library and skipped."""
+    also try sub-wave groups of 16 and 32 lanes.  The workgroup counts are
+    the default (one resident wave of workgroups), 512 and 1024 (two resident
+    waves for the one-wave shapes, which balances columns of uneven cost).
+    Invalid ones are rejected by the library and skipped."""
     nt0 = _default_threads(p)
     nts = [nt for nt in (nt0 // 2, nt0, nt0 * 2) if 64 <= nt <= 1024]
     if nt0 == 64:
         nts = [16, 32] + nts
     orders = [1, 2] if (wide and mam._cost_mode_of(p) != mam.COST_PER_COLUMN) else [0]
     xcds = [1, -1] if wide else [0]
-    wgs = [0, 512] if wide else [0]
+    wgs = [0, 512, 1024] if wide else [0]
     out = []
     for nt in nts:
         for kc in ((1,) if nt < 64 else (1, 2)):
@@ -179,10 +181,13 @@ def tune_batch(problems, iters: int = 6, warm: int = 2, use_cache: bool = True) 
                 continue
             for kc in ((1,) if nt < 64 else (1, 2)):
                 for xcd in (1, -1):
-                    sc = {"threads_per_column": nt, "columns_in_flight": kc, "xcd_remap": xcd}
-                    ms = _time_batch(sub, sc, iters, warm)
-                    if ms is not None and ms < best_ms:
-                        best, best_ms = sc, ms
+                    for wg in (0, 1024):
+                        sc = {"threads_per_column": nt, "columns_in_flight": kc, "xcd_remap": xcd}
+                        if wg:
+                            sc["workgroups"] = wg
+                        ms = _time_batch(sub, sc, iters, warm)
+                        if ms is not None and ms < best_ms:
+                            best, best_ms = sc, ms
         if best is None:
             raise RuntimeError(f"no candidate schedule ran for group {g}")
         out[g] = best

@@ -64,6 +64,7 @@ CASES = {
     "shared_R64": lambda dt: inputs.tiny_problem(2, R=64, S=[64, 64], dtype=dt, shared=True),
     "percol_R65": lambda dt: inputs.tiny_problem(3, R=65, S=[30, 41], dtype=dt),
     "percol_R200": lambda dt: inputs.tiny_problem(4, R=200, S=[17, 60, 5], dtype=dt),
+    "percol_R600": lambda dt: inputs.tiny_problem(16, R=600, S=[11, 7], dtype=dt),
     "percol_R1030": lambda dt: inputs.tiny_problem(5, R=1030, S=[12, 9], dtype=dt),
     "percol_R4099": lambda dt: inputs.tiny_problem(6, R=4099, S=[6, 7], dtype=dt),
     "indexed_R50": lambda dt: indexed_tiny(7, R=50, S=[20, 13], dtype=dt),

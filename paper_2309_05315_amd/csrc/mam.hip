@@ -431,6 +431,12 @@ int default_nwg(int64_t T, int ng, int req, int resident) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(nwg, T));
 }
 
+// Columns a column group takes at a time: its columns in flight when
+// several groups share a workgroup (so they share a segment's columns to
+// within one step), a fixed block of kOneGroupBlock when the workgroup is
+// one group.
+int group_block(const Group& g) { return g.ng == 1 ? mam::kOneGroupBlock : g.kc; }
+
 // Build the tables of every group.  The workspace capacity depends only on
 // the problem sizes and workgroup counts (not on an indexed cost's index),
 // so rebuilding after the index is known never grows it.
@@ -438,11 +444,11 @@ void build_long_schedule(Plan* pl);
 
 // Team sweeps.  A group's workgroups form teams of 'team' workgroups; each
 // team takes an equal contiguous share of the group's column order and
-// deals it out in blocks of NG*KB columns, round robin over its workgroups,
+// deals it out in blocks of NG*kc columns, round robin over its workgroups,
 // so the columns in flight at any time lie close together in memory (a
 // sweep, which HBM serves faster than as many independent streams as there
 // are workgroups).  Every piece of a task a workgroup takes blocks from is
-// one segment, walked with a stride of team*NG*KB columns.  The marginals
+// one segment, walked with a stride of team*NG*kc columns.  The marginals
 // are accumulated per entry, so the number of segments costs nothing but
 // one reload of b^(m) each.
 void build_schedule(Plan* pl) {
@@ -483,7 +489,7 @@ void build_schedule(Plan* pl) {
     g.stream = g.stream_req > 0 ? 1 : (g.stream_req < 0 ? 0 : (plan_bytes > ((size_t)256 << 20) ? 1 : 0));
     g.team = std::max(1, std::min(g.nwg, g.team_req > 0 ? g.team_req : kDefaultTeam));
     const int nteams = (g.nwg + g.team - 1) / g.team;
-    const int64_t blk = (int64_t)g.ng * mam::KB;
+    const int64_t blk = (int64_t)g.ng * group_block(g);  // a block for each of the ng groups
     // segments: at most one per block of a piece, so at most Tg/blk plus
     // the number of pieces (tasks split at the team shares, of which there
     // are at most 1024, the largest workgroup count): a bound that holds for
@@ -1057,6 +1063,7 @@ mam_status launch_columns(Plan* pl, hipStream_t st, int diag, uint8_t* rec, int6
     a.stop = pl->gate;
     a.nwg = g.nwg;
     a.xcd_remap = g.xcd_remap;
+    a.kb = group_block(g);
     const int kc = g.vec == 1 ? 1 : g.kc;
     if (g.nt < 64 && (diag || rec))
       return fail(MAM_EUNSUPPORTED, "diagnostics and the reverse mode need 64 or more threads per column");
@@ -2016,7 +2023,7 @@ void bundle_build(const Plan* pl, const int32_t* bundle_of, int bi, BundleHost* 
       h->seg_m.push_back((int32_t)m);
       h->seg_j0.push_back(p.col_off[m] + (lo - starts[i]));
       h->seg_j1.push_back(p.col_off[m] + (e - starts[i]));
-      h->seg_st.push_back(g.ng * mam::KB);  // contiguous: the groups of one workgroup in turn
+      h->seg_st.push_back(g.ng * group_block(g));  // contiguous: the groups of one workgroup in turn
       lo = e;
     }
   }
@@ -2109,6 +2116,7 @@ mam_status launch_bundle_columns(Plan* pl, const BundleSched& bs, hipStream_t st
   a.stop = nullptr;
   a.nwg = bs.nwg;
   a.xcd_remap = 0;
+  a.kb = group_block(g);
   const int kc = g.vec == 1 ? 1 : g.kc;
   mam::ColFn<T> fn = mam::pick_column<T>(g.nt, g.vpt, g.vec, kc, 0, g.stream);
   if (!fn) return fail(MAM_EUNSUPPORTED, "no column kernel for nt=%d vpt=%d vec=%d kc=%d", g.nt, g.vpt, g.vec, kc);

@@ -459,7 +459,17 @@ struct ColArgs {
   const int32_t* stop;    // null, or a flag: nonzero once a stopping test
                           // held, and then the launch does nothing
   int32_t nwg, xcd_remap;
+  int32_t kb;             // columns a group takes at a time (a block): with
+                          // several groups per workgroup the schedule's
+                          // columns in flight (1, 2 or 4), with one group
+                          // kOneGroupBlock; every instance walking the
+                          // tables has KC dividing it
 };
+
+// The block of a workgroup that is one column group.  Its columns are
+// consecutive whatever the block, and a block of 4 (every KC divides it)
+// keeps the step arithmetic in compile-time constants.
+constexpr int kOneGroupBlock = 4;
 
 constexpr int DIAG_STRIDE = 8;  // W_hat, meas_resid, dtheta_inf, rounds, active, columns
 
@@ -483,8 +493,6 @@ template <> struct MaskWord<1> { using type = uint8_t; };
 template <> struct MaskWord<2> { using type = uint8_t; };
 template <> struct MaskWord<4> { using type = uint8_t; };
 template <> struct MaskWord<8> { using type = uint8_t; };
-
-constexpr int KB = 4;  // column block a group owns at a time (multiple of every KC)
 
 template <int NT> struct GroupShape {
   // a 64-thread group is one wave: four of them share a workgroup;
@@ -672,20 +680,22 @@ column_kernel(ColArgs<T> a) {
     const double* __restrict__ pmm = gptr(P.pm) + (size_t)m * R;
     const double* __restrict__ pv = gptr(P.p);
 
-    // Column steps of this group: blocks of KB columns taken in turn by the
-    // NG groups (and, with a segment stride beyond NG*KB, by the other
+    // Column steps of this group: blocks of kb columns taken in turn by the
+    // NG groups (and, with a segment stride beyond NG*kb, by the other
     // workgroups of a team sweeping the same columns), each walked KC
-    // columns at a time.  The raw loads of the next step are issued before
-    // the current step's threshold rounds and stores, so their HBM latency
-    // overlaps that work.
-    static_assert(KB % KC == 0, "KC must divide the column block");
-    constexpr int SPB = KB / KC;  // steps per block
-    const int64_t gbase = j0 + (int64_t)g * KB;
-    auto step_exists = [&](int64_t i) -> bool { return gbase + (i / SPB) * stride < j1; };
+    // columns at a time.  With kb = KC a group takes one step's columns and
+    // the groups of a workgroup share a segment's columns to within one
+    // step.  The raw loads of the next step are issued before the current
+    // step's threshold rounds and stores, so their HBM latency overlaps that
+    // work.
+    const int kb = NG == 1 ? kOneGroupBlock : uniform_i(a.kb);
+    const int sps = __builtin_ctz(kb / KC);  // log2 of the steps per block
+    const int64_t gbase = j0 + (int64_t)g * kb;
+    auto step_exists = [&](int64_t i) -> bool { return gbase + (i >> sps) * stride < j1; };
     auto step_col = [&](int64_t i, int kc, int64_t& j) -> bool {
-      const int64_t base = gbase + (i / SPB) * stride;
-      const int64_t bend = base + KB < j1 ? base + KB : j1;
-      j = base + (i % SPB) * KC + kc;
+      const int64_t base = gbase + (i >> sps) * stride;
+      const int64_t bend = base + kb < j1 ? base + kb : j1;
+      j = base + (i & ((1 << sps) - 1)) * KC + kc;
       return j < bend;
     };
     auto cost_col = [&](int64_t j) -> const T* {

@@ -16,7 +16,7 @@
 // held per lane, since the groups of a wave are at different columns.
 //
 // Segments and schedule tables are those of the column kernel with
-// NG = 256/NT groups per workgroup; a group takes blocks of KB columns.  No
+// NG = 256/NT groups per workgroup; a group takes blocks of kb columns.  No
 // diagnostics or active-set recording (the host takes the one-wave kernel
 // for those).
 #pragma once
@@ -115,14 +115,17 @@ __global__ void __launch_bounds__(256) subwave_kernel(ColArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < VPT; ++k) nb[k] = (T)(-lds_b[k * NT + tid]);
 
-    // this group's columns: blocks of KB, the block of group g at j0 + g*KB,
-    // the next one 'stride' columns on
-    const int64_t gbase = j0 + (int64_t)g * KB;
-    auto block_exists = [&](int64_t i) { return gbase + (i / KB) * stride < j1; };
+    // this group's columns: blocks of kb (one column: sub-wave groups take
+    // one column in flight), the block of group g at j0 + g*kb, the next one
+    // 'stride' columns on
+    const int kb = uniform_i(a.kb);
+    const int sh = __builtin_ctz(kb);
+    const int64_t gbase = j0 + (int64_t)g * kb;
+    auto block_exists = [&](int64_t i) { return gbase + (i >> sh) * stride < j1; };
     auto col_of = [&](int64_t i, int64_t& j) -> bool {
-      const int64_t base = gbase + (i / KB) * stride;
-      j = base + i % KB;
-      return base < j1 && j < (base + KB < j1 ? base + KB : j1);
+      const int64_t base = gbase + (i >> sh) * stride;
+      j = base + (i & (kb - 1));
+      return base < j1 && j < (base + kb < j1 ? base + kb : j1);
     };
     auto cost_index = [&](int64_t j) -> int64_t {
       if (cost_mode == MAM_COST_INDEXED) return cidx[j];

@@ -927,36 +927,39 @@ mam_status bind(Plan* pl, int i, void* theta, const void* cost, const int32_t* c
 // device tables
 // ---------------------------------------------------------------------------
 template <typename T>
+void fill_probdev_one(Plan* pl, size_t i, mam::ProbDev<T>& d) {
+  const Prob& p = pl->P[i];
+  d.theta = static_cast<T*>(p.theta);
+  d.cost = static_cast<const T*>(p.cost);
+  d.q = static_cast<const T*>(p.q);
+  d.cidx = p.cidx;
+  d.acc = pl->lg.on ? nullptr : at<unsigned long long>(pl, p.o_acc);
+  d.fx = pl->lg.on ? nullptr : at<double>(pl, p.o_fx);
+  d.ld = p.ld;
+  d.cost_ld = p.cost_ld;
+  d.R = (int32_t)p.R;
+  d.cost_mode = p.cost_mode;
+  d.nb = p.nb;
+  d.warm = (p.flags & MAM_FLAG_COLD) ? 0 : 1;
+  d.relaxed = (p.flags & MAM_FLAG_RELAXED) ? 1 : 0;
+  d.rho = p.rho;
+  d.inv_rho = 1.0 / p.rho;
+  d.gamma = p.gamma;
+  d.pm = at<double>(pl, p.o_pm);
+  d.p = at<double>(pl, p.o_p);
+  d.d2part = at<double>(pl, p.o_d2);
+  d.lam = at<double>(pl, p.o_lam);
+  d.t_out = at<double>(pl, p.o_t);
+  d.col_off = at<int64_t>(pl, p.o_coloff);
+  d.Sd = at<double>(pl, p.o_Sd);
+}
+
+template <typename T>
 void fill_probdev(Plan* pl, std::vector<mam::ProbDev<T>>& out) {
   out.resize(pl->P.size());
-  for (size_t i = 0; i < pl->P.size(); ++i) {
-    const Prob& p = pl->P[i];
-    mam::ProbDev<T>& d = out[i];
-    d.theta = static_cast<T*>(p.theta);
-    d.cost = static_cast<const T*>(p.cost);
-    d.q = static_cast<const T*>(p.q);
-    d.cidx = p.cidx;
-    d.acc = pl->lg.on ? nullptr : at<unsigned long long>(pl, p.o_acc);
-    d.fx = pl->lg.on ? nullptr : at<double>(pl, p.o_fx);
-    d.ld = p.ld;
-    d.cost_ld = p.cost_ld;
-    d.R = (int32_t)p.R;
-    d.cost_mode = p.cost_mode;
-    d.nb = p.nb;
-    d.warm = (p.flags & MAM_FLAG_COLD) ? 0 : 1;
-    d.relaxed = (p.flags & MAM_FLAG_RELAXED) ? 1 : 0;
-    d.rho = p.rho;
-    d.inv_rho = 1.0 / p.rho;
-    d.gamma = p.gamma;
-    d.pm = at<double>(pl, p.o_pm);
-    d.p = at<double>(pl, p.o_p);
-    d.d2part = at<double>(pl, p.o_d2);
-    d.lam = at<double>(pl, p.o_lam);
-    d.t_out = at<double>(pl, p.o_t);
-    d.col_off = at<int64_t>(pl, p.o_coloff);
-    d.Sd = at<double>(pl, p.o_Sd);
-  }
+  for (size_t i = 0; i < pl->P.size(); ++i) fill_probdev_one<T>(pl, i, out[i]);
 }
+
 
 // Host staging for the table uploads; the copies complete before it is
 // released (the upload synchronizes the stream).

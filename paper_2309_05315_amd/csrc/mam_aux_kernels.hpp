@@ -51,8 +51,11 @@ marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ 
 __global__ void __launch_bounds__(256)
 fixed_marginal_kernel(const MargTask* __restrict__ tasks, const ProbAux* __restrict__ probs, int save_prev,
                       const int32_t* __restrict__ stop) {
-  if (stop != nullptr && *stop != 0) return;  // early exit: the run has stopped
+  // the stop flag and the task requested together (an early exit then adds
+  // no memory latency in front of the work)
+  const int stopv = stop != nullptr ? *stop : 0;
   const MargTask tk = tasks[blockIdx.x];
+  if (stopv != 0) return;  // early exit: the run has stopped
   close_marginal(tk, probs[tk.prob], save_prev, threadIdx.x);
 }
 
@@ -114,9 +117,10 @@ init_marginal_kernel(const MargTask* __restrict__ tasks, const ProbDev<T>* __res
 __global__ void __launch_bounds__(256)
 close_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ probs, int save_prev,
              const int32_t* __restrict__ stop) {
-  if (stop != nullptr && *stop != 0) return;  // early exit: the run has stopped
   __shared__ double sh[4];
+  const int stopv = stop != nullptr ? *stop : 0;  // requested with the task
   const AvgTask tk = tasks[blockIdx.x];
+  if (stopv != 0) return;  // early exit: the run has stopped
   close_rows(tk, probs[tk.prob], save_prev, threadIdx.x, sh);
 }
 
@@ -124,9 +128,10 @@ close_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ prob
 __global__ void __launch_bounds__(256)
 average_kernel(const AvgTask* __restrict__ tasks, const ProbAux* __restrict__ probs, int save_prev,
                const int32_t* __restrict__ stop) {
-  if (stop != nullptr && *stop != 0) return;  // early exit: the run has stopped
   __shared__ double sh[4];
+  const int stopv = stop != nullptr ? *stop : 0;  // requested with the task
   const AvgTask tk = tasks[blockIdx.x];
+  if (stopv != 0) return;  // early exit: the run has stopped
   close_average(tk, probs[tk.prob], save_prev, threadIdx.x, sh);
 }
 

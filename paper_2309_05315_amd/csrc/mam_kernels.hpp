@@ -650,15 +650,18 @@ column_kernel(ColArgs<T> a) {
   // this group's fixed-point row sums of pi_hat, own slots per thread
   unsigned long long* const fix = lds_fix + (size_t)g * VPT * NT;
 
-  if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;  // early exit: the run has stopped
+  const int wg = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  // The stop flag and this workgroup's segment range are requested together,
+  // so the early exit adds no memory latency in front of the first segment.
+  // Table entries are read through vector loads (the compiler cannot prove
+  // them constant); readfirstlane makes them scalar again.
+  const int stopv = a.stop != nullptr ? *gptr(a.stop) : 0;
+  const int sb0 = a.wg_seg[wg], se0 = a.wg_seg[wg + 1];
+  if (uniform_i(stopv) != 0) return;  // early exit: the run has stopped
+  const int sb = uniform_i(sb0), se = uniform_i(se0);
 
   Rounds<NW, KC> rounds{red_d, red_f, red_i, 0};
   double dW = 0.0, dRes = 0.0, dTh = 0.0, dRounds = 0.0, dAct = 0.0, dCols = 0.0;
-
-  const int wg = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  // table entries are read through vector loads (the compiler cannot prove
-  // them constant); readfirstlane makes them scalar again
-  const int sb = uniform_i(a.wg_seg[wg]), se = uniform_i(a.wg_seg[wg + 1]);
   for (int si = sb; si < se; ++si) {
     const ProbDev<T>& P = a.probs[uniform_i(a.seg_p[si])];
     T* const theta = gptr((T*)uniform_l((int64_t)P.theta));

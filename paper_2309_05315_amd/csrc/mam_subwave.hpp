@@ -70,10 +70,12 @@ __global__ void __launch_bounds__(256) subwave_kernel(ColArgs<T> a) {
   const int lane = gtid & 63;
   unsigned long long* const fix = lds_fix + (size_t)g * VPT * NT;
 
-  if (a.stop != nullptr && uniform_i(*gptr(a.stop)) != 0) return;  // the run has stopped
-
   const int wg = logical_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  const int sb = uniform_i(a.wg_seg[wg]), se = uniform_i(a.wg_seg[wg + 1]);
+  // the stop flag and the segment range requested together
+  const int stopv = a.stop != nullptr ? *gptr(a.stop) : 0;
+  const int sb0 = a.wg_seg[wg], se0 = a.wg_seg[wg + 1];
+  if (uniform_i(stopv) != 0) return;  // the run has stopped
+  const int sb = uniform_i(sb0), se = uniform_i(se0);
   for (int si = sb; si < se; ++si) {
     const ProbDev<T>& P = a.probs[uniform_i(a.seg_p[si])];
     T* const theta = gptr((T*)uniform_l((int64_t)P.theta));

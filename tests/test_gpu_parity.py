@@ -210,8 +210,11 @@ def test_unbalanced_mass_relation_per_iteration(dtype):
     assert min(ts) < 1.0  # the damped branch was taken
 
 
-@pytest.mark.parametrize("gamma", [math.inf, 0.05])
-def test_diagnostics_match_oracle(gamma):
+@pytest.mark.parametrize("gamma,kc", [(math.inf, 1), (0.05, 1), (math.inf, 4)])
+def test_diagnostics_match_oracle(gamma, kc):
+    """With kc = 4 the plain iterations walk the tables four columns per group
+    step and the diagnostics iteration walks the same blocks one column at a
+    time."""
     masses = None if math.isinf(gamma) else [0.7, 1.0, 1.3]
     p = inputs.tiny_problem(5, R=300, S=[40, 70, 25], masses=masses, gamma=gamma, dtype="f64")
     cost, q = blocks(p)
@@ -219,9 +222,10 @@ def test_diagnostics_match_oracle(gamma):
     prev = O.mam(cost, q, p.rho, p.gamma, k - 1)
     ora = O.mam(cost, q, p.rho, p.gamma, k)
     od = O.diagnostics(cost, q, ora["pi_hat"], ora["theta"], prev["theta"])
-    g = run_gpu(p, k, diag=True)
+    g = run_gpu(p, k, diag=True, threads_per_column=64, columns_in_flight=kc)
     gd = g["diag"]
     assert gd["iterations"] == k
+    assert rel(g["p_bar"], ora["p_bar"]) <= 1e-10
     assert gd["rounds_per_column"] >= 1.0 and gd["active_per_column"] >= 1.0
     assert abs(gd["W_hat"] - od["W_hat"]) <= 1e-10 * abs(od["W_hat"])
     assert abs(gd["dist_L"] - od["dist_L"]) <= 1e-8 * max(od["dist_L"], 1e-12)

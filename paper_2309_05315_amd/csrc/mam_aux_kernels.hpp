@@ -413,21 +413,53 @@ adjoint_average_kernel(unsigned long long* __restrict__ wacc, double* __restrict
   const int r = blockIdx.x * 256 + threadIdx.x;
   double vmx = 0.0;
   if (r < R) {
+    // eight measures' loads in flight at a time (a row's values are a chain
+    // of dependent steps otherwise); the sums keep the order m = 0, 1, ...
+    constexpr int U = 8;
     double pbar = 0.0;
-    for (int m = 0; m < M; ++m) {
-      const size_t o = (size_t)m * R + r;
-      // W_new is written back over W_old below, so read it once here
-      const double wn = adj_take_w(wacc, o, sc);
-      const double bb = 2.0 * wn - wold[o] - Sd[m] * V[o];
-      wold[o] = wn;
-      V[o] = bb;  // bbar_m, held until pbar is known
-      pbar += bb / Sd[m];
+    for (int m0 = 0; m0 < M; m0 += U) {
+      unsigned long long wa[U];
+      double wo[U], vv[U], sd[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t o = (size_t)(m0 + u) * R + r;
+        const bool in = m0 + u < M;
+        wa[u] = in ? wacc[o] : 0ull;
+        wo[u] = in ? wold[o] : 0.0;
+        vv[u] = in ? V[o] : 0.0;
+        sd[u] = in ? Sd[m0 + u] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (m0 + u < M) {
+          const size_t o = (size_t)(m0 + u) * R + r;
+          // W_new (then cleared) is written back over W_old
+          const double wn = sc.ok ? adj_from_fixed(wa[u], sc.E) : __builtin_nan("");
+          wacc[o] = 0ull;
+          const double bb = 2.0 * wn - wo[u] - sd[u] * vv[u];
+          wold[o] = wn;
+          V[o] = bb;  // bbar_m, held until pbar is known
+          pbar += bb / sd[u];
+        }
+      }
     }
-    for (int m = 0; m < M; ++m) {
-      const size_t o = (size_t)m * R + r;
-      const double v = -V[o] / Sd[m] + aw[m] * pbar;
-      V[o] = v;
-      vmx = fmax(vmx, adj_mag(v));
+    for (int m0 = 0; m0 < M; m0 += U) {
+      double vv[U], sd[U], a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool in = m0 + u < M;
+        vv[u] = in ? V[(size_t)(m0 + u) * R + r] : 0.0;
+        sd[u] = in ? Sd[m0 + u] : 1.0;
+        a[u] = in ? aw[m0 + u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (m0 + u < M) {
+          const double v = -vv[u] / sd[u] + a[u] * pbar;
+          V[(size_t)(m0 + u) * R + r] = v;
+          vmx = fmax(vmx, adj_mag(v));
+        }
+      }
     }
   }
   adj_raise_block(mx + (slot + 1) % 3, vmx);

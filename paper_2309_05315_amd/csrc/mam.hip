@@ -1272,6 +1272,22 @@ mam_status launch_marginals(Plan* pl, hipStream_t st, int save_prev) {
 }
 
 
+// Copy of a problem's plans (the R stored rows of each column), with 16-byte
+// accesses when both buffers and the column stride allow them.
+template <typename T>
+mam_status launch_plan_copy(T* dst, const T* src, const Prob& p, hipStream_t st) {
+  constexpr int VN = 16 / (int)sizeof(T);
+  const bool vec = p.ld % VN == 0 && reinterpret_cast<uintptr_t>(dst) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(src) % 16 == 0;
+  const int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, p.T));
+  if (vec)
+    hipLaunchKernelGGL((mam::copy_kernel<T, VN>), dim3(blocks), dim3(256), 0, st, dst, p.ld, (int)p.R, src, p.T);
+  else
+    hipLaunchKernelGGL((mam::copy_kernel<T, 1>), dim3(blocks), dim3(256), 0, st, dst, p.ld, (int)p.R, src, p.T);
+  LAUNCH_CHECK("copy_kernel");
+  return MAM_OK;
+}
+
 template <typename T>
 mam_status launch_init(Plan* pl, const void* const* theta0, hipStream_t st) {
   const Layout& L = pl->lay;
@@ -1279,9 +1295,7 @@ mam_status launch_init(Plan* pl, const void* const* theta0, hipStream_t st) {
     Prob& p = pl->P[i];
     const int blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (p.T * p.R + 255) / 256));
     if (theta0 && theta0[i]) {
-      hipLaunchKernelGGL(mam::copy_kernel<T>, dim3(blocks), dim3(256), 0, st, static_cast<T*>(p.theta), p.ld,
-                         (int)p.R, static_cast<const T*>(theta0[i]), p.T);
-      LAUNCH_CHECK("copy_kernel");
+      TRY(launch_plan_copy<T>(static_cast<T*>(p.theta), static_cast<const T*>(theta0[i]), p, st));
     } else {
       hipLaunchKernelGGL(mam::fill_kernel<T>, dim3(blocks), dim3(256), 0, st, static_cast<T*>(p.theta), p.ld,
                          (int)p.R, static_cast<const T*>(p.q), p.T);
@@ -1750,10 +1764,7 @@ uint8_t* mask_slot(Plan* pl, int64_t k) {
 
 template <typename T>
 mam_status launch_copy(T* dst, const T* src, const Prob& p, hipStream_t st) {
-  const int blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (p.T * p.R + 255) / 256));
-  hipLaunchKernelGGL(mam::copy_kernel<T>, dim3(blocks), dim3(256), 0, st, dst, p.ld, (int)p.R, src, p.T);
-  LAUNCH_CHECK("copy_kernel");
-  return MAM_OK;
+  return launch_plan_copy<T>(dst, src, p, st);
 }
 
 // Iterations [k0, k1) with the masks of those at or after 'rec_from'

@@ -266,14 +266,33 @@ fill_kernel(T* __restrict__ theta, int64_t ld, int R, const T* __restrict__ q, i
   }
 }
 
-template <typename T>
+// The R stored rows of T_cols columns at stride ld, src to dst (padding
+// rows untouched): workgroups take columns in turn, a thread moves VEC
+// elements per access with four accesses in flight.
+template <typename T, int VEC>
 __global__ void __launch_bounds__(256)
-copy_kernel(T* __restrict__ theta, int64_t ld, int R, const T* __restrict__ src, int64_t T_cols) {
-  const int64_t total = T_cols * (int64_t)R;
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-    const int64_t j = i / R;
-    const int r = (int)(i - j * R);
-    theta[j * ld + r] = src[j * ld + r];
+copy_kernel(T* __restrict__ dst, int64_t ld, int R, const T* __restrict__ src, int64_t T_cols) {
+  constexpr int U = 4;
+  for (int64_t j = blockIdx.x; j < T_cols; j += gridDim.x) {
+    const T* __restrict__ s = src + j * ld;
+    T* __restrict__ d = dst + j * ld;
+    for (int r0 = (int)threadIdx.x * VEC; r0 < R; r0 += 256 * VEC * U) {
+      T v[U][VEC];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + u * 256 * VEC;
+        if (r + VEC <= R) load_vec<T, VEC>(s + r, v[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + u * 256 * VEC;
+        if (r + VEC <= R) {
+          store_vec<T, VEC>(d + r, v[u]);
+        } else {
+          for (int k = r; k < R; ++k) d[k] = s[k];  // the column's last rows
+        }
+      }
+    }
   }
 }
 

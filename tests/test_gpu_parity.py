@@ -235,6 +235,45 @@ def test_diagnostics_match_oracle(gamma, kc):
     np.testing.assert_allclose(gd["t"], ora["t"], rtol=1e-12)
 
 
+@pytest.mark.parametrize("dtype,R,ld", [("f32", 7, 7), ("f32", 10, 13), ("f64", 5, 5), ("f64", 300, 301)])
+def test_custom_start_with_unaligned_columns(dtype, R, ld):
+    """A caller's theta^0 and plans whose column stride is not a multiple of
+    the vector width (single-element copies and loads): results match the
+    oracle, and the padding rows of theta are never written."""
+    p = inputs.tiny_problem(60 + R, R=R, S=[6, 9], dtype=dtype)
+    dt = torch.float32 if dtype == "f32" else torch.float64
+    cost, q = blocks(p)
+    rng = np.random.default_rng(R)
+    th0 = [np.abs(rng.normal(size=(R, sm))) * 1e-2 for sm in p.S]
+    if dtype == "f32":
+        th0 = [x.astype(np.float32).astype(np.float64) for x in th0]
+    ora = O.mam(cost, q, p.rho, p.gamma, 10, theta0=th0)
+    if p.col_index is None:
+        mode = mam.COST_SHARED
+    elif np.array_equal(p.col_index, np.arange(p.T)):
+        mode = mam.COST_PER_COLUMN
+    else:
+        mode = mam.COST_INDEXED
+    s = mam.Solver(R, p.S, rho=p.rho, gamma=p.gamma, dtype=dt, cost_mode=mode, cost_ncols=p.cost_ncols,
+                   ld=ld, cost_ld=ld)
+    c = torch.full((p.cost_ncols, ld), 7.0, dtype=dt)
+    c[:, :R] = torch.from_numpy(p.cost).to(dt)
+    theta = torch.full((p.T, ld), 123.0, dtype=dt, device="cuda")
+    idx = torch.from_numpy(p.col_index.astype(np.int32)).cuda() if mode == mam.COST_INDEXED else None
+    s.bind(theta, c.cuda(), torch.from_numpy(p.q).to(dt).cuda(), idx)
+    t0 = torch.full((p.T, ld), -5.0, dtype=dt)
+    t0[:, :R] = torch.from_numpy(np.concatenate([x.T for x in th0])).to(dt)
+    s.init(t0.cuda())
+    s.iterate(10)
+    say(f"case R={R} ld={ld} {dtype} schedule={s.schedule()}")
+    assert rel(s.barycenter().cpu().numpy(), ora["p_bar"]) <= TOL[dtype]
+    th = theta.cpu().numpy()
+    assert np.all(th[:, R:] == 123.0)
+    off = np.concatenate([[0], np.cumsum(p.S)])
+    for m in range(p.M):
+        assert rel(th[off[m]:off[m + 1], :R].T, ora["theta"][m], np.inf) <= TOL[dtype]
+
+
 def test_custom_start_and_resume():
     """theta^0 given by the caller; iterate(a) then iterate(b) equals iterate(a+b)."""
     p = inputs.tiny_problem(8, R=128, S=[20, 30], dtype="f64")

@@ -412,14 +412,6 @@ __global__ void zero_kernel(double* p, int n) {
 
 // ---- reverse mode (see mam_adjoint.hpp for the step) ----
 
-// Row r of measure m's W_new from its fixed-point accumulator (which is
-// cleared for the next step); NaN when the step's bound was not finite.
-__device__ __forceinline__ double adj_take_w(unsigned long long* wacc, size_t o, const AdjScale& sc) {
-  const double w = sc.ok ? adj_from_fixed(wacc[o], sc.E) : __builtin_nan("");
-  wacc[o] = 0ull;
-  return w;
-}
-
 // Transposed averaging of one reverse step, per row r:
 //   bbar_m = 2 W_new - W_old - S^m V_m,  pbar = sum_m bbar_m / S^m,
 //   V_m <- -bbar_m / S^m + a_m pbar,  W_old <- W_new,
@@ -452,7 +444,9 @@ adjoint_average_kernel(unsigned long long* __restrict__ wacc, double* __restrict
       for (int u = 0; u < U; ++u) {
         if (m0 + u < M) {
           const size_t o = (size_t)(m0 + u) * R + r;
-          // W_new (then cleared) is written back over W_old
+          // W_new from its fixed-point accumulator, which is cleared for the
+          // next step (NaN when the step's bound was not finite); it is
+          // written back over W_old
           const double wn = sc.ok ? adj_from_fixed(wa[u], sc.E) : __builtin_nan("");
           wacc[o] = 0ull;
           const double bb = 2.0 * wn - wo[u] - sd[u] * vv[u];
@@ -504,13 +498,35 @@ adjoint_unbal1_kernel(unsigned long long* __restrict__ wacc, double* __restrict_
   const int r = blockIdx.x * 256 + threadIdx.x;
   double acc = 0.0;
   if (r < R) {
-    for (int m = 0; m < M; ++m) {
-      const size_t o = (size_t)m * R + r;
-      const double wn = adj_take_w(wacc, o, sc);
-      const double bb = 2.0 * wn - wold[o] - Sd[m] * V[o];
-      wold[o] = wn;
-      bbar[o] = bb;
-      acc += bb * (p_k[r] - pm_k[o]) / Sd[m];
+    // eight measures' loads in flight at a time; the sum keeps the order m = 0, 1, ...
+    constexpr int U = 8;
+    const double pr = p_k[r];
+    for (int m0 = 0; m0 < M; m0 += U) {
+      unsigned long long wa[U];
+      double wo[U], vv[U], sd[U], pmv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t o = (size_t)(m0 + u) * R + r;
+        const bool in = m0 + u < M;
+        wa[u] = in ? wacc[o] : 0ull;
+        wo[u] = in ? wold[o] : 0.0;
+        vv[u] = in ? V[o] : 0.0;
+        sd[u] = in ? Sd[m0 + u] : 1.0;
+        pmv[u] = in ? pm_k[o] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (m0 + u < M) {
+          const size_t o = (size_t)(m0 + u) * R + r;
+          // W_new (accumulator cleared; NaN when the bound was not finite)
+          const double wn = sc.ok ? adj_from_fixed(wa[u], sc.E) : __builtin_nan("");
+          wacc[o] = 0ull;
+          const double bb = 2.0 * wn - wo[u] - sd[u] * vv[u];
+          wold[o] = wn;
+          bbar[o] = bb;
+          acc += bb * (pr - pmv[u]) / sd[u];
+        }
+      }
     }
   }
   acc = wave_sum(acc);

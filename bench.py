@@ -9,8 +9,8 @@ cost gathered by pixel index, rho = 1, plans in FP32 (thresholds, marginals
 and barycenter in FP64).  The default run times the 500 iterations that
 problem is quoted at, then the same 500 iterations with FP64 plans, and
 reports the FP32-vs-FP64 barycenter difference.  Shorter runs of the other
-workloads (balanced FP64 with graph replay, unbalanced, a batch of 256
-problems, the randomized variant, on-device stopping tests, the free-support
+workloads (balanced FP64 with graph replay, unbalanced, unbalanced with the
+measure constraints relaxed, a batch of 256 problems, the randomized variant, on-device stopping tests, the free-support
 workload on the long-column path, the reverse mode) are reported under
 "extras".
 
@@ -87,12 +87,12 @@ def run_gpu(p, steps, warmup, torch, mam):
     return dt, pbar, col_ms / max(n, 1), n, sched
 
 
-def final_state(p, iters, torch, mam):
+def final_state(p, iters, torch, mam, relaxed=False):
     """The state the timed run reached, recomputed untimed with diagnostics
     on its last iteration: objective W_hat = sum c pi_hat, dist_L (the
     marginals' distance to agreement), the measure-constraint residual, the
     threshold passes and active entries per column."""
-    s = mam.solver_for(p, device="cuda:0", diag=True)
+    s = mam.solver_for(p, device="cuda:0", diag=True, relaxed=relaxed)
     s.init()
     s.iterate(iters)
     d = s.diagnostics()
@@ -243,8 +243,8 @@ def cpu_baseline_parallel(p, workers):
                       f"on {host_cpu()}"}
 
 
-EXTRAS = ("balanced_plain", "unbalanced", "batch", "randomized", "stopping", "free_support", "adjoint",
-          "large_rho")
+EXTRAS = ("balanced_plain", "unbalanced", "relaxed", "batch", "randomized", "stopping", "free_support",
+          "adjoint", "large_rho")
 
 
 def extra_workloads(torch, mam, inputs, log, only=None):
@@ -319,6 +319,48 @@ def extra_workloads(torch, mam, inputs, log, only=None):
                                          "first_undamped_iteration": int(np.argmax(ts >= 1.0)) + 1 if np.any(ts >= 1.0) else None}
         log(f"unbalanced: {dt * 1e3:.4f} ms/iter, {dtg * 1e3:.4f} ms/iter graph, column kernel {col / n:.4f} ms, "
             f"t < 1 in {np.mean(ts < 1.0):.1%} of {p3.iters} iterations")
+
+    if want("relaxed"):
+        # the full unbalanced extension: measure constraints relaxed to
+        # sum_r pi_rs <= q_s, the penalty of unassigned mass entering as the
+        # shifted cost c - eta.  Random supports (so no measure point sits on
+        # a barycenter point and leaving mass unassigned can be the cheaper
+        # choice): R = 1024 barycenter points, 32 measures of 1024 points
+        # with masses in [0.5, 1.5], one shared cost, gamma = 0.2, FP32
+        eta, gam, n_it = 0.002, 0.2, 300
+        rng = np.random.default_rng(55)
+        masses = list(rng.uniform(0.5, 1.5, size=32))
+        p5 = inputs.tiny_problem(55, R=1024, S=[1024] * 32, dtype="f32", masses=masses, gamma=gam, shared=True)
+        p5 = dataclasses.replace(p5, cost=(p5.cost - eta).astype(np.float32).astype(np.float64))
+        s = mam.solver_for(p5, relaxed=True)
+        s.init()
+        s.iterate(10)
+        dt = timed(lambda: s.iterate(n_it)) / n_it
+        s.timing(True)
+        s.iterate(100)
+        col, n = s.timing_read()
+        s.timing(False)
+        s.init()
+        s.iterate(n_it)
+        pb = s.barycenter().cpu().numpy()
+        s.close()
+        # the same iterations with the measure constraints kept: how much the
+        # relaxation changes the barycenter
+        s = mam.solver_for(p5)
+        s.init()
+        s.iterate(n_it)
+        pb0 = s.barycenter().cpu().numpy()
+        s.close()
+        d = final_state(p5, n_it, torch, mam, relaxed=True)
+        out["relaxed_R1024_M32_f32"] = {
+            "eta": eta, "gamma": gam, "iterations": n_it, "ms_per_iter": dt * 1e3,
+            "plan_entry_updates_per_s": p5.R * p5.T / dt, "column_kernel_ms": col / n,
+            "column_kernel_GBs": algorithmic_bytes(p5) / (col / n * 1e-3) / 1e9,
+            "barycenter_mass": float(pb.sum()), "barycenter_mass_constraints_kept": float(pb0.sum()),
+            "barycenter_rel_diff_to_constraints_kept": float(np.abs(pb - pb0).max() / np.abs(pb0).max()),
+            "state": d}
+        log(f"relaxed (eta = {eta}): {dt * 1e3:.4f} ms/iter, column kernel {col / n:.4f} ms; barycenter mass "
+            f"{pb.sum():.4f} against {pb0.sum():.4f} with the constraints kept; excess over q {d['meas_resid']:.2e}")
 
     if want("batch"):
         # 256 independent problems (R = k^2, k in 8..32, M in 2..8), FP32, autotuned

@@ -249,6 +249,16 @@ __device__ __forceinline__ float float_down(double x) {
   return (double)f > x ? __int_as_float(f > 0.0f ? b - 1 : (f == 0.0f ? (int)0x80000001 : b + 1)) : f;
 }
 
+// max(a, b) of two results of arithmetic, which are never signaling NaNs:
+// the bare instruction (it returns the other operand for a quiet NaN, as
+// fmax does).  fmax itself first quiets each operand the compiler cannot
+// prove is the result of arithmetic, one more instruction per call.
+__device__ __forceinline__ double max_arith(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // Fixed-point value of pi_hat >= 0 at scale fx = 2^E (round to nearest).
 __device__ __forceinline__ unsigned long long to_fixed(double ph, double fx) {
   return __double2ull_rn(ph * fx);
@@ -793,7 +803,7 @@ column_kernel(ColArgs<T> a) {
       // ---- reflect the step's columns: w = theta + 2b - c/rho (double) ----
       // (a column slot past the segment's end is computed too, on defined
       // values, and then ignored: no select per entry)
-      double w[KC][VPT];
+      double w[KC][VPT], wt[KC];  // wt: the thread's largest w of each column
       T told[DIAG ? KC : 1][DIAG ? VPT : 1];
       bool valid[KC];
       int64_t jj[KC];
@@ -803,6 +813,7 @@ column_kernel(ColArgs<T> a) {
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
           w[kc][k] = ((double)bt[kc][k] + 2.0 * lds_b[k * NT + tid]) - (double)bc[kc][k] * inv_rho;
+          wt[kc] = k == 0 ? w[kc][0] : max_arith(wt[kc], w[kc][k]);
           if constexpr (DIAG) told[kc][k] = bt[kc][k];
         }
       }
@@ -851,21 +862,28 @@ column_kernel(ColArgs<T> a) {
             const double l = lam[kc];
             double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
             int bits = 0;
+            // Most waves of a column hold no active entry at all: one compare
+            // of the thread's largest w settles that case for the whole wave.
+            // Otherwise usually no lane of the wave holds an active entry in
+            // slot k, and a uniform branch keeps that slot to one compare and
+            // one max.
+            if (__ballot(wt[kc] > l) == 0ull) {
+              hi = wt[kc];
+            } else {
 #pragma unroll
-            for (int k = 0; k < VPT; ++k) {
-              // usually no lane of the wave holds an active entry in slot k:
-              // a uniform branch keeps that case to one compare and one max
-              const double x = w[kc][k];
-              const unsigned long long bal = __ballot(x > l);
-              if (bal == 0ull) {
-                hi = fmax(hi, x);
-              } else {
-                const bool in = x > l;
-                n[kc] += __popcll(bal);
-                bits |= (int)in << k;
-                S[kc] += in ? x : 0.0;
-                lo = fmin(lo, in ? x : __builtin_huge_val());
-                hi = fmax(hi, in ? -__builtin_huge_val() : x);
+              for (int k = 0; k < VPT; ++k) {
+                const double x = w[kc][k];
+                const unsigned long long bal = __ballot(x > l);
+                if (bal == 0ull) {
+                  hi = fmax(hi, x);
+                } else {
+                  const bool in = x > l;
+                  n[kc] += __popcll(bal);
+                  bits |= (int)in << k;
+                  S[kc] += in ? x : 0.0;
+                  lo = fmin(lo, in ? x : __builtin_huge_val());
+                  hi = fmax(hi, in ? -__builtin_huge_val() : x);
+                }
               }
             }
             mask[kc] = bits;

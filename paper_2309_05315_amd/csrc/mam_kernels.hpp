@@ -807,15 +807,20 @@ column_kernel(ColArgs<T> a) {
       T told[DIAG ? KC : 1][DIAG ? VPT : 1];
       bool valid[KC];
       int64_t jj[KC];
+      double b2[VPT];  // 2b of this thread's rows, all requested before the first use
+#pragma unroll
+      for (int k = 0; k < VPT; ++k) b2[k] = 2.0 * lds_b[k * NT + tid];
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         valid[kc] = step_col(step, kc, jj[kc]);
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
-          w[kc][k] = ((double)bt[kc][k] + 2.0 * lds_b[k * NT + tid]) - (double)bc[kc][k] * inv_rho;
-          wt[kc] = k == 0 ? w[kc][0] : max_arith(wt[kc], w[kc][k]);
+          w[kc][k] = ((double)bt[kc][k] + b2[k]) - (double)bc[kc][k] * inv_rho;
           if constexpr (DIAG) told[kc][k] = bt[kc][k];
         }
+        wt[kc] = w[kc][0];
+#pragma unroll
+        for (int k = 1; k < VPT; ++k) wt[kc] = max_arith(wt[kc], w[kc][k]);
       }
       // this step's q_s and stored threshold, taken before the buffer is refilled
       double qcol[KC], lcol[KC];

@@ -33,7 +33,10 @@
 // up to summation order.  Started from the column's threshold of the previous
 // iteration, one pass usually both moves to and certifies the root.  The
 // column stays in registers (held as w in double) for all passes; each pass
-// is one compare/select/add per value plus a group reduction.
+// is one compare/select/add per value plus a group reduction, and a wave none
+// of whose values lies above the current threshold (most waves, since active
+// sets are small) settles its part of a pass with one compare of each lane's
+// largest w.
 //
 // Fixed-point row sums.  Every entry is rounded on its own and integer
 // addition is associative, so the sums depend neither on the order in which

@@ -389,3 +389,39 @@ def test_large_rho_regime(dtype):
     d = s.diagnostics()
     say(f"  rho={p.rho:.0f}: rounds/column {d['rounds_per_column']:.2f}, active/column {d['active_per_column']:.1f}")
     assert d["active_per_column"] > 10
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("R,nt", [(1024, 64), (4096, 256), (4096, 1024)])
+def test_threshold_ties_across_waves(dtype, R, nt):
+    """Columns of R rows whose costs take four values only, plus one column
+    of constant cost.  The first iteration starts from theta = q_s / R and
+    b = 0, so w has long runs of exactly equal entries spread over every wave
+    of a column (the constant column ties everywhere: its active set is the
+    whole column).  The projection is unique however the ties fall, so the
+    plans match the oracle entry by entry after one iteration and after
+    fifteen, whichever waves hold the active entries.
+
+    Plan tolerance.  In the constant column lambda comes from a sum of R
+    values of w near -0.5, and pi_hat = w - lambda is only q_s / R: the
+    rounding of that sum (at most about R u max|w| for the oracle's
+    sequential prefix sums, u = 2^-53, |w| <= 1 here) is an absolute error of
+    every plan entry of the column.  The plans are therefore gated at that
+    bound relative to their largest entry when it exceeds the usual
+    tolerance; the barycenter and the marginals keep the usual tolerance."""
+    import dataclasses
+    p = inputs.tiny_problem(41, R=R, S=[6, 5], dtype=dtype, masses=[1.0, 1.0])
+    c = np.round(p.cost * 3.0) / 3.0
+    c[0, :] = 0.5
+    if dtype == "f32":
+        c = c.astype(np.float32).astype(np.float64)
+    p = dataclasses.replace(p, cost=np.ascontiguousarray(c))
+    for iters in (1, 15):
+        g, ora = check(p, iters, gate_theta=False, threads_per_column=nt)
+        for a, b in zip(g["theta"], ora["theta"]):
+            bound = 2.0 * R * 2.0 ** -53 / np.abs(b).max()
+            assert rel(a, b, np.inf) <= max(TOL[dtype], bound)
+        if iters == 1:
+            # the constant column spreads its mass evenly over all rows (up to
+            # the same rounding, cancelled down to q_s / R)
+            np.testing.assert_allclose(np.asarray(g["theta"][0])[:, 0], p.q[0] / p.R, rtol=0, atol=1e-11)
